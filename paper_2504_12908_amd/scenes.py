@@ -1,0 +1,263 @@
+"""Seeded synthetic scene generator (shared input for the GPU library and the oracle).
+
+This module builds geometry and kinematic scripts only: tetrahedral gel pads, closed
+triangle meshes for the rigid (affine) indenters, Dirichlet flags and per-step kinematic
+targets.  It contains none of the simulation method's arithmetic (no energies, no mass
+properties, no contact logic); both solvers derive all of that themselves.
+
+Conventions
+-----------
+* SI units (metres, kilograms, seconds, pascals).
+* Soft body: ``verts`` (n,3) float64, ``tets`` (t,4) int32 with positive orientation,
+  ``dirichlet`` (n,) uint8: 0 free, 1 fixed, 2 moving (prescribed each step).
+* Affine body: ``verts`` (n,3) float64 world positions at creation, ``tris`` (f,3) int32,
+  outward-oriented, closed.
+* Body kinematic target for a step: 12 doubles ``[t0,t1,t2, A00,A01,A02,A10,...,A22]``
+  meaning every creation-pose vertex X0 of that body is mapped to ``A @ X0 + t`` at the
+  end of the step (the paper's kinematic constraints on the affine coordinates, Sec. 3.4 /
+  App. A.5, stated in a frame that does not depend on how a solver parameterises a body).
+* Moving Dirichlet targets for a step: (n_moving,3) world positions, in increasing vertex
+  order of the vertices flagged 2.
+
+Workloads (all lengths in mm in the descriptions, metres in the arrays):
+* ``pad_press_cube(seed)``: 20x20x4 mm pad, Kuhn-split 8x8x2 hex grid (243 verts, 768 tets),
+  bottom fixed; a 10 mm cube offset U(-2,2) mm in x,y from ``default_rng(seed)``, bottom
+  0.05 mm above the pad, lowered 0.05 mm per step for 10 steps, h = 0.01 s.
+* ``pad_press_slide_hull(seed)``: 32x24x6 mm pad on a 32x24x6 grid (5,775 verts,
+  27,648 tets), a 400-point random convex hull (796 tris) of 8 mm extent, 0.05 mm gap,
+  pressed 1.0 mm over 50 steps then slid 2.0 mm in x over 50 steps, h = 0.005 s.
+* ``uniform_batch(n)``: n copies of the 8x8x2 pad, scene i from ``default_rng(1000+i)`` with
+  an 8-point hull (12 tris) of 10 mm extent, xy offset U(-3,3) mm, press depth
+  U(0.3,1.2) mm reached over 10 steps after closing the 0.05 mm gap.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from itertools import permutations
+
+import numpy as np
+
+MM = 1e-3
+
+# Material and contact constants of the pad workloads (E, nu, rho of the gel; rho of the
+# indenter; barrier activation distance and stiffness; Newton tolerance).
+GEL_E = 0.3e6
+GEL_NU = 0.45
+GEL_RHO = 1000.0
+ABD_RHO = 2000.0
+DHAT = 1e-4
+KAPPA = 1e3
+KAPPA_S = 1e8
+NEWTON_TOL = 1e-6
+
+
+@dataclass
+class BodySpec:
+    verts: np.ndarray
+    tris: np.ndarray
+    density: float = ABD_RHO
+    prescribed: bool = True
+
+
+@dataclass
+class SceneSpec:
+    name: str
+    verts: np.ndarray
+    tets: np.ndarray
+    dirichlet: np.ndarray
+    youngs: float
+    poisson: float
+    density: float
+    bodies: list
+    params: dict
+    body_targets: np.ndarray          # (n_steps, n_bodies, 12)
+    dirichlet_targets: np.ndarray     # (n_steps, n_moving, 3)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.body_targets.shape[0])
+
+
+def default_params(h: float) -> dict:
+    return dict(h=h, dhat=DHAT, kappa=KAPPA, kappa_s=KAPPA_S, newton_tol=NEWTON_TOL,
+                gravity=(0.0, 0.0, -9.81), max_newton=100, max_al=30, max_pcg=10000,
+                pcg_eta=1e-4)
+
+
+# ----------------------------------------------------------------------------- meshes
+def kuhn_box(lo, hi, cells):
+    """Box [lo,hi] on an (nx,ny,nz) hex grid, each hex split into the 6 Kuhn tetrahedra.
+
+    Vertex id = i + (nx+1)*(j + (ny+1)*k).  Cells are visited with i fastest, then j, k;
+    inside a cell one tet per permutation of the axes (lexicographic order), following the
+    monotone path corner -> +e_a -> +e_b -> +e_c.  Tets with negative volume get their
+    second and third vertices swapped.
+    """
+    nx, ny, nz = cells
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    xs = [np.linspace(lo[a], hi[a], c + 1) for a, c in enumerate(cells)]
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                             indexing="ij")
+    verts = np.stack([xs[0][ii.ravel()], xs[1][jj.ravel()], xs[2][kk.ravel()]], axis=1)
+
+    def vid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    unit = np.eye(3, dtype=np.int64)
+    tets = []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for perm in permutations(range(3)):
+                    c = np.array([i, j, k])
+                    path = [c.copy()]
+                    for a in perm:
+                        c = c + unit[a]
+                        path.append(c.copy())
+                    t = [vid(*p) for p in path]
+                    p0, p1, p2, p3 = (verts[q] for q in t)
+                    if np.linalg.det(np.stack([p1 - p0, p2 - p0, p3 - p0], axis=1)) < 0:
+                        t[1], t[2] = t[2], t[1]
+                    tets.append(t)
+    return verts, np.asarray(tets, dtype=np.int32)
+
+
+def box_mesh(center, size):
+    """Closed, outward-oriented axis-aligned box surface: 8 verts, 12 tris."""
+    c = np.asarray(center, dtype=np.float64)
+    h = 0.5 * np.asarray(size, dtype=np.float64)
+    signs = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                      [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
+    verts = c + signs * h
+    tris = np.array([[0, 2, 1], [0, 3, 2],      # bottom (-z)
+                     [4, 5, 6], [4, 6, 7],      # top (+z)
+                     [0, 1, 5], [0, 5, 4],      # -y
+                     [1, 2, 6], [1, 6, 5],      # +x
+                     [2, 3, 7], [2, 7, 6],      # +y
+                     [3, 0, 4], [3, 4, 7]],     # -x
+                    dtype=np.int32)
+    return verts, tris
+
+
+def _random_rotation(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def _orient_outward(verts, tris):
+    c = verts.mean(axis=0)
+    out = tris.copy()
+    for f in range(len(out)):
+        a, b, d = verts[out[f]]
+        n = np.cross(b - a, d - a)
+        if np.dot(n, (a + b + d) / 3.0 - c) < 0:
+            out[f, 1], out[f, 2] = out[f, 2], out[f, 1]
+    return out
+
+
+def random_hull(rng, n_points, extent):
+    """n Gaussian directions projected onto a random ellipsoid (semi-axes U(0.6,1)), randomly
+    rotated, scaled so the largest axis-aligned extent equals ``extent``; closed convex-hull
+    triangulation (every point is a hull vertex, so 2n-4 tris), outward oriented, centred at
+    the origin of its bounding box."""
+    from scipy.spatial import ConvexHull
+
+    d = rng.standard_normal((n_points, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    axes = rng.uniform(0.6, 1.0, size=3)
+    pts = (d * axes) @ _random_rotation(rng).T
+    span = pts.max(axis=0) - pts.min(axis=0)
+    pts *= extent / span.max()
+    pts -= 0.5 * (pts.max(axis=0) + pts.min(axis=0))
+    hull = ConvexHull(pts)
+    used = np.unique(hull.simplices)
+    remap = -np.ones(n_points, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    verts = pts[used]
+    tris = remap[hull.simplices].astype(np.int32)
+    return verts, _orient_outward(verts, tris)
+
+
+def translation_targets(offsets):
+    """(n_steps, 3) translations -> (n_steps, 12) targets with A = I."""
+    offsets = np.asarray(offsets, dtype=np.float64)
+    out = np.zeros((len(offsets), 12))
+    out[:, 0:3] = offsets
+    out[:, 3:12] = np.eye(3).ravel()
+    return out
+
+
+def _pad_scene(name, pad_lo, pad_hi, cells, bodies, body_targets, h, meta):
+    verts, tets = kuhn_box(pad_lo, pad_hi, cells)
+    dirichlet = np.zeros(len(verts), dtype=np.uint8)
+    dirichlet[verts[:, 2] == pad_lo[2]] = 1
+    n_steps = body_targets.shape[0]
+    return SceneSpec(name=name, verts=verts, tets=tets, dirichlet=dirichlet,
+                     youngs=GEL_E, poisson=GEL_NU, density=GEL_RHO, bodies=bodies,
+                     params=default_params(h), body_targets=body_targets,
+                     dirichlet_targets=np.zeros((n_steps, 0, 3)), meta=meta)
+
+
+# ----------------------------------------------------------------------------- workloads
+def pad_press_cube(seed: int = 0, n_steps: int = 10) -> SceneSpec:
+    rng = np.random.default_rng(seed)
+    ox, oy = rng.uniform(-2.0, 2.0, size=2) * MM
+    pad_lo = (-10 * MM, -10 * MM, 0.0)
+    pad_hi = (10 * MM, 10 * MM, 4 * MM)
+    gap = 0.05 * MM
+    cube_v, cube_t = box_mesh((ox, oy, pad_hi[2] + gap + 5 * MM), (10 * MM,) * 3)
+    steps = np.arange(1, n_steps + 1)
+    tg = translation_targets(np.stack([0 * steps, 0 * steps, -0.05 * MM * steps], axis=1))
+    return _pad_scene(f"pad_press_cube(seed={seed})", pad_lo, pad_hi, (8, 8, 2),
+                      [BodySpec(cube_v, cube_t)], tg[:, None, :], 0.01,
+                      dict(seed=seed, offset=(ox, oy)))
+
+
+def pad_press_slide_hull(seed: int = 0, n_steps: int = 100, cells=(32, 24, 6),
+                         n_points: int = 400) -> SceneSpec:
+    rng = np.random.default_rng(seed)
+    pad_lo = (-16 * MM, -12 * MM, 0.0)
+    pad_hi = (16 * MM, 12 * MM, 6 * MM)
+    gap = 0.05 * MM
+    hv, ht = random_hull(rng, n_points, 8 * MM)
+    hv = hv + np.array([0.0, 0.0, pad_hi[2] + gap - hv[:, 2].min()])
+    off = np.zeros((n_steps, 3))
+    for s in range(1, n_steps + 1):
+        press = min(s, 50) / 50.0 * 1.0 * MM
+        slide = max(0, s - 50) / 50.0 * 2.0 * MM
+        off[s - 1] = (slide, 0.0, -press)
+    return _pad_scene(f"pad_press_slide_hull(seed={seed})", pad_lo, pad_hi, cells,
+                      [BodySpec(hv, ht)], translation_targets(off)[:, None, :], 0.005,
+                      dict(seed=seed))
+
+
+def batch_member(i: int, n_steps: int = 10) -> SceneSpec:
+    rng = np.random.default_rng(1000 + i)
+    pad_lo = (-10 * MM, -10 * MM, 0.0)
+    pad_hi = (10 * MM, 10 * MM, 4 * MM)
+    gap = 0.05 * MM
+    hv, ht = random_hull(rng, 8, 10 * MM)
+    ox, oy = rng.uniform(-3.0, 3.0, size=2) * MM
+    depth = rng.uniform(0.3, 1.2) * MM
+    hv = hv + np.array([ox, oy, pad_hi[2] + gap - hv[:, 2].min()])
+    steps = np.arange(1, n_steps + 1)
+    dz = -(depth + gap) * steps / n_steps
+    tg = translation_targets(np.stack([0 * dz, 0 * dz, dz], axis=1))
+    return _pad_scene(f"uniform_batch[{i}]", pad_lo, pad_hi, (8, 8, 2),
+                      [BodySpec(hv, ht)], tg[:, None, :], 0.01,
+                      dict(index=i, offset=(ox, oy), depth=depth))
+
+
+def uniform_batch(n: int = 256, n_steps: int = 10):
+    return [batch_member(i, n_steps) for i in range(n)]
+
+
+def apply_target(X0: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """World positions of creation-pose vertices X0 under a 12-double target q."""
+    A = np.asarray(q[3:12]).reshape(3, 3)
+    return X0 @ A.T + np.asarray(q[0:3])
