@@ -1,0 +1,186 @@
+/* taccel: incremental-potential-contact (IPC) time step of a tetrahedral neo-Hookean gel
+ * pad in contact with affine (ABD) rigid bodies, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Taccel, arXiv 2504.12908.  One call of taccel_step / taccel_batch_step advances
+ * every scene by one backward-Euler step, x^{n+1} = argmin E(x) with
+ *   E = 1/2 |x - x^n - h v^n|^2_M + h^2 (Phi_neoHookean + E_ext) + h^2 kappa sum_k b(d_k)
+ * plus the affine-body terms and kinematic constraints (Sec. 3.2 Eq. 1, Sec. 3.3 Eq. 3-5,
+ * Sec. 3.4 Eq. 6; App. A.1-A.5; barrier App. A.3 Eq. A6).  The minimiser is found by a
+ * projected Newton method with block-Jacobi PCG, additive CCD and a backtracking line search.
+ *
+ * Conventions: SI units; 0-based int32 indices; arrays written [n][k] are row-major,
+ * host memory unless a name ends in _device.  Inputs are borrowed for the duration of the
+ * call and copied; the library owns all device state of a scene/batch until destroy.  No
+ * exceptions cross this boundary.  A scene or batch is not thread-safe; distinct objects on
+ * distinct streams are.
+ */
+#ifndef TACCEL_H
+#define TACCEL_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TACCEL_OK = 0,
+  TACCEL_ERR_ARG = 1,              /* bad sizes, indices, degenerate/inverted tets, open body */
+  TACCEL_ERR_HIP = 2,              /* HIP runtime failure (message in taccel_last_error) */
+  TACCEL_NOT_CONVERGED = 3,        /* Newton did not reach the tolerance in max_newton iterations */
+  TACCEL_LINESEARCH_FAILED = 4,    /* step size fell below 1e-12 */
+  TACCEL_AL_FAILED = 5,            /* kinematic targets not met after max_al rounds */
+  TACCEL_NAN = 6,                  /* non-finite gradient or singular preconditioner */
+  TACCEL_INFEASIBLE_TARGET = 7,    /* moving Dirichlet targets would collide or invert */
+  TACCEL_ERR_OOM = 8,              /* device allocation failed */
+  TACCEL_INFEASIBLE = 9            /* initial state interpenetrates or is inverted */
+} taccel_status;
+
+typedef enum { TACCEL_FP64 = 0, TACCEL_MIXED = 1 } taccel_precision;
+
+/* Soft body (the gel pad): nv rest vertices, nt tets of positive orientation.
+ * dirichlet[i]: 0 free, 1 fixed, 2 moving (position prescribed each step); NULL = all free.
+ * Young's modulus E, Poisson ratio nu (neo-Hookean, Sec. 3.1), density rho (lumped mass). */
+typedef struct {
+  int32_t nv;
+  const double* verts;      /* [nv][3] rest = initial positions */
+  int32_t nt;
+  const int32_t* tets;      /* [nt][4] */
+  const uint8_t* dirichlet; /* [nv] or NULL */
+  double youngs, poisson, density;
+} taccel_soft_desc;
+
+/* Affine body (Sec. 3.3): closed, outward-oriented triangle mesh given by its world vertex
+ * positions at creation.  Mass properties come from its enclosed volume.  prescribed = 1:
+ * the body follows a kinematic target each step (augmented Lagrangian, Sec. 3.4). */
+typedef struct {
+  int32_t nv;
+  const double* verts;   /* [nv][3] */
+  int32_t nf;
+  const int32_t* tris;   /* [nf][3], local indices */
+  double density;
+  int32_t prescribed;
+} taccel_body_desc;
+
+typedef struct {
+  double h;           /* time step (s) */
+  double dhat;        /* barrier activation distance (m) */
+  double kappa;       /* barrier stiffness */
+  double kappa_s;     /* affine-body ARAP stiffness (Pa) */
+  double newton_tol;  /* Newton stops when max |dx| <= newton_tol * h * L (L: rest bbox diag) */
+  double gravity[3];
+  int32_t max_newton; /* per Newton loop; 0 -> 100 */
+  int32_t max_al;     /* augmented-Lagrangian rounds; 0 -> 30 */
+  int32_t max_pcg;    /* 0 -> 10000 */
+  double pcg_eta;     /* relative residual of PCG; 0 -> 1e-4 */
+  int32_t precision;  /* taccel_precision */
+} taccel_params;
+
+typedef struct {
+  taccel_soft_desc soft;
+  int32_t n_bodies;
+  const taccel_body_desc* bodies;
+  taccel_params params;
+} taccel_scene_desc;
+
+/* Device memory and stream.  alloc/free may be NULL (then hipMalloc/hipFree); stream NULL
+ * = the null stream.  The library enqueues all device work on `stream`. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+  void* stream; /* hipStream_t */
+} taccel_runtime;
+
+/* Kinematic targets for one step of one scene.
+ * body_targets: [n_bodies][12] = (t[3], A row-major[9]); a creation-pose vertex X0 of a
+ *   prescribed body is to be at A X0 + t at the end of the step (ignored for free bodies).
+ * dirichlet_targets: [n_moving][3] end-of-step positions of the vertices flagged 2, in
+ *   increasing vertex order.  Either pointer may be NULL if there is nothing to prescribe. */
+typedef struct {
+  const double* body_targets;
+  const double* dirichlet_targets;
+} taccel_targets;
+
+typedef struct {
+  int32_t status;        /* taccel_status of this scene */
+  int32_t newton_iters;  /* summed over the step's Newton loops */
+  int32_t al_rounds;     /* Newton loops of the step */
+  int32_t pcg_iters;     /* summed PCG iterations */
+  int32_t n_active;      /* contact pairs with d < dhat in the last Newton iteration */
+  int32_t ls_halvings;   /* summed line-search halvings */
+  double step_ms;        /* wall time of the call (batch: same for all scenes) */
+} taccel_step_stats;
+
+typedef enum {
+  TACCEL_FIELD_X = 0,    /* double[nv][3] soft-vertex positions */
+  TACCEL_FIELD_V = 1,    /* double[nv][3] soft-vertex velocities */
+  TACCEL_FIELD_Q = 2,    /* double[n_bodies][12] body maps (t, A row-major) of creation pose */
+  TACCEL_FIELD_QDOT = 3, /* double[n_bodies][12] their rates */
+  TACCEL_FIELD_BODY_X = 4 /* double[sum body nv][3] body vertex world positions (read only) */
+} taccel_field;
+
+typedef struct taccel_scene taccel_scene;
+typedef struct taccel_batch taccel_batch;
+
+/* Create one scene.  rt may be NULL.  Errors: ARG (bad sizes/indices, degenerate or
+ * inverted tets, body without positive volume), INFEASIBLE (some admissible contact pair is
+ * at distance 0), OOM, HIP. */
+taccel_status taccel_scene_create(const taccel_scene_desc* d, const taccel_runtime* rt,
+                                  taccel_scene** out);
+/* Advance one time step (synchronous: returns after the device work is done).  targets may
+ * be NULL when nothing is prescribed.  On a failure status the scene is rolled back to the
+ * start of the step; stats (nullable) is filled in any case. */
+taccel_status taccel_step(taccel_scene* s, const taccel_targets* targets, taccel_step_stats* stats);
+/* Copy a field to caller-owned host memory; bytes must equal the field size (else ARG). */
+taccel_status taccel_state_read(const taccel_scene* s, taccel_field f, void* dst, size_t bytes);
+/* Overwrite X, V, Q or QDOT (reset / resume). */
+taccel_status taccel_state_write(taccel_scene* s, taccel_field f, const void* src, size_t bytes);
+void taccel_scene_destroy(taccel_scene* s);
+
+/* n independent scenes solved together: every stage is one launch over all scenes,
+ * reductions are per scene, a scene that fails is rolled back without affecting others. */
+taccel_status taccel_batch_create(const taccel_scene_desc* descs, int32_t n,
+                                  const taccel_runtime* rt, taccel_batch** out);
+/* targets: [n] (NULL = none); per_scene (nullable): [n] statuses; stats (nullable): [n].
+ * Returns OK if every scene succeeded, else the first failing scene's status. */
+taccel_status taccel_batch_step(taccel_batch* b, const taccel_targets* targets,
+                                taccel_status* per_scene, taccel_step_stats* stats);
+taccel_status taccel_batch_read(const taccel_batch* b, int32_t scene, taccel_field f, void* dst,
+                                size_t bytes);
+taccel_status taccel_batch_write(taccel_batch* b, int32_t scene, taccel_field f, const void* src,
+                                 size_t bytes);
+void taccel_batch_destroy(taccel_batch* b);
+
+/* Thread-local text of the last error of this thread (empty if none). */
+const char* taccel_last_error(void);
+const char* taccel_status_str(taccel_status s);
+
+/* ---- Element evaluators (run the solver's own device code; for tests) -------------------
+ * Neo-Hookean tets: rest, x [n][4][3]; outputs e [n] (V Psi), g [n][12], H and Hp [n][12][12]
+ * (unprojected / projected Hessian of V Psi).  Any output may be NULL. */
+taccel_status taccel_debug_fem(int32_t n, const double* rest, const double* x, double youngs,
+                               double poisson, double* e, double* g, double* H, double* Hp);
+/* Barrier pairs: kinds [n] (0 point-triangle, 1 edge-edge), x [n][4][3] in local order
+ * (PT: p,t0,t1,t2; EE: a0,a1,b0,b1), mollifier_eps [n] (EE: 1e-3 |a|^2_rest |b|^2_rest).
+ * Outputs kappa*m*b(d), gradient, Hessians, distance type.  Any output may be NULL. */
+taccel_status taccel_debug_barrier(int32_t n, const int32_t* kinds, const double* x,
+                                   const double* mollifier_eps, double dhat, double kappa,
+                                   double* e, double* g, double* H, double* Hp, int32_t* types);
+/* Additive CCD of n pairs moving linearly by p: largest safe fraction t in [0,1]. */
+taccel_status taccel_debug_ccd(int32_t n, const int32_t* kinds, const double* x, const double* p,
+                               double gap_ratio, int32_t max_iter, double* t);
+/* ARAP term |A - R(A)|^2 of n 3x3 matrices (row-major): e, g [n][9], H, Hp [n][9][9]. */
+taccel_status taccel_debug_arap(int32_t n, const double* A, double* e, double* g, double* H,
+                                double* Hp);
+/* Broad phase of a scene on given world positions P0 (and P1 for the swept test, or NULL):
+ * world vertex ids are soft vertices 0..nv-1 then body vertices in order.  Writes up to cap
+ * candidates as 5 int32 (kind, four world ids: PT point + sorted triangle; EE sorted edges,
+ * smaller edge first) and the total count to *n. */
+taccel_status taccel_debug_candidates(taccel_scene* s, const double* P0, const double* P1,
+                                      int32_t* out, int32_t cap, int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

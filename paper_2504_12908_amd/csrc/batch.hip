@@ -1,0 +1,1413 @@
+// Host side of the batched IPC time step: scene setup (mesh topology, mass properties,
+// sparsity pattern) and the per-step Newton / augmented-Lagrangian state machine.  All
+// arithmetic of a step runs in the kernels of kernels.hip; the host only launches them,
+// reads back a handful of per-scene flags and takes the control decisions.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "prims.h"
+
+namespace tc {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+struct ApiError : std::runtime_error {
+  taccel_status st;
+  ApiError(taccel_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHECK(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      throw ApiError(_e == hipErrorOutOfMemory ? TACCEL_ERR_OOM : TACCEL_ERR_HIP,       \
+                     std::string(#expr) + ": " + hipGetErrorString(_e));                \
+  } while (0)
+
+// ------------------------------------------------------------------ device memory
+struct Mem {
+  taccel_runtime rt{};
+  hipStream_t stream = nullptr;
+  void* alloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (rt.alloc) {
+      p = rt.alloc(bytes, rt.ctx);
+      if (!p) throw ApiError(TACCEL_ERR_OOM, "runtime allocator returned NULL");
+    } else {
+      HIPCHECK(hipMalloc(&p, bytes));
+    }
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    if (rt.free) rt.free(p, rt.ctx);
+    else (void)hipFree(p);
+  }
+};
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  Mem* m = nullptr;
+  void ensure(Mem* mem, size_t n) {
+    m = mem;
+    if (n <= cap && p) return;
+    if (p) m->release(p);
+    const size_t c = std::max<size_t>(n, cap + cap / 2);
+    p = static_cast<T*>(m->alloc(sizeof(T) * std::max<size_t>(c, 1)));
+    cap = c;
+  }
+  void upload(Mem* mem, const std::vector<T>& h) {
+    ensure(mem, h.size());
+    if (!h.empty())
+      HIPCHECK(hipMemcpyAsync(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, m->stream));
+  }
+  void free() {
+    if (p && m) m->release(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// ------------------------------------------------------------------ host-side scene data
+struct HostBody {
+  int nv = 0, nf = 0;
+  double com0[3] = {0, 0, 0};
+  std::vector<double> xbar;  // [nv][3]
+  bool prescribed = false;
+  double r0 = 0, rprev = 0;
+};
+struct HostScene {
+  int nv = 0, nb = 0, n_moving = 0;
+  int node0 = 0, node1 = 0;
+  std::vector<int> moving;  // soft vertex ids flagged 2
+  std::vector<HostBody> bodies;
+  std::vector<int> cv_world;  // world id per contact vertex of the scene
+  int cv0 = 0, cv1 = 0, tri0 = 0, tri1 = 0, edge0 = 0, edge1 = 0;
+  double stop = 0, h = 0;
+  int max_newton = 100, max_al = 30, max_pcg = 10000;
+};
+
+// Volume integrals of 1, x, x x^T of a closed triangle mesh by the divergence theorem,
+// reduced to per-face polynomial sums (Eberly, "Polyhedral Mass Properties").
+static void polyhedron_integrals(const double* v, int nf, const int32_t* tris, double out[10]) {
+  for (int k = 0; k < 10; ++k) out[k] = 0.0;
+  auto sub = [](double w0, double w1, double w2, double& f1, double& f2, double& f3, double& g0,
+                double& g1, double& g2) {
+    const double t0 = w0 + w1;
+    f1 = t0 + w2;
+    const double t1 = w0 * w0;
+    const double t2 = t1 + w1 * t0;
+    f2 = t2 + w2 * f1;
+    f3 = w0 * t1 + w1 * t2 + w2 * f2;
+    g0 = f2 + w0 * (f1 + w0);
+    g1 = f2 + w1 * (f1 + w1);
+    g2 = f2 + w2 * (f1 + w2);
+  };
+  for (int f = 0; f < nf; ++f) {
+    const double* p0 = v + 3 * tris[3 * f];
+    const double* p1 = v + 3 * tris[3 * f + 1];
+    const double* p2 = v + 3 * tris[3 * f + 2];
+    const double a[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    const double b[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+    const double d[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    double f1x, f2x, f3x, g0x, g1x, g2x, f1y, f2y, f3y, g0y, g1y, g2y, f1z, f2z, f3z, g0z, g1z, g2z;
+    sub(p0[0], p1[0], p2[0], f1x, f2x, f3x, g0x, g1x, g2x);
+    sub(p0[1], p1[1], p2[1], f1y, f2y, f3y, g0y, g1y, g2y);
+    sub(p0[2], p1[2], p2[2], f1z, f2z, f3z, g0z, g1z, g2z);
+    out[0] += d[0] * f1x;
+    out[1] += d[0] * f2x;
+    out[2] += d[1] * f2y;
+    out[3] += d[2] * f2z;
+    out[4] += d[0] * f3x;
+    out[5] += d[1] * f3y;
+    out[6] += d[2] * f3z;
+    out[7] += d[0] * (p0[1] * g0x + p1[1] * g1x + p2[1] * g2x);
+    out[8] += d[1] * (p0[2] * g0y + p1[2] * g1y + p2[2] * g2y);
+    out[9] += d[2] * (p0[0] * g0z + p1[0] * g1z + p2[0] * g2z);
+  }
+  out[0] /= 6.0;
+  for (int k = 1; k < 4; ++k) out[k] /= 24.0;
+  for (int k = 4; k < 7; ++k) out[k] /= 60.0;
+  for (int k = 7; k < 10; ++k) out[k] /= 120.0;
+}
+
+static void inverse3(const double* A, double* out) {
+  const double c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
+  const double det = A[0] * c0 + A[1] * c1 + A[2] * c2;
+  out[0] = c0 / det;
+  out[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+  out[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+  out[3] = c1 / det;
+  out[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+  out[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+  out[6] = c2 / det;
+  out[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+  out[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+// ------------------------------------------------------------------ implementation
+struct Batch::Impl {
+  Mem mem;
+  int S = 0, Nn = 0, Nt = 0, Nb = 0, Ncv = 0, Ntr = 0, Ned = 0, Nq = 0, nnz = 0;
+  std::vector<HostScene> hs;
+  std::vector<SceneConst> hsc;
+  std::vector<int> h_ntype, h_nscene, h_bnode, h_bscene, h_bpres, h_moving_nodes;
+  // static device data
+  DBuf<SceneConst> d_sc;
+  DBuf<double> x, xn, xhat, v, mass;
+  DBuf<int> nfree, nscene, nbody, ntype;
+  DBuf<int> tv, tscene;
+  DBuf<double> Dminv, tvol, Hloc, gloc;
+  DBuf<int> rowptr, col, diag, cptr, clist, vptr, vlist, brow;
+  DBuf<double> val;
+  DBuf<int> bnode, bscene, bpres, bsnap, bcv0, bcv1;
+  DBuf<double> bmass, bvol, bstar, blam, bkap, bgrad, bhess, bpinv;
+  DBuf<int> cvn, cvb, cvfix, cvscene, cvworld, trv, edv, qkind, qidx, qscene;
+  DBuf<double> cvx, cpos, cdisp, cend, elen2;
+  DBuf<int> act, pdone;
+  // block tables
+  DBuf<int> tn_sc, tn_b0, tn_b1, tn_sblk, tt_sc, tt_b0, tt_b1, tt_sblk;
+  BlockTable TN, TT;
+  // dynamic work buffers
+  BroadPhase bp;
+  DBuf<double> bp_tbox;
+  DBuf<int> bp_tcell, bp_tncell, bp_toff, bp_bcount, bp_bstart, bp_bfill, bp_qcount, bp_qoff;
+  DBuf<int4> bp_entries;
+  DBuf<int> cq, ct, sq, st, cflag, cpos_idx;
+  DBuf<int> pkind, pv, pscene;
+  DBuf<double> pmeps, pg, ph;
+  DBuf<int> hcnt, gcnt, hoff, goff, hidx, gidx, hsrc, gsrc, hidx2, gidx2;
+  DBuf<uint64_t> hkey, gkey, hkey2, gkey2;
+  DBuf<double> hcoef, gcoef;
+  DBuf<int> sflag, segid, segstart, drow, dcol, rowcnt, drowptr;
+  DBuf<double> dval;
+  DBuf<double> g, r, z, p, q, dx, pinv;
+  DBuf<double> P_pq, P_rz0, P_rz1, P_rr, P_gg;
+  DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
+  DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
+  DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs;
+  DBuf<int> scalars;  // device scalars for scan totals
+  DBuf<char> scratch;
+  // pinned host staging
+  int* h_pin = nullptr;
+  size_t h_pin_bytes = 0;
+
+  View view() const {
+    View V;
+    V.S = S; V.Nn = Nn; V.Nt = Nt; V.Nb = Nb; V.Ncv = Ncv; V.Ntr = Ntr; V.Ned = Ned; V.Nq = Nq;
+    V.sc = d_sc.p;
+    V.x = x.p; V.xn = xn.p; V.xhat = xhat.p; V.v = v.p; V.mass = mass.p;
+    V.nfree = nfree.p; V.nscene = nscene.p; V.nbody = nbody.p; V.ntype = ntype.p;
+    V.tv = tv.p; V.Dminv = Dminv.p; V.tvol = tvol.p; V.tscene = tscene.p; V.Hloc = Hloc.p; V.gloc = gloc.p;
+    V.rowptr = rowptr.p; V.col = col.p; V.val = val.p; V.diag = diag.p; V.cptr = cptr.p; V.clist = clist.p;
+    V.vptr = vptr.p; V.vlist = vlist.p;
+    V.bnode = bnode.p; V.bscene = bscene.p; V.bmass = bmass.p; V.bvol = bvol.p; V.bpres = bpres.p;
+    V.bstar = bstar.p; V.blam = blam.p; V.bkap = bkap.p; V.bsnap = bsnap.p; V.bgrad = bgrad.p;
+    V.bhess = bhess.p; V.bpinv = bpinv.p; V.bcv0 = bcv0.p; V.bcv1 = bcv1.p;
+    V.cvn = cvn.p; V.cvb = cvb.p; V.cvx = cvx.p; V.cvfix = cvfix.p; V.cvscene = cvscene.p;
+    V.cvworld = cvworld.p; V.cpos = cpos.p; V.cdisp = cdisp.p; V.trv = trv.p; V.edv = edv.p;
+    V.elen2 = elen2.p; V.qkind = qkind.p; V.qidx = qidx.p; V.qscene = qscene.p;
+    V.act = act.p; V.pdone = pdone.p;
+    return V;
+  }
+
+  hipStream_t stream() const { return mem.stream; }
+  void sync() { HIPCHECK(hipStreamSynchronize(mem.stream)); }
+  template <class T>
+  void d2h(T* dst, const T* src, size_t n) {
+    if (n) HIPCHECK(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyDeviceToHost, mem.stream));
+  }
+  template <class T>
+  void h2d(T* dst, const T* src, size_t n) {
+    if (n) HIPCHECK(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyHostToDevice, mem.stream));
+  }
+  void zero(void* p, size_t bytes) {
+    if (bytes) HIPCHECK(hipMemsetAsync(p, 0, bytes, mem.stream));
+  }
+  int read_int(const int* d) {
+    int v = 0;
+    d2h(&v, d, 1);
+    sync();
+    return v;
+  }
+  void ensure_scratch(size_t bytes) { scratch.ensure(&mem, bytes); }
+  int scan(const int* in, int* out, int n) {
+    ensure_scratch(scan_scratch_bytes(n));
+    HIPCHECK(exclusive_scan(in, out, n, scalars.p, scratch.p, mem.stream));
+    return read_int(scalars.p);
+  }
+  void sort(uint64_t* keys, int* vals, uint64_t* tk, int* tv_, int n, int bits) {
+    ensure_scratch(sort_scratch_bytes(n));
+    HIPCHECK(radix_sort_pairs(keys, vals, tk, tv_, n, bits, scratch.p, mem.stream));
+  }
+
+  void build(const taccel_scene_desc* d, int n);
+  int broad_phase(const double* P0, const double* P1, int all, DBuf<int>& oq, DBuf<int>& ot);
+  void newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail, std::vector<int>& nan_,
+                        std::vector<int>& pcg_it, std::vector<int>& n_active, std::vector<int>& halvings);
+  taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st);
+  void release_all();
+};
+
+static int bits_for(uint64_t v) {
+  int b = 1;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+// ------------------------------------------------------------------ setup
+void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
+  S = n;
+  hs.resize(S);
+  hsc.resize(S);
+  std::vector<double> h_x, h_mass, h_Dminv_aos, h_tvol;
+  std::vector<int> h_nfree, h_nbody, h_tv_aos, h_tscene;
+  std::vector<int> h_bcv0, h_bcv1;
+  std::vector<double> h_bmass, h_bvol;
+  std::vector<int> h_cvn, h_cvb, h_cvfix, h_cvscene, h_cvworld, h_trv, h_edv, h_qkind, h_qidx, h_qscene;
+  std::vector<double> h_cvx, h_elen2;
+  std::vector<int> tn_sc_h, tn_b0_h, tn_b1_h, tn_sblk_h, tt_sc_h, tt_b0_h, tt_b1_h, tt_sblk_h;
+  // static BSR built per scene and concatenated
+  std::vector<int> h_rowptr(1, 0), h_col, h_diag, h_cptr(1, 0), h_clist, h_vptr(1, 0), h_vlist, h_brow;
+  for (int s = 0; s < S; ++s) {
+    const taccel_scene_desc& d = descs[s];
+    HostScene& H = hs[s];
+    const taccel_params& P = d.params;
+    if (!(P.h > 0) || !(P.dhat > 0) || !(P.kappa >= 0) || !(P.newton_tol > 0))
+      throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(s) + ": h, dhat, newton_tol must be > 0");
+    const int nv = d.soft.nv, nt = d.soft.nt, nb = d.n_bodies;
+    if (nv < 0 || nt < 0 || nb < 0 || (nv > 0 && !d.soft.verts) || (nt > 0 && !d.soft.tets) ||
+        (nb > 0 && !d.bodies))
+      throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(s) + ": bad soft/body sizes");
+    H.nv = nv;
+    H.nb = nb;
+    H.h = P.h;
+    H.max_newton = P.max_newton > 0 ? P.max_newton : 100;
+    H.max_al = P.max_al > 0 ? P.max_al : 30;
+    H.max_pcg = P.max_pcg > 0 ? P.max_pcg : 10000;
+    SceneConst& C = hsc[s];
+    std::memset(&C, 0, sizeof(C));
+    C.h = P.h;
+    C.dhat = P.dhat;
+    C.kappa = P.kappa;
+    C.kappa_s = P.kappa_s;
+    C.mu = d.soft.youngs / (2.0 * (1.0 + d.soft.poisson));
+    C.lam = d.soft.youngs * d.soft.poisson / ((1.0 + d.soft.poisson) * (1.0 - 2.0 * d.soft.poisson));
+    C.pcg_eta = P.pcg_eta > 0 ? P.pcg_eta : 1e-4;
+    for (int c = 0; c < 3; ++c) C.grav[c] = P.gravity[c];
+    C.precision = P.precision;
+    // ---- nodes
+    const int node0 = Nn;
+    H.node0 = node0;
+    const int n_soft_pad = (nv + 3) / 4 * 4;
+    const int nn = n_soft_pad + 4 * nb;
+    C.node0 = node0;
+    C.node1 = node0 + nn;
+    H.node1 = C.node1;
+    h_x.resize(3 * (size_t)(node0 + nn), 0.0);
+    h_mass.resize(node0 + nn, 0.0);
+    h_nfree.resize(node0 + nn, 0);
+    h_nbody.resize(node0 + nn, -1);
+    h_ntype.resize(node0 + nn, 3);
+    h_nscene.resize(node0 + nn, s);
+    for (int i = 0; i < nv; ++i) {
+      for (int c = 0; c < 3; ++c) h_x[3 * (size_t)(node0 + i) + c] = d.soft.verts[3 * i + c];
+      const int flag = d.soft.dirichlet ? d.soft.dirichlet[i] : 0;
+      if (flag > 2) throw ApiError(TACCEL_ERR_ARG, "dirichlet flag must be 0, 1 or 2");
+      h_nfree[node0 + i] = flag == 0;
+      h_ntype[node0 + i] = 0;
+      if (flag == 2) {
+        H.moving.push_back(i);
+        h_moving_nodes.push_back(node0 + i);
+      }
+    }
+    H.n_moving = (int)H.moving.size();
+    // ---- tets
+    const int tet0 = Nt;
+    C.tet0 = tet0;
+    C.tet1 = tet0 + nt;
+    std::vector<std::vector<int>> adj(nv);
+    std::vector<std::vector<int>> inc(nv);  // tet*4 + a (global tet ids)
+    for (int e = 0; e < nt; ++e) {
+      int t[4];
+      for (int a = 0; a < 4; ++a) {
+        t[a] = d.soft.tets[4 * e + a];
+        if (t[a] < 0 || t[a] >= nv) throw ApiError(TACCEL_ERR_ARG, "tet index out of range");
+      }
+      double Dm[9];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) Dm[3 * i + k] = d.soft.verts[3 * t[k + 1] + i] - d.soft.verts[3 * t[0] + i];
+      const double det = Dm[0] * (Dm[4] * Dm[8] - Dm[5] * Dm[7]) - Dm[1] * (Dm[3] * Dm[8] - Dm[5] * Dm[6]) +
+                         Dm[2] * (Dm[3] * Dm[7] - Dm[4] * Dm[6]);
+      if (!(det > 0.0)) throw ApiError(TACCEL_ERR_ARG, "inverted or degenerate tet " + std::to_string(e));
+      double Di[9];
+      inverse3(Dm, Di);
+      for (int k = 0; k < 9; ++k) h_Dminv_aos.push_back(Di[k]);
+      const double vol = det / 6.0;
+      h_tvol.push_back(vol);
+      for (int a = 0; a < 4; ++a) {
+        h_tv_aos.push_back(node0 + t[a]);
+        h_mass[node0 + t[a]] += d.soft.density * vol / 4.0;
+        inc[t[a]].push_back(4 * (tet0 + e) + a);
+        for (int b = 0; b < 4; ++b) adj[t[a]].push_back(t[b]);
+      }
+      h_tscene.push_back(s);
+    }
+    // static BSR rows for every node of the scene (soft rows carry the FEM pattern)
+    for (int i = 0; i < nn; ++i) {
+      const int node = node0 + i;
+      if (i < nv) {
+        std::vector<int>& a = adj[i];
+        a.push_back(i);
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+        int dpos = -1;
+        for (int j : a) {
+          if (j == i) dpos = (int)h_col.size();
+          h_col.push_back(node0 + j);
+          h_brow.push_back(node);
+          // contributions (tet, a, b) with tet vertex a = i and b = j
+          for (int code : inc[i]) {
+            const int tet = code >> 2, la = code & 3;
+            for (int lb = 0; lb < 4; ++lb)
+              if (h_tv_aos[4 * tet + lb] == node0 + j) h_clist.push_back(16 * tet + 4 * la + lb);
+          }
+          h_cptr.push_back((int)h_clist.size());
+        }
+        h_diag.push_back(dpos);
+        for (int code : inc[i]) h_vlist.push_back(code);
+      } else {
+        h_diag.push_back(-1);
+      }
+      h_rowptr.push_back((int)h_col.size());
+      h_vptr.push_back((int)h_vlist.size());
+    }
+    // ---- contact surface: boundary faces of the tet mesh
+    struct Face { int k[3]; int o[3]; };
+    std::vector<Face> faces;
+    faces.reserve(4 * (size_t)nt);
+    for (int e = 0; e < nt; ++e) {
+      const int* t = d.soft.tets + 4 * e;
+      const int f[4][3] = {{t[1], t[2], t[3]}, {t[0], t[3], t[2]}, {t[0], t[1], t[3]}, {t[0], t[2], t[1]}};
+      for (int k = 0; k < 4; ++k) {
+        Face F;
+        for (int j = 0; j < 3; ++j) F.o[j] = F.k[j] = f[k][j];
+        std::sort(F.k, F.k + 3);
+        faces.push_back(F);
+      }
+    }
+    std::sort(faces.begin(), faces.end(), [](const Face& a, const Face& b) {
+      return std::lexicographical_compare(a.k, a.k + 3, b.k, b.k + 3);
+    });
+    std::vector<std::array<int, 3>> bfaces;
+    for (size_t i = 0; i < faces.size();) {
+      size_t j = i + 1;
+      while (j < faces.size() && std::equal(faces[i].k, faces[i].k + 3, faces[j].k)) ++j;
+      if (j - i == 1) bfaces.push_back({faces[i].o[0], faces[i].o[1], faces[i].o[2]});
+      else if (j - i > 2) throw ApiError(TACCEL_ERR_ARG, "non-manifold tet mesh (face shared by >2 tets)");
+      i = j;
+    }
+    std::vector<int> soft_cv(nv, -1);
+    for (const auto& f : bfaces)
+      for (int k = 0; k < 3; ++k) soft_cv[f[k]] = 0;
+    const int cv0 = Ncv;
+    H.cv0 = cv0;
+    int ncv = 0;
+    for (int i = 0; i < nv; ++i)
+      if (soft_cv[i] == 0) {
+        soft_cv[i] = cv0 + ncv++;
+        h_cvn.push_back(node0 + i);
+        h_cvb.push_back(-1);
+        for (int c = 0; c < 3; ++c) h_cvx.push_back(0.0);
+        const int flag = d.soft.dirichlet ? d.soft.dirichlet[i] : 0;
+        h_cvfix.push_back(flag == 1);
+        h_cvscene.push_back(s);
+        h_cvworld.push_back(i);
+        H.cv_world.push_back(i);
+      }
+    std::vector<std::array<int, 3>> tris;
+    for (const auto& f : bfaces) tris.push_back({soft_cv[f[0]], soft_cv[f[1]], soft_cv[f[2]]});
+    // ---- affine bodies
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < nv; ++i)
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(lo[c], d.soft.verts[3 * i + c]);
+        hi[c] = std::max(hi[c], d.soft.verts[3 * i + c]);
+      }
+    C.body0 = Nb;
+    int world = nv;
+    for (int b = 0; b < nb; ++b) {
+      const taccel_body_desc& B = d.bodies[b];
+      if (B.nv < 4 || B.nf < 4 || !B.verts || !B.tris || !(B.density > 0))
+        throw ApiError(TACCEL_ERR_ARG, "affine body needs >= 4 vertices, >= 4 faces, density > 0");
+      for (int k = 0; k < 3 * B.nf; ++k)
+        if (B.tris[k] < 0 || B.tris[k] >= B.nv) throw ApiError(TACCEL_ERR_ARG, "body triangle index out of range");
+      double I[10];
+      polyhedron_integrals(B.verts, B.nf, B.tris, I);
+      const double vol = I[0];
+      if (!(vol > 0.0)) throw ApiError(TACCEL_ERR_ARG, "affine body encloses no positive volume");
+      HostBody hb;
+      hb.nv = B.nv;
+      hb.nf = B.nf;
+      hb.prescribed = B.prescribed != 0;
+      for (int c = 0; c < 3; ++c) hb.com0[c] = I[1 + c] / vol;
+      const double sm[9] = {I[4], I[7], I[9], I[7], I[5], I[8], I[9], I[8], I[6]};
+      h_bmass.push_back(B.density * vol);
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) h_bmass.push_back(B.density * (sm[3 * a + c] - vol * hb.com0[a] * hb.com0[c]));
+      h_bvol.push_back(vol);
+      const int bn = node0 + n_soft_pad + 4 * b;
+      h_bnode.push_back(bn);
+      h_bscene.push_back(s);
+      h_bpres.push_back(hb.prescribed);
+      for (int u = 0; u < 4; ++u) {
+        h_nbody[bn + u] = Nb + b;
+        h_ntype[bn + u] = u == 0 ? 1 : 2;
+        h_nfree[bn + u] = 1;
+      }
+      for (int c = 0; c < 3; ++c) {
+        h_x[3 * (size_t)bn + c] = hb.com0[c];
+        h_x[3 * (size_t)(bn + 1 + c) + c] = 1.0;
+      }
+      const int bcv = cv0 + ncv;
+      h_bcv0.push_back(bcv);
+      for (int k = 0; k < B.nv; ++k) {
+        for (int c = 0; c < 3; ++c) {
+          const double xb = B.verts[3 * k + c] - hb.com0[c];
+          hb.xbar.push_back(xb);
+          h_cvx.push_back(xb);
+          lo[c] = std::min(lo[c], B.verts[3 * k + c]);
+          hi[c] = std::max(hi[c], B.verts[3 * k + c]);
+        }
+        h_cvn.push_back(-1);
+        h_cvb.push_back(Nb + b);
+        h_cvfix.push_back(0);
+        h_cvscene.push_back(s);
+        h_cvworld.push_back(world + k);
+        H.cv_world.push_back(world + k);
+      }
+      for (int f = 0; f < B.nf; ++f)
+        tris.push_back({bcv + B.tris[3 * f], bcv + B.tris[3 * f + 1], bcv + B.tris[3 * f + 2]});
+      ncv += B.nv;
+      world += B.nv;
+      h_bcv1.push_back(cv0 + ncv);
+      H.bodies.push_back(hb);
+    }
+    C.body1 = Nb + nb;
+    C.cv0 = cv0;
+    C.cv1 = cv0 + ncv;
+    H.cv1 = C.cv1;
+    // rest positions of contact vertices (for edge rest lengths)
+    auto rest_pos = [&](int cv, double* p) {
+      const int li = cv - cv0;
+      const int w = H.cv_world[li];
+      if (w < nv) {
+        for (int c = 0; c < 3; ++c) p[c] = d.soft.verts[3 * w + c];
+      } else {
+        int off = nv;
+        for (int b = 0; b < nb; ++b) {
+          if (w < off + d.bodies[b].nv) {
+            for (int c = 0; c < 3; ++c) p[c] = d.bodies[b].verts[3 * (w - off) + c];
+            return;
+          }
+          off += d.bodies[b].nv;
+        }
+      }
+    };
+    C.tri0 = Ntr;
+    for (const auto& t : tris)
+      for (int k = 0; k < 3; ++k) h_trv.push_back(t[k]);
+    C.tri1 = Ntr + (int)tris.size();
+    H.tri0 = C.tri0;
+    H.tri1 = C.tri1;
+    std::vector<std::pair<int, int>> edges;
+    for (const auto& t : tris)
+      for (int k = 0; k < 3; ++k) {
+        int a = t[k], b = t[(k + 1) % 3];
+        if (a > b) std::swap(a, b);
+        edges.emplace_back(a, b);
+      }
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    C.edge0 = Ned;
+    for (const auto& e : edges) {
+      h_edv.push_back(e.first);
+      h_edv.push_back(e.second);
+      double pa[3], pb[3];
+      rest_pos(e.first, pa);
+      rest_pos(e.second, pb);
+      h_elen2.push_back((pb[0] - pa[0]) * (pb[0] - pa[0]) + (pb[1] - pa[1]) * (pb[1] - pa[1]) +
+                        (pb[2] - pa[2]) * (pb[2] - pa[2]));
+    }
+    C.edge1 = Ned + (int)edges.size();
+    H.edge0 = C.edge0;
+    H.edge1 = C.edge1;
+    // queries: contact vertices (point-triangle) then edges (edge-edge), scene by scene
+    C.q0 = Nq;
+    for (int k = 0; k < ncv; ++k) {
+      h_qkind.push_back(0);
+      h_qidx.push_back(cv0 + k);
+      h_qscene.push_back(s);
+    }
+    for (size_t k = 0; k < edges.size(); ++k) {
+      h_qkind.push_back(1);
+      h_qidx.push_back(Ned + (int)k);
+      h_qscene.push_back(s);
+    }
+    C.q1 = Nq + ncv + (int)edges.size();
+    // broad-phase grid: cell edge = 2 x mean primitive extent (+ 2 dhat), origin below the
+    // scene's bounding box
+    double ext = 0.0;
+    int next = 0;
+    for (const auto& e : edges) {
+      double pa[3], pb[3];
+      rest_pos(e.first, pa);
+      rest_pos(e.second, pb);
+      ext += std::max(std::fabs(pa[0] - pb[0]), std::max(std::fabs(pa[1] - pb[1]), std::fabs(pa[2] - pb[2])));
+      ++next;
+    }
+    C.cell = 2.0 * (next ? ext / next : 1e-3) + 2.0 * P.dhat;
+    for (int c = 0; c < 3; ++c) C.org[c] = (std::isfinite(lo[c]) ? lo[c] : 0.0) - 2.0 * C.cell;
+    double L = 0.0;
+    for (int c = 0; c < 3; ++c)
+      if (std::isfinite(lo[c])) L += (hi[c] - lo[c]) * (hi[c] - lo[c]);
+    L = std::sqrt(L);
+    C.stop = P.newton_tol * P.h * L;
+    H.stop = C.stop;
+    // block tables
+    tn_sblk_h.push_back((int)tn_sc_h.size());
+    for (int b0 = node0; b0 < node0 + nn; b0 += kNodeChunk) {
+      tn_sc_h.push_back(s);
+      tn_b0_h.push_back(b0);
+      tn_b1_h.push_back(std::min(b0 + kNodeChunk, node0 + nn));
+    }
+    tt_sblk_h.push_back((int)tt_sc_h.size());
+    for (int b0 = tet0; b0 < tet0 + nt; b0 += kTetChunk) {
+      tt_sc_h.push_back(s);
+      tt_b0_h.push_back(b0);
+      tt_b1_h.push_back(std::min(b0 + kTetChunk, tet0 + nt));
+    }
+    Nn += nn;
+    Nt += nt;
+    Nb += nb;
+    Ncv += ncv;
+    Ntr += (int)tris.size();
+    Ned += (int)edges.size();
+    Nq = C.q1;
+  }
+  tn_sblk_h.push_back((int)tn_sc_h.size());
+  tt_sblk_h.push_back((int)tt_sc_h.size());
+  nnz = (int)h_col.size();
+  h_nscene.resize(Nn);
+  // SoA tet arrays
+  std::vector<int> h_tv(4 * (size_t)Nt);
+  std::vector<double> h_Dminv(9 * (size_t)Nt);
+  for (int t = 0; t < Nt; ++t) {
+    for (int a = 0; a < 4; ++a) h_tv[(size_t)a * Nt + t] = h_tv_aos[4 * (size_t)t + a];
+    for (int k = 0; k < 9; ++k) h_Dminv[(size_t)k * Nt + t] = h_Dminv_aos[9 * (size_t)t + k];
+  }
+  // ---- upload
+  Mem* m = &mem;
+  d_sc.upload(m, hsc);
+  x.upload(m, h_x);
+  xn.ensure(m, 3 * (size_t)Nn);
+  xhat.ensure(m, 3 * (size_t)Nn);
+  v.upload(m, std::vector<double>(3 * (size_t)Nn, 0.0));
+  mass.upload(m, h_mass);
+  nfree.upload(m, h_nfree);
+  nscene.upload(m, h_nscene);
+  nbody.upload(m, h_nbody);
+  ntype.upload(m, h_ntype);
+  tv.upload(m, h_tv);
+  tscene.upload(m, h_tscene);
+  Dminv.upload(m, h_Dminv);
+  tvol.upload(m, h_tvol);
+  Hloc.ensure(m, 144 * (size_t)Nt);
+  gloc.ensure(m, 12 * (size_t)Nt);
+  rowptr.upload(m, h_rowptr);
+  col.upload(m, h_col);
+  diag.upload(m, h_diag);
+  cptr.upload(m, h_cptr);
+  clist.upload(m, h_clist);
+  vptr.upload(m, h_vptr);
+  vlist.upload(m, h_vlist);
+  brow.upload(m, h_brow);
+  val.ensure(m, 9 * (size_t)nnz);
+  bnode.upload(m, h_bnode);
+  bscene.upload(m, h_bscene);
+  bpres.upload(m, h_bpres);
+  bsnap.upload(m, std::vector<int>(Nb, 0));
+  bcv0.upload(m, h_bcv0);
+  bcv1.upload(m, h_bcv1);
+  bmass.upload(m, h_bmass);
+  bvol.upload(m, h_bvol);
+  bstar.upload(m, std::vector<double>(12 * (size_t)Nb, 0.0));
+  blam.upload(m, std::vector<double>(12 * (size_t)Nb, 0.0));
+  bkap.upload(m, std::vector<double>(Nb, 1e6));
+  bgrad.ensure(m, 12 * (size_t)Nb);
+  bhess.ensure(m, 144 * (size_t)Nb);
+  bpinv.ensure(m, 144 * (size_t)Nb);
+  cvn.upload(m, h_cvn);
+  cvb.upload(m, h_cvb);
+  cvx.upload(m, h_cvx);
+  cvfix.upload(m, h_cvfix);
+  cvscene.upload(m, h_cvscene);
+  cvworld.upload(m, h_cvworld);
+  cpos.ensure(m, 3 * (size_t)Ncv);
+  cdisp.ensure(m, 3 * (size_t)Ncv);
+  cend.ensure(m, 3 * (size_t)Ncv);
+  trv.upload(m, h_trv);
+  edv.upload(m, h_edv);
+  elen2.upload(m, h_elen2);
+  qkind.upload(m, h_qkind);
+  qidx.upload(m, h_qidx);
+  qscene.upload(m, h_qscene);
+  act.upload(m, std::vector<int>(S, 0));
+  pdone.upload(m, std::vector<int>(S, 1));
+  tn_sc.upload(m, tn_sc_h);
+  tn_b0.upload(m, tn_b0_h);
+  tn_b1.upload(m, tn_b1_h);
+  tn_sblk.upload(m, tn_sblk_h);
+  tt_sc.upload(m, tt_sc_h);
+  tt_b0.upload(m, tt_b0_h);
+  tt_b1.upload(m, tt_b1_h);
+  tt_sblk.upload(m, tt_sblk_h);
+  TN.nblk = (int)tn_sc_h.size();
+  TN.sc = tn_sc.p; TN.b0 = tn_b0.p; TN.b1 = tn_b1.p; TN.sblk = tn_sblk.p;
+  TT.nblk = (int)tt_sc_h.size();
+  TT.sc = tt_sc.p; TT.b0 = tt_b0.p; TT.b1 = tt_b1.p; TT.sblk = tt_sblk.p;
+  // PCG / line-search / misc
+  for (DBuf<double>* b : {&g, &r, &z, &p, &q, &dx}) b->ensure(m, 3 * (size_t)Nn);
+  pinv.ensure(m, 9 * (size_t)Nn);
+  for (DBuf<double>* b : {&P_pq, &P_rz0, &P_rz1, &P_rr, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
+  iters.ensure(m, S);
+  bad.ensure(m, S);
+  infeasible.ensure(m, S);
+  scnt.ensure(m, S + 1);
+  cand_off.ensure(m, S + 1);
+  okflag.ensure(m, S);
+  failflag.ensure(m, S);
+  action.ensure(m, std::max(Nb, 1));
+  snapcand.ensure(m, std::max(Nb, 1));
+  u64s.ensure(m, 2 * (size_t)S + Nb + 1);
+  abase.ensure(m, S);
+  alpha.ensure(m, S);
+  dE.ensure(m, kTrials * (size_t)S);
+  part_nodes.ensure(m, kTrials * (size_t)std::max(TN.nblk, 1));
+  part_tets.ensure(m, kTrials * (size_t)std::max(TT.nblk, 1));
+  e_bodies.ensure(m, kTrials * (size_t)std::max(Nb, 1));
+  scalars.ensure(m, 16);
+  rowcnt.ensure(m, Nn + 1);
+  drowptr.ensure(m, Nn + 1);
+  bp.ntarget = Ntr + Ned;
+  bp_tbox.ensure(m, 6 * (size_t)std::max(bp.ntarget, 1));
+  bp_tcell.ensure(m, 6 * (size_t)std::max(bp.ntarget, 1));
+  bp_tncell.ensure(m, std::max(bp.ntarget, 1));
+  bp_toff.ensure(m, std::max(bp.ntarget, 1));
+  bp_qcount.ensure(m, std::max(Nq, 1));
+  bp_qoff.ensure(m, std::max(Nq, 1));
+  HIPCHECK(hipHostMalloc((void**)&h_pin, 4096, hipHostMallocDefault));
+  h_pin_bytes = 4096;
+  sync();
+}
+
+// Candidates of the active scenes (or all scenes) for boxes over P0 (and P1).  Returns the
+// count; oq/ot receive (query, target) in canonical (scene, kind, i, j) order.
+int Batch::Impl::broad_phase(const double* P0, const double* P1, int all, DBuf<int>& oq,
+                             DBuf<int>& ot) {
+  const View V = view();
+  hipStream_t s = stream();
+  bp.tbox = bp_tbox.p;
+  bp.tcell = bp_tcell.p;
+  bp.tncell = bp_tncell.p;
+  bp.toff = bp_toff.p;
+  bp.qcount = bp_qcount.p;
+  bp.qoff = bp_qoff.p;
+  bp.overflow = scalars.p + 1;
+  zero(bp.overflow, sizeof(int));
+  launch_bp_targets(V, P0, P1, bp, all, s);
+  const int nentries = scan(bp.tncell, bp.toff, bp.ntarget);
+  int table = 1024;
+  while (table < 2 * nentries) table <<= 1;
+  bp_bcount.ensure(&mem, table);
+  bp_bstart.ensure(&mem, table);
+  bp_bfill.ensure(&mem, table);
+  bp_entries.ensure(&mem, std::max(nentries, 1));
+  bp.table_mask = table - 1;
+  bp.bcount = bp_bcount.p;
+  bp.bstart = bp_bstart.p;
+  bp.bfill = bp_bfill.p;
+  bp.entries = bp_entries.p;
+  zero(bp.bcount, sizeof(int) * table);
+  zero(bp.bfill, sizeof(int) * table);
+  launch_bp_count(V, bp, s);
+  scan(bp.bcount, bp.bstart, table);
+  launch_bp_fill(V, bp, s);
+  launch_bp_query(V, P0, P1, bp, all, 0, nullptr, nullptr, s);
+  const int ncand = scan(bp.qcount, bp.qoff, Nq);
+  oq.ensure(&mem, std::max(ncand, 1));
+  ot.ensure(&mem, std::max(ncand, 1));
+  launch_bp_query(V, P0, P1, bp, all, 1, oq.p, ot.p, s);
+  if (read_int(bp.overflow))
+    throw ApiError(TACCEL_NAN, "broad phase: a primitive box spans more than 64 cells per axis "
+                               "(positions exploded or non-finite)");
+  return ncand;
+}
+
+void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail,
+                                   std::vector<int>& nan_, std::vector<int>& pcg_it,
+                                   std::vector<int>& n_active, std::vector<int>& halvings) {
+  hipStream_t s = stream();
+  View V = view();
+  launch_cpos(V, s);
+  // ---- active pairs at the current point
+  const int ncand = broad_phase(cpos.p, nullptr, 0, cq, ct);
+  cflag.ensure(&mem, std::max(ncand, 1));
+  cpos_idx.ensure(&mem, std::max(ncand, 1));
+  launch_narrow(V, ncand, cq.p, ct.p, cflag.p, s);
+  const int np = scan(cflag.p, cpos_idx.p, ncand);
+  pkind.ensure(&mem, std::max(np, 1));
+  pv.ensure(&mem, 4 * (size_t)std::max(np, 1));
+  pmeps.ensure(&mem, std::max(np, 1));
+  pscene.ensure(&mem, std::max(np, 1));
+  pg.ensure(&mem, 12 * (size_t)std::max(np, 1));
+  ph.ensure(&mem, 144 * (size_t)std::max(np, 1));
+  launch_compact_pairs(V, ncand, cq.p, ct.p, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
+  // ---- element derivatives
+  launch_fem_hess(V, s);
+  launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, s);
+  launch_body_hess(V, s);
+  launch_assemble_bsr(V, nnz, brow.p, s);
+  launch_assemble_grad(V, g.p, s);
+  // ---- contact and body blocks: emit, sort by (row, col), reduce
+  const int nitems = np + Nb;
+  hcnt.ensure(&mem, std::max(nitems, 1));
+  gcnt.ensure(&mem, std::max(nitems, 1));
+  hoff.ensure(&mem, std::max(nitems, 1));
+  goff.ensure(&mem, std::max(nitems, 1));
+  launch_contrib_count(V, np, pv.p, hcnt.p, gcnt.p, s);
+  const int nh = scan(hcnt.p, hoff.p, nitems);
+  const int ng = scan(gcnt.p, goff.p, nitems);
+  for (DBuf<uint64_t>* b : {&hkey, &hkey2}) b->ensure(&mem, std::max(nh, 1));
+  for (DBuf<int>* b : {&hidx, &hidx2, &hsrc}) b->ensure(&mem, std::max(nh, 1));
+  hcoef.ensure(&mem, std::max(nh, 1));
+  for (DBuf<uint64_t>* b : {&gkey, &gkey2}) b->ensure(&mem, std::max(ng, 1));
+  for (DBuf<int>* b : {&gidx, &gidx2, &gsrc}) b->ensure(&mem, std::max(ng, 1));
+  gcoef.ensure(&mem, std::max(ng, 1));
+  launch_contrib_emit(V, np, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
+                      gsrc.p, gcoef.p, s);
+  sort(hkey.p, hidx.p, hkey2.p, hidx2.p, nh, bits_for((uint64_t)Nn * (uint64_t)Nn));
+  sort(gkey.p, gidx.p, gkey2.p, gidx2.p, ng, bits_for((uint64_t)Nn));
+  const int nmax = std::max(nh, ng);
+  sflag.ensure(&mem, std::max(nmax, 1));
+  segid.ensure(&mem, std::max(nmax, 1));
+  segstart.ensure(&mem, std::max(nmax, 1) + 1);
+  // Hessian blocks
+  launch_seg_flags(nh, hkey.p, sflag.p, s);
+  const int nseg = scan(sflag.p, segid.p, nh);
+  launch_seg_start(nh, sflag.p, segid.p, segstart.p, s);
+  drow.ensure(&mem, std::max(nseg, 1));
+  dcol.ensure(&mem, std::max(nseg, 1));
+  dval.ensure(&mem, 9 * (size_t)std::max(nseg, 1));
+  zero(rowcnt.p, sizeof(int) * (Nn + 1));
+  launch_reduce_blocks(V, nseg, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p, dcol.p,
+                       dval.p, rowcnt.p, s);
+  scan(rowcnt.p, drowptr.p, Nn + 1);
+  // gradient entries
+  launch_seg_flags(ng, gkey.p, sflag.p, s);
+  const int ngseg = scan(sflag.p, segid.p, ng);
+  launch_seg_start(ng, sflag.p, segid.p, segstart.p, s);
+  launch_reduce_grad(V, ngseg, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
+  // ---- preconditioner and PCG
+  zero(bad.p, sizeof(int) * S);
+  launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, s);
+  PcgBufs B;
+  B.g = g.p; B.r = r.p; B.z = z.p; B.p = p.p; B.q = q.p; B.dx = dx.p; B.pinv = pinv.p;
+  B.drowptr = drowptr.p; B.dcol = dcol.p; B.dval = dval.p;
+  B.P_pq = P_pq.p; B.P_rz0 = P_rz0.p; B.P_rz1 = P_rz1.p; B.P_rr = P_rr.p; B.P_gg = P_gg.p;
+  B.iters = iters.p;
+  int max_pcg = 0;
+  for (const auto& H : hs) max_pcg = std::max(max_pcg, H.max_pcg);
+  B.max_iters = max_pcg;
+  {
+    // pdone = !act
+    std::vector<int> ha(S);
+    d2h(ha.data(), act.p, S);
+    sync();
+    for (int& a : ha) a = !a;
+    h2d(pdone.p, ha.data(), S);
+  }
+  zero(iters.p, sizeof(int) * S);
+  launch_pcg_init(V, TN, B, s);
+  int parity = 0;
+  std::vector<int> hd(S);
+  for (int it = 0; it < max_pcg;) {
+    const int chunk = 8;
+    for (int k = 0; k < chunk; ++k, ++it) {
+      launch_pcg_iteration(V, TN, B, parity, s);
+      parity ^= 1;
+    }
+    d2h(hd.data(), pdone.p, S);
+    sync();
+    bool all = true;
+    for (int k = 0; k < S; ++k) all = all && hd[k];
+    if (all) break;
+  }
+  d2h(pcg_it.data(), iters.p, S);
+  std::vector<int> hbad(S);
+  d2h(hbad.data(), bad.p, S);
+  // ---- convergence check on the Newton direction
+  unsigned long long* pmax = u64s.p;
+  unsigned long long* amin = u64s.p + S;
+  zero(pmax, sizeof(unsigned long long) * S);
+  launch_pmax(V, dx.p, pmax, s);
+  std::vector<unsigned long long> hp(S);
+  d2h(hp.data(), pmax, S);
+  sync();
+  std::vector<int> hact(S);
+  d2h(hact.data(), act.p, S);
+  sync();
+  for (int k = 0; k < S; ++k) {
+    double pm;
+    std::memcpy(&pm, &hp[k], sizeof(double));
+    nan_[k] = hbad[k] || !std::isfinite(pm);
+    last[k] = pm <= hs[k].stop;
+  }
+  // ---- CCD over the swept candidates
+  launch_cdisp(V, dx.p, s);
+  launch_cend(V, cend.p, s);
+  const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
+  {
+    std::vector<unsigned long long> one(S);
+    const double d1 = 1.0;
+    unsigned long long b1;
+    std::memcpy(&b1, &d1, sizeof(double));
+    std::fill(one.begin(), one.end(), b1);
+    h2d(amin, one.data(), S);
+  }
+  launch_ccd(V, nsw, sq.p, st.p, amin, s);
+  std::vector<unsigned long long> ha(S);
+  d2h(ha.data(), amin, S);
+  zero(scnt.p, sizeof(int) * (S + 1));
+  launch_scene_count(V, nsw, sq.p, scnt.p, s);
+  ensure_scratch(scan_scratch_bytes(S + 1));
+  HIPCHECK(exclusive_scan(scnt.p, cand_off.p, S + 1, nullptr, scratch.p, s));
+  sync();
+  std::vector<double> amax(S), alpha_h(S, 0.0);
+  for (int k = 0; k < S; ++k) std::memcpy(&amax[k], &ha[k], sizeof(double));
+  // ---- line search (8 step sizes per launch)
+  e_pairs.ensure(&mem, kTrials * (size_t)std::max(nsw, 1));
+  LsBufs L;
+  L.p = dx.p;
+  L.abase = abase.p;
+  L.part_nodes = part_nodes.p;
+  L.part_tets = part_tets.p;
+  L.e_bodies = e_bodies.p;
+  L.e_pairs = e_pairs.p;
+  L.infeasible = infeasible.p;
+  L.cand_off = cand_off.p;
+  L.dE = dE.p;
+  std::vector<int> pending(S, 0);
+  std::vector<double> base(S);
+  int npending = 0;
+  for (int k = 0; k < S; ++k) {
+    ls_fail[k] = 0;
+    halvings[k] = 0;
+    if (!hact[k] || nan_[k]) continue;
+    if (last[k]) {
+      alpha_h[k] = amax[k];
+    } else {
+      pending[k] = 1;
+      ++npending;
+    }
+    base[k] = amax[k];
+  }
+  std::vector<double> hdE(kTrials * (size_t)S);
+  std::vector<int> hinf(S);
+  for (int round = 0; npending > 0; ++round) {
+    h2d(abase.p, base.data(), S);
+    zero(infeasible.p, sizeof(int) * S);
+    launch_line_search(V, TN, TT, nsw, sq.p, st.p, L, s);
+    d2h(hdE.data(), dE.p, hdE.size());
+    d2h(hinf.data(), infeasible.p, S);
+    sync();
+    for (int k = 0; k < S; ++k) {
+      if (!pending[k]) continue;
+      int pick = -1;
+      for (int j = 0; j < kTrials; ++j) {
+        const double a = std::ldexp(base[k], -j);
+        if (a < 1e-12) break;
+        if (!((hinf[k] >> j) & 1) && hdE[kTrials * k + j] <= 0.0) {
+          pick = j;
+          break;
+        }
+      }
+      if (pick >= 0) {
+        alpha_h[k] = std::ldexp(base[k], -pick);
+        halvings[k] += pick;
+        pending[k] = 0;
+        --npending;
+      } else {
+        halvings[k] += kTrials;
+        base[k] = std::ldexp(base[k], -kTrials);
+        if (base[k] < 1e-12) {
+          ls_fail[k] = 1;
+          pending[k] = 0;
+          --npending;
+        }
+      }
+    }
+  }
+  h2d(alpha.p, alpha_h.data(), S);
+  launch_update(V, dx.p, alpha.p, s);
+  // active pairs per scene (stats)
+  std::vector<int> hps(std::max(np, 1));
+  d2h(hps.data(), pscene.p, np);
+  sync();
+  std::fill(n_active.begin(), n_active.end(), 0);
+  for (int k = 0; k < np; ++k) n_active[hps[k]]++;
+}
+
+taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
+                                taccel_step_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = stream();
+  View V = view();
+  // ---- targets: body y* (host conversion of the public affine maps), moving vertices
+  std::vector<double> hstar(12 * (size_t)Nb, 0.0);
+  std::vector<double> hmove;
+  int bglob = 0;
+  for (int k = 0; k < S; ++k) {
+    const HostScene& H = hs[k];
+    for (int b = 0; b < H.nb; ++b, ++bglob) {
+      const HostBody& hb = H.bodies[b];
+      if (!hb.prescribed) continue;
+      if (!tg || !tg[k].body_targets)
+        throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(k) + " has a prescribed body but no body_targets");
+      const double* q = tg[k].body_targets + 12 * b;
+      const double* A = q + 3;
+      double* y = hstar.data() + 12 * (size_t)bglob;
+      for (int i = 0; i < 3; ++i) {
+        double acc = q[i];
+        for (int j = 0; j < 3; ++j) acc += A[3 * i + j] * hb.com0[j];
+        y[i] = acc;
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) y[3 + 3 * j + i] = A[3 * i + j];
+    }
+    if (H.n_moving > 0) {
+      if (!tg || !tg[k].dirichlet_targets)
+        throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(k) + " has moving vertices but no dirichlet_targets");
+      for (int i = 0; i < 3 * H.n_moving; ++i) hmove.push_back(tg[k].dirichlet_targets[i]);
+    }
+  }
+  h2d(bstar.p, hstar.data(), hstar.size());
+  launch_predict(V, s);
+  DBuf<int> mv_nodes;
+  DBuf<double> mv_tgt;
+  if (!h_moving_nodes.empty()) {
+    mv_nodes.upload(&mem, h_moving_nodes);
+    mv_tgt.upload(&mem, hmove);
+    launch_set_moving(V, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
+  }
+  launch_body_reset(V, 1e6, s);
+  // initial residual of every prescribed body
+  unsigned long long* bres = u64s.p + 2 * S;
+  zero(bres, sizeof(unsigned long long) * (Nb + 1));
+  launch_body_resid(V, bres, s);
+  std::vector<unsigned long long> hres(Nb + 1);
+  d2h(hres.data(), bres, Nb);
+  sync();
+  bglob = 0;
+  for (auto& H : hs)
+    for (auto& hb : H.bodies) {
+      double r;
+      std::memcpy(&r, &hres[bglob++], sizeof(double));
+      hb.r0 = hb.rprev = r;
+    }
+  mv_nodes.free();
+  mv_tgt.free();
+  // ---- per-scene state machine
+  enum { kNewton = 0, kDone = 1, kFailed = 2 };
+  std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
+  std::vector<int> tot_pcg(S, 0), nact_last(S, 0), tot_halv(S, 0);
+  std::vector<int> last(S), lsf(S), nanf(S), pcg_it(S), nact(S), halv(S);
+  std::vector<int> hact(S);
+  std::vector<char> snapped_host(Nb, 0);
+  int guard = 0;
+  for (;;) {
+    int nactive = 0;
+    for (int k = 0; k < S; ++k) {
+      hact[k] = phase[k] == kNewton;
+      nactive += hact[k];
+    }
+    if (nactive == 0) break;
+    if (++guard > 1000000) throw ApiError(TACCEL_ERR_HIP, "internal: step state machine did not terminate");
+    h2d(act.p, hact.data(), S);
+    newton_iteration(last, lsf, nanf, pcg_it, nact, halv);
+    std::vector<int> al_scene(S, 0);
+    bool any_al = false;
+    for (int k = 0; k < S; ++k) {
+      if (!hact[k]) continue;
+      ++nit[k];
+      ++tot_nit[k];
+      tot_pcg[k] += pcg_it[k];
+      tot_halv[k] += halv[k];
+      nact_last[k] = nact[k];
+      if (nanf[k]) { phase[k] = kFailed; status[k] = TACCEL_NAN; continue; }
+      if (lsf[k]) { phase[k] = kFailed; status[k] = TACCEL_LINESEARCH_FAILED; continue; }
+      if (last[k]) {
+        al_scene[k] = 1;
+        any_al = true;
+      } else if (nit[k] >= hs[k].max_newton) {
+        phase[k] = kFailed;
+        status[k] = TACCEL_NOT_CONVERGED;
+      }
+    }
+    if (!any_al) continue;
+    // ---- augmented Lagrangian round for the scenes whose Newton loop converged
+    std::vector<int> pending_scene(S, 0);
+    std::vector<int> candidates(Nb, 0), actions(Nb, 0);
+    bool any_cand = false;
+    zero(bres, sizeof(unsigned long long) * (Nb + 1));
+    launch_body_resid(V, bres, s);
+    d2h(hres.data(), bres, Nb);
+    sync();
+    bglob = 0;
+    for (int k = 0; k < S; ++k)
+      for (int b = 0; b < hs[k].nb; ++b, ++bglob) {
+        HostBody& hb = hs[k].bodies[b];
+        if (!al_scene[k] || !hb.prescribed || snapped_host[bglob]) continue;
+        pending_scene[k] = 1;
+        double rr;
+        std::memcpy(&rr, &hres[bglob], sizeof(double));
+        if (rr <= 1e-3 * hb.r0) {
+          candidates[bglob] = 1;
+          any_cand = true;
+        }
+        actions[bglob] = rr > 0.5 * hb.rprev ? 3 : 2;
+        hb.rprev = rr;
+      }
+    if (any_cand) {
+      // collision-free snap test: move the candidate bodies onto their targets
+      std::vector<int> snap_act(S, 0);
+      bglob = 0;
+      for (int k = 0; k < S; ++k)
+        for (int b = 0; b < hs[k].nb; ++b, ++bglob)
+          if (candidates[bglob]) snap_act[k] = 1;
+      h2d(act.p, snap_act.data(), S);
+      h2d(snapcand.p, candidates.data(), Nb);
+      launch_cpos(V, s);
+      launch_snap_disp(V, snapcand.p, s);
+      launch_cend(V, cend.p, s);
+      const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
+      unsigned long long* amin = u64s.p + S;
+      std::vector<unsigned long long> one(S);
+      const double d1 = 1.0;
+      unsigned long long b1;
+      std::memcpy(&b1, &d1, sizeof(double));
+      std::fill(one.begin(), one.end(), b1);
+      h2d(amin, one.data(), S);
+      launch_ccd(V, nsw, sq.p, st.p, amin, s);
+      std::vector<unsigned long long> ha(S);
+      d2h(ha.data(), amin, S);
+      sync();
+      bglob = 0;
+      for (int k = 0; k < S; ++k) {
+        double a;
+        std::memcpy(&a, &ha[k], sizeof(double));
+        for (int b = 0; b < hs[k].nb; ++b, ++bglob)
+          if (candidates[bglob] && a >= 1.0) {
+            actions[bglob] = 1;
+            snapped_host[bglob] = 1;
+          }
+      }
+    }
+    h2d(action.p, actions.data(), Nb);
+    launch_al_apply(V, action.p, s);
+    for (int k = 0; k < S; ++k) {
+      if (!al_scene[k]) continue;
+      if (!pending_scene[k]) {
+        phase[k] = kDone;
+        continue;
+      }
+      if (rounds[k] >= hs[k].max_al) {
+        phase[k] = kFailed;
+        status[k] = TACCEL_AL_FAILED;
+        continue;
+      }
+      ++rounds[k];
+      nit[k] = 0;
+    }
+  }
+  // ---- finish: velocities for converged scenes, roll back failed ones
+  std::vector<int> ok(S), failed(S);
+  for (int k = 0; k < S; ++k) {
+    ok[k] = status[k] == TACCEL_OK;
+    failed[k] = !ok[k];
+  }
+  h2d(okflag.p, ok.data(), S);
+  h2d(failflag.p, failed.data(), S);
+  launch_velocity(V, okflag.p, s);
+  launch_rollback(V, failflag.p, s);
+  sync();
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  taccel_status first_bad = TACCEL_OK;
+  for (int k = 0; k < S; ++k) {
+    if (per_scene) per_scene[k] = (taccel_status)status[k];
+    if (stats) {
+      stats[k].status = status[k];
+      stats[k].newton_iters = tot_nit[k];
+      stats[k].al_rounds = rounds[k];
+      stats[k].pcg_iters = tot_pcg[k];
+      stats[k].n_active = nact_last[k];
+      stats[k].ls_halvings = tot_halv[k];
+      stats[k].step_ms = ms;
+    }
+    if (status[k] != TACCEL_OK && first_bad == TACCEL_OK) first_bad = (taccel_status)status[k];
+  }
+  return first_bad;
+}
+
+void Batch::Impl::release_all() {
+  if (h_pin) (void)hipHostFree(h_pin);
+  h_pin = nullptr;
+  // DBuf members free themselves through explicit calls below
+}
+
+// ------------------------------------------------------------------ Batch API
+taccel_status Batch::create(const taccel_scene_desc* d, int n, const taccel_runtime* rt,
+                            Batch** out, std::string& err) {
+  Batch* b = new Batch();
+  b->impl_ = new Impl();
+  b->S_ = n;
+  if (rt) {
+    b->impl_->mem.rt = *rt;
+    b->impl_->mem.stream = (hipStream_t)rt->stream;
+  }
+  try {
+    b->impl_->build(d, n);
+  } catch (const ApiError& e) {
+    err = e.what();
+    const taccel_status st = e.st;
+    delete b;
+    return st;
+  }
+  *out = b;
+  return TACCEL_OK;
+}
+
+Batch::~Batch() {
+  if (!impl_) return;
+  Impl& I = *impl_;
+  (void)hipStreamSynchronize(I.mem.stream);
+  I.release_all();
+#define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
+  FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.Hloc, &I.gloc, &I.val, &I.bmass,
+           &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,
+           &I.cend, &I.elen2, &I.bp_tbox, &I.pmeps, &I.pg, &I.ph, &I.hcoef, &I.gcoef, &I.dval, &I.g, &I.r,
+           &I.z, &I.p, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
+           &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs)
+  FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
+           &I.clist, &I.vptr, &I.vlist, &I.brow, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,
+           &I.cvn, &I.cvb, &I.cvfix, &I.cvscene, &I.cvworld, &I.trv, &I.edv, &I.qkind, &I.qidx, &I.qscene,
+           &I.act, &I.pdone, &I.tn_sc, &I.tn_b0, &I.tn_b1, &I.tn_sblk, &I.tt_sc, &I.tt_b0, &I.tt_b1,
+           &I.tt_sblk, &I.bp_tcell, &I.bp_tncell, &I.bp_toff, &I.bp_bcount, &I.bp_bstart, &I.bp_bfill,
+           &I.bp_qcount, &I.bp_qoff, &I.cq, &I.ct, &I.sq, &I.st, &I.cflag, &I.cpos_idx, &I.pkind, &I.pv,
+           &I.pscene, &I.hcnt, &I.gcnt, &I.hoff, &I.goff, &I.hidx, &I.gidx, &I.hsrc, &I.gsrc, &I.hidx2,
+           &I.gidx2, &I.sflag, &I.segid, &I.segstart, &I.drow, &I.dcol, &I.rowcnt, &I.drowptr, &I.iters,
+           &I.bad, &I.infeasible, &I.scnt, &I.cand_off, &I.action, &I.okflag, &I.failflag, &I.snapcand,
+           &I.scalars)
+  I.hkey.free();
+  I.gkey.free();
+  I.hkey2.free();
+  I.gkey2.free();
+  I.u64s.free();
+  I.bp_entries.free();
+  I.scratch.free();
+  I.d_sc.free();
+#undef FREE_ALL
+  delete impl_;
+}
+
+taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st) {
+  try {
+    return impl_->step(t, per_scene, st);
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    return e.st;
+  }
+}
+
+static size_t field_count(const Batch::Impl& I, int k, taccel_field f) {
+  const HostScene& H = I.hs[k];
+  switch (f) {
+    case TACCEL_FIELD_X:
+    case TACCEL_FIELD_V: return 3 * (size_t)H.nv;
+    case TACCEL_FIELD_Q:
+    case TACCEL_FIELD_QDOT: return 12 * (size_t)H.nb;
+    case TACCEL_FIELD_BODY_X: {
+      size_t n = 0;
+      for (const auto& b : H.bodies) n += 3 * (size_t)b.nv;
+      return n;
+    }
+  }
+  return 0;
+}
+
+taccel_status Batch::read(int k, taccel_field f, void* dst, size_t bytes) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    const size_t cnt = field_count(I, k, f);
+    if (bytes != cnt * sizeof(double) || (cnt && !dst))
+      throw ApiError(TACCEL_ERR_ARG, "state_read: size mismatch (expected " + std::to_string(cnt * 8) + " bytes)");
+    const HostScene& H = I.hs[k];
+    double* out = static_cast<double*>(dst);
+    if (f == TACCEL_FIELD_X || f == TACCEL_FIELD_V) {
+      I.d2h(out, (f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, cnt);
+      I.sync();
+      return TACCEL_OK;
+    }
+    const int n_soft_pad = (H.nv + 3) / 4 * 4;
+    std::vector<double> y(12 * (size_t)H.nb);
+    I.d2h(y.data(), (f == TACCEL_FIELD_QDOT ? I.v.p : I.x.p) + 3 * (size_t)(H.node0 + n_soft_pad), y.size());
+    I.sync();
+    size_t o = 0;
+    for (int b = 0; b < H.nb; ++b) {
+      const HostBody& hb = H.bodies[b];
+      const double* yb = y.data() + 12 * b;
+      double A[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[3 * i + j] = yb[3 + 3 * j + i];
+      if (f == TACCEL_FIELD_BODY_X) {
+        for (int v = 0; v < hb.nv; ++v)
+          for (int c = 0; c < 3; ++c) {
+            double acc = yb[c];
+            for (int j = 0; j < 3; ++j) acc += hb.xbar[3 * v + j] * yb[3 + 3 * j + c];
+            out[o++] = acc;
+          }
+        continue;
+      }
+      double* qo = out + 12 * b;
+      for (int i = 0; i < 3; ++i) {
+        double acc = yb[i];
+        for (int j = 0; j < 3; ++j) acc -= A[3 * i + j] * hb.com0[j];
+        qo[i] = acc;
+      }
+      for (int m = 0; m < 9; ++m) qo[3 + m] = A[m];
+    }
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    return e.st;
+  }
+}
+
+taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    if (f == TACCEL_FIELD_BODY_X) throw ApiError(TACCEL_ERR_ARG, "BODY_X is read-only");
+    const size_t cnt = field_count(I, k, f);
+    if (bytes != cnt * sizeof(double) || (cnt && !src)) throw ApiError(TACCEL_ERR_ARG, "state_write: size mismatch");
+    const HostScene& H = I.hs[k];
+    const double* in = static_cast<const double*>(src);
+    if (f == TACCEL_FIELD_X || f == TACCEL_FIELD_V) {
+      I.h2d((f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, in, cnt);
+      I.sync();
+      return TACCEL_OK;
+    }
+    const int n_soft_pad = (H.nv + 3) / 4 * 4;
+    std::vector<double> y(12 * (size_t)H.nb);
+    for (int b = 0; b < H.nb; ++b) {
+      const HostBody& hb = H.bodies[b];
+      const double* q = in + 12 * b;
+      const double* A = q + 3;
+      double* yb = y.data() + 12 * b;
+      for (int i = 0; i < 3; ++i) {
+        double acc = q[i];
+        for (int j = 0; j < 3; ++j) acc += A[3 * i + j] * hb.com0[j];
+        yb[i] = acc;
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) yb[3 + 3 * j + i] = A[3 * i + j];
+    }
+    I.h2d((f == TACCEL_FIELD_QDOT ? I.v.p : I.x.p) + 3 * (size_t)(H.node0 + n_soft_pad), y.data(), y.size());
+    I.sync();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    return e.st;
+  }
+}
+
+taccel_status Batch::debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
+                                      int32_t* n) {
+  try {
+    Impl& I = *impl_;
+    if (I.S != 1) throw ApiError(TACCEL_ERR_ARG, "debug_candidates works on a single scene");
+    const HostScene& H = I.hs[0];
+    std::vector<double> a(3 * (size_t)I.Ncv), b(3 * (size_t)I.Ncv);
+    for (int cv = 0; cv < I.Ncv; ++cv)
+      for (int c = 0; c < 3; ++c) {
+        a[3 * cv + c] = P0[3 * (size_t)H.cv_world[cv] + c];
+        if (P1) b[3 * cv + c] = P1[3 * (size_t)H.cv_world[cv] + c];
+      }
+    DBuf<double> d0, d1;
+    d0.upload(&I.mem, a);
+    if (P1) d1.upload(&I.mem, b);
+    const int nc = I.broad_phase(d0.p, P1 ? d1.p : nullptr, 1, I.cq, I.ct);
+    std::vector<int> hq(std::max(nc, 1)), ht(std::max(nc, 1)), qk(I.Nq), qi(I.Nq), tr(3 * (size_t)I.Ntr),
+        ed(2 * (size_t)I.Ned);
+    I.d2h(hq.data(), I.cq.p, nc);
+    I.d2h(ht.data(), I.ct.p, nc);
+    I.d2h(qk.data(), I.qkind.p, I.Nq);
+    I.d2h(qi.data(), I.qidx.p, I.Nq);
+    I.d2h(tr.data(), I.trv.p, tr.size());
+    I.d2h(ed.data(), I.edv.p, ed.size());
+    I.sync();
+    d0.free();
+    d1.free();
+    *n = nc;
+    for (int k = 0; k < nc && k < cap; ++k) {
+      int rec[5];
+      const int qq = hq[k], t = ht[k];
+      rec[0] = qk[qq];
+      if (qk[qq] == 0) {
+        rec[1] = H.cv_world[qi[qq]];
+        int w[3] = {H.cv_world[tr[3 * t]], H.cv_world[tr[3 * t + 1]], H.cv_world[tr[3 * t + 2]]};
+        std::sort(w, w + 3);
+        rec[2] = w[0]; rec[3] = w[1]; rec[4] = w[2];
+      } else {
+        const int e1 = qi[qq];
+        int a0 = H.cv_world[ed[2 * e1]], a1 = H.cv_world[ed[2 * e1 + 1]];
+        int b0 = H.cv_world[ed[2 * t]], b1 = H.cv_world[ed[2 * t + 1]];
+        if (a0 > a1) std::swap(a0, a1);
+        if (b0 > b1) std::swap(b0, b1);
+        if (std::make_pair(b0, b1) < std::make_pair(a0, a1)) { std::swap(a0, b0); std::swap(a1, b1); }
+        rec[1] = a0; rec[2] = a1; rec[3] = b0; rec[4] = b1;
+      }
+      for (int j = 0; j < 5; ++j) out[5 * k + j] = rec[j];
+    }
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    return e.st;
+  }
+}
+
+}  // namespace tc

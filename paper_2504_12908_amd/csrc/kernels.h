@@ -1,0 +1,132 @@
+// Kernel launchers of the IPC time step.  All launches go on the given stream.
+#pragma once
+#include "solver.h"
+
+namespace tc {
+
+// Scene-aligned block table: block k covers elements [b0[k], b1[k]) of scene sc[k].
+struct BlockTable {
+  int nblk = 0;
+  const int* sc = nullptr;
+  const int* b0 = nullptr;
+  const int* b1 = nullptr;
+  const int* sblk = nullptr;  // [S+1] first block of each scene (device)
+};
+
+// Broad-phase working set.
+struct BroadPhase {
+  int ntarget = 0;          // tris then edges
+  double* tbox = nullptr;   // [ntarget][6]
+  int* tcell = nullptr;     // [ntarget][6]
+  int* tncell = nullptr;    // [ntarget]
+  int* toff = nullptr;      // [ntarget]
+  int table_mask = 0;
+  int* bcount = nullptr;    // [table]
+  int* bstart = nullptr;    // [table]
+  int* bfill = nullptr;     // [table]
+  int4* entries = nullptr;  // (target, cx, cy, cz)
+  int* qcount = nullptr;    // [Nq]
+  int* qoff = nullptr;      // [Nq]
+  int* overflow = nullptr;  // set when a box spans too many cells (exploded positions)
+};
+
+void launch_predict(const View& V, hipStream_t s);
+void launch_set_moving(const View& V, int n, const int* nodes, const double* tgt, hipStream_t s);
+void launch_cpos(const View& V, hipStream_t s);
+void launch_cdisp(const View& V, const double* p, hipStream_t s);
+void launch_cend(const View& V, double* cend, hipStream_t s);
+void launch_snap_disp(const View& V, const int* cand, hipStream_t s);
+void launch_body_resid(const View& V, unsigned long long* res, hipStream_t s);
+
+// broad phase
+void launch_bp_targets(const View& V, const double* P0, const double* P1, BroadPhase& bp,
+                       int all_scenes, hipStream_t s);
+void launch_bp_count(const View& V, BroadPhase& bp, hipStream_t s);
+void launch_bp_fill(const View& V, BroadPhase& bp, hipStream_t s);
+void launch_bp_query(const View& V, const double* P0, const double* P1, BroadPhase& bp,
+                     int all_scenes, int emit, int* cand_q, int* cand_t, hipStream_t s);
+
+// narrow phase: flag candidates with d < dhat at cpos
+void launch_narrow(const View& V, int n, const int* cand_q, const int* cand_t, int* flag,
+                   hipStream_t s);
+void launch_compact_pairs(const View& V, int n, const int* cand_q, const int* cand_t,
+                          const int* flag, const int* pos, int* pkind, int* pv, double* pmeps,
+                          int* pscene, hipStream_t s);
+
+// element derivatives
+void launch_fem_hess(const View& V, hipStream_t s);
+void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
+                         const double* pmeps, double* pg, double* ph, hipStream_t s);
+void launch_body_hess(const View& V, hipStream_t s);
+
+// assembly
+void launch_assemble_bsr(const View& V, int nnz, const int* brow, hipStream_t s);
+void launch_assemble_grad(const View& V, double* g, hipStream_t s);
+void launch_contrib_count(const View& V, int np, const int* pv, int* hcnt, int* gcnt,
+                          hipStream_t s);
+void launch_contrib_emit(const View& V, int np, const int* pv, const int* hoff, const int* goff,
+                         uint64_t* hkey, int* hidx, int* hsrc, double* hcoef, uint64_t* gkey,
+                         int* gidx, int* gsrc, double* gcoef, hipStream_t s);
+void launch_seg_flags(int n, const uint64_t* keys, int* flags, hipStream_t s);
+void launch_seg_start(int n, const int* flags, const int* segid, int* segstart, hipStream_t s);
+void launch_reduce_blocks(const View& V, int nseg, const uint64_t* keys, const int* idx,
+                          const int* segstart, const int* src, const double* coef,
+                          const double* ph, int* drow, int* dcol, double* dval, int* rowcnt,
+                          hipStream_t s);
+void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int* idx,
+                        const int* segstart, const int* src, const double* coef,
+                        const double* pg, double* g, hipStream_t s);
+void launch_precond(const View& V, const int* drowptr, const int* dcol, const double* dval,
+                    double* pinv, int* bad, hipStream_t s);
+
+// PCG over node-block table T; partial sums per block
+struct PcgBufs {
+  double *g, *r, *z, *p, *q, *dx;
+  double* pinv;
+  const int* drowptr;
+  const int* dcol;
+  const double* dval;
+  double *P_pq, *P_rz0, *P_rz1, *P_rr, *P_gg;
+  int* iters;
+  int max_iters;
+};
+void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
+void launch_pcg_iteration(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
+                          hipStream_t s);
+
+// convergence, CCD, line search, update
+void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s);
+void launch_ccd(const View& V, int n, const int* cand_q, const int* cand_t,
+                unsigned long long* amin, hipStream_t s);
+void launch_scene_count(const View& V, int n, const int* cand_q, int* cnt, hipStream_t s);
+struct LsBufs {
+  const double* p;        // node-space direction
+  const double* abase;    // [S] largest trial step of this launch
+  double* part_nodes;     // [node blocks][8]
+  double* part_tets;      // [tet blocks][8]
+  double* e_bodies;       // [Nb][8]
+  double* e_pairs;        // [ncand][8]
+  int* infeasible;        // [S] bit k: trial k hits J <= 0 or d <= 0
+  const int* cand_off;    // [S+1]
+  double* dE;             // [S][8]
+};
+void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, int ncand,
+                        const int* cand_q, const int* cand_t, const LsBufs& L, hipStream_t s);
+void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s);
+void launch_al_apply(const View& V, const int* action, hipStream_t s);
+void launch_body_reset(const View& V, double kappa0, hipStream_t s);
+void launch_velocity(const View& V, const int* ok, hipStream_t s);
+void launch_rollback(const View& V, const int* failed, hipStream_t s);
+
+// debug evaluators
+void launch_debug_fem(int n, const double* x, const double* Dminv, const double* vol, double mu,
+                      double lam, double* e, double* g, double* H, double* Hp, hipStream_t s);
+void launch_debug_barrier(int n, const int* kinds, const double* x, const double* meps,
+                          double dhat, double kappa, double* e, double* g, double* H, double* Hp,
+                          int* types, hipStream_t s);
+void launch_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,
+                      int max_iter, double* t, hipStream_t s);
+void launch_debug_arap(int n, const double* A, double* e, double* g, double* H, double* Hp,
+                       hipStream_t s);
+
+}  // namespace tc

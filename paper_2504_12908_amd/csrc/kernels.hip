@@ -1,0 +1,1393 @@
+// Kernels of the batched IPC time step (gfx950, wave64).
+//
+// Layout: node vectors are AoS [node][3] (gathers read 24 contiguous bytes); tet data is
+// SoA ([k][Nt]) so consecutive threads read consecutive words.  Scenes are concatenated;
+// node- and tet-parallel kernels that reduce use scene-aligned block tables so every
+// partial sum belongs to one scene and per-scene reductions run in a fixed order
+// (deterministic results, independent of what else is in the batch).
+#include "contact.h"
+#include "elastic.h"
+#include "kernels.h"
+
+namespace tc {
+namespace {
+
+constexpr int TPB = 256;
+inline int nblk(int n, int t = TPB) { return n <= 0 ? 0 : (n + t - 1) / t; }
+__device__ __forceinline__ int gid() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
+// Deterministic sum over a 256-thread workgroup (fixed butterfly + fixed wave order).
+__device__ double block_sum256(double v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  const double r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return r;
+}
+
+__device__ double scene_sum(const double* P, const int* sblk, int s) {
+  double acc = 0.0;
+  for (int k = sblk[s]; k < sblk[s + 1]; ++k) acc += P[k];
+  return acc;
+}
+
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void atomic_min_pos(unsigned long long* a, double v) {
+  atomicMin(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// ------------------------------------------------------------------ predict & positions
+__global__ void k_predict(View V) {
+  const int n = gid();
+  if (n >= V.Nn) return;
+  const SceneConst& sc = V.sc[V.nscene[n]];
+  const int type = V.ntype[n];
+  const double h = sc.h;
+  for (int c = 0; c < 3; ++c) {
+    const double x = V.x[3 * n + c];
+    V.xn[3 * n + c] = x;
+    double xh = x;
+    if (type == 0 || type == 1 || type == 2) xh = x + h * V.v[3 * n + c];
+    if (type == 0 || (type == 1 && !V.bpres[V.nbody[n]])) xh += h * h * sc.grav[c];
+    V.xhat[3 * n + c] = xh;
+  }
+}
+
+__global__ void k_set_moving(View V, int n, const int* nodes, const double* tgt) {
+  const int k = gid();
+  if (k >= n) return;
+  for (int c = 0; c < 3; ++c) V.x[3 * nodes[k] + c] = tgt[3 * k + c];
+}
+
+__device__ __forceinline__ void body_point(const View& V, const double* y, int cv, double* out) {
+  for (int c = 0; c < 3; ++c) {
+    double acc = y[c];
+    for (int j = 0; j < 3; ++j) acc += V.cvx[3 * cv + j] * y[3 + 3 * j + c];
+    out[c] = acc;
+  }
+}
+
+// World position (or displacement, for a node-space direction) of each contact vertex.
+__global__ void k_cmap(View V, const double* src, double* out) {
+  const int cv = gid();
+  if (cv >= V.Ncv) return;
+  const int n = V.cvn[cv];
+  if (n >= 0) {
+    for (int c = 0; c < 3; ++c) out[3 * cv + c] = src[3 * n + c];
+  } else {
+    const int n0 = V.bnode[V.cvb[cv]];
+    body_point(V, src + 3 * n0, cv, out + 3 * cv);
+  }
+}
+
+__global__ void k_cend(View V, double* cend) {
+  const int k = gid();
+  if (k >= 3 * V.Ncv) return;
+  cend[k] = V.cpos[k] + V.cdisp[k];
+}
+
+// Displacement of the bodies flagged in cand from y to y* (everything else frozen).
+__global__ void k_snap_disp(View V, const int* cand) {
+  const int cv = gid();
+  if (cv >= V.Ncv) return;
+  const int b = V.cvb[cv];
+  double d[3] = {0, 0, 0};
+  if (b >= 0 && cand[b]) {
+    double a[3], t[3];
+    body_point(V, V.x + 3 * V.bnode[b], cv, a);
+    body_point(V, V.bstar + 12 * b, cv, t);
+    for (int c = 0; c < 3; ++c) d[c] = t[c] - a[c];
+  }
+  for (int c = 0; c < 3; ++c) V.cdisp[3 * cv + c] = d[c];
+}
+
+// Largest vertex distance between the current and the target pose of each body.
+__global__ void k_body_resid(View V, unsigned long long* res) {
+  const int cv = gid();
+  if (cv >= V.Ncv) return;
+  const int b = V.cvb[cv];
+  if (b < 0 || !V.bpres[b]) return;
+  double a[3], t[3];
+  body_point(V, V.x + 3 * V.bnode[b], cv, a);
+  body_point(V, V.bstar + 12 * b, cv, t);
+  const double r = sqrt((a[0] - t[0]) * (a[0] - t[0]) + (a[1] - t[1]) * (a[1] - t[1]) +
+                        (a[2] - t[2]) * (a[2] - t[2]));
+  atomic_max_pos(res + b, r);
+}
+
+// ------------------------------------------------------------------ broad phase
+__device__ __forceinline__ int cell_of(double v, double org, double inv) {
+  // fmin/fmax map NaN to the bound, so the result is always a finite cell index
+  const double c = fmax(-1048576.0, fmin(1048576.0, floor((v - org) * inv)));
+  return (int)c;
+}
+__device__ __forceinline__ int bucket_of(int s, int cx, int cy, int cz, int mask) {
+  uint64_t h = (uint64_t)(uint32_t)s * 0x9E3779B97F4A7C15ull;
+  h ^= (uint64_t)(uint32_t)cx * 0xC2B2AE3D27D4EB4Full;
+  h ^= (uint64_t)(uint32_t)cy * 0x165667B19E3779F9ull;
+  h ^= (uint64_t)(uint32_t)cz * 0xD6E8FEB86659FD93ull;
+  h ^= h >> 29;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 32;
+  return (int)(h & (uint64_t)mask);
+}
+__device__ void prim_box(const double* P0, const double* P1, const int* ids, int n, double* lo,
+                         double* hi) {
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = INFINITY;
+    hi[c] = -INFINITY;
+  }
+  for (int k = 0; k < n; ++k)
+    for (int c = 0; c < 3; ++c) {
+      const double a = P0[3 * ids[k] + c];
+      lo[c] = fmin(lo[c], a);
+      hi[c] = fmax(hi[c], a);
+      if (P1) {
+        const double b = P1[3 * ids[k] + c];
+        lo[c] = fmin(lo[c], b);
+        hi[c] = fmax(hi[c], b);
+      }
+    }
+}
+// Cell range of a box grown by dhat.  A range longer than kMaxSpan cells per axis only
+// arises from exploded positions; it is clamped (keeping every loop bounded) and flagged so
+// the host can fail the step instead of using an incomplete candidate set.
+constexpr int kMaxSpan = 64;
+__device__ void cell_range(const SceneConst& sc, const double* lo, const double* hi, int* cl,
+                           int* overflow) {
+  const double inv = 1.0 / sc.cell;
+  for (int c = 0; c < 3; ++c) {
+    cl[c] = cell_of(lo[c] - sc.dhat, sc.org[c], inv);
+    cl[3 + c] = cell_of(hi[c] + sc.dhat, sc.org[c], inv);
+    if (cl[3 + c] < cl[c]) cl[3 + c] = cl[c];
+    if (cl[3 + c] - cl[c] >= kMaxSpan) {
+      cl[3 + c] = cl[c] + kMaxSpan - 1;
+      atomicOr(overflow, 1);
+    }
+  }
+}
+__device__ __forceinline__ int target_ids(const View& V, int t, int* ids) {
+  if (t < V.Ntr) {
+    ids[0] = V.trv[3 * t];
+    ids[1] = V.trv[3 * t + 1];
+    ids[2] = V.trv[3 * t + 2];
+    return 3;
+  }
+  const int e = t - V.Ntr;
+  ids[0] = V.edv[2 * e];
+  ids[1] = V.edv[2 * e + 1];
+  return 2;
+}
+
+__global__ void k_bp_targets(View V, const double* P0, const double* P1, BroadPhase bp, int all) {
+  const int t = gid();
+  if (t >= bp.ntarget) return;
+  int ids[3];
+  const int n = target_ids(V, t, ids);
+  const int s = V.cvscene[ids[0]];
+  if (!all && !V.act[s]) {
+    bp.tncell[t] = 0;
+    return;
+  }
+  double lo[3], hi[3];
+  prim_box(P0, P1, ids, n, lo, hi);
+  int cl[6];
+  cell_range(V.sc[s], lo, hi, cl, bp.overflow);
+  for (int c = 0; c < 3; ++c) {
+    bp.tbox[6 * t + c] = lo[c];
+    bp.tbox[6 * t + 3 + c] = hi[c];
+  }
+  for (int k = 0; k < 6; ++k) bp.tcell[6 * t + k] = cl[k];
+  int cnt = 1;
+  for (int c = 0; c < 3; ++c) cnt *= cl[3 + c] - cl[c] + 1;
+  bp.tncell[t] = cnt;
+}
+
+__global__ void k_bp_count(View V, BroadPhase bp) {
+  const int t = gid();
+  if (t >= bp.ntarget || bp.tncell[t] == 0) return;
+  int ids[3];
+  target_ids(V, t, ids);
+  const int s = V.cvscene[ids[0]];
+  const int* cl = bp.tcell + 6 * t;
+  for (int z = cl[2]; z <= cl[5]; ++z)
+    for (int y = cl[1]; y <= cl[4]; ++y)
+      for (int x = cl[0]; x <= cl[3]; ++x)
+        atomicAdd(bp.bcount + bucket_of(s, x, y, z, bp.table_mask), 1);
+}
+
+__global__ void k_bp_fill(View V, BroadPhase bp) {
+  const int t = gid();
+  if (t >= bp.ntarget || bp.tncell[t] == 0) return;
+  int ids[3];
+  target_ids(V, t, ids);
+  const int s = V.cvscene[ids[0]];
+  const int* cl = bp.tcell + 6 * t;
+  for (int z = cl[2]; z <= cl[5]; ++z)
+    for (int y = cl[1]; y <= cl[4]; ++y)
+      for (int x = cl[0]; x <= cl[3]; ++x) {
+        const int b = bucket_of(s, x, y, z, bp.table_mask);
+        const int pos = bp.bstart[b] + atomicAdd(bp.bfill + b, 1);
+        bp.entries[pos] = make_int4(t, x, y, z);
+      }
+}
+
+__device__ __forceinline__ bool boxes_close(const double* a, const double* b, double dhat) {
+  for (int c = 0; c < 3; ++c)
+    if (!(a[c] - dhat <= b[3 + c] && b[c] - dhat <= a[3 + c])) return false;
+  return true;
+}
+
+__global__ void k_bp_query(View V, const double* P0, const double* P1, BroadPhase bp, int all,
+                           int emit, int* cand_q, int* cand_t) {
+  const int q = gid();
+  if (q >= V.Nq) return;
+  const int s = V.qscene[q];
+  if (!all && !V.act[s]) {
+    if (!emit) bp.qcount[q] = 0;
+    return;
+  }
+  const int kind = V.qkind[q], i = V.qidx[q];
+  int qids[2];
+  int nq;
+  if (kind == 0) {
+    qids[0] = i;
+    nq = 1;
+  } else {
+    qids[0] = V.edv[2 * i];
+    qids[1] = V.edv[2 * i + 1];
+    nq = 2;
+  }
+  const SceneConst& sc = V.sc[s];
+  double qb[6];
+  prim_box(P0, P1, qids, nq, qb, qb + 3);
+  int ql[6];
+  cell_range(sc, qb, qb + 3, ql, bp.overflow);
+  const int off = emit ? bp.qoff[q] : 0;
+  int cnt = 0;
+  const int qb0 = V.cvb[qids[0]];
+  for (int z = ql[2]; z <= ql[5]; ++z)
+    for (int y = ql[1]; y <= ql[4]; ++y)
+      for (int x = ql[0]; x <= ql[3]; ++x) {
+        const int b = bucket_of(s, x, y, z, bp.table_mask);
+        const int e0 = bp.bstart[b], e1 = e0 + bp.bcount[b];
+        for (int e = e0; e < e1; ++e) {
+          const int4 ent = bp.entries[e];
+          if (ent.y != x || ent.z != y || ent.w != z) continue;
+          const int t = ent.x;
+          int tid[3];
+          int tn, tgt;
+          if (kind == 0) {
+            if (t >= V.Ntr) continue;
+            tn = target_ids(V, t, tid);
+            tgt = t;
+            const int v = qids[0];
+            if (V.cvscene[tid[0]] != s) continue;
+            if (v == tid[0] || v == tid[1] || v == tid[2]) continue;
+            if (qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) continue;
+            if (V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]) continue;
+          } else {
+            if (t < V.Ntr) continue;
+            tgt = t - V.Ntr;
+            if (tgt <= i) continue;
+            tn = target_ids(V, t, tid);
+            if (V.cvscene[tid[0]] != s) continue;
+            if (qids[0] == tid[0] || qids[0] == tid[1] || qids[1] == tid[0] || qids[1] == tid[1]) continue;
+            if (qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) continue;
+            if (V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]) continue;
+          }
+          (void)tn;
+          const int* tl = bp.tcell + 6 * t;
+          if (max(ql[0], tl[0]) != x || max(ql[1], tl[1]) != y || max(ql[2], tl[2]) != z) continue;
+          if (!boxes_close(qb, bp.tbox + 6 * t, sc.dhat)) continue;
+          if (emit) {
+            cand_q[off + cnt] = q;
+            cand_t[off + cnt] = tgt;
+          }
+          ++cnt;
+        }
+      }
+  if (!emit) {
+    bp.qcount[q] = cnt;
+    return;
+  }
+  // canonical order inside the query: ascending target
+  for (int a = 1; a < cnt; ++a) {
+    const int key = cand_t[off + a];
+    int b = a - 1;
+    while (b >= 0 && cand_t[off + b] > key) {
+      cand_t[off + b + 1] = cand_t[off + b];
+      --b;
+    }
+    cand_t[off + b + 1] = key;
+  }
+}
+
+// ------------------------------------------------------------------ narrow phase
+__device__ __forceinline__ int cand_verts(const View& V, int q, int t, int* ids) {
+  const int kind = V.qkind[q], i = V.qidx[q];
+  if (kind == 0) {
+    ids[0] = i;
+    ids[1] = V.trv[3 * t];
+    ids[2] = V.trv[3 * t + 1];
+    ids[3] = V.trv[3 * t + 2];
+  } else {
+    ids[0] = V.edv[2 * i];
+    ids[1] = V.edv[2 * i + 1];
+    ids[2] = V.edv[2 * t];
+    ids[3] = V.edv[2 * t + 1];
+  }
+  return kind;
+}
+__device__ __forceinline__ void gather12(const double* P, const int* ids, double* x12) {
+  for (int v = 0; v < 4; ++v)
+    for (int c = 0; c < 3; ++c) x12[3 * v + c] = P[3 * ids[v] + c];
+}
+
+__global__ void k_narrow(View V, int n, const int* cq, const int* ct, int* flag) {
+  const int k = gid();
+  if (k >= n) return;
+  int ids[4];
+  const int kind = cand_verts(V, cq[k], ct[k], ids);
+  double x12[12];
+  gather12(V.cpos, ids, x12);
+  const double dhat = V.sc[V.qscene[cq[k]]].dhat;
+  flag[k] = pair_sqdist(kind, x12, nullptr) < dhat * dhat ? 1 : 0;
+}
+
+__global__ void k_compact_pairs(View V, int n, const int* cq, const int* ct, const int* flag,
+                                const int* pos, int* pkind, int* pv, double* pmeps, int* pscene) {
+  const int k = gid();
+  if (k >= n || !flag[k]) return;
+  const int o = pos[k];
+  int ids[4];
+  const int kind = cand_verts(V, cq[k], ct[k], ids);
+  pkind[o] = kind;
+  for (int v = 0; v < 4; ++v) pv[4 * o + v] = ids[v];
+  pmeps[o] = kind == 1 ? 1e-3 * V.elen2[V.qidx[cq[k]]] * V.elen2[ct[k]] : 0.0;
+  pscene[o] = V.qscene[cq[k]];
+}
+
+// ------------------------------------------------------------------ FEM (4 lanes per tet)
+__global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
+  const int g = gid();
+  const int t = g >> 2, a = g & 3;
+  if (t >= V.Nt) return;
+  const int s = V.tscene[t];
+  if (!V.act[s]) return;
+  const SceneConst& sc = V.sc[s];
+  double x12[12], Dm[9];
+  for (int v = 0; v < 4; ++v) {
+    const int node = V.tv[v * V.Nt + t];
+    for (int c = 0; c < 3; ++c) x12[3 * v + c] = V.x[3 * node + c];
+  }
+  for (int k = 0; k < 9; ++k) Dm[k] = V.Dminv[k * V.Nt + t];
+  const double scale = sc.h * sc.h * V.tvol[t];
+  double F[9], P[9], w[12];
+  deformation_gradient(x12, Dm, F);
+  nh_stress(F, sc.mu, sc.lam, P);
+  pullback(P, Dm, scale, w);
+  for (int c = 0; c < 3; ++c) V.gloc[12 * t + 3 * a + c] = w[3 * a + c];
+  Modes m;
+  nh_modes(F, sc.mu, sc.lam, m);
+  double acc[36];
+  for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double lk = m.lam[k];
+    if (!(lk > 0.0)) continue;
+    double Q[9];
+    mode_matrix(m, k, Q);
+    pullback(Q, Dm, 1.0, w);
+    for (int i = 0; i < 3; ++i) {
+      const double wi = lk * w[3 * a + i];
+      for (int j = 0; j < 12; ++j) acc[12 * i + j] += wi * w[j];
+    }
+  }
+  double* out = V.Hloc + 144 * (size_t)t + 36 * a;
+  for (int b = 0; b < 4; ++b)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) out[9 * b + 3 * i + j] = scale * acc[12 * i + 3 * b + j];
+}
+
+// ------------------------------------------------------------------ barrier (1 thread/pair)
+constexpr int kBarrierTPB = 16;  // 2 x 144 doubles of LDS per thread: 36 KB per workgroup
+__global__ void __launch_bounds__(kBarrierTPB) k_barrier_hess(View V, int np, const int* pkind,
+                                                              const int* pv, const double* pmeps,
+                                                              double* pg, double* ph) {
+  __shared__ double Hs[144 * kBarrierTPB];
+  __shared__ double Ws[144 * kBarrierTPB];
+  const int k = gid();
+  if (k >= np) return;
+  int ids[4];
+  for (int v = 0; v < 4; ++v) ids[v] = pv[4 * k + v];
+  const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
+  double x12[12], g[12], e;
+  gather12(V.cpos, ids, x12);
+  double* H = Hs + threadIdx.x;
+  double* W = Ws + threadIdx.x;
+  barrier_pair(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, &e, g, H, kBarrierTPB);
+  psd_project_strided<12>(H, W, kBarrierTPB);
+  for (int i = 0; i < 12; ++i) pg[12 * (size_t)k + i] = g[i];
+  for (int i = 0; i < 144; ++i) ph[144 * (size_t)k + i] = H[i * kBarrierTPB];
+}
+
+// ------------------------------------------------------------------ affine bodies
+// Inertia 1/2 dy^T My dy with My = diag(m I3, Q (x) I3), y = [p; c1; c2; c3].
+__device__ void my_apply(const double* bm, const double* dy, double* out) {
+  for (int c = 0; c < 3; ++c) out[c] = bm[0] * dy[c];
+  for (int j = 0; j < 3; ++j)
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += bm[1 + 3 * j + k] * dy[3 + 3 * k + c];
+      out[3 + 3 * j + c] = acc;
+    }
+}
+__device__ __forceinline__ double my_entry(const double* bm, int r, int c) {
+  const int ur = r / 3, uc = c / 3;
+  if ((r % 3) != (c % 3)) return 0.0;
+  if (ur == 0 || uc == 0) return (ur == 0 && uc == 0) ? bm[0] : 0.0;
+  return bm[1 + 3 * (ur - 1) + (uc - 1)];
+}
+
+__global__ void k_body_hess(View V) {
+  const int b = gid();
+  if (b >= V.Nb) return;
+  const int s = V.bscene[b];
+  if (!V.act[s] || V.bsnap[b]) return;
+  const SceneConst& sc = V.sc[s];
+  const int n0 = V.bnode[b];
+  const double* y = V.x + 3 * n0;
+  const double* yh = V.xhat + 3 * n0;
+  const double* bm = V.bmass + 10 * b;
+  double dy[12], g[12];
+  for (int k = 0; k < 12; ++k) dy[k] = y[k] - yh[k];
+  my_apply(bm, dy, g);
+  double* H = V.bhess + 144 * b;
+  for (int r = 0; r < 12; ++r)
+    for (int c = 0; c < 12; ++c) H[12 * r + c] = my_entry(bm, r, c);
+  double A[9], gA[9], e;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = y[3 + 3 * j + i];
+  Modes m;
+  arap_modes(A, m, &e, gA);
+  const double ks = sc.h * sc.h * sc.kappa_s * V.bvol[b];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) g[3 + 3 * j + i] += ks * gA[3 * i + j];
+  for (int k = 0; k < 9; ++k) {
+    const double lk = m.lam[k];
+    if (!(lk > 0.0)) continue;
+    double Q[9];
+    mode_matrix(m, k, Q);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int ii = 0; ii < 3; ++ii)
+          for (int jj = 0; jj < 3; ++jj)
+            H[12 * (3 + 3 * j + i) + 3 + 3 * jj + ii] += ks * lk * Q[3 * i + j] * Q[3 * ii + jj];
+  }
+  if (V.bpres[b]) {
+    const double kap = V.bkap[b];
+    double c[12], mc[12], ml[12];
+    for (int k = 0; k < 12; ++k) c[k] = y[k] - V.bstar[12 * b + k];
+    my_apply(bm, c, mc);
+    my_apply(bm, V.blam + 12 * b, ml);
+    for (int k = 0; k < 12; ++k) g[k] += kap * mc[k] - ml[k];
+    for (int r = 0; r < 12; ++r)
+      for (int cc = 0; cc < 12; ++cc) H[12 * r + cc] += kap * my_entry(bm, r, cc);
+  }
+  for (int k = 0; k < 12; ++k) V.bgrad[12 * b + k] = g[k];
+}
+
+// ------------------------------------------------------------------ assembly
+__global__ void k_assemble_bsr(View V, int nnz, const int* brow) {
+  const int k = gid();
+  if (k >= nnz) return;
+  const int row = brow[k];
+  if (!V.act[V.nscene[row]]) return;
+  double acc[9];
+  for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+  for (int c = V.cptr[k]; c < V.cptr[k + 1]; ++c) {
+    const int code = V.clist[c];
+    const double* blk = V.Hloc + 144 * (size_t)(code >> 4) + 9 * (code & 15);
+    for (int i = 0; i < 9; ++i) acc[i] += blk[i];
+  }
+  if (V.col[k] == row && V.ntype[row] == 0) {
+    const double m = V.mass[row];
+    acc[0] += m;
+    acc[4] += m;
+    acc[8] += m;
+  }
+  for (int i = 0; i < 9; ++i) V.val[9 * (size_t)k + i] = acc[i];
+}
+
+__global__ void k_assemble_grad(View V, double* g) {
+  const int n = gid();
+  if (n >= V.Nn) return;
+  if (!V.act[V.nscene[n]]) return;
+  double acc[3] = {0, 0, 0};
+  if (V.ntype[n] == 0 && V.nfree[n]) {
+    const double m = V.mass[n];
+    for (int c = 0; c < 3; ++c) acc[c] = m * (V.x[3 * n + c] - V.xhat[3 * n + c]);
+    for (int k = V.vptr[n]; k < V.vptr[n + 1]; ++k) {
+      const int code = V.vlist[k];
+      const double* gl = V.gloc + 12 * (size_t)(code >> 2) + 3 * (code & 3);
+      for (int c = 0; c < 3; ++c) acc[c] += gl[c];
+    }
+  }
+  for (int c = 0; c < 3; ++c) g[3 * n + c] = acc[c];
+}
+
+// Node entries (node, weight) through which a contact vertex moves.
+__device__ __forceinline__ int vertex_nodes(const View& V, int cv, int* node, double* w) {
+  const int n = V.cvn[cv];
+  if (n >= 0) {
+    if (!V.nfree[n]) return 0;
+    node[0] = n;
+    w[0] = 1.0;
+    return 1;
+  }
+  const int b = V.cvb[cv];
+  if (V.bsnap[b]) return 0;
+  const int n0 = V.bnode[b];
+  node[0] = n0;
+  w[0] = 1.0;
+  for (int j = 0; j < 3; ++j) {
+    node[1 + j] = n0 + 1 + j;
+    w[1 + j] = V.cvx[3 * cv + j];
+  }
+  return 4;
+}
+
+__global__ void k_contrib_count(View V, int np, const int* pv, int* hcnt, int* gcnt) {
+  const int k = gid();
+  if (k >= np + V.Nb) return;
+  int tot = 0;
+  if (k < np) {
+    int node[4];
+    double w[4];
+    for (int a = 0; a < 4; ++a) tot += vertex_nodes(V, pv[4 * k + a], node, w);
+  } else {
+    const int b = k - np;
+    if (V.act[V.bscene[b]] && !V.bsnap[b]) tot = 4;
+  }
+  hcnt[k] = tot * tot;
+  gcnt[k] = tot;
+}
+
+// Contribution source codes: >= 0 pair block/vector, < 0 body block/vector (-1 - code).
+__global__ void k_contrib_emit(View V, int np, const int* pv, const int* hoff, const int* goff,
+                               uint64_t* hkey, int* hidx, int* hsrc, double* hcoef, uint64_t* gkey,
+                               int* gidx, int* gsrc, double* gcoef) {
+  const int k = gid();
+  if (k >= np + V.Nb) return;
+  const uint64_t Nn = (uint64_t)V.Nn;
+  int ho = hoff[k], go = goff[k];
+  if (k < np) {
+    int node[4][4], cnt[4];
+    double w[4][4];
+    for (int a = 0; a < 4; ++a) cnt[a] = vertex_nodes(V, pv[4 * k + a], node[a], w[a]);
+    for (int a = 0; a < 4; ++a)
+      for (int ia = 0; ia < cnt[a]; ++ia) {
+        gkey[go] = (uint64_t)node[a][ia];
+        gidx[go] = go;
+        gsrc[go] = 4 * k + a;
+        gcoef[go] = w[a][ia];
+        ++go;
+        for (int b = 0; b < 4; ++b)
+          for (int ib = 0; ib < cnt[b]; ++ib) {
+            hkey[ho] = (uint64_t)node[a][ia] * Nn + (uint64_t)node[b][ib];
+            hidx[ho] = ho;
+            hsrc[ho] = 16 * k + 4 * a + b;
+            hcoef[ho] = w[a][ia] * w[b][ib];
+            ++ho;
+          }
+      }
+  } else {
+    const int b = k - np;
+    if (!V.act[V.bscene[b]] || V.bsnap[b]) return;
+    const int n0 = V.bnode[b];
+    for (int u = 0; u < 4; ++u) {
+      gkey[go] = (uint64_t)(n0 + u);
+      gidx[go] = go;
+      gsrc[go] = -1 - (4 * b + u);
+      gcoef[go] = 1.0;
+      ++go;
+      for (int w = 0; w < 4; ++w) {
+        hkey[ho] = (uint64_t)(n0 + u) * Nn + (uint64_t)(n0 + w);
+        hidx[ho] = ho;
+        hsrc[ho] = -1 - (16 * b + 4 * u + w);
+        hcoef[ho] = 1.0;
+        ++ho;
+      }
+    }
+  }
+}
+
+__global__ void k_seg_flags(int n, const uint64_t* keys, int* flags) {
+  const int i = gid();
+  if (i >= n) return;
+  flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+__global__ void k_seg_start(int n, const int* flags, const int* segid, int* segstart) {
+  const int i = gid();
+  if (i >= n) return;
+  if (flags[i]) segstart[segid[i]] = i;
+  if (i == n - 1) segstart[segid[i] + flags[i]] = n;
+}
+
+__global__ void k_reduce_blocks(View V, int nseg, const uint64_t* keys, const int* idx,
+                                const int* segstart, const int* src, const double* coef,
+                                const double* ph, int* drow, int* dcol, double* dval, int* rowcnt) {
+  const int k = gid();
+  if (k >= nseg) return;
+  const int i0 = segstart[k], i1 = segstart[k + 1];
+  const uint64_t key = keys[i0];
+  const int row = (int)(key / (uint64_t)V.Nn), col = (int)(key % (uint64_t)V.Nn);
+  double acc[9];
+  for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const int c = idx[i];
+    const int code = src[c];
+    const double w = coef[c];
+    const double* M;
+    int a, b;
+    if (code >= 0) {
+      M = ph + 144 * (size_t)(code >> 4);
+      a = (code >> 2) & 3;
+      b = code & 3;
+    } else {
+      const int cc = -1 - code;
+      M = V.bhess + 144 * (size_t)(cc >> 4);
+      a = (cc >> 2) & 3;
+      b = cc & 3;
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) acc[3 * r + q] += w * M[12 * (3 * a + r) + 3 * b + q];
+  }
+  drow[k] = row;
+  dcol[k] = col;
+  for (int i = 0; i < 9; ++i) dval[9 * (size_t)k + i] = acc[i];
+  atomicAdd(rowcnt + row, 1);
+}
+
+__global__ void k_reduce_grad(View V, int nseg, const uint64_t* keys, const int* idx,
+                              const int* segstart, const int* src, const double* coef,
+                              const double* pg, double* g) {
+  const int k = gid();
+  if (k >= nseg) return;
+  const int i0 = segstart[k], i1 = segstart[k + 1];
+  const int node = (int)keys[i0];
+  double acc[3] = {0, 0, 0};
+  for (int i = i0; i < i1; ++i) {
+    const int c = idx[i];
+    const int code = src[c];
+    const double w = coef[c];
+    const double* v = code >= 0 ? pg + 12 * (size_t)(code >> 2) + 3 * (code & 3)
+                                : V.bgrad + 12 * (size_t)((-1 - code) >> 2) + 3 * ((-1 - code) & 3);
+    for (int q = 0; q < 3; ++q) acc[q] += w * v[q];
+  }
+  for (int q = 0; q < 3; ++q) g[3 * node + q] += acc[q];
+}
+
+__global__ void k_precond_soft(View V, const int* drowptr, const int* dcol, const double* dval,
+                               double* pinv, int* bad) {
+  const int n = gid();
+  if (n >= V.Nn) return;
+  const int s = V.nscene[n];
+  if (!V.act[s]) return;
+  double* out = pinv + 9 * (size_t)n;
+  if (V.ntype[n] != 0 || !V.nfree[n]) {
+    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    return;
+  }
+  double D[9];
+  const double* sd = V.val + 9 * (size_t)V.diag[n];
+  for (int i = 0; i < 9; ++i) D[i] = sd[i];
+  for (int k = drowptr[n]; k < drowptr[n + 1]; ++k)
+    if (dcol[k] == n)
+      for (int i = 0; i < 9; ++i) D[i] += dval[9 * (size_t)k + i];
+  double C[9];
+  cofactor3(D, C);
+  const double det = D[0] * C[0] + D[1] * C[1] + D[2] * C[2];
+  if (!(det > 0.0) || !isfinite(det)) {
+    bad[s] = 1;
+    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    return;
+  }
+  // D symmetric: inverse = C^T / det = C / det
+  for (int i = 0; i < 9; ++i) out[i] = C[i] / det;
+}
+
+__global__ void k_precond_body(View V, const int* drowptr, const int* dcol, const double* dval,
+                               int* bad) {
+  const int b = gid();
+  if (b >= V.Nb) return;
+  const int s = V.bscene[b];
+  if (!V.act[s] || V.bsnap[b]) return;
+  const int n0 = V.bnode[b];
+  double M[144];
+  for (int i = 0; i < 144; ++i) M[i] = 0.0;
+  for (int u = 0; u < 4; ++u)
+    for (int k = drowptr[n0 + u]; k < drowptr[n0 + u + 1]; ++k) {
+      const int w = dcol[k] - n0;
+      if (w < 0 || w > 3) continue;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[12 * (3 * u + i) + 3 * w + j] = dval[9 * (size_t)k + 3 * i + j];
+    }
+  if (!spd_inverse<12>(M, V.bpinv + 144 * b)) bad[s] = 1;
+}
+
+// ------------------------------------------------------------------ PCG
+// z = M^{-1} r for the node n (local index li inside the block; rs stages r in LDS).
+__device__ __forceinline__ void precond_apply(const View& V, const double* pinv, int n, int n0blk,
+                                              const double (*rs)[3], double* z) {
+  const int type = V.ntype[n];
+  if (!V.nfree[n]) {
+    z[0] = z[1] = z[2] = 0.0;
+    return;
+  }
+  if (type == 0) {
+    const double* P = pinv + 9 * (size_t)n;
+    const int li = n - n0blk;
+    for (int i = 0; i < 3; ++i) z[i] = P[3 * i] * rs[li][0] + P[3 * i + 1] * rs[li][1] + P[3 * i + 2] * rs[li][2];
+    return;
+  }
+  const int b = V.nbody[n];
+  const int u = n - V.bnode[b];
+  const int l0 = V.bnode[b] - n0blk;
+  const double* P = V.bpinv + 144 * b;
+  for (int i = 0; i < 3; ++i) {
+    double acc = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int j = 0; j < 3; ++j) acc += P[12 * (3 * u + i) + 3 * w + j] * rs[l0 + w][j];
+    z[i] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_pcg_init(View V, BlockTable T, PcgBufs B) {
+  __shared__ double rs[TPB][3];
+  __shared__ double red[4];
+  const int s = T.sc[blockIdx.x];
+  if (V.pdone[s]) return;
+  const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
+  const int n = n0 + threadIdx.x;
+  const bool live = n < n1;
+  double r[3] = {0, 0, 0};
+  if (live) {
+    const bool f = V.nfree[n];
+    for (int c = 0; c < 3; ++c) {
+      r[c] = f ? -B.g[3 * n + c] : 0.0;
+      B.r[3 * n + c] = r[c];
+      B.dx[3 * n + c] = 0.0;
+    }
+  }
+  for (int c = 0; c < 3; ++c) rs[threadIdx.x][c] = r[c];
+  __syncthreads();
+  double z[3] = {0, 0, 0};
+  if (live) {
+    precond_apply(V, B.pinv, n, n0, rs, z);
+    for (int c = 0; c < 3; ++c) {
+      B.z[3 * n + c] = z[c];
+      B.p[3 * n + c] = z[c];
+    }
+  }
+  const double rz = block_sum256(r[0] * z[0] + r[1] * z[1] + r[2] * z[2], red);
+  const double rr = block_sum256(r[0] * r[0] + r[1] * r[1] + r[2] * r[2], red);
+  if (threadIdx.x == 0) {
+    B.P_rz0[blockIdx.x] = rz;
+    B.P_gg[blockIdx.x] = rr;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_pcg_spmv(View V, BlockTable T, PcgBufs B) {
+  __shared__ double red[4];
+  const int s = T.sc[blockIdx.x];
+  if (V.pdone[s]) return;
+  const int n = T.b0[blockIdx.x] + threadIdx.x;
+  double q[3] = {0, 0, 0}, pn[3] = {0, 0, 0};
+  if (n < T.b1[blockIdx.x] && V.nfree[n]) {
+    for (int k = V.rowptr[n]; k < V.rowptr[n + 1]; ++k) {
+      const double* A = V.val + 9 * (size_t)k;
+      const double* p = B.p + 3 * V.col[k];
+      for (int i = 0; i < 3; ++i) q[i] += A[3 * i] * p[0] + A[3 * i + 1] * p[1] + A[3 * i + 2] * p[2];
+    }
+    for (int k = B.drowptr[n]; k < B.drowptr[n + 1]; ++k) {
+      const double* A = B.dval + 9 * (size_t)k;
+      const double* p = B.p + 3 * B.dcol[k];
+      for (int i = 0; i < 3; ++i) q[i] += A[3 * i] * p[0] + A[3 * i + 1] * p[1] + A[3 * i + 2] * p[2];
+    }
+    for (int c = 0; c < 3; ++c) pn[c] = B.p[3 * n + c];
+  }
+  if (n < T.b1[blockIdx.x])
+    for (int c = 0; c < 3; ++c) B.q[3 * n + c] = q[c];
+  const double pq = block_sum256(pn[0] * q[0] + pn[1] * q[1] + pn[2] * q[2], red);
+  if (threadIdx.x == 0) B.P_pq[blockIdx.x] = pq;
+}
+
+__global__ void __launch_bounds__(TPB) k_pcg_update1(View V, BlockTable T, PcgBufs B, int parity) {
+  __shared__ double rs[TPB][3];
+  __shared__ double red[4];
+  __shared__ double alpha_s;
+  const int s = T.sc[blockIdx.x];
+  if (V.pdone[s]) return;
+  const double* Prz = parity ? B.P_rz1 : B.P_rz0;
+  double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
+  if (threadIdx.x == 0) {
+    const double rz = scene_sum(Prz, T.sblk, s), pq = scene_sum(B.P_pq, T.sblk, s);
+    alpha_s = pq > 0.0 ? rz / pq : 0.0;
+  }
+  __syncthreads();
+  const double alpha = alpha_s;
+  const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
+  const int n = n0 + threadIdx.x;
+  const bool live = n < n1;
+  double r[3] = {0, 0, 0};
+  if (live) {
+    for (int c = 0; c < 3; ++c) {
+      B.dx[3 * n + c] += alpha * B.p[3 * n + c];
+      r[c] = B.r[3 * n + c] - alpha * B.q[3 * n + c];
+      B.r[3 * n + c] = r[c];
+    }
+  }
+  for (int c = 0; c < 3; ++c) rs[threadIdx.x][c] = r[c];
+  __syncthreads();
+  double z[3] = {0, 0, 0};
+  if (live) {
+    precond_apply(V, B.pinv, n, n0, rs, z);
+    for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
+  }
+  const double rz = block_sum256(r[0] * z[0] + r[1] * z[1] + r[2] * z[2], red);
+  const double rr = block_sum256(r[0] * r[0] + r[1] * r[1] + r[2] * r[2], red);
+  if (threadIdx.x == 0) {
+    Prz_new[blockIdx.x] = rz;
+    B.P_rr[blockIdx.x] = rr;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_pcg_update2(View V, BlockTable T, PcgBufs B, int parity) {
+  __shared__ double beta_s;
+  __shared__ int conv_s;
+  const int s = T.sc[blockIdx.x];
+  if (V.pdone[s]) return;
+  const double* Prz_old = parity ? B.P_rz1 : B.P_rz0;
+  const double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
+  const bool first = blockIdx.x == T.sblk[s];
+  if (threadIdx.x == 0) {
+    const double rzn = scene_sum(Prz_new, T.sblk, s), rzo = scene_sum(Prz_old, T.sblk, s);
+    const double rr = scene_sum(B.P_rr, T.sblk, s), gg = scene_sum(B.P_gg, T.sblk, s);
+    const double eta = V.sc[s].pcg_eta;
+    conv_s = (rr <= eta * eta * gg) || !(rzn > 0.0) || !(rzo > 0.0);
+    beta_s = conv_s ? 0.0 : rzn / rzo;
+  }
+  __syncthreads();
+  if (conv_s) {
+    if (first && threadIdx.x == 0) V.pdone[s] = 1;
+    return;
+  }
+  const int n = T.b0[blockIdx.x] + threadIdx.x;
+  if (n < T.b1[blockIdx.x]) {
+    const double beta = beta_s;
+    for (int c = 0; c < 3; ++c) B.p[3 * n + c] = B.z[3 * n + c] + beta * B.p[3 * n + c];
+  }
+  if (first && threadIdx.x == 0) {
+    const int it = ++B.iters[s];
+    if (it >= B.max_iters) V.pdone[s] = 1;
+  }
+}
+
+// ------------------------------------------------------------------ convergence & CCD
+__global__ void k_pmax(View V, const double* p, unsigned long long* pmax) {
+  const int k = gid();
+  if (k < V.Nn) {
+    const int n = k;
+    if (V.ntype[n] == 0 && V.nfree[n] && V.act[V.nscene[n]]) {
+      const double m = fmax(fabs(p[3 * n]), fmax(fabs(p[3 * n + 1]), fabs(p[3 * n + 2])));
+      atomic_max_pos(pmax + V.nscene[n], m);
+    }
+    return;
+  }
+  const int cv = k - V.Nn;
+  if (cv >= V.Ncv) return;
+  const int b = V.cvb[cv];
+  if (b < 0 || V.bsnap[b] || !V.act[V.bscene[b]]) return;
+  double d[3];
+  body_point(V, p + 3 * V.bnode[b], cv, d);
+  atomic_max_pos(pmax + V.bscene[b], fmax(fabs(d[0]), fmax(fabs(d[1]), fabs(d[2]))));
+}
+
+__global__ void k_ccd(View V, int n, const int* cq, const int* ct, unsigned long long* amin) {
+  const int k = gid();
+  if (k >= n) return;
+  int ids[4];
+  const int kind = cand_verts(V, cq[k], ct[k], ids);
+  double x12[12], p12[12];
+  gather12(V.cpos, ids, x12);
+  gather12(V.cdisp, ids, p12);
+  const double t = accd(kind, x12, p12, 0.1, 100000);
+  atomic_min_pos(amin + V.qscene[cq[k]], t);
+}
+
+__global__ void k_scene_count(View V, int n, const int* cq, int* cnt) {
+  const int k = gid();
+  if (k >= n) return;
+  atomicAdd(cnt + V.qscene[cq[k]], 1);
+}
+
+// ------------------------------------------------------------------ line search
+__device__ __forceinline__ double trial_alpha(const double* abase, int s, int k) {
+  return ldexp(abase[s], -k);
+}
+
+__global__ void __launch_bounds__(TPB) k_ls_nodes(View V, BlockTable T, LsBufs L) {
+  __shared__ double red[4];
+  const int s = T.sc[blockIdx.x];
+  if (!V.act[s]) return;
+  const int n = T.b0[blockIdx.x] + threadIdx.x;
+  double pe = 0.0, pp = 0.0, m = 0.0;
+  if (n < T.b1[blockIdx.x] && V.ntype[n] == 0 && V.nfree[n]) {
+    m = V.mass[n];
+    for (int c = 0; c < 3; ++c) {
+      const double pc = L.p[3 * n + c];
+      pe += pc * (V.x[3 * n + c] - V.xhat[3 * n + c]);
+      pp += pc * pc;
+    }
+  }
+  for (int k = 0; k < kTrials; ++k) {
+    const double a = trial_alpha(L.abase, s, k);
+    const double dE = block_sum256(0.5 * m * (2.0 * a * pe + a * a * pp), red);
+    if (threadIdx.x == 0) L.part_nodes[kTrials * blockIdx.x + k] = dE;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_ls_tets(View V, BlockTable T, LsBufs L) {
+  __shared__ double red[4];
+  const int s = T.sc[blockIdx.x];
+  if (!V.act[s]) return;
+  const SceneConst& sc = V.sc[s];
+  const int t = T.b0[blockIdx.x] + threadIdx.x;
+  const bool live = t < T.b1[blockIdx.x];
+  double x12[12], p12[12], Dm[9], e0 = 0.0, scale = 0.0;
+  if (live) {
+    for (int v = 0; v < 4; ++v) {
+      const int node = V.tv[v * V.Nt + t];
+      for (int c = 0; c < 3; ++c) {
+        x12[3 * v + c] = V.x[3 * node + c];
+        p12[3 * v + c] = L.p[3 * node + c];
+      }
+    }
+    for (int k = 0; k < 9; ++k) Dm[k] = V.Dminv[k * V.Nt + t];
+    double F[9];
+    deformation_gradient(x12, Dm, F);
+    e0 = nh_density(F, sc.mu, sc.lam);
+    scale = sc.h * sc.h * V.tvol[t];
+  }
+  int bad = 0;
+  for (int k = 0; k < kTrials; ++k) {
+    double dE = 0.0;
+    if (live) {
+      const double a = trial_alpha(L.abase, s, k);
+      double xt[12], F[9];
+      for (int i = 0; i < 12; ++i) xt[i] = x12[i] + a * p12[i];
+      deformation_gradient(xt, Dm, F);
+      const double e = nh_density(F, sc.mu, sc.lam);
+      if (isinf(e)) bad |= 1 << k;
+      else dE = scale * (e - e0);
+    }
+    dE = block_sum256(dE, red);
+    if (threadIdx.x == 0) L.part_tets[kTrials * blockIdx.x + k] = dE;
+  }
+  if (bad) atomicOr(L.infeasible + s, bad);
+}
+
+__device__ double body_energy(const View& V, int b, const double* y, const SceneConst& sc) {
+  const double* bm = V.bmass + 10 * b;
+  const double* yh = V.xhat + 3 * V.bnode[b];
+  double dy[12], My[12];
+  for (int k = 0; k < 12; ++k) dy[k] = y[k] - yh[k];
+  my_apply(bm, dy, My);
+  double e = 0.0;
+  for (int k = 0; k < 12; ++k) e += 0.5 * dy[k] * My[k];
+  double A[9], gA[9], ea;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = y[3 + 3 * j + i];
+  Modes m;
+  arap_modes(A, m, &ea, gA);
+  e += sc.h * sc.h * sc.kappa_s * V.bvol[b] * ea;
+  if (V.bpres[b]) {
+    double c[12], Mc[12];
+    for (int k = 0; k < 12; ++k) c[k] = y[k] - V.bstar[12 * b + k];
+    my_apply(bm, c, Mc);
+    double cc = 0.0, lc = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      cc += c[k] * Mc[k];
+      lc += V.blam[12 * b + k] * Mc[k];
+    }
+    e += 0.5 * V.bkap[b] * cc - lc;
+  }
+  return e;
+}
+
+__global__ void k_ls_bodies(View V, LsBufs L) {
+  const int b = gid();
+  if (b >= V.Nb) return;
+  const int s = V.bscene[b];
+  for (int k = 0; k < kTrials; ++k) L.e_bodies[kTrials * b + k] = 0.0;
+  if (!V.act[s] || V.bsnap[b]) return;
+  const SceneConst& sc = V.sc[s];
+  const double* y = V.x + 3 * V.bnode[b];
+  const double* p = L.p + 3 * V.bnode[b];
+  const double e0 = body_energy(V, b, y, sc);
+  for (int k = 0; k < kTrials; ++k) {
+    const double a = trial_alpha(L.abase, s, k);
+    double yt[12];
+    for (int i = 0; i < 12; ++i) yt[i] = y[i] + a * p[i];
+    L.e_bodies[kTrials * b + k] = body_energy(V, b, yt, sc) - e0;
+  }
+}
+
+__global__ void k_ls_pairs(View V, int n, const int* cq, const int* ct, LsBufs L) {
+  const int k = gid();
+  if (k >= n) return;
+  const int s = V.qscene[cq[k]];
+  const SceneConst& sc = V.sc[s];
+  int ids[4];
+  const int kind = cand_verts(V, cq[k], ct[k], ids);
+  double x12[12], p12[12];
+  gather12(V.cpos, ids, x12);
+  gather12(V.cdisp, ids, p12);
+  const double meps = kind == 1 ? 1e-3 * V.elen2[V.qidx[cq[k]]] * V.elen2[ct[k]] : 0.0;
+  const double kap = sc.h * sc.h * sc.kappa;
+  const double e0 = barrier_energy(kind, x12, meps, sc.dhat, kap);
+  int bad = 0;
+  for (int j = 0; j < kTrials; ++j) {
+    const double a = trial_alpha(L.abase, s, j);
+    double xt[12];
+    for (int i = 0; i < 12; ++i) xt[i] = x12[i] + a * p12[i];
+    const double e = barrier_energy(kind, xt, meps, sc.dhat, kap);
+    double d = 0.0;
+    if (isinf(e)) bad |= 1 << j;
+    else d = e - e0;
+    L.e_pairs[kTrials * (size_t)k + j] = d;
+  }
+  if (bad) atomicOr(L.infeasible + s, bad);
+}
+
+__global__ void k_ls_reduce(View V, BlockTable TN, BlockTable TT, LsBufs L) {
+  const int s = blockIdx.x;
+  if (!V.act[s]) return;
+  const int k = threadIdx.x;
+  if (k >= kTrials) return;
+  double acc = 0.0;
+  for (int b = TN.sblk[s]; b < TN.sblk[s + 1]; ++b) acc += L.part_nodes[kTrials * b + k];
+  double acc_t = 0.0;
+  for (int b = TT.sblk[s]; b < TT.sblk[s + 1]; ++b) acc_t += L.part_tets[kTrials * b + k];
+  double acc_b = 0.0;
+  for (int b = V.sc[s].body0; b < V.sc[s].body1; ++b) acc_b += L.e_bodies[kTrials * b + k];
+  double acc_p = 0.0;
+  for (int c = L.cand_off[s]; c < L.cand_off[s + 1]; ++c) acc_p += L.e_pairs[kTrials * (size_t)c + k];
+  L.dE[kTrials * s + k] = ((acc + acc_t) + acc_b) + acc_p;
+}
+
+__global__ void k_update(View V, const double* p, const double* alpha) {
+  const int n = gid();
+  if (n >= V.Nn) return;
+  const int s = V.nscene[n];
+  if (!V.act[s] || !V.nfree[n]) return;
+  const double a = alpha[s];
+  for (int c = 0; c < 3; ++c) V.x[3 * n + c] += a * p[3 * n + c];
+}
+
+// action: 0 none, 1 snap onto the target, 2 multiplier update, 3 update and double kappa
+__global__ void k_al_apply(View V, const int* action) {
+  const int b = gid();
+  if (b >= V.Nb) return;
+  const int act = action[b];
+  if (act == 0) return;
+  const int n0 = V.bnode[b];
+  if (act == 1) {
+    for (int k = 0; k < 12; ++k) V.x[3 * n0 + k] = V.bstar[12 * b + k];
+    V.bsnap[b] = 1;
+    for (int u = 0; u < 4; ++u) V.nfree[n0 + u] = 0;
+    return;
+  }
+  const double kap = V.bkap[b];
+  for (int k = 0; k < 12; ++k) V.blam[12 * b + k] -= kap * (V.x[3 * n0 + k] - V.bstar[12 * b + k]);
+  if (act == 3) V.bkap[b] = 2.0 * kap;
+}
+
+// Start of a step: multipliers cleared, penalty reset, every body unsnapped (its 4
+// pseudo-nodes become unknowns again).
+__global__ void k_body_reset(View V, double kappa0) {
+  const int b = gid();
+  if (b >= V.Nb) return;
+  for (int k = 0; k < 12; ++k) V.blam[12 * b + k] = 0.0;
+  V.bkap[b] = kappa0;
+  V.bsnap[b] = 0;
+  for (int u = 0; u < 4; ++u) V.nfree[V.bnode[b] + u] = 1;
+}
+
+__global__ void k_velocity(View V, const int* ok) {
+  const int n = gid();
+  if (n >= V.Nn) return;
+  const int s = V.nscene[n];
+  if (!ok[s]) return;
+  const double inv = 1.0 / V.sc[s].h;
+  for (int c = 0; c < 3; ++c) V.v[3 * n + c] = (V.x[3 * n + c] - V.xn[3 * n + c]) * inv;
+}
+
+__global__ void k_rollback(View V, const int* failed) {
+  const int n = gid();
+  if (n >= V.Nn) return;
+  if (!failed[V.nscene[n]]) return;
+  for (int c = 0; c < 3; ++c) V.x[3 * n + c] = V.xn[3 * n + c];
+}
+
+// ------------------------------------------------------------------ debug evaluators
+__global__ void k_debug_fem(int n, const double* x, const double* Dminv, const double* vol,
+                            double mu, double lam, double* e, double* g, double* H, double* Hp) {
+  const int t = gid();
+  if (t >= n) return;
+  const double* x12 = x + 12 * t;
+  const double* Dm = Dminv + 9 * t;
+  double F[9];
+  deformation_gradient(x12, Dm, F);
+  const double psi = nh_density(F, mu, lam);
+  if (e) e[t] = vol[t] * psi;
+  if (isinf(psi)) return;
+  double P[9], w[12];
+  nh_stress(F, mu, lam, P);
+  pullback(P, Dm, vol[t], w);
+  if (g)
+    for (int i = 0; i < 12; ++i) g[12 * t + i] = w[i];
+  Modes m;
+  nh_modes(F, mu, lam, m);
+  for (int pass = 0; pass < 2; ++pass) {
+    double* out = pass == 0 ? H : Hp;
+    if (!out) continue;
+    out += 144 * (size_t)t;
+    for (int i = 0; i < 144; ++i) out[i] = 0.0;
+    for (int k = 0; k < 9; ++k) {
+      const double lk = pass == 0 ? m.lam[k] : fmax(m.lam[k], 0.0);
+      double Q[9];
+      mode_matrix(m, k, Q);
+      pullback(Q, Dm, 1.0, w);
+      for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) out[12 * i + j] += vol[t] * lk * w[i] * w[j];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBarrierTPB) k_debug_barrier(int n, const int* kinds,
+                                                               const double* x, const double* meps,
+                                                               double dhat, double kappa, double* e,
+                                                               double* g, double* H, double* Hp,
+                                                               int* types) {
+  __shared__ double Hs[144 * kBarrierTPB];
+  __shared__ double Ws[144 * kBarrierTPB];
+  const int k = gid();
+  if (k >= n) return;
+  double* Hl = Hs + threadIdx.x;
+  double* Wl = Ws + threadIdx.x;
+  double ee, gg[12];
+  const int type = barrier_pair(kinds[k], x + 12 * k, meps[k], dhat, kappa, &ee, gg, Hl, kBarrierTPB);
+  if (e) e[k] = ee;
+  if (types) types[k] = type;
+  if (g)
+    for (int i = 0; i < 12; ++i) g[12 * k + i] = gg[i];
+  if (H)
+    for (int i = 0; i < 144; ++i) H[144 * (size_t)k + i] = Hl[i * kBarrierTPB];
+  psd_project_strided<12>(Hl, Wl, kBarrierTPB);
+  if (Hp)
+    for (int i = 0; i < 144; ++i) Hp[144 * (size_t)k + i] = Hl[i * kBarrierTPB];
+}
+
+__global__ void k_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,
+                            int max_iter, double* t) {
+  const int k = gid();
+  if (k >= n) return;
+  t[k] = accd(kinds[k], x + 12 * k, p + 12 * k, gap, max_iter);
+}
+
+__global__ void k_debug_arap(int n, const double* A, double* e, double* g, double* H, double* Hp) {
+  const int k = gid();
+  if (k >= n) return;
+  Modes m;
+  double ee, gA[9];
+  arap_modes(A + 9 * k, m, &ee, gA);
+  if (e) e[k] = ee;
+  if (g)
+    for (int i = 0; i < 9; ++i) g[9 * k + i] = gA[i];
+  for (int pass = 0; pass < 2; ++pass) {
+    double* out = pass == 0 ? H : Hp;
+    if (!out) continue;
+    out += 81 * (size_t)k;
+    for (int i = 0; i < 81; ++i) out[i] = 0.0;
+    for (int q = 0; q < 9; ++q) {
+      const double lk = pass == 0 ? m.lam[q] : fmax(m.lam[q], 0.0);
+      double Q[9];
+      mode_matrix(m, q, Q);
+      for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 9; ++j) out[9 * i + j] += lk * Q[i] * Q[j];
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+#define LAUNCH(kern, n, tpb, s, ...)                                          \
+  do {                                                                        \
+    const int _nb = nblk((n), (tpb));                                         \
+    if (_nb > 0) hipLaunchKernelGGL(kern, dim3(_nb), dim3(tpb), 0, s, __VA_ARGS__); \
+  } while (0)
+
+void launch_predict(const View& V, hipStream_t s) { LAUNCH(k_predict, V.Nn, TPB, s, V); }
+void launch_set_moving(const View& V, int n, const int* nodes, const double* tgt, hipStream_t s) {
+  LAUNCH(k_set_moving, n, TPB, s, V, n, nodes, tgt);
+}
+void launch_cpos(const View& V, hipStream_t s) { LAUNCH(k_cmap, V.Ncv, TPB, s, V, V.x, V.cpos); }
+void launch_cdisp(const View& V, const double* p, hipStream_t s) {
+  LAUNCH(k_cmap, V.Ncv, TPB, s, V, p, V.cdisp);
+}
+void launch_cend(const View& V, double* cend, hipStream_t s) {
+  LAUNCH(k_cend, 3 * V.Ncv, TPB, s, V, cend);
+}
+void launch_snap_disp(const View& V, const int* cand, hipStream_t s) {
+  LAUNCH(k_snap_disp, V.Ncv, TPB, s, V, cand);
+}
+void launch_body_resid(const View& V, unsigned long long* res, hipStream_t s) {
+  LAUNCH(k_body_resid, V.Ncv, TPB, s, V, res);
+}
+void launch_bp_targets(const View& V, const double* P0, const double* P1, BroadPhase& bp, int all,
+                       hipStream_t s) {
+  LAUNCH(k_bp_targets, bp.ntarget, TPB, s, V, P0, P1, bp, all);
+}
+void launch_bp_count(const View& V, BroadPhase& bp, hipStream_t s) {
+  LAUNCH(k_bp_count, bp.ntarget, TPB, s, V, bp);
+}
+void launch_bp_fill(const View& V, BroadPhase& bp, hipStream_t s) {
+  LAUNCH(k_bp_fill, bp.ntarget, TPB, s, V, bp);
+}
+void launch_bp_query(const View& V, const double* P0, const double* P1, BroadPhase& bp, int all,
+                     int emit, int* cand_q, int* cand_t, hipStream_t s) {
+  LAUNCH(k_bp_query, V.Nq, 128, s, V, P0, P1, bp, all, emit, cand_q, cand_t);
+}
+void launch_narrow(const View& V, int n, const int* cq, const int* ct, int* flag, hipStream_t s) {
+  LAUNCH(k_narrow, n, TPB, s, V, n, cq, ct, flag);
+}
+void launch_compact_pairs(const View& V, int n, const int* cq, const int* ct, const int* flag,
+                          const int* pos, int* pkind, int* pv, double* pmeps, int* pscene,
+                          hipStream_t s) {
+  LAUNCH(k_compact_pairs, n, TPB, s, V, n, cq, ct, flag, pos, pkind, pv, pmeps, pscene);
+}
+void launch_fem_hess(const View& V, hipStream_t s) { LAUNCH(k_fem_hess, 4 * V.Nt, TPB, s, V); }
+void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
+                         const double* pmeps, double* pg, double* ph, hipStream_t s) {
+  LAUNCH(k_barrier_hess, np, kBarrierTPB, s, V, np, pkind, pv, pmeps, pg, ph);
+}
+void launch_body_hess(const View& V, hipStream_t s) { LAUNCH(k_body_hess, V.Nb, 64, s, V); }
+void launch_assemble_bsr(const View& V, int nnz, const int* brow, hipStream_t s) {
+  LAUNCH(k_assemble_bsr, nnz, TPB, s, V, nnz, brow);
+}
+void launch_assemble_grad(const View& V, double* g, hipStream_t s) {
+  LAUNCH(k_assemble_grad, V.Nn, TPB, s, V, g);
+}
+void launch_contrib_count(const View& V, int np, const int* pv, int* hcnt, int* gcnt,
+                          hipStream_t s) {
+  LAUNCH(k_contrib_count, np + V.Nb, TPB, s, V, np, pv, hcnt, gcnt);
+}
+void launch_contrib_emit(const View& V, int np, const int* pv, const int* hoff, const int* goff,
+                         uint64_t* hkey, int* hidx, int* hsrc, double* hcoef, uint64_t* gkey,
+                         int* gidx, int* gsrc, double* gcoef, hipStream_t s) {
+  LAUNCH(k_contrib_emit, np + V.Nb, TPB, s, V, np, pv, hoff, goff, hkey, hidx, hsrc, hcoef, gkey,
+         gidx, gsrc, gcoef);
+}
+void launch_seg_flags(int n, const uint64_t* keys, int* flags, hipStream_t s) {
+  LAUNCH(k_seg_flags, n, TPB, s, n, keys, flags);
+}
+void launch_seg_start(int n, const int* flags, const int* segid, int* segstart, hipStream_t s) {
+  LAUNCH(k_seg_start, n, TPB, s, n, flags, segid, segstart);
+}
+void launch_reduce_blocks(const View& V, int nseg, const uint64_t* keys, const int* idx,
+                          const int* segstart, const int* src, const double* coef,
+                          const double* ph, int* drow, int* dcol, double* dval, int* rowcnt,
+                          hipStream_t s) {
+  LAUNCH(k_reduce_blocks, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, ph, drow, dcol,
+         dval, rowcnt);
+}
+void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int* idx,
+                        const int* segstart, const int* src, const double* coef,
+                        const double* pg, double* g, hipStream_t s) {
+  LAUNCH(k_reduce_grad, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, pg, g);
+}
+void launch_precond(const View& V, const int* drowptr, const int* dcol, const double* dval,
+                    double* pinv, int* bad, hipStream_t s) {
+  LAUNCH(k_precond_soft, V.Nn, TPB, s, V, drowptr, dcol, dval, pinv, bad);
+  LAUNCH(k_precond_body, V.Nb, 64, s, V, drowptr, dcol, dval, bad);
+}
+void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
+  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_init, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
+}
+void launch_pcg_iteration(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
+                          hipStream_t s) {
+  if (T.nblk <= 0) return;
+  hipLaunchKernelGGL(k_pcg_spmv, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
+  hipLaunchKernelGGL(k_pcg_update1, dim3(T.nblk), dim3(TPB), 0, s, V, T, B, parity);
+  hipLaunchKernelGGL(k_pcg_update2, dim3(T.nblk), dim3(TPB), 0, s, V, T, B, parity);
+}
+void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s) {
+  LAUNCH(k_pmax, V.Nn + V.Ncv, TPB, s, V, p, pmax);
+}
+void launch_ccd(const View& V, int n, const int* cq, const int* ct, unsigned long long* amin,
+                hipStream_t s) {
+  LAUNCH(k_ccd, n, 64, s, V, n, cq, ct, amin);
+}
+void launch_scene_count(const View& V, int n, const int* cq, int* cnt, hipStream_t s) {
+  LAUNCH(k_scene_count, n, TPB, s, V, n, cq, cnt);
+}
+void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, int ncand,
+                        const int* cq, const int* ct, const LsBufs& L, hipStream_t s) {
+  if (TN.nblk > 0) hipLaunchKernelGGL(k_ls_nodes, dim3(TN.nblk), dim3(TPB), 0, s, V, TN, L);
+  if (TT.nblk > 0) hipLaunchKernelGGL(k_ls_tets, dim3(TT.nblk), dim3(TPB), 0, s, V, TT, L);
+  LAUNCH(k_ls_bodies, V.Nb, 64, s, V, L);
+  LAUNCH(k_ls_pairs, ncand, 64, s, V, ncand, cq, ct, L);
+  hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(64), 0, s, V, TN, TT, L);
+}
+void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s) {
+  LAUNCH(k_update, V.Nn, TPB, s, V, p, alpha);
+}
+void launch_al_apply(const View& V, const int* action, hipStream_t s) {
+  LAUNCH(k_al_apply, V.Nb, 64, s, V, action);
+}
+void launch_body_reset(const View& V, double kappa0, hipStream_t s) {
+  LAUNCH(k_body_reset, V.Nb, 64, s, V, kappa0);
+}
+void launch_velocity(const View& V, const int* ok, hipStream_t s) {
+  LAUNCH(k_velocity, V.Nn, TPB, s, V, ok);
+}
+void launch_rollback(const View& V, const int* failed, hipStream_t s) {
+  LAUNCH(k_rollback, V.Nn, TPB, s, V, failed);
+}
+void launch_debug_fem(int n, const double* x, const double* Dminv, const double* vol, double mu,
+                      double lam, double* e, double* g, double* H, double* Hp, hipStream_t s) {
+  LAUNCH(k_debug_fem, n, 64, s, n, x, Dminv, vol, mu, lam, e, g, H, Hp);
+}
+void launch_debug_barrier(int n, const int* kinds, const double* x, const double* meps,
+                          double dhat, double kappa, double* e, double* g, double* H, double* Hp,
+                          int* types, hipStream_t s) {
+  LAUNCH(k_debug_barrier, n, kBarrierTPB, s, n, kinds, x, meps, dhat, kappa, e, g, H, Hp, types);
+}
+void launch_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,
+                      int max_iter, double* t, hipStream_t s) {
+  LAUNCH(k_debug_ccd, n, 64, s, n, kinds, x, p, gap, max_iter, t);
+}
+void launch_debug_arap(int n, const double* A, double* e, double* g, double* H, double* Hp,
+                       hipStream_t s) {
+  LAUNCH(k_debug_arap, n, 64, s, n, A, e, g, H, Hp);
+}
+
+}  // namespace tc

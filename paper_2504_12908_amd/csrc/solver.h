@@ -1,0 +1,110 @@
+// Internal interface of the batched IPC time-step solver (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/taccel.h"
+
+namespace tc {
+
+constexpr int kTrials = 8;        // line-search step sizes evaluated per launch
+constexpr int kNodeChunk = 256;   // nodes per workgroup in node-parallel kernels (multiple of 4)
+constexpr int kTetChunk = 256;
+
+// Per-scene constants, resident on the device.
+struct SceneConst {
+  double h, dhat, kappa, kappa_s, stop, mu, lam, pcg_eta;
+  double grav[3];
+  double cell, org[3];
+  int node0, node1, tet0, tet1, cv0, cv1, q0, q1, body0, body1, tri0, tri1, edge0, edge1;
+  int precision, pad;
+};
+
+// Raw device pointers of a batch; passed by value to every kernel.
+struct View {
+  int S, Nn, Nt, Nb, Ncv, Ntr, Ned, Nq;
+  const SceneConst* sc;
+  // nodes: soft vertices, padding, 4 pseudo-nodes per affine body (p, c1, c2, c3)
+  double *x, *xn, *xhat, *v;
+  const double* mass;
+  int* nfree;        // 1 if the node's 3 dofs are unknowns
+  const int* nscene;
+  const int* nbody;  // body of a pseudo-node, -1 otherwise
+  const int* ntype;  // 0 soft, 1 body p, 2 body c, 3 padding
+  // tets (SoA)
+  const int* tv;      // [4][Nt] node ids
+  const double* Dminv;  // [9][Nt]
+  const double* tvol;
+  const int* tscene;
+  double* Hloc;  // [Nt][16][9]
+  double* gloc;  // [Nt][12]
+  // static BSR over nodes (FEM pattern)
+  const int* rowptr;
+  const int* col;
+  double* val;
+  const int* diag;
+  const int* cptr;
+  const int* clist;  // tet*16 + a*4 + b
+  const int* vptr;
+  const int* vlist;  // tet*4 + a
+  // bodies
+  const int* bnode;
+  const int* bscene;
+  const double* bmass;  // m, Q[9]
+  const double* bvol;
+  const int* bpres;
+  double* bstar;  // y* [12]
+  double* blam;   // multipliers [12]
+  double* bkap;   // penalty
+  int* bsnap;
+  double* bgrad;  // [12]
+  double* bhess;  // [144]
+  double* bpinv;  // [144]
+  const int* bcv0;
+  const int* bcv1;
+  // contact vertices and primitives
+  const int* cvn;
+  const int* cvb;
+  const double* cvx;  // xbar [3]
+  const int* cvfix;
+  const int* cvscene;
+  const int* cvworld;
+  double* cpos;
+  double* cdisp;
+  const int* trv;  // [Ntr][3] contact-vertex ids
+  const int* edv;  // [Ned][2]
+  const double* elen2;
+  const int* qkind;  // 0: vertex (PT query), 1: edge (EE query)
+  const int* qidx;
+  const int* qscene;
+  // per-scene state
+  int* act;    // scene takes part in the current Newton iteration
+  int* pdone;  // PCG finished for the scene
+};
+
+// A batch of independent scenes solved together.
+class Batch {
+ public:
+  static taccel_status create(const taccel_scene_desc* d, int n, const taccel_runtime* rt,
+                              Batch** out, std::string& err);
+  ~Batch();
+  taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st);
+  taccel_status read(int scene, taccel_field f, void* dst, size_t bytes);
+  taccel_status write(int scene, taccel_field f, const void* src, size_t bytes);
+  taccel_status debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
+                                 int32_t* n);
+  int num_scenes() const { return S_; }
+
+  struct Impl;
+  Impl* impl_ = nullptr;
+
+ private:
+  int S_ = 0;
+};
+
+void set_last_error(const std::string& msg);
+
+}  // namespace tc
