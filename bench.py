@@ -1,0 +1,121 @@
+"""Benchmark: Newton-converged env-steps/s of the IPC time step on one MI355X.
+
+Workload (one scene, FP64): a 32x24x6 mm gel pad meshed as a 32x24x6 hex grid split into
+6 tets per hex (5,775 vertices, 27,648 tets, bottom face fixed, neo-Hookean E = 0.3 MPa,
+nu = 0.45) pressed by a rigid 400-point random convex hull (796 triangles, 8 mm extent)
+that is lowered 1.0 mm over 50 steps and then slid 2 mm over 50 steps, h = 0.005 s,
+dhat = 1e-4 m, kappa = 1e3, Newton tolerance 1e-6.  Synthetic seeded input (seed 0).
+
+A step is one call of taccel_step (predict, Newton loops with broad phase, narrow phase,
+barrier / FEM / affine-body derivatives, assembly, PCG, CCD, line search, augmented
+Lagrangian rounds and snap, velocity update).  After W warm-up steps, K steps are timed
+with the device synchronised on both sides.  The PCG sparse matrix-vector kernel is timed
+with HIP events on the solver's stream over the timed region (roofline field).  The CPU
+FP64 oracle is timed on a bounded sample of the same workload (cpu_baseline field).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Newton-converged env-steps/sec on 1 GPU; p50/p99 step latency; vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(spec, k_warm, k_timed):
+    """Oracle on the host: warm-up steps, then time k_timed steps (one scene, one core)."""
+    from oracle import binding as O
+
+    o = O.OracleScene(spec)
+    for k in range(k_warm):
+        o.step(k)
+    t0 = time.perf_counter()
+    ok = 0
+    for k in range(k_warm, k_warm + k_timed):
+        rc, _ = o.step(k)
+        ok += rc == 0
+    dt = time.perf_counter() - t0
+    return dict(value=ok / dt, unit="env-steps/s", cores=1, kind="oracle",
+                sample=f"steps {k_warm}..{k_warm + k_timed - 1} of the same scene after "
+                       f"{k_warm} warm-up step(s); one scene on one host core; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (scenes shard across GPUs without "
+              "communication; no multi-GPU run is part of it)", file=sys.stderr)
+        sys.exit(1)
+    import numpy as np
+
+    from paper_2504_12908_amd import scenes, taccel
+
+    spec = scenes.pad_press_slide_hull(0)
+    W, K = args.warmup, args.steps
+    if W + K > spec.n_steps:
+        sys.exit(f"warmup + steps must be <= {spec.n_steps}")
+    sc = taccel.Scene(spec)
+    for k in range(W):
+        rc, st = sc.step(k)
+        print(f"warmup step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
+              f"pcg={st['pcg_iters']} {st['step_ms']:.1f} ms", file=sys.stderr, flush=True)
+    taccel.device_synchronize()
+    taccel.profile_reset()
+    taccel.profile_enable(True)
+    lat = []
+    ok = 0
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(W, W + K):
+        ts = time.perf_counter()
+        rc, st = sc.step(k)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        ok += rc == taccel.OK
+        stats.append(st)
+        print(f"step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
+              f"al={st['al_rounds']} pcg={st['pcg_iters']} active={st['n_active']} "
+              f"{lat[-1]:.1f} ms", file=sys.stderr, flush=True)
+    taccel.device_synchronize()
+    dt = time.perf_counter() - t0
+    taccel.profile_enable(False)
+    prof = taccel.profile_query("spmv")
+    n_l = max(prof["launches"], 1)
+    avg_ms = prof["total_ms"] / n_l
+    bytes_per_launch = prof["bytes"] / n_l
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    out = dict(
+        metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
+        ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload="gel pad 32x24x6 grid (5775 verts, 27648 tets) pressed and slid "
+                             "by a 400-point convex hull (796 tris), 1 scene, FP64",
+                    scenes=1, h=spec.params["h"], step_range=[W, W + K - 1],
+                    precision="fp64"),
+        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+        newton_iters_per_step=float(np.mean([s["newton_iters"] for s in stats])),
+        pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
+        roofline=dict(bound="hbm", kernel="k_pcg_spmv", achieved=achieved, peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                      launches=prof["launches"], avg_launch_us=avg_ms * 1e3,
+                      algorithmic_bytes_per_launch=bytes_per_launch),
+    )
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, 1, 1)
+        v = out["cpu_baseline"]["value"]
+        out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / v if v > 0 else None
+    sc.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

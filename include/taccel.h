@@ -180,6 +180,18 @@ taccel_status taccel_debug_arap(int32_t n, const double* A, double* e, double* g
 taccel_status taccel_debug_candidates(taccel_scene* s, const double* P0, const double* P1,
                                       int32_t* out, int32_t cap, int32_t* n);
 
+/* ---- Measurement --------------------------------------------------------------------
+ * Process-wide HIP-event timing of the PCG sparse matrix-vector kernel ("spmv"), off by
+ * default.  While enabled, every SpMV launch is bracketed by two events on the scene's
+ * stream; query returns the summed kernel milliseconds, the number of launches and the
+ * summed algorithmic bytes (values, indices and vectors the product must move once). */
+void taccel_profile_enable(int32_t on);
+void taccel_profile_reset(void);
+taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t* launches,
+                                   double* algorithmic_bytes);
+/* hipDeviceSynchronize on the current device. */
+taccel_status taccel_device_synchronize(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,11 @@
 
 namespace tc {
 
+Profiler& profiler() {
+  static Profiler p;
+  return p;
+}
+
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error_cstr() { return g_last_error.c_str(); }
@@ -165,6 +170,8 @@ struct Batch::Impl {
   std::vector<HostScene> hs;
   std::vector<SceneConst> hsc;
   std::vector<int> h_ntype, h_nscene, h_bnode, h_bscene, h_bpres, h_moving_nodes;
+  std::vector<double> spmv_static_bytes;  // per scene: algorithmic bytes of the FEM part of SpMV
+  std::vector<hipEvent_t> ev_pool;
   // static device data
   DBuf<SceneConst> d_sc;
   DBuf<double> x, xn, xhat, v, mass;
@@ -612,6 +619,15 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   tt_sblk_h.push_back((int)tt_sc_h.size());
   nnz = (int)h_col.size();
   h_nscene.resize(Nn);
+  // Algorithmic bytes of one SpMV over the static (FEM) pattern: for every free row its
+  // blocks (72 B values + 4 B column), row pointer (4 B), free flag (4 B), the 24 B of x
+  // read and the 24 B of y written; plus 24 B of x per free node gathered once.
+  spmv_static_bytes.assign(S, 0.0);
+  for (int n = 0; n < Nn; ++n) {
+    if (!h_nfree[n]) continue;
+    const int nb_row = h_rowptr[n + 1] - h_rowptr[n];
+    spmv_static_bytes[h_nscene[n]] += 76.0 * nb_row + 4.0 + 4.0 + 24.0 + 24.0;
+  }
   // SoA tet arrays
   std::vector<int> h_tv(4 * (size_t)Nt);
   std::vector<double> h_Dminv(9 * (size_t)Nt);
@@ -854,14 +870,49 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_pcg_init(V, TN, B, s);
   int parity = 0;
   std::vector<int> hd(S);
+  Profiler& prof = profiler();
+  double launch_bytes = 0.0;
+  if (prof.on) {
+    std::vector<int> ha(S);
+    d2h(ha.data(), act.p, S);
+    sync();
+    for (int k = 0; k < S; ++k)
+      if (ha[k]) launch_bytes += spmv_static_bytes[k];
+    // dynamic (contact and body) blocks: 72 B values + 4 B column each, 4 B row pointer per node
+    launch_bytes += 76.0 * nseg + 4.0 * Nn;
+  }
+  size_t ev_used = 0;
   for (int it = 0; it < max_pcg;) {
     const int chunk = 8;
     for (int k = 0; k < chunk; ++k, ++it) {
-      launch_pcg_iteration(V, TN, B, parity, s);
+      if (prof.on) {
+        while (ev_pool.size() < ev_used + 2) {
+          hipEvent_t e;
+          HIPCHECK(hipEventCreate(&e));
+          ev_pool.push_back(e);
+        }
+        HIPCHECK(hipEventRecord(ev_pool[ev_used], s));
+        launch_pcg_spmv(V, TN, B, s);
+        HIPCHECK(hipEventRecord(ev_pool[ev_used + 1], s));
+        ev_used += 2;
+      } else {
+        launch_pcg_spmv(V, TN, B, s);
+      }
+      launch_pcg_update(V, TN, B, parity, s);
       parity ^= 1;
     }
     d2h(hd.data(), pdone.p, S);
     sync();
+    if (prof.on) {
+      for (size_t e = 0; e < ev_used; e += 2) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, ev_pool[e], ev_pool[e + 1]));
+        prof.spmv_ms += ms;
+        prof.spmv_launches += 1;
+        prof.spmv_bytes += launch_bytes;
+      }
+      ev_used = 0;
+    }
     bool all = true;
     for (int k = 0; k < S; ++k) all = all && hd[k];
     if (all) break;
@@ -1215,6 +1266,7 @@ Batch::~Batch() {
   Impl& I = *impl_;
   (void)hipStreamSynchronize(I.mem.stream);
   I.release_all();
+  for (hipEvent_t e : I.ev_pool) (void)hipEventDestroy(e);
 #define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
   FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.Hloc, &I.gloc, &I.val, &I.bmass,
            &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,

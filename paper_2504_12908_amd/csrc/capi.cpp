@@ -251,4 +251,28 @@ taccel_status taccel_debug_arap(int32_t n, const double* A, double* e, double* g
   return fetch(Hp, dHp, 81 * (size_t)n);
 }
 
+void taccel_profile_enable(int32_t on) { tc::profiler().on = on != 0; }
+
+void taccel_profile_reset(void) {
+  tc::Profiler& p = tc::profiler();
+  p.spmv_ms = 0.0;
+  p.spmv_launches = 0;
+  p.spmv_bytes = 0.0;
+}
+
+taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t* launches,
+                                   double* algorithmic_bytes) {
+  if (!kernel || std::strcmp(kernel, "spmv") != 0)
+    return fail(TACCEL_ERR_ARG, "profile_query: only \"spmv\" is instrumented");
+  const tc::Profiler& p = tc::profiler();
+  if (total_ms) *total_ms = p.spmv_ms;
+  if (launches) *launches = p.spmv_launches;
+  if (algorithmic_bytes) *algorithmic_bytes = p.spmv_bytes;
+  return TACCEL_OK;
+}
+
+taccel_status taccel_device_synchronize(void) {
+  return hip_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
+}
+
 }  // extern "C"

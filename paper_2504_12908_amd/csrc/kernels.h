@@ -91,8 +91,18 @@ struct PcgBufs {
   int max_iters;
 };
 void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
-void launch_pcg_iteration(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
-                          hipStream_t s);
+void launch_pcg_spmv(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
+void launch_pcg_update(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
+                       hipStream_t s);
+
+// Process-wide kernel timing with HIP events (off by default).
+struct Profiler {
+  bool on = false;
+  double spmv_ms = 0.0;
+  long long spmv_launches = 0;
+  double spmv_bytes = 0.0;
+};
+Profiler& profiler();
 
 // convergence, CCD, line search, update
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s);

@@ -1332,10 +1332,12 @@ void launch_precond(const View& V, const int* drowptr, const int* dcol, const do
 void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
   if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_init, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
 }
-void launch_pcg_iteration(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
-                          hipStream_t s) {
+void launch_pcg_spmv(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
+  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_spmv, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
+}
+void launch_pcg_update(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
+                       hipStream_t s) {
   if (T.nblk <= 0) return;
-  hipLaunchKernelGGL(k_pcg_spmv, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
   hipLaunchKernelGGL(k_pcg_update1, dim3(T.nblk), dim3(TPB), 0, s, V, T, B, parity);
   hipLaunchKernelGGL(k_pcg_update2, dim3(T.nblk), dim3(TPB), 0, s, V, T, B, parity);
 }

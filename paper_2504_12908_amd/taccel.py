@@ -103,6 +103,8 @@ def lib():
         L.taccel_debug_ccd.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_int32, _dp]
         L.taccel_debug_arap.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.taccel_debug_candidates.argtypes = [C.c_void_p, _dp, _dp, _ip, C.c_int32, _ip]
+        L.taccel_profile_enable.argtypes = [C.c_int32]
+        L.taccel_profile_query.argtypes = [C.c_char_p, _dp, C.POINTER(C.c_int64), _dp]
         _lib = L
     return _lib
 
@@ -306,6 +308,28 @@ class Batch:
     def write(self, i, field, arr):
         a = _f64(arr)
         _check(lib().taccel_batch_write(self.h, i, field, a.ctypes.data, a.nbytes), "batch_write")
+
+
+# ------------------------------------------------------------------ measurement
+def profile_enable(on=True):
+    lib().taccel_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().taccel_profile_reset()
+
+
+def profile_query(kernel="spmv"):
+    ms = C.c_double()
+    n = C.c_int64()
+    b = C.c_double()
+    _check(lib().taccel_profile_query(kernel.encode(), C.byref(ms), C.byref(n), C.byref(b)),
+           "profile_query")
+    return dict(total_ms=ms.value, launches=n.value, bytes=b.value)
+
+
+def device_synchronize():
+    _check(lib().taccel_device_synchronize(), "device_synchronize")
 
 
 # ------------------------------------------------------------------ element evaluators
