@@ -186,8 +186,13 @@ struct Batch::Impl {
   DBuf<double> cvx, cpos, cdisp, cend, elen2;
   DBuf<int> act, pdone;
   // block tables
-  DBuf<int> tn_sc, tn_b0, tn_b1, tn_sblk, tt_sc, tt_b0, tt_b1, tt_sblk;
-  BlockTable TN, TT;
+  DBuf<int> tn_sc, tn_b0, tn_b1, tn_sblk, tt_sc, tt_b0, tt_b1, tt_sblk, ts_sc, ts_b0, ts_b1, ts_sblk;
+  BlockTable TN, TT, TS;
+  // candidate list that covers every pair that can be closer than dhat at the current
+  // positions (the swept set of the last Newton iteration, valid until something moves
+  // outside its sweep)
+  bool cover_valid = false;
+  int n_cover = 0;
   // dynamic work buffers
   BroadPhase bp;
   DBuf<double> bp_tbox;
@@ -287,6 +292,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   std::vector<int> h_cvn, h_cvb, h_cvfix, h_cvscene, h_cvworld, h_trv, h_edv, h_qkind, h_qidx, h_qscene;
   std::vector<double> h_cvx, h_elen2;
   std::vector<int> tn_sc_h, tn_b0_h, tn_b1_h, tn_sblk_h, tt_sc_h, tt_b0_h, tt_b1_h, tt_sblk_h;
+  std::vector<int> ts_sc_h, ts_b0_h, ts_b1_h, ts_sblk_h;
   // static BSR built per scene and concatenated
   std::vector<int> h_rowptr(1, 0), h_col, h_diag, h_cptr(1, 0), h_clist, h_vptr(1, 0), h_vlist, h_brow;
   for (int s = 0; s < S; ++s) {
@@ -601,6 +607,12 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
       tn_b0_h.push_back(b0);
       tn_b1_h.push_back(std::min(b0 + kNodeChunk, node0 + nn));
     }
+    ts_sblk_h.push_back((int)ts_sc_h.size());
+    for (int b0 = node0; b0 < node0 + nn; b0 += kRowChunk) {
+      ts_sc_h.push_back(s);
+      ts_b0_h.push_back(b0);
+      ts_b1_h.push_back(std::min(b0 + kRowChunk, node0 + nn));
+    }
     tt_sblk_h.push_back((int)tt_sc_h.size());
     for (int b0 = tet0; b0 < tet0 + nt; b0 += kTetChunk) {
       tt_sc_h.push_back(s);
@@ -617,6 +629,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   }
   tn_sblk_h.push_back((int)tn_sc_h.size());
   tt_sblk_h.push_back((int)tt_sc_h.size());
+  ts_sblk_h.push_back((int)ts_sc_h.size());
   nnz = (int)h_col.size();
   h_nscene.resize(Nn);
   // Algorithmic bytes of one SpMV over the static (FEM) pattern: for every free row its
@@ -705,10 +718,17 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   TN.sc = tn_sc.p; TN.b0 = tn_b0.p; TN.b1 = tn_b1.p; TN.sblk = tn_sblk.p;
   TT.nblk = (int)tt_sc_h.size();
   TT.sc = tt_sc.p; TT.b0 = tt_b0.p; TT.b1 = tt_b1.p; TT.sblk = tt_sblk.p;
+  ts_sc.upload(m, ts_sc_h);
+  ts_b0.upload(m, ts_b0_h);
+  ts_b1.upload(m, ts_b1_h);
+  ts_sblk.upload(m, ts_sblk_h);
+  TS.nblk = (int)ts_sc_h.size();
+  TS.sc = ts_sc.p; TS.b0 = ts_b0.p; TS.b1 = ts_b1.p; TS.sblk = ts_sblk.p;
   // PCG / line-search / misc
   for (DBuf<double>* b : {&g, &r, &z, &p, &q, &dx}) b->ensure(m, 3 * (size_t)Nn);
   pinv.ensure(m, 9 * (size_t)Nn);
-  for (DBuf<double>* b : {&P_pq, &P_rz0, &P_rz1, &P_rr, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
+  for (DBuf<double>* b : {&P_rz0, &P_rz1, &P_rr, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
+  P_pq.ensure(m, std::max(TS.nblk, 1));
   iters.ensure(m, S);
   bad.ensure(m, S);
   infeasible.ensure(m, S);
@@ -789,11 +809,23 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   hipStream_t s = stream();
   View V = view();
   launch_cpos(V, s);
-  // ---- active pairs at the current point
-  const int ncand = broad_phase(cpos.p, nullptr, 0, cq, ct);
+  // ---- active pairs at the current point: from the covering set of the previous
+  // iteration when it is still valid, else from a static broad phase
+  int ncand;
+  const int* cqp;
+  const int* ctp;
+  if (cover_valid) {
+    ncand = n_cover;
+    cqp = sq.p;
+    ctp = st.p;
+  } else {
+    ncand = broad_phase(cpos.p, nullptr, 0, cq, ct);
+    cqp = cq.p;
+    ctp = ct.p;
+  }
   cflag.ensure(&mem, std::max(ncand, 1));
   cpos_idx.ensure(&mem, std::max(ncand, 1));
-  launch_narrow(V, ncand, cq.p, ct.p, cflag.p, s);
+  launch_narrow(V, ncand, cqp, ctp, cflag.p, s);
   const int np = scan(cflag.p, cpos_idx.p, ncand);
   pkind.ensure(&mem, std::max(np, 1));
   pv.ensure(&mem, 4 * (size_t)std::max(np, 1));
@@ -801,7 +833,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   pscene.ensure(&mem, std::max(np, 1));
   pg.ensure(&mem, 12 * (size_t)std::max(np, 1));
   ph.ensure(&mem, 144 * (size_t)std::max(np, 1));
-  launch_compact_pairs(V, ncand, cq.p, ct.p, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
+  launch_compact_pairs(V, ncand, cqp, ctp, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
   // ---- element derivatives
   launch_fem_hess(V, s);
   launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, s);
@@ -883,7 +915,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   }
   size_t ev_used = 0;
   for (int it = 0; it < max_pcg;) {
-    const int chunk = 8;
+    const int chunk = 16;
     for (int k = 0; k < chunk; ++k, ++it) {
       if (prof.on) {
         while (ev_pool.size() < ev_used + 2) {
@@ -892,13 +924,13 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
           ev_pool.push_back(e);
         }
         HIPCHECK(hipEventRecord(ev_pool[ev_used], s));
-        launch_pcg_spmv(V, TN, B, s);
+        launch_pcg_spmv(V, TS, B, s);
         HIPCHECK(hipEventRecord(ev_pool[ev_used + 1], s));
         ev_used += 2;
       } else {
-        launch_pcg_spmv(V, TN, B, s);
+        launch_pcg_spmv(V, TS, B, s);
       }
-      launch_pcg_update(V, TN, B, parity, s);
+      launch_pcg_update(V, TN, TS, B, parity, s);
       parity ^= 1;
     }
     d2h(hd.data(), pdone.p, S);
@@ -941,6 +973,8 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_cdisp(V, dx.p, s);
   launch_cend(V, cend.p, s);
   const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
+  n_cover = nsw;
+  cover_valid = true;
   {
     std::vector<unsigned long long> one(S);
     const double d1 = 1.0;
@@ -952,10 +986,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_ccd(V, nsw, sq.p, st.p, amin, s);
   std::vector<unsigned long long> ha(S);
   d2h(ha.data(), amin, S);
-  zero(scnt.p, sizeof(int) * (S + 1));
-  launch_scene_count(V, nsw, sq.p, scnt.p, s);
-  ensure_scratch(scan_scratch_bytes(S + 1));
-  HIPCHECK(exclusive_scan(scnt.p, cand_off.p, S + 1, nullptr, scratch.p, s));
+  launch_scene_offsets(V, nsw, sq.p, cand_off.p, s);
   sync();
   std::vector<double> amax(S), alpha_h(S, 0.0);
   for (int k = 0; k < S; ++k) std::memcpy(&amax[k], &ha[k], sizeof(double));
@@ -1075,6 +1106,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
     launch_set_moving(V, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
   }
   launch_body_reset(V, 1e6, s);
+  cover_valid = false;
   // initial residual of every prescribed body
   unsigned long long* bres = u64s.p + 2 * S;
   zero(bres, sizeof(unsigned long long) * (Nb + 1));
@@ -1165,6 +1197,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       launch_snap_disp(V, snapcand.p, s);
       launch_cend(V, cend.p, s);
       const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
+      cover_valid = false;
       unsigned long long* amin = u64s.p + S;
       std::vector<unsigned long long> one(S);
       const double d1 = 1.0;
@@ -1273,6 +1306,7 @@ Batch::~Batch() {
            &I.cend, &I.elen2, &I.bp_tbox, &I.pmeps, &I.pg, &I.ph, &I.hcoef, &I.gcoef, &I.dval, &I.g, &I.r,
            &I.z, &I.p, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
            &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs)
+  FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
            &I.clist, &I.vptr, &I.vlist, &I.brow, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,
            &I.cvn, &I.cvb, &I.cvfix, &I.cvscene, &I.cvworld, &I.trv, &I.edv, &I.qkind, &I.qidx, &I.qscene,

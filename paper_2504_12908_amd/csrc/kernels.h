@@ -91,9 +91,9 @@ struct PcgBufs {
   int max_iters;
 };
 void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
-void launch_pcg_spmv(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
-void launch_pcg_update(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
-                       hipStream_t s);
+void launch_pcg_spmv(const View& V, const BlockTable& TS, const PcgBufs& B, hipStream_t s);
+void launch_pcg_update(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+                       int parity, hipStream_t s);
 
 // Process-wide kernel timing with HIP events (off by default).
 struct Profiler {
@@ -108,7 +108,7 @@ Profiler& profiler();
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s);
 void launch_ccd(const View& V, int n, const int* cand_q, const int* cand_t,
                 unsigned long long* amin, hipStream_t s);
-void launch_scene_count(const View& V, int n, const int* cand_q, int* cnt, hipStream_t s);
+void launch_scene_offsets(const View& V, int n, const int* cand_q, int* off, hipStream_t s);
 struct LsBufs {
   const double* p;        // node-space direction
   const double* abase;    // [S] largest trial step of this launch

@@ -355,8 +355,9 @@ __global__ void k_narrow(View V, int n, const int* cq, const int* ct, int* flag)
   const int kind = cand_verts(V, cq[k], ct[k], ids);
   double x12[12];
   gather12(V.cpos, ids, x12);
-  const double dhat = V.sc[V.qscene[cq[k]]].dhat;
-  flag[k] = pair_sqdist(kind, x12, nullptr) < dhat * dhat ? 1 : 0;
+  const int s = V.qscene[cq[k]];
+  const double dhat = V.sc[s].dhat;
+  flag[k] = V.act[s] && pair_sqdist(kind, x12, nullptr) < dhat * dhat ? 1 : 0;
 }
 
 __global__ void k_compact_pairs(View V, int n, const int* cq, const int* ct, const int* flag,
@@ -414,26 +415,119 @@ __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
       for (int j = 0; j < 3; ++j) out[9 * b + 3 * i + j] = scale * acc[12 * i + 3 * b + j];
 }
 
-// ------------------------------------------------------------------ barrier (1 thread/pair)
-constexpr int kBarrierTPB = 16;  // 2 x 144 doubles of LDS per thread: 36 KB per workgroup
-__global__ void __launch_bounds__(kBarrierTPB) k_barrier_hess(View V, int np, const int* pkind,
-                                                              const int* pv, const double* pmeps,
-                                                              double* pg, double* ph) {
-  __shared__ double Hs[144 * kBarrierTPB];
-  __shared__ double Ws[144 * kBarrierTPB];
-  const int k = gid();
+// ------------------------------------------------------------------ wave-parallel Jacobi
+// PSD projection (eigenvalues clamped at 0) of a symmetric 12x12 matrix by one wavefront:
+// parallel cyclic Jacobi with the round-robin ("tournament") ordering, 6 disjoint rotations
+// per round applied together as A <- J^T A J, V <- V J.  A and V live in LDS (double
+// buffered); on return A holds the projected matrix.  All 64 lanes of the workgroup call it.
+struct WaveJacobiLds {
+  double A[2][144];
+  double V[2][144];
+  double c[6], s[6];
+  double red[1];
+};
+__device__ __forceinline__ int tour_index(int pos, int r) {  // index at a tournament position
+  return pos == 0 ? 0 : 1 + (pos - 1 + r) % 11;
+}
+__device__ __forceinline__ int tour_pos(int idx, int r) {
+  return idx == 0 ? 0 : 1 + ((idx - 1 - r) % 11 + 11) % 11;
+}
+__device__ void wave_psd12(WaveJacobiLds& L) {
+  const int lane = threadIdx.x;
+  int cur = 0;
+  for (int e = lane; e < 144; e += 64) L.V[0][e] = (e / 12 == e % 12) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = lane; e < 144; e += 64) {
+      const double a = L.A[cur][e];
+      tot += a * a;
+      if (e / 12 != e % 12) off += a * a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      tot += __shfl_xor(tot, o, 64);
+    }
+    if (off <= 1e-30 * tot) break;
+    for (int r = 0; r < 11; ++r) {
+      if (lane < 6) {
+        int p = tour_index(lane, r), q = tour_index(11 - lane, r);
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double apq = L.A[cur][12 * p + q];
+        double c = 1.0, sn = 0.0;
+        if (apq != 0.0) {
+          const double theta = (L.A[cur][12 * q + q] - L.A[cur][12 * p + p]) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sn = t * c;
+        }
+        L.c[lane] = c;
+        L.s[lane] = sn;
+      }
+      __syncthreads();
+      const int nxt = cur ^ 1;
+      for (int e = lane; e < 288; e += 64) {
+        const bool isV = e >= 144;
+        const int ee = isV ? e - 144 : e;
+        const int i = ee / 12, j = ee % 12;
+        // rotation acting on column j: partner index and coefficients
+        const int pj = tour_pos(j, r), kj = pj < 6 ? pj : 11 - pj;
+        const int oj = tour_index(11 - pj, r);
+        const double cj = L.c[kj], sj = L.s[kj];
+        // J[j][j] = c; J[oj][j] = -s if j is the smaller index of its pair, else +s
+        const double jjj = cj, joj = j < oj ? -sj : sj;
+        if (isV) {
+          L.V[nxt][ee] = L.V[cur][12 * i + j] * jjj + L.V[cur][12 * i + oj] * joj;
+        } else {
+          const int pi = tour_pos(i, r), ki = pi < 6 ? pi : 11 - pi;
+          const int oi = tour_index(11 - pi, r);
+          const double ci = L.c[ki], si = L.s[ki];
+          const double jii = ci, joi = i < oi ? -si : si;
+          const double a_ij = L.A[cur][12 * i + j], a_ioj = L.A[cur][12 * i + oj];
+          const double a_oij = L.A[cur][12 * oi + j], a_oioj = L.A[cur][12 * oi + oj];
+          L.A[nxt][ee] = jii * (a_ij * jjj + a_ioj * joj) + joi * (a_oij * jjj + a_oioj * joj);
+        }
+      }
+      __syncthreads();
+      cur = nxt;
+    }
+  }
+  // rebuild with clamped eigenvalues: out_ij = sum_k V_ik max(w_k, 0) V_jk
+  const int nxt = cur ^ 1;
+  for (int e = lane; e < 144; e += 64) {
+    const int i = e / 12, j = e % 12;
+    double acc = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      const double w = L.A[cur][13 * k];
+      if (w > 0.0) acc += L.V[cur][12 * i + k] * w * L.V[cur][12 * j + k];
+    }
+    L.A[nxt][e] = acc;
+  }
+  __syncthreads();
+  for (int e = lane; e < 144; e += 64) L.A[0][e] = L.A[nxt][e];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ barrier (1 wave per pair)
+__global__ void __launch_bounds__(64) k_barrier_hess(View V, int np, const int* pkind,
+                                                     const int* pv, const double* pmeps, double* pg,
+                                                     double* ph) {
+  __shared__ WaveJacobiLds L;
+  __shared__ double g_s[12];
+  const int k = blockIdx.x;
   if (k >= np) return;
-  int ids[4];
-  for (int v = 0; v < 4; ++v) ids[v] = pv[4 * k + v];
-  const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
-  double x12[12], g[12], e;
-  gather12(V.cpos, ids, x12);
-  double* H = Hs + threadIdx.x;
-  double* W = Ws + threadIdx.x;
-  barrier_pair(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, &e, g, H, kBarrierTPB);
-  psd_project_strided<12>(H, W, kBarrierTPB);
-  for (int i = 0; i < 12; ++i) pg[12 * (size_t)k + i] = g[i];
-  for (int i = 0; i < 144; ++i) ph[144 * (size_t)k + i] = H[i * kBarrierTPB];
+  if (threadIdx.x == 0) {
+    int ids[4];
+    for (int v = 0; v < 4; ++v) ids[v] = pv[4 * k + v];
+    const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
+    double x12[12], e;
+    gather12(V.cpos, ids, x12);
+    barrier_pair(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, &e, g_s, L.A[0], 1);
+  }
+  __syncthreads();
+  wave_psd12(L);
+  if (threadIdx.x < 12) pg[12 * (size_t)k + threadIdx.x] = g_s[threadIdx.x];
+  for (int e = threadIdx.x; e < 144; e += 64) ph[144 * (size_t)k + e] = L.A[0][e];
 }
 
 // ------------------------------------------------------------------ affine bodies
@@ -722,29 +816,68 @@ __global__ void k_precond_soft(View V, const int* drowptr, const int* dcol, cons
   for (int i = 0; i < 9; ++i) out[i] = C[i] / det;
 }
 
-__global__ void k_precond_body(View V, const int* drowptr, const int* dcol, const double* dval,
-                               int* bad) {
-  const int b = gid();
-  if (b >= V.Nb) return;
+// Inverse of the 12x12 block of an affine body (its 4 pseudo-nodes) by one wavefront:
+// Gauss-Jordan with partial pivoting on [M | I] held in LDS.
+__global__ void __launch_bounds__(64) k_precond_body(View V, const int* drowptr, const int* dcol,
+                                                     const double* dval, int* bad) {
+  __shared__ double M[12][24];
+  __shared__ double f[12];
+  __shared__ int piv_s;
+  const int b = blockIdx.x;
   const int s = V.bscene[b];
   if (!V.act[s] || V.bsnap[b]) return;
+  const int lane = threadIdx.x;
   const int n0 = V.bnode[b];
-  double M[144];
-  for (int i = 0; i < 144; ++i) M[i] = 0.0;
-  for (int u = 0; u < 4; ++u)
+  for (int e = lane; e < 288; e += 64) M[e / 24][e % 24] = (e % 24 >= 12 && e % 24 - 12 == e / 24) ? 1.0 : 0.0;
+  __syncthreads();
+  if (lane < 4) {
+    const int u = lane;
     for (int k = drowptr[n0 + u]; k < drowptr[n0 + u + 1]; ++k) {
       const int w = dcol[k] - n0;
       if (w < 0 || w > 3) continue;
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[12 * (3 * u + i) + 3 * w + j] = dval[9 * (size_t)k + 3 * i + j];
+        for (int j = 0; j < 3; ++j) M[3 * u + i][3 * w + j] = dval[9 * (size_t)k + 3 * i + j];
     }
-  if (!spd_inverse<12>(M, V.bpinv + 144 * b)) bad[s] = 1;
+  }
+  __syncthreads();
+  for (int c = 0; c < 12; ++c) {
+    if (lane == 0) {
+      int p = c;
+      for (int r = c + 1; r < 12; ++r)
+        if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+      piv_s = p;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (!(fabs(M[p][c]) > 0.0)) {
+      if (lane == 0) bad[s] = 1;
+      return;
+    }
+    if (p != c && lane < 24) {
+      const double t = M[c][lane];
+      M[c][lane] = M[p][lane];
+      M[p][lane] = t;
+    }
+    __syncthreads();
+    const double inv = 1.0 / M[c][c];
+    __syncthreads();
+    if (lane < 24) M[c][lane] *= inv;
+    if (lane < 12) f[lane] = M[lane][c];
+    __syncthreads();
+    for (int e = lane; e < 288; e += 64) {
+      const int r = e / 24, k = e % 24;
+      if (r != c) M[r][k] -= f[r] * M[c][k];
+    }
+    __syncthreads();
+  }
+  for (int e = lane; e < 144; e += 64) V.bpinv[144 * (size_t)b + e] = M[e / 12][12 + e % 12];
 }
 
 // ------------------------------------------------------------------ PCG
 // z = M^{-1} r for the node n (local index li inside the block; rs stages r in LDS).
 __device__ __forceinline__ void precond_apply(const View& V, const double* pinv, int n, int n0blk,
                                               const double (*rs)[3], double* z) {
+  // rs: r of the nodes of this block (a body's 4 pseudo-nodes never straddle blocks)
   const int type = V.ntype[n];
   if (!V.nfree[n]) {
     z[0] = z[1] = z[2] = 0.0;
@@ -768,9 +901,24 @@ __device__ __forceinline__ void precond_apply(const View& V, const double* pinv,
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_pcg_init(View V, BlockTable T, PcgBufs B) {
-  __shared__ double rs[TPB][3];
-  __shared__ double red[4];
+// Node-parallel PCG kernels run one wavefront (64 nodes) per block of the table T; the
+// sparse product runs 16 lanes per block-row over the table TS (16 rows per block).
+constexpr int kWave = 64;
+constexpr int kRowLanes = 16;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+// Sum of a scene's block partials by one wavefront (fixed assignment and fixed tree).
+__device__ __forceinline__ double scene_sum_wave(const double* P, const int* sblk, int s) {
+  double acc = 0.0;
+  for (int k = sblk[s] + (int)threadIdx.x; k < sblk[s + 1]; k += kWave) acc += P[k];
+  return wave_sum(acc);
+}
+
+__global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable T, PcgBufs B) {
+  __shared__ double rs[kWave][3];
   const int s = T.sc[blockIdx.x];
   if (V.pdone[s]) return;
   const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
@@ -795,53 +943,66 @@ __global__ void __launch_bounds__(TPB) k_pcg_init(View V, BlockTable T, PcgBufs 
       B.p[3 * n + c] = z[c];
     }
   }
-  const double rz = block_sum256(r[0] * z[0] + r[1] * z[1] + r[2] * z[2], red);
-  const double rr = block_sum256(r[0] * r[0] + r[1] * r[1] + r[2] * r[2], red);
+  const double rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
+  const double rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (threadIdx.x == 0) {
     B.P_rz0[blockIdx.x] = rz;
     B.P_gg[blockIdx.x] = rr;
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_pcg_spmv(View V, BlockTable T, PcgBufs B) {
+__global__ void __launch_bounds__(TPB) k_pcg_spmv(View V, BlockTable TS, PcgBufs B) {
   __shared__ double red[4];
-  const int s = T.sc[blockIdx.x];
+  const int s = TS.sc[blockIdx.x];
   if (V.pdone[s]) return;
-  const int n = T.b0[blockIdx.x] + threadIdx.x;
-  double q[3] = {0, 0, 0}, pn[3] = {0, 0, 0};
-  if (n < T.b1[blockIdx.x] && V.nfree[n]) {
-    for (int k = V.rowptr[n]; k < V.rowptr[n + 1]; ++k) {
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int row = TS.b0[blockIdx.x] + (int)(threadIdx.x / kRowLanes);
+  const bool inrange = row < TS.b1[blockIdx.x];
+  const bool live = inrange && V.nfree[row];
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  if (live) {
+    for (int k = V.rowptr[row] + sub; k < V.rowptr[row + 1]; k += kRowLanes) {
       const double* A = V.val + 9 * (size_t)k;
       const double* p = B.p + 3 * V.col[k];
-      for (int i = 0; i < 3; ++i) q[i] += A[3 * i] * p[0] + A[3 * i + 1] * p[1] + A[3 * i + 2] * p[2];
+      const double p0 = p[0], p1 = p[1], p2 = p[2];
+      q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
+      q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
+      q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
     }
-    for (int k = B.drowptr[n]; k < B.drowptr[n + 1]; ++k) {
+    for (int k = B.drowptr[row] + sub; k < B.drowptr[row + 1]; k += kRowLanes) {
       const double* A = B.dval + 9 * (size_t)k;
       const double* p = B.p + 3 * B.dcol[k];
-      for (int i = 0; i < 3; ++i) q[i] += A[3 * i] * p[0] + A[3 * i + 1] * p[1] + A[3 * i + 2] * p[2];
+      const double p0 = p[0], p1 = p[1], p2 = p[2];
+      q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
+      q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
+      q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
     }
-    for (int c = 0; c < 3; ++c) pn[c] = B.p[3 * n + c];
   }
-  if (n < T.b1[blockIdx.x])
-    for (int c = 0; c < 3; ++c) B.q[3 * n + c] = q[c];
-  const double pq = block_sum256(pn[0] * q[0] + pn[1] * q[1] + pn[2] * q[2], red);
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+    q0 += __shfl_xor(q0, off, kRowLanes);
+    q1 += __shfl_xor(q1, off, kRowLanes);
+    q2 += __shfl_xor(q2, off, kRowLanes);
+  }
+  double pq = 0.0;
+  if (inrange && sub == 0) {
+    B.q[3 * row] = q0;
+    B.q[3 * row + 1] = q1;
+    B.q[3 * row + 2] = q2;
+    if (live) pq = B.p[3 * row] * q0 + B.p[3 * row + 1] * q1 + B.p[3 * row + 2] * q2;
+  }
+  pq = block_sum256(pq, red);
   if (threadIdx.x == 0) B.P_pq[blockIdx.x] = pq;
 }
 
-__global__ void __launch_bounds__(TPB) k_pcg_update1(View V, BlockTable T, PcgBufs B, int parity) {
-  __shared__ double rs[TPB][3];
-  __shared__ double red[4];
-  __shared__ double alpha_s;
+__global__ void __launch_bounds__(kWave) k_pcg_update1(View V, BlockTable T, BlockTable TS,
+                                                       PcgBufs B, int parity) {
+  __shared__ double rs[kWave][3];
   const int s = T.sc[blockIdx.x];
   if (V.pdone[s]) return;
   const double* Prz = parity ? B.P_rz1 : B.P_rz0;
   double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
-  if (threadIdx.x == 0) {
-    const double rz = scene_sum(Prz, T.sblk, s), pq = scene_sum(B.P_pq, T.sblk, s);
-    alpha_s = pq > 0.0 ? rz / pq : 0.0;
-  }
-  __syncthreads();
-  const double alpha = alpha_s;
+  const double rzs = scene_sum_wave(Prz, T.sblk, s), pqs = scene_sum_wave(B.P_pq, TS.sblk, s);
+  const double alpha = pqs > 0.0 ? rzs / pqs : 0.0;
   const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
   const int n = n0 + threadIdx.x;
   const bool live = n < n1;
@@ -860,39 +1021,32 @@ __global__ void __launch_bounds__(TPB) k_pcg_update1(View V, BlockTable T, PcgBu
     precond_apply(V, B.pinv, n, n0, rs, z);
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
-  const double rz = block_sum256(r[0] * z[0] + r[1] * z[1] + r[2] * z[2], red);
-  const double rr = block_sum256(r[0] * r[0] + r[1] * r[1] + r[2] * r[2], red);
+  const double rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
+  const double rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (threadIdx.x == 0) {
     Prz_new[blockIdx.x] = rz;
     B.P_rr[blockIdx.x] = rr;
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_pcg_update2(View V, BlockTable T, PcgBufs B, int parity) {
-  __shared__ double beta_s;
-  __shared__ int conv_s;
+__global__ void __launch_bounds__(kWave) k_pcg_update2(View V, BlockTable T, PcgBufs B, int parity) {
   const int s = T.sc[blockIdx.x];
   if (V.pdone[s]) return;
   const double* Prz_old = parity ? B.P_rz1 : B.P_rz0;
   const double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
-  const bool first = blockIdx.x == T.sblk[s];
-  if (threadIdx.x == 0) {
-    const double rzn = scene_sum(Prz_new, T.sblk, s), rzo = scene_sum(Prz_old, T.sblk, s);
-    const double rr = scene_sum(B.P_rr, T.sblk, s), gg = scene_sum(B.P_gg, T.sblk, s);
-    const double eta = V.sc[s].pcg_eta;
-    conv_s = (rr <= eta * eta * gg) || !(rzn > 0.0) || !(rzo > 0.0);
-    beta_s = conv_s ? 0.0 : rzn / rzo;
-  }
-  __syncthreads();
-  if (conv_s) {
+  const bool first = (int)blockIdx.x == T.sblk[s];
+  const double rzn = scene_sum_wave(Prz_new, T.sblk, s), rzo = scene_sum_wave(Prz_old, T.sblk, s);
+  const double rr = scene_sum_wave(B.P_rr, T.sblk, s), gg = scene_sum_wave(B.P_gg, T.sblk, s);
+  const double eta = V.sc[s].pcg_eta;
+  const bool conv = (rr <= eta * eta * gg) || !(rzn > 0.0) || !(rzo > 0.0);
+  if (conv) {
     if (first && threadIdx.x == 0) V.pdone[s] = 1;
     return;
   }
+  const double beta = rzn / rzo;
   const int n = T.b0[blockIdx.x] + threadIdx.x;
-  if (n < T.b1[blockIdx.x]) {
-    const double beta = beta_s;
+  if (n < T.b1[blockIdx.x])
     for (int c = 0; c < 3; ++c) B.p[3 * n + c] = B.z[3 * n + c] + beta * B.p[3 * n + c];
-  }
   if (first && threadIdx.x == 0) {
     const int it = ++B.iters[s];
     if (it >= B.max_iters) V.pdone[s] = 1;
@@ -900,23 +1054,37 @@ __global__ void __launch_bounds__(TPB) k_pcg_update2(View V, BlockTable T, PcgBu
 }
 
 // ------------------------------------------------------------------ convergence & CCD
+// Largest displacement component of the Newton direction per scene: free soft vertices and
+// affine-body vertices (J p).  Lanes of a wave that share a scene combine before the atomic.
 __global__ void k_pmax(View V, const double* p, unsigned long long* pmax) {
   const int k = gid();
+  double m = 0.0;
+  int s = -1;
   if (k < V.Nn) {
     const int n = k;
     if (V.ntype[n] == 0 && V.nfree[n] && V.act[V.nscene[n]]) {
-      const double m = fmax(fabs(p[3 * n]), fmax(fabs(p[3 * n + 1]), fabs(p[3 * n + 2])));
-      atomic_max_pos(pmax + V.nscene[n], m);
+      m = fmax(fabs(p[3 * n]), fmax(fabs(p[3 * n + 1]), fabs(p[3 * n + 2])));
+      s = V.nscene[n];
     }
-    return;
+  } else if (k - V.Nn < V.Ncv) {
+    const int cv = k - V.Nn;
+    const int b = V.cvb[cv];
+    if (b >= 0 && !V.bsnap[b] && V.act[V.bscene[b]]) {
+      double d[3];
+      body_point(V, p + 3 * V.bnode[b], cv, d);
+      m = fmax(fabs(d[0]), fmax(fabs(d[1]), fabs(d[2])));
+      s = V.bscene[b];
+    }
   }
-  const int cv = k - V.Nn;
-  if (cv >= V.Ncv) return;
-  const int b = V.cvb[cv];
-  if (b < 0 || V.bsnap[b] || !V.act[V.bscene[b]]) return;
-  double d[3];
-  body_point(V, p + 3 * V.bnode[b], cv, d);
-  atomic_max_pos(pmax + V.bscene[b], fmax(fabs(d[0]), fmax(fabs(d[1]), fabs(d[2]))));
+  // wave-uniform scene: reduce in registers, one atomic per wave
+  const int s0 = __shfl(s, 0, 64);
+  const bool uniform = __all(s == s0);
+  if (uniform) {
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && s0 >= 0) atomic_max_pos(pmax + s0, m);
+  } else if (s >= 0) {
+    atomic_max_pos(pmax + s, m);
+  }
 }
 
 __global__ void k_ccd(View V, int n, const int* cq, const int* ct, unsigned long long* amin) {
@@ -931,10 +1099,13 @@ __global__ void k_ccd(View V, int n, const int* cq, const int* ct, unsigned long
   atomic_min_pos(amin + V.qscene[cq[k]], t);
 }
 
-__global__ void k_scene_count(View V, int n, const int* cq, int* cnt) {
+// off[s] = first candidate of scene s (candidates are sorted by scene); off[S] = n.
+__global__ void k_scene_offsets(View V, int n, const int* cq, int* off) {
   const int k = gid();
-  if (k >= n) return;
-  atomicAdd(cnt + V.qscene[cq[k]], 1);
+  if (k > n) return;
+  const int cur = k < n ? V.qscene[cq[k]] : V.S;
+  const int prev = k > 0 ? V.qscene[cq[k - 1]] : -1;
+  for (int s = prev + 1; s <= cur; ++s) off[s] = k;
 }
 
 // ------------------------------------------------------------------ line search
@@ -942,8 +1113,7 @@ __device__ __forceinline__ double trial_alpha(const double* abase, int s, int k)
   return ldexp(abase[s], -k);
 }
 
-__global__ void __launch_bounds__(TPB) k_ls_nodes(View V, BlockTable T, LsBufs L) {
-  __shared__ double red[4];
+__global__ void __launch_bounds__(kWave) k_ls_nodes(View V, BlockTable T, LsBufs L) {
   const int s = T.sc[blockIdx.x];
   if (!V.act[s]) return;
   const int n = T.b0[blockIdx.x] + threadIdx.x;
@@ -958,7 +1128,7 @@ __global__ void __launch_bounds__(TPB) k_ls_nodes(View V, BlockTable T, LsBufs L
   }
   for (int k = 0; k < kTrials; ++k) {
     const double a = trial_alpha(L.abase, s, k);
-    const double dE = block_sum256(0.5 * m * (2.0 * a * pe + a * a * pp), red);
+    const double dE = wave_sum(0.5 * m * (2.0 * a * pe + a * a * pp));
     if (threadIdx.x == 0) L.part_nodes[kTrials * blockIdx.x + k] = dE;
   }
 }
@@ -1076,20 +1246,21 @@ __global__ void k_ls_pairs(View V, int n, const int* cq, const int* ct, LsBufs L
   if (bad) atomicOr(L.infeasible + s, bad);
 }
 
-__global__ void k_ls_reduce(View V, BlockTable TN, BlockTable TT, LsBufs L) {
+__global__ void __launch_bounds__(TPB) k_ls_reduce(View V, BlockTable TN, BlockTable TT, LsBufs L) {
+  __shared__ double red[4];
   const int s = blockIdx.x;
   if (!V.act[s]) return;
-  const int k = threadIdx.x;
-  if (k >= kTrials) return;
-  double acc = 0.0;
-  for (int b = TN.sblk[s]; b < TN.sblk[s + 1]; ++b) acc += L.part_nodes[kTrials * b + k];
-  double acc_t = 0.0;
-  for (int b = TT.sblk[s]; b < TT.sblk[s + 1]; ++b) acc_t += L.part_tets[kTrials * b + k];
-  double acc_b = 0.0;
-  for (int b = V.sc[s].body0; b < V.sc[s].body1; ++b) acc_b += L.e_bodies[kTrials * b + k];
-  double acc_p = 0.0;
-  for (int c = L.cand_off[s]; c < L.cand_off[s + 1]; ++c) acc_p += L.e_pairs[kTrials * (size_t)c + k];
-  L.dE[kTrials * s + k] = ((acc + acc_t) + acc_b) + acc_p;
+  const int t = threadIdx.x;
+  for (int k = 0; k < kTrials; ++k) {
+    double acc = 0.0;
+    for (int b = TN.sblk[s] + t; b < TN.sblk[s + 1]; b += TPB) acc += L.part_nodes[kTrials * b + k];
+    for (int b = TT.sblk[s] + t; b < TT.sblk[s + 1]; b += TPB) acc += L.part_tets[kTrials * b + k];
+    for (int b = V.sc[s].body0 + t; b < V.sc[s].body1; b += TPB) acc += L.e_bodies[kTrials * b + k];
+    for (int c = L.cand_off[s] + t; c < L.cand_off[s + 1]; c += TPB)
+      acc += L.e_pairs[kTrials * (size_t)c + k];
+    acc = block_sum256(acc, red);
+    if (t == 0) L.dE[kTrials * s + k] = acc;
+  }
 }
 
 __global__ void k_update(View V, const double* p, const double* alpha) {
@@ -1181,28 +1352,27 @@ __global__ void k_debug_fem(int n, const double* x, const double* Dminv, const d
   }
 }
 
-__global__ void __launch_bounds__(kBarrierTPB) k_debug_barrier(int n, const int* kinds,
-                                                               const double* x, const double* meps,
-                                                               double dhat, double kappa, double* e,
-                                                               double* g, double* H, double* Hp,
-                                                               int* types) {
-  __shared__ double Hs[144 * kBarrierTPB];
-  __shared__ double Ws[144 * kBarrierTPB];
-  const int k = gid();
+__global__ void __launch_bounds__(64) k_debug_barrier(int n, const int* kinds, const double* x,
+                                                      const double* meps, double dhat, double kappa,
+                                                      double* e, double* g, double* H, double* Hp,
+                                                      int* types) {
+  __shared__ WaveJacobiLds L;
+  const int k = blockIdx.x;
   if (k >= n) return;
-  double* Hl = Hs + threadIdx.x;
-  double* Wl = Ws + threadIdx.x;
-  double ee, gg[12];
-  const int type = barrier_pair(kinds[k], x + 12 * k, meps[k], dhat, kappa, &ee, gg, Hl, kBarrierTPB);
-  if (e) e[k] = ee;
-  if (types) types[k] = type;
-  if (g)
-    for (int i = 0; i < 12; ++i) g[12 * k + i] = gg[i];
+  if (threadIdx.x == 0) {
+    double ee, gg[12];
+    const int type = barrier_pair(kinds[k], x + 12 * k, meps[k], dhat, kappa, &ee, gg, L.A[0], 1);
+    if (e) e[k] = ee;
+    if (types) types[k] = type;
+    if (g)
+      for (int i = 0; i < 12; ++i) g[12 * k + i] = gg[i];
+  }
+  __syncthreads();
   if (H)
-    for (int i = 0; i < 144; ++i) H[144 * (size_t)k + i] = Hl[i * kBarrierTPB];
-  psd_project_strided<12>(Hl, Wl, kBarrierTPB);
+    for (int i = threadIdx.x; i < 144; i += 64) H[144 * (size_t)k + i] = L.A[0][i];
+  wave_psd12(L);
   if (Hp)
-    for (int i = 0; i < 144; ++i) Hp[144 * (size_t)k + i] = Hl[i * kBarrierTPB];
+    for (int i = threadIdx.x; i < 144; i += 64) Hp[144 * (size_t)k + i] = L.A[0][i];
 }
 
 __global__ void k_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,
@@ -1287,7 +1457,7 @@ void launch_compact_pairs(const View& V, int n, const int* cq, const int* ct, co
 void launch_fem_hess(const View& V, hipStream_t s) { LAUNCH(k_fem_hess, 4 * V.Nt, TPB, s, V); }
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
                          const double* pmeps, double* pg, double* ph, hipStream_t s) {
-  LAUNCH(k_barrier_hess, np, kBarrierTPB, s, V, np, pkind, pv, pmeps, pg, ph);
+  if (np > 0) hipLaunchKernelGGL(k_barrier_hess, dim3(np), dim3(64), 0, s, V, np, pkind, pv, pmeps, pg, ph);
 }
 void launch_body_hess(const View& V, hipStream_t s) { LAUNCH(k_body_hess, V.Nb, 64, s, V); }
 void launch_assemble_bsr(const View& V, int nnz, const int* brow, hipStream_t s) {
@@ -1327,19 +1497,19 @@ void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int
 void launch_precond(const View& V, const int* drowptr, const int* dcol, const double* dval,
                     double* pinv, int* bad, hipStream_t s) {
   LAUNCH(k_precond_soft, V.Nn, TPB, s, V, drowptr, dcol, dval, pinv, bad);
-  LAUNCH(k_precond_body, V.Nb, 64, s, V, drowptr, dcol, dval, bad);
+  if (V.Nb > 0) hipLaunchKernelGGL(k_precond_body, dim3(V.Nb), dim3(64), 0, s, V, drowptr, dcol, dval, bad);
 }
 void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
-  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_init, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
+  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_init, dim3(T.nblk), dim3(kWave), 0, s, V, T, B);
 }
-void launch_pcg_spmv(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
-  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_spmv, dim3(T.nblk), dim3(TPB), 0, s, V, T, B);
+void launch_pcg_spmv(const View& V, const BlockTable& TS, const PcgBufs& B, hipStream_t s) {
+  if (TS.nblk > 0) hipLaunchKernelGGL(k_pcg_spmv, dim3(TS.nblk), dim3(TPB), 0, s, V, TS, B);
 }
-void launch_pcg_update(const View& V, const BlockTable& T, const PcgBufs& B, int parity,
-                       hipStream_t s) {
+void launch_pcg_update(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+                       int parity, hipStream_t s) {
   if (T.nblk <= 0) return;
-  hipLaunchKernelGGL(k_pcg_update1, dim3(T.nblk), dim3(TPB), 0, s, V, T, B, parity);
-  hipLaunchKernelGGL(k_pcg_update2, dim3(T.nblk), dim3(TPB), 0, s, V, T, B, parity);
+  hipLaunchKernelGGL(k_pcg_update1, dim3(T.nblk), dim3(kWave), 0, s, V, T, TS, B, parity);
+  hipLaunchKernelGGL(k_pcg_update2, dim3(T.nblk), dim3(kWave), 0, s, V, T, B, parity);
 }
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s) {
   LAUNCH(k_pmax, V.Nn + V.Ncv, TPB, s, V, p, pmax);
@@ -1348,16 +1518,16 @@ void launch_ccd(const View& V, int n, const int* cq, const int* ct, unsigned lon
                 hipStream_t s) {
   LAUNCH(k_ccd, n, 64, s, V, n, cq, ct, amin);
 }
-void launch_scene_count(const View& V, int n, const int* cq, int* cnt, hipStream_t s) {
-  LAUNCH(k_scene_count, n, TPB, s, V, n, cq, cnt);
+void launch_scene_offsets(const View& V, int n, const int* cq, int* off, hipStream_t s) {
+  LAUNCH(k_scene_offsets, n + 1, TPB, s, V, n, cq, off);
 }
 void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, int ncand,
                         const int* cq, const int* ct, const LsBufs& L, hipStream_t s) {
-  if (TN.nblk > 0) hipLaunchKernelGGL(k_ls_nodes, dim3(TN.nblk), dim3(TPB), 0, s, V, TN, L);
+  if (TN.nblk > 0) hipLaunchKernelGGL(k_ls_nodes, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, L);
   if (TT.nblk > 0) hipLaunchKernelGGL(k_ls_tets, dim3(TT.nblk), dim3(TPB), 0, s, V, TT, L);
   LAUNCH(k_ls_bodies, V.Nb, 64, s, V, L);
   LAUNCH(k_ls_pairs, ncand, 64, s, V, ncand, cq, ct, L);
-  hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(64), 0, s, V, TN, TT, L);
+  hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(TPB), 0, s, V, TN, TT, L);
 }
 void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s) {
   LAUNCH(k_update, V.Nn, TPB, s, V, p, alpha);
@@ -1381,7 +1551,7 @@ void launch_debug_fem(int n, const double* x, const double* Dminv, const double*
 void launch_debug_barrier(int n, const int* kinds, const double* x, const double* meps,
                           double dhat, double kappa, double* e, double* g, double* H, double* Hp,
                           int* types, hipStream_t s) {
-  LAUNCH(k_debug_barrier, n, kBarrierTPB, s, n, kinds, x, meps, dhat, kappa, e, g, H, Hp, types);
+  if (n > 0) hipLaunchKernelGGL(k_debug_barrier, dim3(n), dim3(64), 0, s, n, kinds, x, meps, dhat, kappa, e, g, H, Hp, types);
 }
 void launch_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,
                       int max_iter, double* t, hipStream_t s) {

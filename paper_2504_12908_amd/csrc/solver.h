@@ -11,7 +11,8 @@
 namespace tc {
 
 constexpr int kTrials = 8;        // line-search step sizes evaluated per launch
-constexpr int kNodeChunk = 256;   // nodes per workgroup in node-parallel kernels (multiple of 4)
+constexpr int kNodeChunk = 64;    // nodes per workgroup in node-parallel kernels (multiple of 4)
+constexpr int kRowChunk = 16;     // block-rows per workgroup of the sparse product
 constexpr int kTetChunk = 256;
 
 // Per-scene constants, resident on the device.
