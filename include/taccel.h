@@ -83,8 +83,10 @@ typedef struct {
   taccel_params params;
 } taccel_scene_desc;
 
-/* Device memory and stream.  alloc/free may be NULL (then hipMalloc/hipFree); stream NULL
- * = the null stream.  The library enqueues all device work on `stream`. */
+/* Device memory and stream.  alloc/free may be NULL (then hipMalloc/hipFree).  stream NULL:
+ * the library creates a non-blocking stream of default priority for the object.  All device
+ * work of a scene/batch is enqueued on that one stream (the PCG loop is replayed from a HIP
+ * graph captured on it, so it must not be the legacy null stream). */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);

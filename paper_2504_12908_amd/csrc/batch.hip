@@ -43,6 +43,7 @@ struct ApiError : std::runtime_error {
 struct Mem {
   taccel_runtime rt{};
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   void* alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
     void* p = nullptr;
@@ -171,6 +172,7 @@ struct Batch::Impl {
   std::vector<SceneConst> hsc;
   std::vector<int> h_ntype, h_nscene, h_bnode, h_bscene, h_bpres, h_moving_nodes;
   std::vector<double> spmv_static_bytes;  // per scene: algorithmic bytes of the FEM part of SpMV
+  std::vector<double> spmv_free_nodes;
   std::vector<hipEvent_t> ev_pool;
   // static device data
   DBuf<SceneConst> d_sc;
@@ -197,7 +199,7 @@ struct Batch::Impl {
   BroadPhase bp;
   DBuf<double> bp_tbox;
   DBuf<int> bp_tcell, bp_tncell, bp_toff, bp_bcount, bp_bstart, bp_bfill, bp_qcount, bp_qoff;
-  DBuf<int4> bp_entries;
+  DBuf<BpEntry> bp_entries;
   DBuf<int> cq, ct, sq, st, cflag, cpos_idx;
   DBuf<int> pkind, pv, pscene;
   DBuf<double> pmeps, pg, ph;
@@ -206,7 +208,7 @@ struct Batch::Impl {
   DBuf<double> hcoef, gcoef;
   DBuf<int> sflag, segid, segstart, drow, dcol, rowcnt, drowptr;
   DBuf<double> dval;
-  DBuf<double> g, r, z, p, q, dx, pinv;
+  DBuf<double> g, r, z, p, p1, q, dx, pinv;
   DBuf<double> P_pq, P_rz0, P_rz1, P_rr, P_gg;
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
@@ -266,6 +268,13 @@ struct Batch::Impl {
     HIPCHECK(radix_sort_pairs(keys, vals, tk, tv_, n, bits, scratch.p, mem.stream));
   }
 
+  // PCG chunks replayed as a HIP graph (16 iterations = 32 kernels); re-captured when a
+  // buffer it reads is reallocated or profiling is switched
+  hipGraph_t pcg_graph = nullptr;
+  hipGraphExec_t pcg_exec = nullptr;
+  std::vector<const void*> pcg_key;
+  static constexpr int kPcgChunk = 16;
+  void run_pcg(const View& V, const PcgBufs& B, int nseg);
   void build(const taccel_scene_desc* d, int n);
   int broad_phase(const double* P0, const double* P1, int all, DBuf<int>& oq, DBuf<int>& ot);
   void newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail, std::vector<int>& nan_,
@@ -636,8 +645,10 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   // blocks (72 B values + 4 B column), row pointer (4 B), free flag (4 B), the 24 B of x
   // read and the 24 B of y written; plus 24 B of x per free node gathered once.
   spmv_static_bytes.assign(S, 0.0);
+  spmv_free_nodes.assign(S, 0.0);
   for (int n = 0; n < Nn; ++n) {
     if (!h_nfree[n]) continue;
+    spmv_free_nodes[h_nscene[n]] += 1.0;
     const int nb_row = h_rowptr[n + 1] - h_rowptr[n];
     spmv_static_bytes[h_nscene[n]] += 76.0 * nb_row + 4.0 + 4.0 + 24.0 + 24.0;
   }
@@ -725,7 +736,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   TS.nblk = (int)ts_sc_h.size();
   TS.sc = ts_sc.p; TS.b0 = ts_b0.p; TS.b1 = ts_b1.p; TS.sblk = ts_sblk.p;
   // PCG / line-search / misc
-  for (DBuf<double>* b : {&g, &r, &z, &p, &q, &dx}) b->ensure(m, 3 * (size_t)Nn);
+  for (DBuf<double>* b : {&g, &r, &z, &p, &p1, &q, &dx}) b->ensure(m, 3 * (size_t)Nn);
   pinv.ensure(m, 9 * (size_t)Nn);
   for (DBuf<double>* b : {&P_rz0, &P_rz1, &P_rr, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
   P_pq.ensure(m, std::max(TS.nblk, 1));
@@ -801,6 +812,72 @@ int Batch::Impl::broad_phase(const double* P0, const double* P1, int all, DBuf<i
     throw ApiError(TACCEL_NAN, "broad phase: a primitive box spans more than 64 cells per axis "
                                "(positions exploded or non-finite)");
   return ncand;
+}
+
+void Batch::Impl::run_pcg(const View& V, const PcgBufs& B, int nseg) {
+  hipStream_t s = stream();
+  Profiler& prof = profiler();
+  double launch_bytes = 0.0;
+  if (prof.on) {
+    std::vector<int> ha(S);
+    d2h(ha.data(), act.p, S);
+    sync();
+    for (int k = 0; k < S; ++k)
+      if (ha[k]) launch_bytes += spmv_static_bytes[k];
+    // dynamic (contact and body) blocks: 72 B values + 4 B column each, 4 B row pointer per
+    // node; the direction update adds z and p_{k-1} read and p_k written (72 B per free node)
+    launch_bytes += 76.0 * nseg + 4.0 * Nn;
+    for (int k = 0; k < S; ++k)
+      if (ha[k]) launch_bytes += 72.0 * spmv_free_nodes[k];
+  }
+  if (prof.on)
+    while (ev_pool.size() < 2 * (size_t)kPcgChunk) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+  const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, V.bpinv,
+                                        reinterpret_cast<const void*>((intptr_t)prof.on)};
+  if (!pcg_exec || key != pcg_key) {
+    if (pcg_exec) HIPCHECK(hipGraphExecDestroy(pcg_exec));
+    if (pcg_graph) HIPCHECK(hipGraphDestroy(pcg_graph));
+    pcg_exec = nullptr;
+    pcg_graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kPcgChunk; ++k) {
+      if (prof.on) HIPCHECK(hipEventRecord(ev_pool[2 * k], s));
+      launch_pcg_spmv(V, TN, TS, B, k & 1, s);
+      if (prof.on) HIPCHECK(hipEventRecord(ev_pool[2 * k + 1], s));
+      launch_pcg_update(V, TN, TS, B, k & 1, s);
+    }
+    HIPCHECK(hipStreamEndCapture(s, &pcg_graph));
+    HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
+    pcg_key = key;
+  }
+  std::vector<int> hd(S), it0(S, 0), it1(S);
+  for (int it = 0; it < B.max_iters; it += kPcgChunk) {
+    HIPCHECK(hipGraphLaunch(pcg_exec, s));
+    d2h(hd.data(), pdone.p, S);
+    if (prof.on) d2h(it1.data(), iters.p, S);
+    sync();
+    if (prof.on) {
+      // event pairs of iterations that did work (every scene's iterations run in order)
+      int real = 0;
+      for (int k = 0; k < S; ++k) real = std::max(real, it1[k] - it0[k] + (hd[k] && it1[k] > it0[k] ? 0 : 0));
+      real = std::min(real, kPcgChunk);
+      for (int e = 0; e < real; ++e) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, ev_pool[2 * e], ev_pool[2 * e + 1]));
+        prof.spmv_ms += ms;
+        prof.spmv_launches += 1;
+        prof.spmv_bytes += launch_bytes;
+      }
+      it0 = it1;
+    }
+    bool all = true;
+    for (int k = 0; k < S; ++k) all = all && hd[k];
+    if (all) break;
+  }
 }
 
 void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail,
@@ -883,7 +960,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   zero(bad.p, sizeof(int) * S);
   launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, s);
   PcgBufs B;
-  B.g = g.p; B.r = r.p; B.z = z.p; B.p = p.p; B.q = q.p; B.dx = dx.p; B.pinv = pinv.p;
+  B.g = g.p; B.r = r.p; B.z = z.p; B.p0 = p.p; B.p1 = p1.p; B.q = q.p; B.dx = dx.p; B.pinv = pinv.p;
   B.drowptr = drowptr.p; B.dcol = dcol.p; B.dval = dval.p;
   B.P_pq = P_pq.p; B.P_rz0 = P_rz0.p; B.P_rz1 = P_rz1.p; B.P_rr = P_rr.p; B.P_gg = P_gg.p;
   B.iters = iters.p;
@@ -900,55 +977,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   }
   zero(iters.p, sizeof(int) * S);
   launch_pcg_init(V, TN, B, s);
-  int parity = 0;
-  std::vector<int> hd(S);
-  Profiler& prof = profiler();
-  double launch_bytes = 0.0;
-  if (prof.on) {
-    std::vector<int> ha(S);
-    d2h(ha.data(), act.p, S);
-    sync();
-    for (int k = 0; k < S; ++k)
-      if (ha[k]) launch_bytes += spmv_static_bytes[k];
-    // dynamic (contact and body) blocks: 72 B values + 4 B column each, 4 B row pointer per node
-    launch_bytes += 76.0 * nseg + 4.0 * Nn;
-  }
-  size_t ev_used = 0;
-  for (int it = 0; it < max_pcg;) {
-    const int chunk = 16;
-    for (int k = 0; k < chunk; ++k, ++it) {
-      if (prof.on) {
-        while (ev_pool.size() < ev_used + 2) {
-          hipEvent_t e;
-          HIPCHECK(hipEventCreate(&e));
-          ev_pool.push_back(e);
-        }
-        HIPCHECK(hipEventRecord(ev_pool[ev_used], s));
-        launch_pcg_spmv(V, TS, B, s);
-        HIPCHECK(hipEventRecord(ev_pool[ev_used + 1], s));
-        ev_used += 2;
-      } else {
-        launch_pcg_spmv(V, TS, B, s);
-      }
-      launch_pcg_update(V, TN, TS, B, parity, s);
-      parity ^= 1;
-    }
-    d2h(hd.data(), pdone.p, S);
-    sync();
-    if (prof.on) {
-      for (size_t e = 0; e < ev_used; e += 2) {
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, ev_pool[e], ev_pool[e + 1]));
-        prof.spmv_ms += ms;
-        prof.spmv_launches += 1;
-        prof.spmv_bytes += launch_bytes;
-      }
-      ev_used = 0;
-    }
-    bool all = true;
-    for (int k = 0; k < S; ++k) all = all && hd[k];
-    if (all) break;
-  }
+  run_pcg(V, B, nseg);
   d2h(pcg_it.data(), iters.p, S);
   std::vector<int> hbad(S);
   d2h(hbad.data(), bad.p, S);
@@ -1282,6 +1311,16 @@ taccel_status Batch::create(const taccel_scene_desc* d, int n, const taccel_runt
     b->impl_->mem.rt = *rt;
     b->impl_->mem.stream = (hipStream_t)rt->stream;
   }
+  if (!b->impl_->mem.stream) {
+    // a stream of our own (default priority): the PCG chunks are captured into a graph,
+    // which the null stream does not allow
+    if (hipStreamCreateWithFlags(&b->impl_->mem.stream, hipStreamNonBlocking) != hipSuccess) {
+      err = "hipStreamCreateWithFlags failed";
+      delete b;
+      return TACCEL_ERR_HIP;
+    }
+    b->impl_->mem.own_stream = true;
+  }
   try {
     b->impl_->build(d, n);
   } catch (const ApiError& e) {
@@ -1300,11 +1339,13 @@ Batch::~Batch() {
   (void)hipStreamSynchronize(I.mem.stream);
   I.release_all();
   for (hipEvent_t e : I.ev_pool) (void)hipEventDestroy(e);
+  if (I.pcg_exec) (void)hipGraphExecDestroy(I.pcg_exec);
+  if (I.pcg_graph) (void)hipGraphDestroy(I.pcg_graph);
 #define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
   FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.Hloc, &I.gloc, &I.val, &I.bmass,
            &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,
            &I.cend, &I.elen2, &I.bp_tbox, &I.pmeps, &I.pg, &I.ph, &I.hcoef, &I.gcoef, &I.dval, &I.g, &I.r,
-           &I.z, &I.p, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
+           &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
            &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs)
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
@@ -1326,6 +1367,7 @@ Batch::~Batch() {
   I.scratch.free();
   I.d_sc.free();
 #undef FREE_ALL
+  if (I.mem.own_stream) (void)hipStreamDestroy(I.mem.stream);
   delete impl_;
 }
 

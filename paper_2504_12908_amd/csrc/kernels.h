@@ -13,6 +13,12 @@ struct BlockTable {
   const int* sblk = nullptr;  // [S+1] first block of each scene (device)
 };
 
+// Hash-table entry: a target primitive inserted for one cell, with its box.
+struct BpEntry {
+  int t, cx, cy, cz;
+  double lo[3], hi[3];
+};
+
 // Broad-phase working set.
 struct BroadPhase {
   int ntarget = 0;          // tris then edges
@@ -24,7 +30,7 @@ struct BroadPhase {
   int* bcount = nullptr;    // [table]
   int* bstart = nullptr;    // [table]
   int* bfill = nullptr;     // [table]
-  int4* entries = nullptr;  // (target, cx, cy, cz)
+  BpEntry* entries = nullptr;
   int* qcount = nullptr;    // [Nq]
   int* qoff = nullptr;      // [Nq]
   int* overflow = nullptr;  // set when a box spans too many cells (exploded positions)
@@ -81,7 +87,7 @@ void launch_precond(const View& V, const int* drowptr, const int* dcol, const do
 
 // PCG over node-block table T; partial sums per block
 struct PcgBufs {
-  double *g, *r, *z, *p, *q, *dx;
+  double *g, *r, *z, *p0, *p1, *q, *dx;
   double* pinv;
   const int* drowptr;
   const int* dcol;
@@ -91,7 +97,8 @@ struct PcgBufs {
   int max_iters;
 };
 void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
-void launch_pcg_spmv(const View& V, const BlockTable& TS, const PcgBufs& B, hipStream_t s);
+void launch_pcg_spmv(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+                     int parity, hipStream_t s);
 void launch_pcg_update(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
                        int parity, hipStream_t s);
 

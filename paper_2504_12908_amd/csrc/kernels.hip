@@ -125,8 +125,10 @@ __device__ __forceinline__ int cell_of(double v, double org, double inv) {
   const double c = fmax(-1048576.0, fmin(1048576.0, floor((v - org) * inv)));
   return (int)c;
 }
-__device__ __forceinline__ int bucket_of(int s, int cx, int cy, int cz, int mask) {
-  uint64_t h = (uint64_t)(uint32_t)s * 0x9E3779B97F4A7C15ull;
+// Bucket of (scene, cell, primitive type): triangles and edges of one cell land in different
+// buckets so a point query never scans edges and an edge query never scans triangles.
+__device__ __forceinline__ int bucket_of(int s, int cx, int cy, int cz, int type, int mask) {
+  uint64_t h = (uint64_t)(uint32_t)(2 * s + type) * 0x9E3779B97F4A7C15ull;
   h ^= (uint64_t)(uint32_t)cx * 0xC2B2AE3D27D4EB4Full;
   h ^= (uint64_t)(uint32_t)cy * 0x165667B19E3779F9ull;
   h ^= (uint64_t)(uint32_t)cz * 0xD6E8FEB86659FD93ull;
@@ -214,10 +216,11 @@ __global__ void k_bp_count(View V, BroadPhase bp) {
   target_ids(V, t, ids);
   const int s = V.cvscene[ids[0]];
   const int* cl = bp.tcell + 6 * t;
+  const int type = t < V.Ntr ? 0 : 1;
   for (int z = cl[2]; z <= cl[5]; ++z)
     for (int y = cl[1]; y <= cl[4]; ++y)
       for (int x = cl[0]; x <= cl[3]; ++x)
-        atomicAdd(bp.bcount + bucket_of(s, x, y, z, bp.table_mask), 1);
+        atomicAdd(bp.bcount + bucket_of(s, x, y, z, type, bp.table_mask), 1);
 }
 
 __global__ void k_bp_fill(View V, BroadPhase bp) {
@@ -227,18 +230,29 @@ __global__ void k_bp_fill(View V, BroadPhase bp) {
   target_ids(V, t, ids);
   const int s = V.cvscene[ids[0]];
   const int* cl = bp.tcell + 6 * t;
+  const int type = t < V.Ntr ? 0 : 1;
+  BpEntry E;
+  E.t = t;
+  for (int c = 0; c < 3; ++c) {
+    E.lo[c] = bp.tbox[6 * t + c];
+    E.hi[c] = bp.tbox[6 * t + 3 + c];
+  }
   for (int z = cl[2]; z <= cl[5]; ++z)
     for (int y = cl[1]; y <= cl[4]; ++y)
       for (int x = cl[0]; x <= cl[3]; ++x) {
-        const int b = bucket_of(s, x, y, z, bp.table_mask);
+        const int b = bucket_of(s, x, y, z, type, bp.table_mask);
         const int pos = bp.bstart[b] + atomicAdd(bp.bfill + b, 1);
-        bp.entries[pos] = make_int4(t, x, y, z);
+        E.cx = x;
+        E.cy = y;
+        E.cz = z;
+        bp.entries[pos] = E;
       }
 }
 
-__device__ __forceinline__ bool boxes_close(const double* a, const double* b, double dhat) {
+__device__ __forceinline__ bool boxes_close_lohi(const double* a, const double* lo,
+                                                 const double* hi, double dhat) {
   for (int c = 0; c < 3; ++c)
-    if (!(a[c] - dhat <= b[3 + c] && b[c] - dhat <= a[3 + c])) return false;
+    if (!(a[c] - dhat <= hi[c] && lo[c] - dhat <= a[3 + c])) return false;
   return true;
 }
 
@@ -270,20 +284,28 @@ __global__ void k_bp_query(View V, const double* P0, const double* P1, BroadPhas
   const int off = emit ? bp.qoff[q] : 0;
   int cnt = 0;
   const int qb0 = V.cvb[qids[0]];
+  const double inv = 1.0 / sc.cell;
   for (int z = ql[2]; z <= ql[5]; ++z)
     for (int y = ql[1]; y <= ql[4]; ++y)
       for (int x = ql[0]; x <= ql[3]; ++x) {
-        const int b = bucket_of(s, x, y, z, bp.table_mask);
+        const int b = bucket_of(s, x, y, z, kind, bp.table_mask);
         const int e0 = bp.bstart[b], e1 = e0 + bp.bcount[b];
         for (int e = e0; e < e1; ++e) {
-          const int4 ent = bp.entries[e];
-          if (ent.y != x || ent.z != y || ent.w != z) continue;
-          const int t = ent.x;
+          const BpEntry& E = bp.entries[e];
+          // cheap rejections first: hash collision, owner cell, box predicate
+          if (E.cx != x || E.cy != y || E.cz != z) continue;
+          const int t = E.t;
+          if (kind == 1 && t - V.Ntr <= i) continue;
+          if (max(ql[0], cell_of(E.lo[0] - sc.dhat, sc.org[0], inv)) != x ||
+              max(ql[1], cell_of(E.lo[1] - sc.dhat, sc.org[1], inv)) != y ||
+              max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) != z)
+            continue;
+          if (!boxes_close_lohi(qb, E.lo, E.hi, sc.dhat)) continue;
+          // admissibility (topology)
           int tid[3];
-          int tn, tgt;
+          int tgt;
           if (kind == 0) {
-            if (t >= V.Ntr) continue;
-            tn = target_ids(V, t, tid);
+            target_ids(V, t, tid);
             tgt = t;
             const int v = qids[0];
             if (V.cvscene[tid[0]] != s) continue;
@@ -291,19 +313,13 @@ __global__ void k_bp_query(View V, const double* P0, const double* P1, BroadPhas
             if (qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) continue;
             if (V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]) continue;
           } else {
-            if (t < V.Ntr) continue;
             tgt = t - V.Ntr;
-            if (tgt <= i) continue;
-            tn = target_ids(V, t, tid);
+            target_ids(V, t, tid);
             if (V.cvscene[tid[0]] != s) continue;
             if (qids[0] == tid[0] || qids[0] == tid[1] || qids[1] == tid[0] || qids[1] == tid[1]) continue;
             if (qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) continue;
             if (V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]) continue;
           }
-          (void)tn;
-          const int* tl = bp.tcell + 6 * t;
-          if (max(ql[0], tl[0]) != x || max(ql[1], tl[1]) != y || max(ql[2], tl[2]) != z) continue;
-          if (!boxes_close(qb, bp.tbox + 6 * t, sc.dhat)) continue;
           if (emit) {
             cand_q[off + cnt] = q;
             cand_t[off + cnt] = tgt;
@@ -917,6 +933,12 @@ __device__ __forceinline__ double scene_sum_wave(const double* P, const int* sbl
   return wave_sum(acc);
 }
 
+// Preconditioned CG with two kernels per iteration k (parity = k & 1):
+//   k_pcg_dir_spmv: convergence test on |r_k|; beta_k = rz_k / rz_{k-1};
+//                   p_k = z_k + beta_k p_{k-1} (written to the other p buffer) and
+//                   q_k = A p_k with p_k formed on the fly from z and p_{k-1};
+//   k_pcg_update:   alpha_k = rz_k / (p_k . q_k); x += alpha p; r -= alpha q; z = M^{-1} r.
+// p_{-1} = 0 and rz_{-1} = 1 make iteration 0 start with p_0 = z_0.
 __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable T, PcgBufs B) {
   __shared__ double rs[kWave][3];
   const int s = T.sc[blockIdx.x];
@@ -931,6 +953,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable T, PcgBuf
       r[c] = f ? -B.g[3 * n + c] : 0.0;
       B.r[3 * n + c] = r[c];
       B.dx[3 * n + c] = 0.0;
+      B.p0[3 * n + c] = 0.0;
     }
   }
   for (int c = 0; c < 3; ++c) rs[threadIdx.x][c] = r[c];
@@ -938,23 +961,46 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable T, PcgBuf
   double z[3] = {0, 0, 0};
   if (live) {
     precond_apply(V, B.pinv, n, n0, rs, z);
-    for (int c = 0; c < 3; ++c) {
-      B.z[3 * n + c] = z[c];
-      B.p[3 * n + c] = z[c];
-    }
+    for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
   const double rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
   const double rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (threadIdx.x == 0) {
     B.P_rz0[blockIdx.x] = rz;
+    B.P_rz1[blockIdx.x] = 1.0;
     B.P_gg[blockIdx.x] = rr;
+    B.P_rr[blockIdx.x] = rr;
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_pcg_spmv(View V, BlockTable TS, PcgBufs B) {
+__global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable T, BlockTable TS, PcgBufs B,
+                                                      int parity) {
   __shared__ double red[4];
+  __shared__ double beta_s;
+  __shared__ int conv_s;
   const int s = TS.sc[blockIdx.x];
   if (V.pdone[s]) return;
+  const double* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
+  const double* Prz_old = parity ? B.P_rz0 : B.P_rz1;
+  const double* pold = parity ? B.p1 : B.p0;
+  double* pnew = parity ? B.p0 : B.p1;
+  if (threadIdx.x < kWave) {
+    const double rzc = scene_sum_wave(Prz_cur, T.sblk, s), rzo = scene_sum_wave(Prz_old, T.sblk, s);
+    const double rr = scene_sum_wave(B.P_rr, T.sblk, s), gg = scene_sum_wave(B.P_gg, T.sblk, s);
+    if (threadIdx.x == 0) {
+      const double eta = V.sc[s].pcg_eta;
+      // iters[s] is only written by k_pcg_update, so every block sees the same count here
+      conv_s = (rr <= eta * eta * gg) || !(rzc > 0.0) || !(rzo > 0.0) || B.iters[s] >= B.max_iters;
+      beta_s = conv_s ? 0.0 : rzc / rzo;
+    }
+  }
+  __syncthreads();
+  const bool first = (int)blockIdx.x == TS.sblk[s];
+  if (conv_s) {
+    if (first && threadIdx.x == 0) V.pdone[s] = 1;
+    return;
+  }
+  const double beta = beta_s;
   const int sub = threadIdx.x & (kRowLanes - 1);
   const int row = TS.b0[blockIdx.x] + (int)(threadIdx.x / kRowLanes);
   const bool inrange = row < TS.b1[blockIdx.x];
@@ -963,16 +1009,20 @@ __global__ void __launch_bounds__(TPB) k_pcg_spmv(View V, BlockTable TS, PcgBufs
   if (live) {
     for (int k = V.rowptr[row] + sub; k < V.rowptr[row + 1]; k += kRowLanes) {
       const double* A = V.val + 9 * (size_t)k;
-      const double* p = B.p + 3 * V.col[k];
-      const double p0 = p[0], p1 = p[1], p2 = p[2];
+      const int c = V.col[k];
+      const double p0 = B.z[3 * c] + beta * pold[3 * c];
+      const double p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
+      const double p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
       q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
       q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
       q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
     }
     for (int k = B.drowptr[row] + sub; k < B.drowptr[row + 1]; k += kRowLanes) {
       const double* A = B.dval + 9 * (size_t)k;
-      const double* p = B.p + 3 * B.dcol[k];
-      const double p0 = p[0], p1 = p[1], p2 = p[2];
+      const int c = B.dcol[k];
+      const double p0 = B.z[3 * c] + beta * pold[3 * c];
+      const double p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
+      const double p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
       q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
       q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
       q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
@@ -985,23 +1035,29 @@ __global__ void __launch_bounds__(TPB) k_pcg_spmv(View V, BlockTable TS, PcgBufs
   }
   double pq = 0.0;
   if (inrange && sub == 0) {
+    double pn[3];
+    for (int c = 0; c < 3; ++c) {
+      pn[c] = B.z[3 * row + c] + beta * pold[3 * row + c];
+      pnew[3 * row + c] = pn[c];
+    }
     B.q[3 * row] = q0;
     B.q[3 * row + 1] = q1;
     B.q[3 * row + 2] = q2;
-    if (live) pq = B.p[3 * row] * q0 + B.p[3 * row + 1] * q1 + B.p[3 * row + 2] * q2;
+    if (live) pq = pn[0] * q0 + pn[1] * q1 + pn[2] * q2;
   }
   pq = block_sum256(pq, red);
   if (threadIdx.x == 0) B.P_pq[blockIdx.x] = pq;
 }
 
-__global__ void __launch_bounds__(kWave) k_pcg_update1(View V, BlockTable T, BlockTable TS,
-                                                       PcgBufs B, int parity) {
+__global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable T, BlockTable TS,
+                                                      PcgBufs B, int parity) {
   __shared__ double rs[kWave][3];
   const int s = T.sc[blockIdx.x];
   if (V.pdone[s]) return;
-  const double* Prz = parity ? B.P_rz1 : B.P_rz0;
+  const double* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
-  const double rzs = scene_sum_wave(Prz, T.sblk, s), pqs = scene_sum_wave(B.P_pq, TS.sblk, s);
+  const double* pk = parity ? B.p0 : B.p1;
+  const double rzs = scene_sum_wave(Prz_cur, T.sblk, s), pqs = scene_sum_wave(B.P_pq, TS.sblk, s);
   const double alpha = pqs > 0.0 ? rzs / pqs : 0.0;
   const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
   const int n = n0 + threadIdx.x;
@@ -1009,7 +1065,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_update1(View V, BlockTable T, Blo
   double r[3] = {0, 0, 0};
   if (live) {
     for (int c = 0; c < 3; ++c) {
-      B.dx[3 * n + c] += alpha * B.p[3 * n + c];
+      B.dx[3 * n + c] += alpha * pk[3 * n + c];
       r[c] = B.r[3 * n + c] - alpha * B.q[3 * n + c];
       B.r[3 * n + c] = r[c];
     }
@@ -1026,30 +1082,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_update1(View V, BlockTable T, Blo
   if (threadIdx.x == 0) {
     Prz_new[blockIdx.x] = rz;
     B.P_rr[blockIdx.x] = rr;
-  }
-}
-
-__global__ void __launch_bounds__(kWave) k_pcg_update2(View V, BlockTable T, PcgBufs B, int parity) {
-  const int s = T.sc[blockIdx.x];
-  if (V.pdone[s]) return;
-  const double* Prz_old = parity ? B.P_rz1 : B.P_rz0;
-  const double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
-  const bool first = (int)blockIdx.x == T.sblk[s];
-  const double rzn = scene_sum_wave(Prz_new, T.sblk, s), rzo = scene_sum_wave(Prz_old, T.sblk, s);
-  const double rr = scene_sum_wave(B.P_rr, T.sblk, s), gg = scene_sum_wave(B.P_gg, T.sblk, s);
-  const double eta = V.sc[s].pcg_eta;
-  const bool conv = (rr <= eta * eta * gg) || !(rzn > 0.0) || !(rzo > 0.0);
-  if (conv) {
-    if (first && threadIdx.x == 0) V.pdone[s] = 1;
-    return;
-  }
-  const double beta = rzn / rzo;
-  const int n = T.b0[blockIdx.x] + threadIdx.x;
-  if (n < T.b1[blockIdx.x])
-    for (int c = 0; c < 3; ++c) B.p[3 * n + c] = B.z[3 * n + c] + beta * B.p[3 * n + c];
-  if (first && threadIdx.x == 0) {
-    const int it = ++B.iters[s];
-    if (it >= B.max_iters) V.pdone[s] = 1;
+    if ((int)blockIdx.x == T.sblk[s]) ++B.iters[s];
   }
 }
 
@@ -1502,14 +1535,13 @@ void launch_precond(const View& V, const int* drowptr, const int* dcol, const do
 void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
   if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_init, dim3(T.nblk), dim3(kWave), 0, s, V, T, B);
 }
-void launch_pcg_spmv(const View& V, const BlockTable& TS, const PcgBufs& B, hipStream_t s) {
-  if (TS.nblk > 0) hipLaunchKernelGGL(k_pcg_spmv, dim3(TS.nblk), dim3(TPB), 0, s, V, TS, B);
+void launch_pcg_spmv(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+                     int parity, hipStream_t s) {
+  if (TS.nblk > 0) hipLaunchKernelGGL(k_pcg_dir_spmv, dim3(TS.nblk), dim3(TPB), 0, s, V, T, TS, B, parity);
 }
 void launch_pcg_update(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
                        int parity, hipStream_t s) {
-  if (T.nblk <= 0) return;
-  hipLaunchKernelGGL(k_pcg_update1, dim3(T.nblk), dim3(kWave), 0, s, V, T, TS, B, parity);
-  hipLaunchKernelGGL(k_pcg_update2, dim3(T.nblk), dim3(kWave), 0, s, V, T, B, parity);
+  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_update, dim3(T.nblk), dim3(kWave), 0, s, V, T, TS, B, parity);
 }
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s) {
   LAUNCH(k_pmax, V.Nn + V.Ncv, TPB, s, V, p, pmax);
