@@ -82,6 +82,8 @@ def main():
         lat.append((time.perf_counter() - ts) * 1e3)
         ok += rc == taccel.OK
         stats.append(st)
+        if rc != taccel.OK:
+            print(f"step {k} failed: {taccel.lib().taccel_last_error().decode()}", file=sys.stderr)
         print(f"step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
               f"al={st['al_rounds']} pcg={st['pcg_iters']} active={st['n_active']} "
               f"{lat[-1]:.1f} ms", file=sys.stderr, flush=True)
@@ -104,7 +106,7 @@ def main():
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         newton_iters_per_step=float(np.mean([s["newton_iters"] for s in stats])),
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
-        roofline=dict(bound="hbm", kernel="k_pcg_spmv", achieved=achieved, peak=HBM_PEAK_GBS,
+        roofline=dict(bound="hbm", kernel="k_pcg_dir_spmv", achieved=achieved, peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
                       launches=prof["launches"], avg_launch_us=avg_ms * 1e3,
                       algorithmic_bytes_per_launch=bytes_per_launch),

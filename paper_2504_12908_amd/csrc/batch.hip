@@ -836,34 +836,22 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufs& B, int nseg) {
       HIPCHECK(hipEventCreate(&e));
       ev_pool.push_back(e);
     }
-  const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, V.bpinv,
-                                        reinterpret_cast<const void*>((intptr_t)prof.on)};
-  if (!pcg_exec || key != pcg_key) {
-    if (pcg_exec) HIPCHECK(hipGraphExecDestroy(pcg_exec));
-    if (pcg_graph) HIPCHECK(hipGraphDestroy(pcg_graph));
-    pcg_exec = nullptr;
-    pcg_graph = nullptr;
-    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < kPcgChunk; ++k) {
-      if (prof.on) HIPCHECK(hipEventRecord(ev_pool[2 * k], s));
-      launch_pcg_spmv(V, TN, TS, B, k & 1, s);
-      if (prof.on) HIPCHECK(hipEventRecord(ev_pool[2 * k + 1], s));
-      launch_pcg_update(V, TN, TS, B, k & 1, s);
-    }
-    HIPCHECK(hipStreamEndCapture(s, &pcg_graph));
-    HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
-    pcg_key = key;
-  }
   std::vector<int> hd(S), it0(S, 0), it1(S);
-  for (int it = 0; it < B.max_iters; it += kPcgChunk) {
-    HIPCHECK(hipGraphLaunch(pcg_exec, s));
-    d2h(hd.data(), pdone.p, S);
-    if (prof.on) d2h(it1.data(), iters.p, S);
-    sync();
-    if (prof.on) {
-      // event pairs of iterations that did work (every scene's iterations run in order)
+  if (prof.on) {
+    // measured path: eager launches with a HIP event pair around every SpMV
+    for (int it = 0; it < B.max_iters; it += kPcgChunk) {
+      for (int k = 0; k < kPcgChunk; ++k) {
+        HIPCHECK(hipEventRecord(ev_pool[2 * k], s));
+        launch_pcg_spmv(V, TN, TS, B, k & 1, s);
+        HIPCHECK(hipEventRecord(ev_pool[2 * k + 1], s));
+        launch_pcg_update(V, TN, TS, B, k & 1, s);
+      }
+      d2h(hd.data(), pdone.p, S);
+      d2h(it1.data(), iters.p, S);
+      sync();
+      // event pairs of iterations that did work (a scene's iterations run in order)
       int real = 0;
-      for (int k = 0; k < S; ++k) real = std::max(real, it1[k] - it0[k] + (hd[k] && it1[k] > it0[k] ? 0 : 0));
+      for (int k = 0; k < S; ++k) real = std::max(real, it1[k] - it0[k]);
       real = std::min(real, kPcgChunk);
       for (int e = 0; e < real; ++e) {
         float ms = 0.f;
@@ -873,7 +861,37 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufs& B, int nseg) {
         prof.spmv_bytes += launch_bytes;
       }
       it0 = it1;
+      bool all = true;
+      for (int k = 0; k < S; ++k) all = all && hd[k];
+      if (all) break;
     }
+    return;
+  }
+  const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, V.bpinv};
+  if (!pcg_exec || key != pcg_key) {
+    if (pcg_exec) HIPCHECK(hipGraphExecDestroy(pcg_exec));
+    if (pcg_graph) HIPCHECK(hipGraphDestroy(pcg_graph));
+    pcg_exec = nullptr;
+    pcg_graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kPcgChunk; ++k) {
+      launch_pcg_spmv(V, TN, TS, B, k & 1, s);
+      launch_pcg_update(V, TN, TS, B, k & 1, s);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);  // always ends the capture
+    if (ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      HIPCHECK(ec);
+    }
+    pcg_graph = graph;
+    HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
+    pcg_key = key;
+  }
+  for (int it = 0; it < B.max_iters; it += kPcgChunk) {
+    HIPCHECK(hipGraphLaunch(pcg_exec, s));
+    d2h(hd.data(), pdone.p, S);
+    sync();
     bool all = true;
     for (int k = 0; k < S; ++k) all = all && hd[k];
     if (all) break;
@@ -1376,6 +1394,19 @@ taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, tac
     return impl_->step(t, per_scene, st);
   } catch (const ApiError& e) {
     set_last_error(e.what());
+    // roll every scene back to the start of the step (positions saved by the predictor)
+    Impl& I = *impl_;
+    (void)hipStreamSynchronize(I.mem.stream);
+    (void)hipMemcpyAsync(I.x.p, I.xn.p, sizeof(double) * 3 * (size_t)I.Nn, hipMemcpyDeviceToDevice,
+                         I.mem.stream);
+    (void)hipStreamSynchronize(I.mem.stream);
+    if (per_scene)
+      for (int k = 0; k < S_; ++k) per_scene[k] = e.st;
+    if (st)
+      for (int k = 0; k < S_; ++k) {
+        std::memset(&st[k], 0, sizeof(st[k]));
+        st[k].status = e.st;
+      }
     return e.st;
   }
 }
