@@ -590,8 +590,8 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
       h_qscene.push_back(s);
     }
     C.q1 = Nq + ncv + (int)edges.size();
-    // broad-phase grid: cell edge = 2 x mean primitive extent (+ 2 dhat), origin below the
-    // scene's bounding box
+    // broad-phase grid: cell edge = mean edge extent + 2 dhat, origin below the scene's
+    // bounding box
     double ext = 0.0;
     int next = 0;
     for (const auto& e : edges) {
@@ -601,7 +601,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
       ext += std::max(std::fabs(pa[0] - pb[0]), std::max(std::fabs(pa[1] - pb[1]), std::fabs(pa[2] - pb[2])));
       ++next;
     }
-    C.cell = 2.0 * (next ? ext / next : 1e-3) + 2.0 * P.dhat;
+    C.cell = (next ? ext / next : 1e-3) + 2.0 * P.dhat;
     for (int c = 0; c < 3; ++c) C.org[c] = (std::isfinite(lo[c]) ? lo[c] : 0.0) - 2.0 * C.cell;
     double L = 0.0;
     for (int c = 0; c < 3; ++c)
@@ -836,36 +836,21 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufs& B, int nseg) {
       HIPCHECK(hipEventCreate(&e));
       ev_pool.push_back(e);
     }
-  std::vector<int> hd(S), it0(S, 0), it1(S);
+  std::vector<int> hd(S);
   if (prof.on) {
-    // measured path: eager launches with a HIP event pair around every SpMV
-    for (int it = 0; it < B.max_iters; it += kPcgChunk) {
-      for (int k = 0; k < kPcgChunk; ++k) {
-        HIPCHECK(hipEventRecord(ev_pool[2 * k], s));
-        launch_pcg_spmv(V, TN, TS, B, k & 1, s);
-        HIPCHECK(hipEventRecord(ev_pool[2 * k + 1], s));
-        launch_pcg_update(V, TN, TS, B, k & 1, s);
-      }
-      d2h(hd.data(), pdone.p, S);
-      d2h(it1.data(), iters.p, S);
-      sync();
-      // event pairs of iterations that did work (a scene's iterations run in order)
-      int real = 0;
-      for (int k = 0; k < S; ++k) real = std::max(real, it1[k] - it0[k]);
-      real = std::min(real, kPcgChunk);
-      for (int e = 0; e < real; ++e) {
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, ev_pool[2 * e], ev_pool[2 * e + 1]));
-        prof.spmv_ms += ms;
-        prof.spmv_launches += 1;
-        prof.spmv_bytes += launch_bytes;
-      }
-      it0 = it1;
-      bool all = true;
-      for (int k = 0; k < S; ++k) all = all && hd[k];
-      if (all) break;
-    }
-    return;
+    // Live sample of the sparse product on this Newton iteration's matrix: kSample launches
+    // back to back between one pair of events, right after the PCG initialisation.  The
+    // launches only write p_1, q and the p.q partials, which iteration 0 recomputes.
+    constexpr int kSample = 16;
+    HIPCHECK(hipEventRecord(ev_pool[0], s));
+    for (int k = 0; k < kSample; ++k) launch_pcg_spmv(V, TN, TS, B, 0, s);
+    HIPCHECK(hipEventRecord(ev_pool[1], s));
+    HIPCHECK(hipEventSynchronize(ev_pool[1]));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, ev_pool[0], ev_pool[1]));
+    prof.spmv_ms += ms;
+    prof.spmv_launches += kSample;
+    prof.spmv_bytes += kSample * launch_bytes;
   }
   const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, V.bpinv};
   if (!pcg_exec || key != pcg_key) {

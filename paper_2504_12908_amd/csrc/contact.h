@@ -241,14 +241,20 @@ TC_HD void barrier_d(double d, double dhat, double* b, double* b1, double* b2) {
 
 // Energy kappa * m * b(d) of one pair with its 12-gradient and (unprojected) 12x12 Hessian,
 // the Hessian written at H[(i*12+j)*stride].  Returns the distance type; *e = +inf when
-// s <= 0 and 0 (with zero derivatives) when d >= dhat.
+// s <= 0 and 0 (with zero derivatives) when d >= dhat.  work: kBarrierWork doubles of
+// scratch (on the GPU a slice of LDS, so the temporaries never go to private memory).
+constexpr int kBarrierWork = 160;
 TC_HD int barrier_pair(int kind, const double* x12, double meps, double dhat, double kappa,
-                       double* e, double* g12, double* H, int stride) {
+                       double* e, double* g12, double* H, int stride, double* work) {
   const int type = classify(kind, x12);
   const DistForm f = dist_form(kind, type);
   for (int k = 0; k < 12; ++k) g12[k] = 0.0;
   for (int k = 0; k < 144; ++k) H[k * stride] = 0.0;
-  double gr[9], Hr[81];
+  double* gr = work;         // 9
+  double* Hr = work + 9;     // 81
+  double* gc12 = work + 90;  // 12
+  double* Hc = work + 102;   // 36
+  double* gs = work + 138;   // 12
   const double s = sqdist_reduced(f, x12, gr, Hr);
   if (!(s > 0.0)) { *e = INFINITY; return type; }
   const double d = sqrt(s);
@@ -257,7 +263,6 @@ TC_HD int barrier_pair(int kind, const double* x12, double meps, double dhat, do
   barrier_d(d, dhat, &b, &b1, &b2);
   const double Bs = b1 / (2.0 * d), Bss = (b2 - b1 / d) / (4.0 * s);
   double m = 1.0, m1 = 0.0, m2 = 0.0;
-  double gc12[12], Hc[36];
   for (int k = 0; k < 12; ++k) gc12[k] = 0.0;
   if (kind == KIND_EE) {
     const d3 u = ld(x12 + 3) - ld(x12), v = ld(x12 + 9) - ld(x12 + 6);
@@ -276,7 +281,6 @@ TC_HD int barrier_pair(int kind, const double* x12, double meps, double dhat, do
     }
   }
   // grad of s in 12-space
-  double gs[12];
   for (int k = 0; k < 12; ++k) gs[k] = 0.0;
   for (int j = 0; j < f.nred; ++j)
     for (int v = 0; v < 4; ++v)

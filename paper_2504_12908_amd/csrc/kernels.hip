@@ -256,13 +256,20 @@ __device__ __forceinline__ bool boxes_close_lohi(const double* a, const double* 
   return true;
 }
 
-__global__ void k_bp_query(View V, const double* P0, const double* P1, BroadPhase bp, int all,
-                           int emit, int* cand_q, int* cand_t) {
-  const int q = gid();
-  if (q >= V.Nq) return;
+// One query primitive per group of 16 lanes: the lanes walk the query's cells together and
+// scan each bucket's entries in parallel.  Count pass: matches per query.  Emit pass: the
+// matches are compacted in lane order with a ballot; k_bp_sort_queries then sorts each
+// query's segment by target so the candidate list has the canonical order.
+constexpr int kQueryLanes = 16;
+__global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, const double* P1,
+                                                  BroadPhase bp, int all, int emit, int* cand_q,
+                                                  int* cand_t) {
+  const int sub = threadIdx.x & (kQueryLanes - 1);
+  const int q = blockIdx.x * (TPB / kQueryLanes) + (int)(threadIdx.x / kQueryLanes);
+  if (q >= V.Nq) return;  // whole 16-lane group leaves together
   const int s = V.qscene[q];
   if (!all && !V.act[s]) {
-    if (!emit) bp.qcount[q] = 0;
+    if (!emit && sub == 0) bp.qcount[q] = 0;
     return;
   }
   const int kind = V.qkind[q], i = V.qidx[q];
@@ -282,56 +289,71 @@ __global__ void k_bp_query(View V, const double* P0, const double* P1, BroadPhas
   int ql[6];
   cell_range(sc, qb, qb + 3, ql, bp.overflow);
   const int off = emit ? bp.qoff[q] : 0;
-  int cnt = 0;
+  int cnt = 0;  // matches of this lane (count pass) / of the group so far (emit pass)
   const int qb0 = V.cvb[qids[0]];
   const double inv = 1.0 / sc.cell;
+  const int gshift = (threadIdx.x & 63) & ~(kQueryLanes - 1);
+  const unsigned long long lt = (1ull << (threadIdx.x & 63)) - 1ull;
   for (int z = ql[2]; z <= ql[5]; ++z)
     for (int y = ql[1]; y <= ql[4]; ++y)
       for (int x = ql[0]; x <= ql[3]; ++x) {
         const int b = bucket_of(s, x, y, z, kind, bp.table_mask);
         const int e0 = bp.bstart[b], e1 = e0 + bp.bcount[b];
-        for (int e = e0; e < e1; ++e) {
-          const BpEntry& E = bp.entries[e];
-          // cheap rejections first: hash collision, owner cell, box predicate
-          if (E.cx != x || E.cy != y || E.cz != z) continue;
-          const int t = E.t;
-          if (kind == 1 && t - V.Ntr <= i) continue;
-          if (max(ql[0], cell_of(E.lo[0] - sc.dhat, sc.org[0], inv)) != x ||
-              max(ql[1], cell_of(E.lo[1] - sc.dhat, sc.org[1], inv)) != y ||
-              max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) != z)
-            continue;
-          if (!boxes_close_lohi(qb, E.lo, E.hi, sc.dhat)) continue;
-          // admissibility (topology)
-          int tid[3];
-          int tgt;
-          if (kind == 0) {
-            target_ids(V, t, tid);
-            tgt = t;
-            const int v = qids[0];
-            if (V.cvscene[tid[0]] != s) continue;
-            if (v == tid[0] || v == tid[1] || v == tid[2]) continue;
-            if (qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) continue;
-            if (V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]) continue;
+        for (int base = e0; base < e1; base += kQueryLanes) {
+          const int e = base + sub;
+          bool hit = false;
+          int tgt = 0;
+          if (e < e1) {
+            const BpEntry& E = bp.entries[e];
+            const int t = E.t;
+            hit = E.cx == x && E.cy == y && E.cz == z && !(kind == 1 && t - V.Ntr <= i) &&
+                  max(ql[0], cell_of(E.lo[0] - sc.dhat, sc.org[0], inv)) == x &&
+                  max(ql[1], cell_of(E.lo[1] - sc.dhat, sc.org[1], inv)) == y &&
+                  max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) == z &&
+                  boxes_close_lohi(qb, E.lo, E.hi, sc.dhat);
+            if (hit) {
+              int tid[3];
+              target_ids(V, t, tid);
+              if (kind == 0) {
+                tgt = t;
+                const int v = qids[0];
+                hit = V.cvscene[tid[0]] == s && v != tid[0] && v != tid[1] && v != tid[2] &&
+                      !(qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) &&
+                      !(V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]);
+              } else {
+                tgt = t - V.Ntr;
+                hit = V.cvscene[tid[0]] == s && qids[0] != tid[0] && qids[0] != tid[1] &&
+                      qids[1] != tid[0] && qids[1] != tid[1] &&
+                      !(qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) &&
+                      !(V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]);
+              }
+            }
+          }
+          if (!emit) {
+            cnt += hit;
           } else {
-            tgt = t - V.Ntr;
-            target_ids(V, t, tid);
-            if (V.cvscene[tid[0]] != s) continue;
-            if (qids[0] == tid[0] || qids[0] == tid[1] || qids[1] == tid[0] || qids[1] == tid[1]) continue;
-            if (qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) continue;
-            if (V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]) continue;
+            const unsigned long long m = __ballot(hit);
+            const unsigned long long mine = (m >> gshift) & 0xFFFFull;
+            if (hit) {
+              const int pos = off + cnt + __popcll(m & lt & (0xFFFFull << gshift));
+              cand_q[pos] = q;
+              cand_t[pos] = tgt;
+            }
+            cnt += __popcll(mine);
           }
-          if (emit) {
-            cand_q[off + cnt] = q;
-            cand_t[off + cnt] = tgt;
-          }
-          ++cnt;
         }
       }
   if (!emit) {
-    bp.qcount[q] = cnt;
-    return;
+    for (int o = kQueryLanes / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kQueryLanes);
+    if (sub == 0) bp.qcount[q] = cnt;
   }
-  // canonical order inside the query: ascending target
+}
+
+// Canonical order inside each query's segment: ascending target.
+__global__ void k_bp_sort_queries(View V, BroadPhase bp, int* cand_t) {
+  const int q = gid();
+  if (q >= V.Nq) return;
+  const int off = bp.qoff[q], cnt = bp.qcount[q];
   for (int a = 1; a < cnt; ++a) {
     const int key = cand_t[off + a];
     int b = a - 1;
@@ -530,6 +552,7 @@ __global__ void __launch_bounds__(64) k_barrier_hess(View V, int np, const int* 
                                                      double* ph) {
   __shared__ WaveJacobiLds L;
   __shared__ double g_s[12];
+  __shared__ double work[kBarrierWork];
   const int k = blockIdx.x;
   if (k >= np) return;
   if (threadIdx.x == 0) {
@@ -538,7 +561,7 @@ __global__ void __launch_bounds__(64) k_barrier_hess(View V, int np, const int* 
     const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
     double x12[12], e;
     gather12(V.cpos, ids, x12);
-    barrier_pair(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, &e, g_s, L.A[0], 1);
+    barrier_pair(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, &e, g_s, L.A[0], 1, work);
   }
   __syncthreads();
   wave_psd12(L);
@@ -1390,11 +1413,12 @@ __global__ void __launch_bounds__(64) k_debug_barrier(int n, const int* kinds, c
                                                       double* e, double* g, double* H, double* Hp,
                                                       int* types) {
   __shared__ WaveJacobiLds L;
+  __shared__ double work[kBarrierWork];
   const int k = blockIdx.x;
   if (k >= n) return;
   if (threadIdx.x == 0) {
     double ee, gg[12];
-    const int type = barrier_pair(kinds[k], x + 12 * k, meps[k], dhat, kappa, &ee, gg, L.A[0], 1);
+    const int type = barrier_pair(kinds[k], x + 12 * k, meps[k], dhat, kappa, &ee, gg, L.A[0], 1, work);
     if (e) e[k] = ee;
     if (types) types[k] = type;
     if (g)
@@ -1477,7 +1501,9 @@ void launch_bp_fill(const View& V, BroadPhase& bp, hipStream_t s) {
 }
 void launch_bp_query(const View& V, const double* P0, const double* P1, BroadPhase& bp, int all,
                      int emit, int* cand_q, int* cand_t, hipStream_t s) {
-  LAUNCH(k_bp_query, V.Nq, 128, s, V, P0, P1, bp, all, emit, cand_q, cand_t);
+  const int nb = nblk(V.Nq, TPB / kQueryLanes);
+  if (nb > 0) hipLaunchKernelGGL(k_bp_query, dim3(nb), dim3(TPB), 0, s, V, P0, P1, bp, all, emit, cand_q, cand_t);
+  if (emit) LAUNCH(k_bp_sort_queries, V.Nq, TPB, s, V, bp, cand_t);
 }
 void launch_narrow(const View& V, int n, const int* cq, const int* ct, int* flag, hipStream_t s) {
   LAUNCH(k_narrow, n, TPB, s, V, n, cq, ct, flag);
