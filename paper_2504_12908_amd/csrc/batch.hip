@@ -195,6 +195,7 @@ struct Batch::Impl {
   // outside its sweep)
   bool cover_valid = false;
   int n_cover = 0;
+  bool device_touched = false;
   // dynamic work buffers
   BroadPhase bp;
   DBuf<double> bp_tbox;
@@ -215,6 +216,8 @@ struct Batch::Impl {
   DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs;
   DBuf<int> scalars;  // device scalars for scan totals
   DBuf<char> scratch;
+  DBuf<int> mv_nodes;
+  DBuf<double> mv_tgt;
   // pinned host staging
   int* h_pin = nullptr;
   size_t h_pin_bytes = 0;
@@ -659,7 +662,14 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     for (int a = 0; a < 4; ++a) h_tv[(size_t)a * Nt + t] = h_tv_aos[4 * (size_t)t + a];
     for (int k = 0; k < 9; ++k) h_Dminv[(size_t)k * Nt + t] = h_Dminv_aos[9 * (size_t)t + k];
   }
-  // ---- upload
+  // ---- upload (everything above is host-side validation and setup)
+  if (!mem.stream) {
+    // a stream of our own (default priority): the PCG chunks are captured into a graph,
+    // which the null stream does not allow
+    HIPCHECK(hipStreamCreateWithFlags(&mem.stream, hipStreamNonBlocking));
+    mem.own_stream = true;
+  }
+  device_touched = true;
   Mem* m = &mem;
   d_sc.upload(m, hsc);
   x.upload(m, h_x);
@@ -768,6 +778,21 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   bp_qoff.ensure(m, std::max(Nq, 1));
   HIPCHECK(hipHostMalloc((void**)&h_pin, 4096, hipHostMallocDefault));
   h_pin_bytes = 4096;
+  // The initial state must have every admissible pair at positive distance (the barrier is
+  // infinite at contact); tets were checked on the host.
+  {
+    const View V = view();
+    launch_cpos(V, mem.stream);
+    const int nc = broad_phase(cpos.p, nullptr, 1, cq, ct);
+    zero(bad.p, sizeof(int) * S);
+    launch_touching(V, nc, cq.p, ct.p, bad.p, mem.stream);
+    std::vector<int> hb(S);
+    d2h(hb.data(), bad.p, S);
+    sync();
+    for (int k = 0; k < S; ++k)
+      if (hb[k]) throw ApiError(TACCEL_INFEASIBLE, "scene " + std::to_string(k) +
+                                                       ": a contact pair is at zero distance");
+  }
   sync();
 }
 
@@ -1130,12 +1155,44 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   }
   h2d(bstar.p, hstar.data(), hstar.size());
   launch_predict(V, s);
-  DBuf<int> mv_nodes;
-  DBuf<double> mv_tgt;
+  std::vector<int> infeasible_target(S, 0);
   if (!h_moving_nodes.empty()) {
     mv_nodes.upload(&mem, h_moving_nodes);
     mv_tgt.upload(&mem, hmove);
-    launch_set_moving(V, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
+    // The prescribed vertices jump to their targets; the jump must be collision-free and
+    // keep every tet positive (INFEASIBLE_TARGET otherwise).  Positions after the jump are
+    // staged in r (free at this point).
+    HIPCHECK(hipMemcpyAsync(r.p, x.p, sizeof(double) * 3 * (size_t)Nn, hipMemcpyDeviceToDevice, s));
+    launch_set_moving(r.p, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
+    launch_cpos(V, s);
+    launch_cmap(V, r.p, cend.p, s);
+    launch_diff3(3 * Ncv, cend.p, cpos.p, cdisp.p, s);
+    std::vector<int> all_on(S, 1);
+    h2d(act.p, all_on.data(), S);
+    const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
+    unsigned long long* amin = u64s.p + S;
+    {
+      std::vector<unsigned long long> one(S);
+      const double d1 = 1.0;
+      unsigned long long b1;
+      std::memcpy(&b1, &d1, sizeof(double));
+      std::fill(one.begin(), one.end(), b1);
+      h2d(amin, one.data(), S);
+    }
+    launch_ccd(V, nsw, sq.p, st.p, amin, s);
+    zero(bad.p, sizeof(int) * S);
+    launch_tets_positive(V, r.p, bad.p, s);
+    std::vector<unsigned long long> ha(S);
+    std::vector<int> hb(S);
+    d2h(ha.data(), amin, S);
+    d2h(hb.data(), bad.p, S);
+    sync();
+    for (int k = 0; k < S; ++k) {
+      double a;
+      std::memcpy(&a, &ha[k], sizeof(double));
+      infeasible_target[k] = hs[k].n_moving > 0 && (a < 1.0 || hb[k]);
+    }
+    launch_set_moving(x.p, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
   }
   launch_body_reset(V, 1e6, s);
   cover_valid = false;
@@ -1153,11 +1210,14 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       std::memcpy(&r, &hres[bglob++], sizeof(double));
       hb.r0 = hb.rprev = r;
     }
-  mv_nodes.free();
-  mv_tgt.free();
   // ---- per-scene state machine
   enum { kNewton = 0, kDone = 1, kFailed = 2 };
   std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
+  for (int k = 0; k < S; ++k)
+    if (infeasible_target[k]) {
+      phase[k] = kFailed;
+      status[k] = TACCEL_INFEASIBLE_TARGET;
+    }
   std::vector<int> tot_pcg(S, 0), nact_last(S, 0), tot_halv(S, 0);
   std::vector<int> last(S), lsf(S), nanf(S), pcg_it(S), nact(S), halv(S);
   std::vector<int> hact(S);
@@ -1314,16 +1374,6 @@ taccel_status Batch::create(const taccel_scene_desc* d, int n, const taccel_runt
     b->impl_->mem.rt = *rt;
     b->impl_->mem.stream = (hipStream_t)rt->stream;
   }
-  if (!b->impl_->mem.stream) {
-    // a stream of our own (default priority): the PCG chunks are captured into a graph,
-    // which the null stream does not allow
-    if (hipStreamCreateWithFlags(&b->impl_->mem.stream, hipStreamNonBlocking) != hipSuccess) {
-      err = "hipStreamCreateWithFlags failed";
-      delete b;
-      return TACCEL_ERR_HIP;
-    }
-    b->impl_->mem.own_stream = true;
-  }
   try {
     b->impl_->build(d, n);
   } catch (const ApiError& e) {
@@ -1339,6 +1389,10 @@ taccel_status Batch::create(const taccel_scene_desc* d, int n, const taccel_runt
 Batch::~Batch() {
   if (!impl_) return;
   Impl& I = *impl_;
+  if (!I.device_touched) {  // rejected before any device call
+    delete impl_;
+    return;
+  }
   (void)hipStreamSynchronize(I.mem.stream);
   I.release_all();
   for (hipEvent_t e : I.ev_pool) (void)hipEventDestroy(e);
@@ -1368,6 +1422,8 @@ Batch::~Batch() {
   I.u64s.free();
   I.bp_entries.free();
   I.scratch.free();
+  I.mv_nodes.free();
+  I.mv_tgt.free();
   I.d_sc.free();
 #undef FREE_ALL
   if (I.mem.own_stream) (void)hipStreamDestroy(I.mem.stream);

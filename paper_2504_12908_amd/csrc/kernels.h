@@ -37,7 +37,11 @@ struct BroadPhase {
 };
 
 void launch_predict(const View& V, hipStream_t s);
-void launch_set_moving(const View& V, int n, const int* nodes, const double* tgt, hipStream_t s);
+void launch_set_moving(double* x, int n, const int* nodes, const double* tgt, hipStream_t s);
+void launch_touching(const View& V, int n, const int* cand_q, const int* cand_t, int* bad, hipStream_t s);
+void launch_diff3(int n3, const double* a, const double* b, double* out, hipStream_t s);
+void launch_tets_positive(const View& V, const double* x, int* bad, hipStream_t s);
+void launch_cmap(const View& V, const double* src, double* out, hipStream_t s);
 void launch_cpos(const View& V, hipStream_t s);
 void launch_cdisp(const View& V, const double* p, hipStream_t s);
 void launch_cend(const View& V, double* cend, hipStream_t s);

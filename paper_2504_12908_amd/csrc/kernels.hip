@@ -57,10 +57,10 @@ __global__ void k_predict(View V) {
   }
 }
 
-__global__ void k_set_moving(View V, int n, const int* nodes, const double* tgt) {
+__global__ void k_set_moving(double* x, int n, const int* nodes, const double* tgt) {
   const int k = gid();
   if (k >= n) return;
-  for (int c = 0; c < 3; ++c) V.x[3 * nodes[k] + c] = tgt[3 * k + c];
+  for (int c = 0; c < 3; ++c) x[3 * nodes[k] + c] = tgt[3 * k + c];
 }
 
 __device__ __forceinline__ void body_point(const View& V, const double* y, int cv, double* out) {
@@ -384,6 +384,36 @@ __device__ __forceinline__ int cand_verts(const View& V, int q, int t, int* ids)
 __device__ __forceinline__ void gather12(const double* P, const int* ids, double* x12) {
   for (int v = 0; v < 4; ++v)
     for (int c = 0; c < 3; ++c) x12[3 * v + c] = P[3 * ids[v] + c];
+}
+
+// Flag scenes with a candidate pair at zero distance (not a feasible IPC state).
+__global__ void k_touching(View V, int n, const int* cq, const int* ct, int* bad) {
+  const int k = gid();
+  if (k >= n) return;
+  int ids[4];
+  const int kind = cand_verts(V, cq[k], ct[k], ids);
+  double x12[12];
+  gather12(V.cpos, ids, x12);
+  if (!(pair_sqdist(kind, x12, nullptr) > 0.0)) bad[V.qscene[cq[k]]] = 1;
+}
+
+__global__ void k_diff3(int n3, const double* a, const double* b, double* out) {
+  const int k = gid();
+  if (k < n3) out[k] = a[k] - b[k];
+}
+
+// Flag scenes with a tet of non-positive det F at positions x.
+__global__ void k_tets_positive(View V, const double* x, int* bad) {
+  const int t = gid();
+  if (t >= V.Nt) return;
+  double x12[12], Dm[9], F[9];
+  for (int v = 0; v < 4; ++v) {
+    const int node = V.tv[v * V.Nt + t];
+    for (int c = 0; c < 3; ++c) x12[3 * v + c] = x[3 * node + c];
+  }
+  for (int k = 0; k < 9; ++k) Dm[k] = V.Dminv[k * V.Nt + t];
+  deformation_gradient(x12, Dm, F);
+  if (!(det3(F) > 0.0)) bad[V.tscene[t]] = 1;
 }
 
 __global__ void k_narrow(View V, int n, const int* cq, const int* ct, int* flag) {
@@ -1473,8 +1503,20 @@ __global__ void k_debug_arap(int n, const double* A, double* e, double* g, doubl
   } while (0)
 
 void launch_predict(const View& V, hipStream_t s) { LAUNCH(k_predict, V.Nn, TPB, s, V); }
-void launch_set_moving(const View& V, int n, const int* nodes, const double* tgt, hipStream_t s) {
-  LAUNCH(k_set_moving, n, TPB, s, V, n, nodes, tgt);
+void launch_set_moving(double* x, int n, const int* nodes, const double* tgt, hipStream_t s) {
+  LAUNCH(k_set_moving, n, TPB, s, x, n, nodes, tgt);
+}
+void launch_touching(const View& V, int n, const int* cq, const int* ct, int* bad, hipStream_t s) {
+  LAUNCH(k_touching, n, TPB, s, V, n, cq, ct, bad);
+}
+void launch_diff3(int n3, const double* a, const double* b, double* out, hipStream_t s) {
+  LAUNCH(k_diff3, n3, TPB, s, n3, a, b, out);
+}
+void launch_tets_positive(const View& V, const double* x, int* bad, hipStream_t s) {
+  LAUNCH(k_tets_positive, V.Nt, TPB, s, V, x, bad);
+}
+void launch_cmap(const View& V, const double* src, double* out, hipStream_t s) {
+  LAUNCH(k_cmap, V.Ncv, TPB, s, V, src, out);
 }
 void launch_cpos(const View& V, hipStream_t s) { LAUNCH(k_cmap, V.Ncv, TPB, s, V, V.x, V.cpos); }
 void launch_cdisp(const View& V, const double* p, hipStream_t s) {

@@ -41,3 +41,77 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(taccel, "_lib", None)
     with pytest.raises(RuntimeError):
         taccel.lib()
+
+
+# ---------------------------------------------------------------- argument validation
+# The library validates a scene description on the host before any device call, so these
+# error paths run without a GPU.
+def _lib_or_skip():
+    from paper_2504_12908_amd import taccel
+    if not os.path.exists(taccel.LIB_PATH):
+        pytest.skip("libtaccel.so not built")
+    return taccel
+
+
+def _bad_spec(mutate):
+    import copy
+
+    from paper_2504_12908_amd import scenes
+    spec = copy.deepcopy(scenes.pad_press_cube(0))
+    mutate(spec)
+    return spec
+
+
+def _expect_arg_error(T, spec, needle):
+    with pytest.raises(T.TaccelError) as ei:
+        T.Scene(spec)
+    assert ei.value.status == T.ERR_ARG
+    assert needle in str(ei.value)
+
+
+def test_rejects_inverted_tet():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.tets[5, 1], s.tets[5, 2] = s.tets[5, 2], s.tets[5, 1]
+    _expect_arg_error(T, _bad_spec(m), "inverted or degenerate tet 5")
+
+
+def test_rejects_tet_index_out_of_range():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.tets[0, 0] = len(s.verts)
+    _expect_arg_error(T, _bad_spec(m), "tet index out of range")
+
+
+def test_rejects_bad_dirichlet_flag():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.dirichlet[3] = 7
+    _expect_arg_error(T, _bad_spec(m), "dirichlet flag")
+
+
+def test_rejects_inside_out_body():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.bodies[0].tris = s.bodies[0].tris[:, ::-1].copy()
+    _expect_arg_error(T, _bad_spec(m), "no positive volume")
+
+
+def test_rejects_nonpositive_time_step():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.params["h"] = 0.0
+    _expect_arg_error(T, _bad_spec(m), "must be > 0")
+
+
+def test_rejects_body_triangle_index():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.bodies[0].tris[2, 1] = 99
+    _expect_arg_error(T, _bad_spec(m), "body triangle index out of range")
