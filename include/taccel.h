@@ -72,8 +72,11 @@ typedef struct {
   int32_t max_newton; /* per Newton loop; 0 -> 100 */
   int32_t max_al;     /* augmented-Lagrangian rounds; 0 -> 30 */
   int32_t max_pcg;    /* 0 -> 10000 */
-  double pcg_eta;     /* relative residual of PCG; 0 -> 1e-4 */
-  int32_t precision;  /* taccel_precision */
+  double pcg_eta;     /* relative residual of PCG; 0 -> 1e-4 (FP64) or 1e-3 (MIXED) */
+  int32_t precision;  /* taccel_precision.  MIXED: Hessian blocks, their assembly, the sparse
+                         product and the whole PCG in FP32 (FP32 accumulation); positions,
+                         gradients, energies, distances, barrier, CCD, line search and the
+                         Newton test in FP64.  All scenes of a batch share one precision. */
 } taccel_params;
 
 typedef struct {

@@ -171,7 +171,7 @@ struct Batch::Impl {
   std::vector<HostScene> hs;
   std::vector<SceneConst> hsc;
   std::vector<int> h_ntype, h_nscene, h_bnode, h_bscene, h_bpres, h_moving_nodes;
-  std::vector<double> spmv_static_bytes;  // per scene: algorithmic bytes of the FEM part of SpMV
+  std::vector<double> spmv_static_blocks;  // per scene: stored blocks of free rows
   std::vector<double> spmv_free_nodes;
   std::vector<hipEvent_t> ev_pool;
   // static device data
@@ -196,6 +196,7 @@ struct Batch::Impl {
   bool cover_valid = false;
   int n_cover = 0;
   bool device_touched = false;
+  int mixed = 0;  // 1: FP32 Hessian blocks, assembly, SpMV and PCG (taccel_precision MIXED)
   // dynamic work buffers
   BroadPhase bp;
   DBuf<double> bp_tbox;
@@ -277,7 +278,10 @@ struct Batch::Impl {
   hipGraphExec_t pcg_exec = nullptr;
   std::vector<const void*> pcg_key;
   static constexpr int kPcgChunk = 16;
-  void run_pcg(const View& V, const PcgBufs& B, int nseg);
+  template <class T>
+  void run_pcg(const View& V, const PcgBufsT<T>& B, int nseg);
+  template <class T>
+  PcgBufsT<T> pcg_bufs();
   void build(const taccel_scene_desc* d, int n);
   int broad_phase(const double* P0, const double* P1, int all, DBuf<int>& oq, DBuf<int>& ot);
   void newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail, std::vector<int>& nan_,
@@ -331,9 +335,14 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     C.kappa_s = P.kappa_s;
     C.mu = d.soft.youngs / (2.0 * (1.0 + d.soft.poisson));
     C.lam = d.soft.youngs * d.soft.poisson / ((1.0 + d.soft.poisson) * (1.0 - 2.0 * d.soft.poisson));
-    C.pcg_eta = P.pcg_eta > 0 ? P.pcg_eta : 1e-4;
+    C.pcg_eta = P.pcg_eta > 0 ? P.pcg_eta : (P.precision == TACCEL_MIXED ? 1e-3 : 1e-4);
     for (int c = 0; c < 3; ++c) C.grav[c] = P.gravity[c];
     C.precision = P.precision;
+    if (P.precision != TACCEL_FP64 && P.precision != TACCEL_MIXED)
+      throw ApiError(TACCEL_ERR_ARG, "precision must be TACCEL_FP64 or TACCEL_MIXED");
+    if (s == 0) mixed = P.precision == TACCEL_MIXED;
+    else if (mixed != (P.precision == TACCEL_MIXED))
+      throw ApiError(TACCEL_ERR_ARG, "all scenes of a batch must use the same precision");
     // ---- nodes
     const int node0 = Nn;
     H.node0 = node0;
@@ -644,16 +653,13 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   ts_sblk_h.push_back((int)ts_sc_h.size());
   nnz = (int)h_col.size();
   h_nscene.resize(Nn);
-  // Algorithmic bytes of one SpMV over the static (FEM) pattern: for every free row its
-  // blocks (72 B values + 4 B column), row pointer (4 B), free flag (4 B), the 24 B of x
-  // read and the 24 B of y written; plus 24 B of x per free node gathered once.
-  spmv_static_bytes.assign(S, 0.0);
+  // Size of the static (FEM) part of one sparse product: blocks of free rows, free nodes.
+  spmv_static_blocks.assign(S, 0.0);
   spmv_free_nodes.assign(S, 0.0);
   for (int n = 0; n < Nn; ++n) {
     if (!h_nfree[n]) continue;
     spmv_free_nodes[h_nscene[n]] += 1.0;
-    const int nb_row = h_rowptr[n + 1] - h_rowptr[n];
-    spmv_static_bytes[h_nscene[n]] += 76.0 * nb_row + 4.0 + 4.0 + 24.0 + 24.0;
+    spmv_static_blocks[h_nscene[n]] += h_rowptr[n + 1] - h_rowptr[n];
   }
   // SoA tet arrays
   std::vector<int> h_tv(4 * (size_t)Nt);
@@ -839,7 +845,34 @@ int Batch::Impl::broad_phase(const double* P0, const double* P1, int all, DBuf<i
   return ncand;
 }
 
-void Batch::Impl::run_pcg(const View& V, const PcgBufs& B, int nseg) {
+template <class T>
+PcgBufsT<T> Batch::Impl::pcg_bufs() {
+  PcgBufsT<T> B;
+  B.g = g.p;
+  B.r = reinterpret_cast<T*>(r.p);
+  B.z = reinterpret_cast<T*>(z.p);
+  B.p0 = reinterpret_cast<T*>(p.p);
+  B.p1 = reinterpret_cast<T*>(p1.p);
+  B.q = reinterpret_cast<T*>(q.p);
+  B.dx = dx.p;
+  B.pinv = reinterpret_cast<const T*>(pinv.p);
+  B.drowptr = drowptr.p;
+  B.dcol = dcol.p;
+  B.dval = reinterpret_cast<const T*>(dval.p);
+  B.P_pq = reinterpret_cast<T*>(P_pq.p);
+  B.P_rz0 = reinterpret_cast<T*>(P_rz0.p);
+  B.P_rz1 = reinterpret_cast<T*>(P_rz1.p);
+  B.P_rr = reinterpret_cast<T*>(P_rr.p);
+  B.P_gg = reinterpret_cast<T*>(P_gg.p);
+  B.iters = iters.p;
+  int max_pcg = 0;
+  for (const auto& H : hs) max_pcg = std::max(max_pcg, H.max_pcg);
+  B.max_iters = max_pcg;
+  return B;
+}
+
+template <class T>
+void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
   hipStream_t s = stream();
   Profiler& prof = profiler();
   double launch_bytes = 0.0;
@@ -847,13 +880,17 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufs& B, int nseg) {
     std::vector<int> ha(S);
     d2h(ha.data(), act.p, S);
     sync();
+    // static part: per free row its blocks (9 values + 4 B column), 4 B row pointer, 4 B flag,
+    // x read and y written once
+    const double w0 = sizeof(T);
     for (int k = 0; k < S; ++k)
-      if (ha[k]) launch_bytes += spmv_static_bytes[k];
-    // dynamic (contact and body) blocks: 72 B values + 4 B column each, 4 B row pointer per
-    // node; the direction update adds z and p_{k-1} read and p_k written (72 B per free node)
-    launch_bytes += 76.0 * nseg + 4.0 * Nn;
+      if (ha[k]) launch_bytes += (9 * w0 + 4.0) * spmv_static_blocks[k] + (8.0 + 6 * w0) * spmv_free_nodes[k];
+    // dynamic (contact and body) blocks: values + 4 B column each, 4 B row pointer per
+    // node; the direction update adds z and p_{k-1} read and p_k written per free node
+    const double w = sizeof(T);
+    launch_bytes += (9 * w + 4.0) * nseg + 4.0 * Nn;
     for (int k = 0; k < S; ++k)
-      if (ha[k]) launch_bytes += 72.0 * spmv_free_nodes[k];
+      if (ha[k]) launch_bytes += 9.0 * w * spmv_free_nodes[k];
   }
   if (prof.on)
     while (ev_pool.size() < 2 * (size_t)kPcgChunk) {
@@ -940,10 +977,10 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   ph.ensure(&mem, 144 * (size_t)std::max(np, 1));
   launch_compact_pairs(V, ncand, cqp, ctp, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
   // ---- element derivatives
-  launch_fem_hess(V, s);
+  launch_fem_hess(V, mixed, s);
   launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, s);
   launch_body_hess(V, s);
-  launch_assemble_bsr(V, nnz, brow.p, s);
+  launch_assemble_bsr(V, nnz, brow.p, mixed, s);
   launch_assemble_grad(V, g.p, s);
   // ---- contact and body blocks: emit, sort by (row, col), reduce
   const int nitems = np + Nb;
@@ -977,7 +1014,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   dval.ensure(&mem, 9 * (size_t)std::max(nseg, 1));
   zero(rowcnt.p, sizeof(int) * (Nn + 1));
   launch_reduce_blocks(V, nseg, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p, dcol.p,
-                       dval.p, rowcnt.p, s);
+                       dval.p, rowcnt.p, mixed, s);
   scan(rowcnt.p, drowptr.p, Nn + 1);
   // gradient entries
   launch_seg_flags(ng, gkey.p, sflag.p, s);
@@ -986,15 +1023,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_reduce_grad(V, ngseg, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
   // ---- preconditioner and PCG
   zero(bad.p, sizeof(int) * S);
-  launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, s);
-  PcgBufs B;
-  B.g = g.p; B.r = r.p; B.z = z.p; B.p0 = p.p; B.p1 = p1.p; B.q = q.p; B.dx = dx.p; B.pinv = pinv.p;
-  B.drowptr = drowptr.p; B.dcol = dcol.p; B.dval = dval.p;
-  B.P_pq = P_pq.p; B.P_rz0 = P_rz0.p; B.P_rz1 = P_rz1.p; B.P_rr = P_rr.p; B.P_gg = P_gg.p;
-  B.iters = iters.p;
-  int max_pcg = 0;
-  for (const auto& H : hs) max_pcg = std::max(max_pcg, H.max_pcg);
-  B.max_iters = max_pcg;
+  launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, mixed, s);
   {
     // pdone = !act
     std::vector<int> ha(S);
@@ -1004,8 +1033,15 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     h2d(pdone.p, ha.data(), S);
   }
   zero(iters.p, sizeof(int) * S);
-  launch_pcg_init(V, TN, B, s);
-  run_pcg(V, B, nseg);
+  if (mixed) {
+    const PcgBufsT<float> B = pcg_bufs<float>();
+    launch_pcg_init(V, TN, B, s);
+    run_pcg(V, B, nseg);
+  } else {
+    const PcgBufsT<double> B = pcg_bufs<double>();
+    launch_pcg_init(V, TN, B, s);
+    run_pcg(V, B, nseg);
+  }
   d2h(pcg_it.data(), iters.p, S);
   std::vector<int> hbad(S);
   d2h(hbad.data(), bad.p, S);

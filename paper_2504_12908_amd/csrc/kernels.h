@@ -64,13 +64,13 @@ void launch_compact_pairs(const View& V, int n, const int* cand_q, const int* ca
                           int* pscene, hipStream_t s);
 
 // element derivatives
-void launch_fem_hess(const View& V, hipStream_t s);
+void launch_fem_hess(const View& V, int mixed, hipStream_t s);
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
                          const double* pmeps, double* pg, double* ph, hipStream_t s);
 void launch_body_hess(const View& V, hipStream_t s);
 
 // assembly
-void launch_assemble_bsr(const View& V, int nnz, const int* brow, hipStream_t s);
+void launch_assemble_bsr(const View& V, int nnz, const int* brow, int mixed, hipStream_t s);
 void launch_assemble_grad(const View& V, double* g, hipStream_t s);
 void launch_contrib_count(const View& V, int np, const int* pv, int* hcnt, int* gcnt,
                           hipStream_t s);
@@ -81,29 +81,37 @@ void launch_seg_flags(int n, const uint64_t* keys, int* flags, hipStream_t s);
 void launch_seg_start(int n, const int* flags, const int* segid, int* segstart, hipStream_t s);
 void launch_reduce_blocks(const View& V, int nseg, const uint64_t* keys, const int* idx,
                           const int* segstart, const int* src, const double* coef,
-                          const double* ph, int* drow, int* dcol, double* dval, int* rowcnt,
-                          hipStream_t s);
+                          const double* ph, int* drow, int* dcol, void* dval, int* rowcnt,
+                          int mixed, hipStream_t s);
 void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int* idx,
                         const int* segstart, const int* src, const double* coef,
                         const double* pg, double* g, hipStream_t s);
-void launch_precond(const View& V, const int* drowptr, const int* dcol, const double* dval,
-                    double* pinv, int* bad, hipStream_t s);
+void launch_precond(const View& V, const int* drowptr, const int* dcol, const void* dval,
+                    void* pinv, int* bad, int mixed, hipStream_t s);
 
-// PCG over node-block table T; partial sums per block
-struct PcgBufs {
-  double *g, *r, *z, *p0, *p1, *q, *dx;
-  double* pinv;
+// PCG over the node-block table TN (vector updates) and the row table TS (sparse product);
+// partial sums per block.  T is the arithmetic of the linear solve (double, or float in the
+// mixed-precision mode); the gradient g and the solution dx stay double.
+template <class T>
+struct PcgBufsT {
+  const double* g;
+  T *r, *z, *p0, *p1, *q;
+  double* dx;
+  const T* pinv;
   const int* drowptr;
   const int* dcol;
-  const double* dval;
-  double *P_pq, *P_rz0, *P_rz1, *P_rr, *P_gg;
+  const T* dval;
+  T *P_pq, *P_rz0, *P_rz1, *P_rr, *P_gg;
   int* iters;
   int max_iters;
 };
-void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s);
-void launch_pcg_spmv(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+template <class T>
+void launch_pcg_init(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, hipStream_t s);
+template <class T>
+void launch_pcg_spmv(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                      int parity, hipStream_t s);
-void launch_pcg_update(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+template <class T>
+void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                        int parity, hipStream_t s);
 
 // Process-wide kernel timing with HIP events (off by default).

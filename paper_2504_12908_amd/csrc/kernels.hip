@@ -442,6 +442,7 @@ __global__ void k_compact_pairs(View V, int n, const int* cq, const int* ct, con
 }
 
 // ------------------------------------------------------------------ FEM (4 lanes per tet)
+template <class T>
 __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
   const int g = gid();
   const int t = g >> 2, a = g & 3;
@@ -477,10 +478,10 @@ __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
       for (int j = 0; j < 12; ++j) acc[12 * i + j] += wi * w[j];
     }
   }
-  double* out = V.Hloc + 144 * (size_t)t + 36 * a;
+  T* out = reinterpret_cast<T*>(V.Hloc) + 144 * (size_t)t + 36 * a;
   for (int b = 0; b < 4; ++b)
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) out[9 * b + 3 * i + j] = scale * acc[12 * i + 3 * b + j];
+      for (int j = 0; j < 3; ++j) out[9 * b + 3 * i + j] = (T)(scale * acc[12 * i + 3 * b + j]);
 }
 
 // ------------------------------------------------------------------ wave-parallel Jacobi
@@ -666,25 +667,28 @@ __global__ void k_body_hess(View V) {
 }
 
 // ------------------------------------------------------------------ assembly
+template <class T>
 __global__ void k_assemble_bsr(View V, int nnz, const int* brow) {
   const int k = gid();
   if (k >= nnz) return;
   const int row = brow[k];
   if (!V.act[V.nscene[row]]) return;
-  double acc[9];
-  for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+  T acc[9];
+  for (int i = 0; i < 9; ++i) acc[i] = (T)0;
+  const T* H = reinterpret_cast<const T*>(V.Hloc);
   for (int c = V.cptr[k]; c < V.cptr[k + 1]; ++c) {
     const int code = V.clist[c];
-    const double* blk = V.Hloc + 144 * (size_t)(code >> 4) + 9 * (code & 15);
+    const T* blk = H + 144 * (size_t)(code >> 4) + 9 * (code & 15);
     for (int i = 0; i < 9; ++i) acc[i] += blk[i];
   }
   if (V.col[k] == row && V.ntype[row] == 0) {
-    const double m = V.mass[row];
+    const T m = (T)V.mass[row];
     acc[0] += m;
     acc[4] += m;
     acc[8] += m;
   }
-  for (int i = 0; i < 9; ++i) V.val[9 * (size_t)k + i] = acc[i];
+  T* val = reinterpret_cast<T*>(V.val);
+  for (int i = 0; i < 9; ++i) val[9 * (size_t)k + i] = acc[i];
 }
 
 __global__ void k_assemble_grad(View V, double* g) {
@@ -802,16 +806,17 @@ __global__ void k_seg_start(int n, const int* flags, const int* segid, int* segs
   if (i == n - 1) segstart[segid[i] + flags[i]] = n;
 }
 
+template <class T>
 __global__ void k_reduce_blocks(View V, int nseg, const uint64_t* keys, const int* idx,
                                 const int* segstart, const int* src, const double* coef,
-                                const double* ph, int* drow, int* dcol, double* dval, int* rowcnt) {
+                                const double* ph, int* drow, int* dcol, T* dval, int* rowcnt) {
   const int k = gid();
   if (k >= nseg) return;
   const int i0 = segstart[k], i1 = segstart[k + 1];
   const uint64_t key = keys[i0];
   const int row = (int)(key / (uint64_t)V.Nn), col = (int)(key % (uint64_t)V.Nn);
-  double acc[9];
-  for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+  T acc[9];
+  for (int i = 0; i < 9; ++i) acc[i] = (T)0;
   for (int i = i0; i < i1; ++i) {
     const int c = idx[i];
     const int code = src[c];
@@ -829,7 +834,7 @@ __global__ void k_reduce_blocks(View V, int nseg, const uint64_t* keys, const in
       b = cc & 3;
     }
     for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) acc[3 * r + q] += w * M[12 * (3 * a + r) + 3 * b + q];
+      for (int q = 0; q < 3; ++q) acc[3 * r + q] += (T)(w * M[12 * (3 * a + r) + 3 * b + q]);
   }
   drow[k] = row;
   dcol[k] = col;
@@ -856,39 +861,41 @@ __global__ void k_reduce_grad(View V, int nseg, const uint64_t* keys, const int*
   for (int q = 0; q < 3; ++q) g[3 * node + q] += acc[q];
 }
 
-__global__ void k_precond_soft(View V, const int* drowptr, const int* dcol, const double* dval,
-                               double* pinv, int* bad) {
+template <class T>
+__global__ void k_precond_soft(View V, const int* drowptr, const int* dcol, const T* dval,
+                               T* pinv, int* bad) {
   const int n = gid();
   if (n >= V.Nn) return;
   const int s = V.nscene[n];
   if (!V.act[s]) return;
-  double* out = pinv + 9 * (size_t)n;
+  T* out = pinv + 9 * (size_t)n;
   if (V.ntype[n] != 0 || !V.nfree[n]) {
-    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    for (int i = 0; i < 9; ++i) out[i] = (T)0;
     return;
   }
   double D[9];
-  const double* sd = V.val + 9 * (size_t)V.diag[n];
-  for (int i = 0; i < 9; ++i) D[i] = sd[i];
+  const T* sd = reinterpret_cast<const T*>(V.val) + 9 * (size_t)V.diag[n];
+  for (int i = 0; i < 9; ++i) D[i] = (double)sd[i];
   for (int k = drowptr[n]; k < drowptr[n + 1]; ++k)
     if (dcol[k] == n)
-      for (int i = 0; i < 9; ++i) D[i] += dval[9 * (size_t)k + i];
+      for (int i = 0; i < 9; ++i) D[i] += (double)dval[9 * (size_t)k + i];
   double C[9];
   cofactor3(D, C);
   const double det = D[0] * C[0] + D[1] * C[1] + D[2] * C[2];
   if (!(det > 0.0) || !isfinite(det)) {
     bad[s] = 1;
-    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    for (int i = 0; i < 9; ++i) out[i] = (T)0;
     return;
   }
   // D symmetric: inverse = C^T / det = C / det
-  for (int i = 0; i < 9; ++i) out[i] = C[i] / det;
+  for (int i = 0; i < 9; ++i) out[i] = (T)(C[i] / det);
 }
 
 // Inverse of the 12x12 block of an affine body (its 4 pseudo-nodes) by one wavefront:
 // Gauss-Jordan with partial pivoting on [M | I] held in LDS.
+template <class T>
 __global__ void __launch_bounds__(64) k_precond_body(View V, const int* drowptr, const int* dcol,
-                                                     const double* dval, int* bad) {
+                                                     const T* dval, int* bad) {
   __shared__ double M[12][24];
   __shared__ double f[12];
   __shared__ int piv_s;
@@ -905,7 +912,7 @@ __global__ void __launch_bounds__(64) k_precond_body(View V, const int* drowptr,
       const int w = dcol[k] - n0;
       if (w < 0 || w > 3) continue;
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[3 * u + i][3 * w + j] = dval[9 * (size_t)k + 3 * i + j];
+        for (int j = 0; j < 3; ++j) M[3 * u + i][3 * w + j] = (double)dval[9 * (size_t)k + 3 * i + j];
     }
   }
   __syncthreads();
@@ -939,21 +946,23 @@ __global__ void __launch_bounds__(64) k_precond_body(View V, const int* drowptr,
     }
     __syncthreads();
   }
-  for (int e = lane; e < 144; e += 64) V.bpinv[144 * (size_t)b + e] = M[e / 12][12 + e % 12];
+  T* bpinv = reinterpret_cast<T*>(V.bpinv);
+  for (int e = lane; e < 144; e += 64) bpinv[144 * (size_t)b + e] = (T)M[e / 12][12 + e % 12];
 }
 
 // ------------------------------------------------------------------ PCG
 // z = M^{-1} r for the node n (local index li inside the block; rs stages r in LDS).
-__device__ __forceinline__ void precond_apply(const View& V, const double* pinv, int n, int n0blk,
-                                              const double (*rs)[3], double* z) {
+template <class T>
+__device__ __forceinline__ void precond_apply(const View& V, const T* pinv, int n, int n0blk,
+                                              const T (*rs)[3], T* z) {
   // rs: r of the nodes of this block (a body's 4 pseudo-nodes never straddle blocks)
   const int type = V.ntype[n];
   if (!V.nfree[n]) {
-    z[0] = z[1] = z[2] = 0.0;
+    z[0] = z[1] = z[2] = (T)0;
     return;
   }
   if (type == 0) {
-    const double* P = pinv + 9 * (size_t)n;
+    const T* P = pinv + 9 * (size_t)n;
     const int li = n - n0blk;
     for (int i = 0; i < 3; ++i) z[i] = P[3 * i] * rs[li][0] + P[3 * i + 1] * rs[li][1] + P[3 * i + 2] * rs[li][2];
     return;
@@ -961,9 +970,9 @@ __device__ __forceinline__ void precond_apply(const View& V, const double* pinv,
   const int b = V.nbody[n];
   const int u = n - V.bnode[b];
   const int l0 = V.bnode[b] - n0blk;
-  const double* P = V.bpinv + 144 * b;
+  const T* P = reinterpret_cast<const T*>(V.bpinv) + 144 * b;
   for (int i = 0; i < 3; ++i) {
-    double acc = 0.0;
+    T acc = (T)0;
     for (int w = 0; w < 4; ++w)
       for (int j = 0; j < 3; ++j) acc += P[12 * (3 * u + i) + 3 * w + j] * rs[l0 + w][j];
     z[i] = acc;
@@ -975,15 +984,27 @@ __device__ __forceinline__ void precond_apply(const View& V, const double* pinv,
 constexpr int kWave = 64;
 constexpr int kRowLanes = 16;
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 // Sum of a scene's block partials by one wavefront (fixed assignment and fixed tree).
-__device__ __forceinline__ double scene_sum_wave(const double* P, const int* sblk, int s) {
-  double acc = 0.0;
+template <class T>
+__device__ __forceinline__ T scene_sum_wave(const T* P, const int* sblk, int s) {
+  T acc = (T)0;
   for (int k = sblk[s] + (int)threadIdx.x; k < sblk[s + 1]; k += kWave) acc += P[k];
   return wave_sum(acc);
+}
+template <class T>
+__device__ T block_sum256t(T v, T* lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  const T r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return r;
 }
 
 // Preconditioned CG with two kernels per iteration k (parity = k & 1):
@@ -992,59 +1013,61 @@ __device__ __forceinline__ double scene_sum_wave(const double* P, const int* sbl
 //                   q_k = A p_k with p_k formed on the fly from z and p_{k-1};
 //   k_pcg_update:   alpha_k = rz_k / (p_k . q_k); x += alpha p; r -= alpha q; z = M^{-1} r.
 // p_{-1} = 0 and rz_{-1} = 1 make iteration 0 start with p_0 = z_0.
-__global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable T, PcgBufs B) {
-  __shared__ double rs[kWave][3];
-  const int s = T.sc[blockIdx.x];
+template <class T>
+__global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBufsT<T> B) {
+  __shared__ T rs[kWave][3];
+  const int s = TN.sc[blockIdx.x];
   if (V.pdone[s]) return;
-  const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
+  const int n0 = TN.b0[blockIdx.x], n1 = TN.b1[blockIdx.x];
   const int n = n0 + threadIdx.x;
   const bool live = n < n1;
-  double r[3] = {0, 0, 0};
+  T r[3] = {(T)0, (T)0, (T)0};
   if (live) {
     const bool f = V.nfree[n];
     for (int c = 0; c < 3; ++c) {
-      r[c] = f ? -B.g[3 * n + c] : 0.0;
+      r[c] = f ? (T)(-B.g[3 * n + c]) : (T)0;
       B.r[3 * n + c] = r[c];
       B.dx[3 * n + c] = 0.0;
-      B.p0[3 * n + c] = 0.0;
+      B.p0[3 * n + c] = (T)0;
     }
   }
   for (int c = 0; c < 3; ++c) rs[threadIdx.x][c] = r[c];
   __syncthreads();
-  double z[3] = {0, 0, 0};
+  T z[3] = {(T)0, (T)0, (T)0};
   if (live) {
-    precond_apply(V, B.pinv, n, n0, rs, z);
+    precond_apply<T>(V, B.pinv, n, n0, rs, z);
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
-  const double rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
-  const double rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const T rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
+  const T rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (threadIdx.x == 0) {
     B.P_rz0[blockIdx.x] = rz;
-    B.P_rz1[blockIdx.x] = 1.0;
+    B.P_rz1[blockIdx.x] = (T)1;
     B.P_gg[blockIdx.x] = rr;
     B.P_rr[blockIdx.x] = rr;
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable T, BlockTable TS, PcgBufs B,
+template <class T>
+__global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, BlockTable TS, PcgBufsT<T> B,
                                                       int parity) {
-  __shared__ double red[4];
-  __shared__ double beta_s;
+  __shared__ T red[4];
+  __shared__ T beta_s;
   __shared__ int conv_s;
   const int s = TS.sc[blockIdx.x];
   if (V.pdone[s]) return;
-  const double* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
-  const double* Prz_old = parity ? B.P_rz0 : B.P_rz1;
-  const double* pold = parity ? B.p1 : B.p0;
-  double* pnew = parity ? B.p0 : B.p1;
+  const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
+  const T* Prz_old = parity ? B.P_rz0 : B.P_rz1;
+  const T* pold = parity ? B.p1 : B.p0;
+  T* pnew = parity ? B.p0 : B.p1;
   if (threadIdx.x < kWave) {
-    const double rzc = scene_sum_wave(Prz_cur, T.sblk, s), rzo = scene_sum_wave(Prz_old, T.sblk, s);
-    const double rr = scene_sum_wave(B.P_rr, T.sblk, s), gg = scene_sum_wave(B.P_gg, T.sblk, s);
+    const T rzc = scene_sum_wave(Prz_cur, TN.sblk, s), rzo = scene_sum_wave(Prz_old, TN.sblk, s);
+    const T rr = scene_sum_wave(B.P_rr, TN.sblk, s), gg = scene_sum_wave(B.P_gg, TN.sblk, s);
     if (threadIdx.x == 0) {
-      const double eta = V.sc[s].pcg_eta;
+      const T eta = (T)V.sc[s].pcg_eta;
       // iters[s] is only written by k_pcg_update, so every block sees the same count here
-      conv_s = (rr <= eta * eta * gg) || !(rzc > 0.0) || !(rzo > 0.0) || B.iters[s] >= B.max_iters;
-      beta_s = conv_s ? 0.0 : rzc / rzo;
+      conv_s = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters;
+      beta_s = conv_s ? (T)0 : rzc / rzo;
     }
   }
   __syncthreads();
@@ -1053,29 +1076,29 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable T, Bloc
     if (first && threadIdx.x == 0) V.pdone[s] = 1;
     return;
   }
-  const double beta = beta_s;
+  const T beta = beta_s;
   const int sub = threadIdx.x & (kRowLanes - 1);
   const int row = TS.b0[blockIdx.x] + (int)(threadIdx.x / kRowLanes);
   const bool inrange = row < TS.b1[blockIdx.x];
   const bool live = inrange && V.nfree[row];
-  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  T q0 = (T)0, q1 = (T)0, q2 = (T)0;
   if (live) {
     for (int k = V.rowptr[row] + sub; k < V.rowptr[row + 1]; k += kRowLanes) {
-      const double* A = V.val + 9 * (size_t)k;
+      const T* A = reinterpret_cast<const T*>(V.val) + 9 * (size_t)k;
       const int c = V.col[k];
-      const double p0 = B.z[3 * c] + beta * pold[3 * c];
-      const double p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
-      const double p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
+      const T p0 = B.z[3 * c] + beta * pold[3 * c];
+      const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
+      const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
       q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
       q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
       q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
     }
     for (int k = B.drowptr[row] + sub; k < B.drowptr[row + 1]; k += kRowLanes) {
-      const double* A = B.dval + 9 * (size_t)k;
+      const T* A = B.dval + 9 * (size_t)k;
       const int c = B.dcol[k];
-      const double p0 = B.z[3 * c] + beta * pold[3 * c];
-      const double p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
-      const double p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
+      const T p0 = B.z[3 * c] + beta * pold[3 * c];
+      const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
+      const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
       q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
       q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
       q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
@@ -1086,9 +1109,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable T, Bloc
     q1 += __shfl_xor(q1, off, kRowLanes);
     q2 += __shfl_xor(q2, off, kRowLanes);
   }
-  double pq = 0.0;
+  T pq = (T)0;
   if (inrange && sub == 0) {
-    double pn[3];
+    T pn[3];
     for (int c = 0; c < 3; ++c) {
       pn[c] = B.z[3 * row + c] + beta * pold[3 * row + c];
       pnew[3 * row + c] = pn[c];
@@ -1098,44 +1121,45 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable T, Bloc
     B.q[3 * row + 2] = q2;
     if (live) pq = pn[0] * q0 + pn[1] * q1 + pn[2] * q2;
   }
-  pq = block_sum256(pq, red);
+  pq = block_sum256t(pq, red);
   if (threadIdx.x == 0) B.P_pq[blockIdx.x] = pq;
 }
 
-__global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable T, BlockTable TS,
-                                                      PcgBufs B, int parity) {
-  __shared__ double rs[kWave][3];
-  const int s = T.sc[blockIdx.x];
+template <class T>
+__global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, BlockTable TS,
+                                                      PcgBufsT<T> B, int parity) {
+  __shared__ T rs[kWave][3];
+  const int s = TN.sc[blockIdx.x];
   if (V.pdone[s]) return;
-  const double* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
-  double* Prz_new = parity ? B.P_rz0 : B.P_rz1;
-  const double* pk = parity ? B.p0 : B.p1;
-  const double rzs = scene_sum_wave(Prz_cur, T.sblk, s), pqs = scene_sum_wave(B.P_pq, TS.sblk, s);
-  const double alpha = pqs > 0.0 ? rzs / pqs : 0.0;
-  const int n0 = T.b0[blockIdx.x], n1 = T.b1[blockIdx.x];
+  const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
+  T* Prz_new = parity ? B.P_rz0 : B.P_rz1;
+  const T* pk = parity ? B.p0 : B.p1;
+  const T rzs = scene_sum_wave(Prz_cur, TN.sblk, s), pqs = scene_sum_wave(B.P_pq, TS.sblk, s);
+  const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
+  const int n0 = TN.b0[blockIdx.x], n1 = TN.b1[blockIdx.x];
   const int n = n0 + threadIdx.x;
   const bool live = n < n1;
-  double r[3] = {0, 0, 0};
+  T r[3] = {(T)0, (T)0, (T)0};
   if (live) {
     for (int c = 0; c < 3; ++c) {
-      B.dx[3 * n + c] += alpha * pk[3 * n + c];
+      B.dx[3 * n + c] += (double)(alpha * pk[3 * n + c]);
       r[c] = B.r[3 * n + c] - alpha * B.q[3 * n + c];
       B.r[3 * n + c] = r[c];
     }
   }
   for (int c = 0; c < 3; ++c) rs[threadIdx.x][c] = r[c];
   __syncthreads();
-  double z[3] = {0, 0, 0};
+  T z[3] = {(T)0, (T)0, (T)0};
   if (live) {
-    precond_apply(V, B.pinv, n, n0, rs, z);
+    precond_apply<T>(V, B.pinv, n, n0, rs, z);
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
-  const double rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
-  const double rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const T rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
+  const T rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (threadIdx.x == 0) {
     Prz_new[blockIdx.x] = rz;
     B.P_rr[blockIdx.x] = rr;
-    if ((int)blockIdx.x == T.sblk[s]) ++B.iters[s];
+    if ((int)blockIdx.x == TN.sblk[s]) ++B.iters[s];
   }
 }
 
@@ -1555,14 +1579,18 @@ void launch_compact_pairs(const View& V, int n, const int* cq, const int* ct, co
                           hipStream_t s) {
   LAUNCH(k_compact_pairs, n, TPB, s, V, n, cq, ct, flag, pos, pkind, pv, pmeps, pscene);
 }
-void launch_fem_hess(const View& V, hipStream_t s) { LAUNCH(k_fem_hess, 4 * V.Nt, TPB, s, V); }
+void launch_fem_hess(const View& V, int mixed, hipStream_t s) {
+  if (mixed) LAUNCH(k_fem_hess<float>, 4 * V.Nt, TPB, s, V);
+  else LAUNCH(k_fem_hess<double>, 4 * V.Nt, TPB, s, V);
+}
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
                          const double* pmeps, double* pg, double* ph, hipStream_t s) {
   if (np > 0) hipLaunchKernelGGL(k_barrier_hess, dim3(np), dim3(64), 0, s, V, np, pkind, pv, pmeps, pg, ph);
 }
 void launch_body_hess(const View& V, hipStream_t s) { LAUNCH(k_body_hess, V.Nb, 64, s, V); }
-void launch_assemble_bsr(const View& V, int nnz, const int* brow, hipStream_t s) {
-  LAUNCH(k_assemble_bsr, nnz, TPB, s, V, nnz, brow);
+void launch_assemble_bsr(const View& V, int nnz, const int* brow, int mixed, hipStream_t s) {
+  if (mixed) LAUNCH(k_assemble_bsr<float>, nnz, TPB, s, V, nnz, brow);
+  else LAUNCH(k_assemble_bsr<double>, nnz, TPB, s, V, nnz, brow);
 }
 void launch_assemble_grad(const View& V, double* g, hipStream_t s) {
   LAUNCH(k_assemble_grad, V.Nn, TPB, s, V, g);
@@ -1585,32 +1613,58 @@ void launch_seg_start(int n, const int* flags, const int* segid, int* segstart, 
 }
 void launch_reduce_blocks(const View& V, int nseg, const uint64_t* keys, const int* idx,
                           const int* segstart, const int* src, const double* coef,
-                          const double* ph, int* drow, int* dcol, double* dval, int* rowcnt,
-                          hipStream_t s) {
-  LAUNCH(k_reduce_blocks, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, ph, drow, dcol,
-         dval, rowcnt);
+                          const double* ph, int* drow, int* dcol, void* dval, int* rowcnt,
+                          int mixed, hipStream_t s) {
+  if (mixed)
+    LAUNCH(k_reduce_blocks<float>, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, ph, drow,
+           dcol, static_cast<float*>(dval), rowcnt);
+  else
+    LAUNCH(k_reduce_blocks<double>, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, ph, drow,
+           dcol, static_cast<double*>(dval), rowcnt);
 }
 void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int* idx,
                         const int* segstart, const int* src, const double* coef,
                         const double* pg, double* g, hipStream_t s) {
   LAUNCH(k_reduce_grad, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, pg, g);
 }
-void launch_precond(const View& V, const int* drowptr, const int* dcol, const double* dval,
-                    double* pinv, int* bad, hipStream_t s) {
-  LAUNCH(k_precond_soft, V.Nn, TPB, s, V, drowptr, dcol, dval, pinv, bad);
-  if (V.Nb > 0) hipLaunchKernelGGL(k_precond_body, dim3(V.Nb), dim3(64), 0, s, V, drowptr, dcol, dval, bad);
+void launch_precond(const View& V, const int* drowptr, const int* dcol, const void* dval,
+                    void* pinv, int* bad, int mixed, hipStream_t s) {
+  if (mixed) {
+    LAUNCH(k_precond_soft<float>, V.Nn, TPB, s, V, drowptr, dcol, static_cast<const float*>(dval),
+           static_cast<float*>(pinv), bad);
+    if (V.Nb > 0)
+      hipLaunchKernelGGL(k_precond_body<float>, dim3(V.Nb), dim3(64), 0, s, V, drowptr, dcol,
+                         static_cast<const float*>(dval), bad);
+  } else {
+    LAUNCH(k_precond_soft<double>, V.Nn, TPB, s, V, drowptr, dcol, static_cast<const double*>(dval),
+           static_cast<double*>(pinv), bad);
+    if (V.Nb > 0)
+      hipLaunchKernelGGL(k_precond_body<double>, dim3(V.Nb), dim3(64), 0, s, V, drowptr, dcol,
+                         static_cast<const double*>(dval), bad);
+  }
 }
-void launch_pcg_init(const View& V, const BlockTable& T, const PcgBufs& B, hipStream_t s) {
-  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_init, dim3(T.nblk), dim3(kWave), 0, s, V, T, B);
+template <class T>
+void launch_pcg_init(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, hipStream_t s) {
+  if (TN.nblk > 0) hipLaunchKernelGGL(k_pcg_init<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, B);
 }
-void launch_pcg_spmv(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+template <class T>
+void launch_pcg_spmv(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                      int parity, hipStream_t s) {
-  if (TS.nblk > 0) hipLaunchKernelGGL(k_pcg_dir_spmv, dim3(TS.nblk), dim3(TPB), 0, s, V, T, TS, B, parity);
+  if (TS.nblk > 0)
+    hipLaunchKernelGGL(k_pcg_dir_spmv<T>, dim3(TS.nblk), dim3(TPB), 0, s, V, TN, TS, B, parity);
 }
-void launch_pcg_update(const View& V, const BlockTable& T, const BlockTable& TS, const PcgBufs& B,
+template <class T>
+void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                        int parity, hipStream_t s) {
-  if (T.nblk > 0) hipLaunchKernelGGL(k_pcg_update, dim3(T.nblk), dim3(kWave), 0, s, V, T, TS, B, parity);
+  if (TN.nblk > 0)
+    hipLaunchKernelGGL(k_pcg_update<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, TS, B, parity);
 }
+template void launch_pcg_init<double>(const View&, const BlockTable&, const PcgBufsT<double>&, hipStream_t);
+template void launch_pcg_init<float>(const View&, const BlockTable&, const PcgBufsT<float>&, hipStream_t);
+template void launch_pcg_spmv<double>(const View&, const BlockTable&, const BlockTable&, const PcgBufsT<double>&, int, hipStream_t);
+template void launch_pcg_spmv<float>(const View&, const BlockTable&, const BlockTable&, const PcgBufsT<float>&, int, hipStream_t);
+template void launch_pcg_update<double>(const View&, const BlockTable&, const BlockTable&, const PcgBufsT<double>&, int, hipStream_t);
+template void launch_pcg_update<float>(const View&, const BlockTable&, const BlockTable&, const PcgBufsT<float>&, int, hipStream_t);
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s) {
   LAUNCH(k_pmax, V.Nn + V.Ncv, TPB, s, V, p, pmax);
 }

@@ -172,7 +172,7 @@ class _Desc:
         d.params.max_newton = p.get("max_newton", 100)
         d.params.max_al = p.get("max_al", 30)
         d.params.max_pcg = p.get("max_pcg", 10000)
-        d.params.pcg_eta = p.get("pcg_eta", 1e-4)
+        d.params.pcg_eta = overrides.get("pcg_eta", 0.0) if overrides else 0.0
         d.params.precision = precision
         self.desc = d
         self.nv = len(verts)

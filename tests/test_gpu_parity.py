@@ -185,6 +185,27 @@ def test_c1_step_teacher_forced(T, oracle_lib, seed):
     g.close()
 
 
+@pytest.mark.parametrize("seed", [1])
+def test_c1_mixed_precision_teacher_forced(T, oracle_lib, seed):
+    """Mixed precision (FP32 Hessian/SpMV/PCG, FP64 gradient, contact and CCD): every
+    teacher-forced step within 1e-4 of the pad thickness (4 mm) of the FP64 oracle."""
+    spec = S.pad_press_cube(seed)
+    say(f"mixed precision teacher-forced steps: {spec.name}")
+    o = oracle_lib.OracleScene(spec)
+    g = T.Scene(spec, precision=T.MIXED)
+    tol = 1e-4 * 4e-3
+    for k in range(spec.n_steps):
+        x, v, q, qd = o.get_state()
+        g.set_state(x, v, q, qd)
+        rc_o, _ = o.step(k)
+        rc_g, st_g = g.step(k)
+        assert rc_o == 0 and rc_g == T.OK, (k, T.STATUS_NAMES[rc_g], st_g)
+        err = np.abs(g.read(T.FIELD_X) - o.get_state()[0]).max()
+        say(f"  step {k}: newton {st_g['newton_iters']} pcg {st_g['pcg_iters']} err {err:.3e} (tol {tol:.1e})")
+        assert err <= tol
+    g.close()
+
+
 def test_batch_equals_single(T):
     specs = [S.batch_member(i) for i in range(3)]
     say("batch of 3 vs single scenes, 2 steps")
