@@ -33,7 +33,8 @@ typedef enum {
   TACCEL_NAN = 6,                  /* non-finite gradient or singular preconditioner */
   TACCEL_INFEASIBLE_TARGET = 7,    /* moving Dirichlet targets would collide or invert */
   TACCEL_ERR_OOM = 8,              /* device allocation failed */
-  TACCEL_INFEASIBLE = 9            /* initial state interpenetrates or is inverted */
+  TACCEL_INFEASIBLE = 9,           /* initial state interpenetrates or is inverted */
+  TACCEL_CANCELLED = 10            /* server request dropped by taccel_server_destroy */
 } taccel_status;
 
 typedef enum { TACCEL_FP64 = 0, TACCEL_MIXED = 1 } taccel_precision;
@@ -156,6 +157,69 @@ taccel_status taccel_batch_read(const taccel_batch* b, int32_t scene, taccel_fie
 taccel_status taccel_batch_write(taccel_batch* b, int32_t scene, taccel_field f, const void* src,
                                  size_t bytes);
 void taccel_batch_destroy(taccel_batch* b);
+
+/* ---- Serving: continuous batching of time-step requests -------------------------------
+ * A request is one scene plus a script of n_steps per-step targets (a rollout, e.g. one
+ * tactile press-and-slide episode, Sec. 5).  Requests are admitted in arrival order into
+ * cohorts: a cohort is one resident batch (as taccel_batch_*) with its own stream and host
+ * thread that advances all its unfinished requests by one step per call; a request that
+ * finishes or fails stops being stepped while the others go on, and the cohort's device
+ * memory is released with its last request.  A new cohort is formed whenever requests are
+ * waiting, fewer than max_cohorts run, and the estimated footprint of the requests taken fits
+ * hbm_budget_bytes minus what running cohorts hold, so cohorts formed at different times
+ * run concurrently.  A request's results are bitwise the same as stepping its scene alone
+ * with taccel_step.  All calls are thread-safe. */
+typedef struct {
+  double hbm_budget_bytes; /* device memory the server may hold (> 0) */
+  int32_t max_cohort;      /* requests per cohort (<= 0: 64) */
+  int32_t max_cohorts;     /* cohorts running at once (<= 0: 8) */
+  double coalesce_ms;      /* wait before forming a cohort so near-simultaneous arrivals
+                              share it (<= 0: 1 ms) */
+} taccel_server_params;
+
+typedef struct {
+  uint64_t req_id;
+  int32_t status;      /* OK, or the status of the failing step (the request stops there),
+                          ERR_OOM (can never fit the budget), INFEASIBLE, CANCELLED, ... */
+  int32_t n_steps;     /* steps requested */
+  int32_t steps_done;  /* steps attempted (the last one failed if status != OK) */
+  double wait_ms;      /* submit -> admission into a cohort */
+  double run_ms;       /* admission -> completion */
+  double mean_step_ms; /* per-step latency of the cohort calls that stepped this request */
+  double max_step_ms;
+} taccel_completion;
+
+typedef struct taccel_server taccel_server;
+
+/* rt (nullable): alloc/free/ctx apply to every cohort; rt->stream is ignored (each cohort
+ * creates its own).  Errors: ARG. */
+taccel_status taccel_server_create(const taccel_server_params* p, const taccel_runtime* rt,
+                                   taccel_server** out);
+/* Queue a request; d and per_step ([n_steps], NULL if nothing is prescribed) are copied.
+ * The scene is checked on the host now (ARG and its message, nothing queued); checks that
+ * need the device (INFEASIBLE) are reported through its completion. */
+taccel_status taccel_server_submit(taccel_server* s, const taccel_scene_desc* d, int32_t n_steps,
+                                   const taccel_targets* per_step, uint64_t* req_id);
+/* Move up to cap completions (in completion order) into out, waiting up to wait_ms for the
+ * first one if none is ready; *n = number written. */
+taccel_status taccel_server_poll(taccel_server* s, taccel_completion* out, int32_t cap, int32_t* n,
+                                 int32_t wait_ms);
+/* Final state of a completed request: fields X, V, Q, QDOT as taccel_state_read (after the
+ * last successful step).  ARG if unknown, unfinished or released, or on a size mismatch. */
+taccel_status taccel_server_read(taccel_server* s, uint64_t req_id, taccel_field f, void* dst,
+                                 size_t bytes);
+/* Wall time of each step call of a completed request: up to cap values, *n = steps. */
+taccel_status taccel_server_step_latencies(taccel_server* s, uint64_t req_id, double* out,
+                                           int32_t cap, int32_t* n);
+/* Forget a completed request (its final state and latencies). */
+taccel_status taccel_server_release(taccel_server* s, uint64_t req_id);
+/* Requests waiting for admission, cohorts running, device bytes held by running cohorts and
+ * the peak of that figure (any pointer may be NULL). */
+taccel_status taccel_server_info(taccel_server* s, int32_t* queued, int32_t* running_cohorts,
+                                 double* used_bytes, double* peak_bytes);
+/* Cancel queued requests, stop running cohorts after their current step (their requests
+ * complete as CANCELLED), wait for all threads and free everything. */
+void taccel_server_destroy(taccel_server* s);
 
 /* Thread-local text of the last error of this thread (empty if none). */
 const char* taccel_last_error(void);

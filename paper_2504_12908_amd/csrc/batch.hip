@@ -196,6 +196,8 @@ struct Batch::Impl {
   bool cover_valid = false;
   int n_cover = 0;
   bool device_touched = false;
+  bool xn_valid = false;
+  bool validate_only = false;  // build() stops after the host-side checks  // xn holds the positions at the start of the current step
   int mixed = 0;  // 1: FP32 Hessian blocks, assembly, SpMV and PCG (taccel_precision MIXED)
   // dynamic work buffers
   BroadPhase bp;
@@ -286,7 +288,9 @@ struct Batch::Impl {
   int broad_phase(const double* P0, const double* P1, int all, DBuf<int>& oq, DBuf<int>& ot);
   void newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail, std::vector<int>& nan_,
                         std::vector<int>& pcg_it, std::vector<int>& n_active, std::vector<int>& halvings);
-  taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st);
+  taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st,
+                     const int* mask);
+  size_t device_bytes() const;
   void release_all();
 };
 
@@ -669,6 +673,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     for (int k = 0; k < 9; ++k) h_Dminv[(size_t)k * Nt + t] = h_Dminv_aos[9 * (size_t)t + k];
   }
   // ---- upload (everything above is host-side validation and setup)
+  if (validate_only) return;
   if (!mem.stream) {
     // a stream of our own (default priority): the PCG chunks are captured into a graph,
     // which the null stream does not allow
@@ -1157,16 +1162,21 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
 }
 
 taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
-                                taccel_step_stats* stats) {
+                                taccel_step_stats* stats, const int* mask) {
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = stream();
   View V = view();
   // ---- targets: body y* (host conversion of the public affine maps), moving vertices
   std::vector<double> hstar(12 * (size_t)Nb, 0.0);
   std::vector<double> hmove;
+  std::vector<int> hmove_nodes;
   int bglob = 0;
   for (int k = 0; k < S; ++k) {
     const HostScene& H = hs[k];
+    if (mask && !mask[k]) {  // scene not stepped this call
+      bglob += H.nb;
+      continue;
+    }
     for (int b = 0; b < H.nb; ++b, ++bglob) {
       const HostBody& hb = H.bodies[b];
       if (!hb.prescribed) continue;
@@ -1187,23 +1197,27 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       if (!tg || !tg[k].dirichlet_targets)
         throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(k) + " has moving vertices but no dirichlet_targets");
       for (int i = 0; i < 3 * H.n_moving; ++i) hmove.push_back(tg[k].dirichlet_targets[i]);
+      for (int v : H.moving) hmove_nodes.push_back(H.node0 + v);
     }
   }
+  xn_valid = false;
   h2d(bstar.p, hstar.data(), hstar.size());
   launch_predict(V, s);
+  xn_valid = true;
   std::vector<int> infeasible_target(S, 0);
-  if (!h_moving_nodes.empty()) {
-    mv_nodes.upload(&mem, h_moving_nodes);
+  if (!hmove_nodes.empty()) {
+    mv_nodes.upload(&mem, hmove_nodes);
     mv_tgt.upload(&mem, hmove);
     // The prescribed vertices jump to their targets; the jump must be collision-free and
     // keep every tet positive (INFEASIBLE_TARGET otherwise).  Positions after the jump are
     // staged in r (free at this point).
     HIPCHECK(hipMemcpyAsync(r.p, x.p, sizeof(double) * 3 * (size_t)Nn, hipMemcpyDeviceToDevice, s));
-    launch_set_moving(r.p, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
+    launch_set_moving(r.p, (int)hmove_nodes.size(), mv_nodes.p, mv_tgt.p, s);
     launch_cpos(V, s);
     launch_cmap(V, r.p, cend.p, s);
     launch_diff3(3 * Ncv, cend.p, cpos.p, cdisp.p, s);
     std::vector<int> all_on(S, 1);
+    for (int k = 0; k < S; ++k) all_on[k] = (!mask || mask[k]) && hs[k].n_moving > 0;
     h2d(act.p, all_on.data(), S);
     const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
     unsigned long long* amin = u64s.p + S;
@@ -1228,7 +1242,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       std::memcpy(&a, &ha[k], sizeof(double));
       infeasible_target[k] = hs[k].n_moving > 0 && (a < 1.0 || hb[k]);
     }
-    launch_set_moving(x.p, (int)h_moving_nodes.size(), mv_nodes.p, mv_tgt.p, s);
+    launch_set_moving(x.p, (int)hmove_nodes.size(), mv_nodes.p, mv_tgt.p, s);
   }
   launch_body_reset(V, 1e6, s);
   cover_valid = false;
@@ -1249,11 +1263,13 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   // ---- per-scene state machine
   enum { kNewton = 0, kDone = 1, kFailed = 2 };
   std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
-  for (int k = 0; k < S; ++k)
+  for (int k = 0; k < S; ++k) {
     if (infeasible_target[k]) {
       phase[k] = kFailed;
       status[k] = TACCEL_INFEASIBLE_TARGET;
     }
+    if (mask && !mask[k]) phase[k] = kDone;
+  }
   std::vector<int> tot_pcg(S, 0), nact_last(S, 0), tot_halv(S, 0);
   std::vector<int> last(S), lsf(S), nanf(S), pcg_it(S), nact(S), halv(S);
   std::vector<int> hact(S);
@@ -1368,8 +1384,9 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   // ---- finish: velocities for converged scenes, roll back failed ones
   std::vector<int> ok(S), failed(S);
   for (int k = 0; k < S; ++k) {
-    ok[k] = status[k] == TACCEL_OK;
-    failed[k] = !ok[k];
+    const bool stepped = !mask || mask[k];
+    ok[k] = stepped && status[k] == TACCEL_OK;
+    failed[k] = stepped && status[k] != TACCEL_OK;
   }
   h2d(okflag.p, ok.data(), S);
   h2d(failflag.p, failed.data(), S);
@@ -1392,6 +1409,25 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
     if (status[k] != TACCEL_OK && first_bad == TACCEL_OK) first_bad = (taccel_status)status[k];
   }
   return first_bad;
+}
+
+size_t Batch::Impl::device_bytes() const {
+  size_t n = 0;
+  auto add = [&](const auto& buf) { n += buf.cap * sizeof(*buf.p); };
+  add(x); add(xn); add(xhat); add(v); add(mass); add(Dminv); add(tvol); add(Hloc); add(gloc); add(val);
+  add(bmass); add(bvol); add(bstar); add(blam); add(bkap); add(bgrad); add(bhess); add(bpinv); add(cvx);
+  add(cpos); add(cdisp); add(cend); add(elen2); add(bp_tbox); add(pmeps); add(pg); add(ph); add(hcoef);
+  add(gcoef); add(dval); add(g); add(r); add(z); add(p); add(p1); add(q); add(dx); add(pinv);
+  add(nfree); add(nscene); add(nbody); add(ntype); add(tv); add(tscene); add(rowptr); add(col);
+  add(diag); add(cptr); add(clist); add(vptr); add(vlist); add(brow); add(cvn); add(cvb); add(cvfix);
+  add(cvscene); add(cvworld); add(trv); add(edv); add(qkind); add(qidx); add(qscene); add(bp_tcell);
+  add(bp_tncell); add(bp_toff); add(bp_bcount); add(bp_bstart); add(bp_bfill); add(bp_qcount);
+  add(bp_qoff); add(bp_entries); add(cq); add(ct); add(sq); add(st); add(cflag); add(cpos_idx);
+  add(pkind); add(pv); add(pscene); add(hcnt); add(gcnt); add(hoff); add(goff); add(hidx); add(gidx);
+  add(hsrc); add(gsrc); add(hidx2); add(gidx2); add(hkey); add(gkey); add(hkey2); add(gkey2);
+  add(sflag); add(segid); add(segstart); add(drow); add(dcol); add(rowcnt); add(drowptr); add(scratch);
+  add(e_pairs); add(part_nodes); add(part_tets);
+  return n;
 }
 
 void Batch::Impl::release_all() {
@@ -1419,6 +1455,18 @@ taccel_status Batch::create(const taccel_scene_desc* d, int n, const taccel_runt
     return st;
   }
   *out = b;
+  return TACCEL_OK;
+}
+
+taccel_status Batch::validate(const taccel_scene_desc* d, int n, std::string& err) {
+  Impl I;
+  I.validate_only = true;
+  try {
+    I.build(d, n);
+  } catch (const ApiError& e) {
+    err = e.what();
+    return e.st;
+  }
   return TACCEL_OK;
 }
 
@@ -1466,16 +1514,19 @@ Batch::~Batch() {
   delete impl_;
 }
 
-taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st) {
+taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st,
+                          const int* mask) {
   try {
-    return impl_->step(t, per_scene, st);
+    return impl_->step(t, per_scene, st, mask);
   } catch (const ApiError& e) {
     set_last_error(e.what());
     // roll every scene back to the start of the step (positions saved by the predictor)
     Impl& I = *impl_;
+    // (when the error came before the predictor, nothing has been moved yet)
     (void)hipStreamSynchronize(I.mem.stream);
-    (void)hipMemcpyAsync(I.x.p, I.xn.p, sizeof(double) * 3 * (size_t)I.Nn, hipMemcpyDeviceToDevice,
-                         I.mem.stream);
+    if (I.xn_valid)
+      (void)hipMemcpyAsync(I.x.p, I.xn.p, sizeof(double) * 3 * (size_t)I.Nn, hipMemcpyDeviceToDevice,
+                           I.mem.stream);
     (void)hipStreamSynchronize(I.mem.stream);
     if (per_scene)
       for (int k = 0; k < S_; ++k) per_scene[k] = e.st;
@@ -1590,6 +1641,8 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
     return e.st;
   }
 }
+
+size_t Batch::device_bytes() const { return impl_->device_bytes(); }
 
 taccel_status Batch::debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
                                       int32_t* n) {

@@ -71,6 +71,7 @@ const char* taccel_status_str(taccel_status s) {
     case TACCEL_INFEASIBLE_TARGET: return "INFEASIBLE_TARGET";
     case TACCEL_ERR_OOM: return "ERR_OOM";
     case TACCEL_INFEASIBLE: return "INFEASIBLE";
+    case TACCEL_CANCELLED: return "CANCELLED";
   }
   return "UNKNOWN";
 }

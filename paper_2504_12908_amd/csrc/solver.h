@@ -91,8 +91,13 @@ class Batch {
  public:
   static taccel_status create(const taccel_scene_desc* d, int n, const taccel_runtime* rt,
                               Batch** out, std::string& err);
+  // host-side checks of create() only (no device call)
+  static taccel_status validate(const taccel_scene_desc* d, int n, std::string& err);
   ~Batch();
-  taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st);
+  // mask (nullable): scenes with mask[k] == 0 are left untouched by this call
+  taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st,
+                     const int* mask = nullptr);
+  size_t device_bytes() const;
   taccel_status read(int scene, taccel_field f, void* dst, size_t bytes);
   taccel_status write(int scene, taccel_field f, const void* src, size_t bytes);
   taccel_status debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,

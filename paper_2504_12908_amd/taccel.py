@@ -18,11 +18,11 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
 OK, ERR_ARG, ERR_HIP, NOT_CONVERGED, LINESEARCH_FAILED, AL_FAILED, NAN, INFEASIBLE_TARGET, \
-    ERR_OOM, INFEASIBLE = range(10)
+    ERR_OOM, INFEASIBLE, CANCELLED = range(11)
 FP64, MIXED = 0, 1
 FIELD_X, FIELD_V, FIELD_Q, FIELD_QDOT, FIELD_BODY_X = range(5)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_HIP", "NOT_CONVERGED", "LINESEARCH_FAILED", "AL_FAILED",
-                "NAN", "INFEASIBLE_TARGET", "ERR_OOM", "INFEASIBLE"]
+                "NAN", "INFEASIBLE_TARGET", "ERR_OOM", "INFEASIBLE", "CANCELLED"]
 
 
 class taccel_soft_desc(C.Structure):
@@ -69,6 +69,20 @@ class taccel_step_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class taccel_server_params(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_double), ("max_cohort", C.c_int32),
+                ("max_cohorts", C.c_int32), ("coalesce_ms", C.c_double)]
+
+
+class taccel_completion(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("status", C.c_int32), ("n_steps", C.c_int32),
+                ("steps_done", C.c_int32), ("wait_ms", C.c_double), ("run_ms", C.c_double),
+                ("mean_step_ms", C.c_double), ("max_step_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -103,6 +117,17 @@ def lib():
         L.taccel_debug_ccd.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_int32, _dp]
         L.taccel_debug_arap.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.taccel_debug_candidates.argtypes = [C.c_void_p, _dp, _dp, _ip, C.c_int32, _ip]
+        L.taccel_server_create.argtypes = [C.POINTER(taccel_server_params),
+                                           C.POINTER(taccel_runtime), C.POINTER(C.c_void_p)]
+        L.taccel_server_submit.argtypes = [C.c_void_p, C.POINTER(taccel_scene_desc), C.c_int32,
+                                           C.POINTER(taccel_targets), C.POINTER(C.c_uint64)]
+        L.taccel_server_poll.argtypes = [C.c_void_p, C.POINTER(taccel_completion), C.c_int32,
+                                         _ip, C.c_int32]
+        L.taccel_server_read.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.c_size_t]
+        L.taccel_server_step_latencies.argtypes = [C.c_void_p, C.c_uint64, _dp, C.c_int32, _ip]
+        L.taccel_server_release.argtypes = [C.c_void_p, C.c_uint64]
+        L.taccel_server_info.argtypes = [C.c_void_p, _ip, _ip, _dp, _dp]
+        L.taccel_server_destroy.argtypes = [C.c_void_p]
         L.taccel_profile_enable.argtypes = [C.c_int32]
         L.taccel_profile_query.argtypes = [C.c_char_p, _dp, C.POINTER(C.c_int64), _dp]
         _lib = L
@@ -113,7 +138,7 @@ class TaccelError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
         msg = lib().taccel_last_error().decode()
-        super().__init__(f"{where}: {STATUS_NAMES[status] if 0 <= status < 10 else status}: {msg}")
+        super().__init__(f"{where}: {STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
 
 
 def _check(status, where):
@@ -308,6 +333,70 @@ class Batch:
     def write(self, i, field, arr):
         a = _f64(arr)
         _check(lib().taccel_batch_write(self.h, i, field, a.ctypes.data, a.nbytes), "batch_write")
+
+
+class Server:
+    """Continuous-batching server of rollout requests (taccel_server_*)."""
+
+    def __init__(self, hbm_budget_bytes, max_cohort=64, max_cohorts=8, coalesce_ms=1.0):
+        p = taccel_server_params(float(hbm_budget_bytes), int(max_cohort), int(max_cohorts),
+                                 float(coalesce_ms))
+        h = C.c_void_p()
+        _check(lib().taccel_server_create(C.byref(p), None, C.byref(h)), "taccel_server_create")
+        self.h = h
+        self._desc = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().taccel_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def submit(self, spec, n_steps=None, first_step=0, precision=FP64, **overrides):
+        """Queue steps first_step .. first_step + n_steps - 1 of spec's target script."""
+        n_steps = spec.n_steps - first_step if n_steps is None else n_steps
+        d = _Desc(spec, precision, overrides)
+        ts = [_Targets(spec, first_step + k) for k in range(n_steps)]
+        arr = (taccel_targets * n_steps)(*[t.t for t in ts])
+        rid = C.c_uint64()
+        _check(lib().taccel_server_submit(self.h, C.byref(d.desc), n_steps, arr, C.byref(rid)),
+               "taccel_server_submit")
+        self._desc[rid.value] = d
+        return rid.value
+
+    def poll(self, cap=64, wait_ms=0):
+        out = (taccel_completion * cap)()
+        n = C.c_int32()
+        _check(lib().taccel_server_poll(self.h, out, cap, C.byref(n), int(wait_ms)), "server_poll")
+        return [out[i].as_dict() for i in range(n.value)]
+
+    def read(self, rid, field):
+        out = np.zeros(_field_shape(self._desc[rid], field))
+        _check(lib().taccel_server_read(self.h, rid, field, out.ctypes.data, out.nbytes),
+               "server_read")
+        return out
+
+    def step_latencies(self, rid):
+        n = C.c_int32()
+        _check(lib().taccel_server_step_latencies(self.h, rid, None, 0, C.byref(n)),
+               "server_step_latencies")
+        out = np.zeros(max(n.value, 1))
+        _check(lib().taccel_server_step_latencies(self.h, rid, _d(out), n.value, C.byref(n)),
+               "server_step_latencies")
+        return out[:n.value]
+
+    def release(self, rid):
+        _check(lib().taccel_server_release(self.h, rid), "server_release")
+        self._desc.pop(rid, None)
+
+    def info(self):
+        q, c = C.c_int32(), C.c_int32()
+        u, pk = C.c_double(), C.c_double()
+        _check(lib().taccel_server_info(self.h, C.byref(q), C.byref(c), C.byref(u), C.byref(pk)),
+               "server_info")
+        return dict(queued=q.value, running_cohorts=c.value, used_bytes=u.value,
+                    peak_bytes=pk.value)
 
 
 # ------------------------------------------------------------------ measurement

@@ -115,3 +115,27 @@ def test_rejects_body_triangle_index():
     def m(s):
         s.bodies[0].tris[2, 1] = 99
     _expect_arg_error(T, _bad_spec(m), "body triangle index out of range")
+
+
+# ---------------------------------------------------------------- serving, host side only
+def test_server_rejects_bad_params():
+    T = _lib_or_skip()
+    with pytest.raises(T.TaccelError) as ei:
+        T.Server(hbm_budget_bytes=0.0)
+    assert ei.value.status == T.ERR_ARG
+
+
+def test_server_submit_validates_on_host():
+    # the scene is checked before it is queued: nothing reaches the device
+    T = _lib_or_skip()
+    srv = T.Server(hbm_budget_bytes=1e9)
+
+    def m(s):
+        s.tets[5, 1], s.tets[5, 2] = s.tets[5, 2], s.tets[5, 1]
+    with pytest.raises(T.TaccelError) as ei:
+        srv.submit(_bad_spec(m), 3)
+    assert ei.value.status == T.ERR_ARG
+    assert "inverted or degenerate tet 5" in str(ei.value)
+    assert srv.info()["queued"] == 0
+    assert srv.poll(wait_ms=0) == []
+    srv.close()
