@@ -45,26 +45,25 @@ def cpu_baseline(spec, k_warm, k_timed):
                        f"{k_warm} warm-up step(s); one scene on one host core; {dt:.1f} s")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (scenes shard across GPUs without "
-              "communication; no multi-GPU run is part of it)", file=sys.stderr)
-        sys.exit(1)
-    import numpy as np
+def _spmv_roofline(taccel):
+    prof = taccel.profile_query("spmv")
+    n_l = max(prof["launches"], 1)
+    avg_ms = prof["total_ms"] / n_l
+    bytes_per_launch = prof["bytes"] / n_l
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return dict(bound="hbm", kernel="k_pcg_dir_spmv", achieved=achieved, peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                launches=prof["launches"], avg_launch_us=avg_ms * 1e3,
+                algorithmic_bytes_per_launch=bytes_per_launch)
 
-    from paper_2504_12908_amd import scenes, taccel
 
+def run_single(args, taccel, scenes, np):
     spec = scenes.pad_press_slide_hull(0)
     W, K = args.warmup, args.steps
     if W + K > spec.n_steps:
         sys.exit(f"warmup + steps must be <= {spec.n_steps}")
-    sc = taccel.Scene(spec)
+    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    sc = taccel.Scene(spec, precision=prec)
     for k in range(W):
         rc, st = sc.step(k)
         print(f"warmup step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
@@ -90,32 +89,160 @@ def main():
     taccel.device_synchronize()
     dt = time.perf_counter() - t0
     taccel.profile_enable(False)
-    prof = taccel.profile_query("spmv")
-    n_l = max(prof["launches"], 1)
-    avg_ms = prof["total_ms"] / n_l
-    bytes_per_launch = prof["bytes"] / n_l
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     out = dict(
         metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64", data="synthetic",
+        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
         config=dict(workload="gel pad 32x24x6 grid (5775 verts, 27648 tets) pressed and slid "
-                             "by a 400-point convex hull (796 tris), 1 scene, FP64",
+                             "by a 400-point convex hull (796 tris), 1 scene",
                     scenes=1, h=spec.params["h"], step_range=[W, W + K - 1],
-                    precision="fp64"),
+                    precision=args.precision),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         newton_iters_per_step=float(np.mean([s["newton_iters"] for s in stats])),
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
-        roofline=dict(bound="hbm", kernel="k_pcg_dir_spmv", achieved=achieved, peak=HBM_PEAK_GBS,
-                      unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
-                      launches=prof["launches"], avg_launch_us=avg_ms * 1e3,
-                      algorithmic_bytes_per_launch=bytes_per_launch),
+        roofline=_spmv_roofline(taccel),
     )
+    sc.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, 1, 1)
         v = out["cpu_baseline"]["value"]
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / v if v > 0 else None
-    sc.close()
+    return out
+
+
+def run_batch(args, taccel, scenes, np):
+    """Uniform batch: n copies of the small pad with seeded hull indenters, one launch per
+    stage over all scenes."""
+    n = args.scenes
+    specs = scenes.uniform_batch(n)
+    W, K = args.warmup, args.steps
+    if W + K > specs[0].n_steps:
+        sys.exit(f"warmup + steps must be <= {specs[0].n_steps}")
+    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    b = taccel.Batch(specs, precision=prec)
+    for k in range(W):
+        rc, per, st = b.step(k)
+        print(f"warmup step {k}: rc={taccel.STATUS_NAMES[rc]} {st[0]['step_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    taccel.device_synchronize()
+    taccel.profile_reset()
+    taccel.profile_enable(True)
+    lat, ok, newton = [], 0, []
+    t0 = time.perf_counter()
+    for k in range(W, W + K):
+        ts = time.perf_counter()
+        rc, per, st = b.step(k)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        ok += int((per == taccel.OK).sum())
+        newton.append(max(s["newton_iters"] for s in st))
+        print(f"step {k}: ok={int((per == taccel.OK).sum())}/{n} max_newton={newton[-1]} "
+              f"{lat[-1]:.1f} ms", file=sys.stderr, flush=True)
+    taccel.device_synchronize()
+    dt = time.perf_counter() - t0
+    taccel.profile_enable(False)
+    out = dict(
+        metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
+        ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        config=dict(workload=f"uniform batch of {n} small pads (243 verts, 768 tets) with "
+                             "8-point hull indenters, pressed over 10 steps",
+                    scenes=n, precision=args.precision, step_range=[W, W + K - 1]),
+        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+        roofline=_spmv_roofline(taccel),
+    )
+    b.close()
+    return out
+
+
+def run_serving(args, taccel, scenes, np):
+    """Serving stream: Poisson arrivals, each request a 50-step rollout of a pad of random
+    resolution with 1-3 hull indenters; continuous batching under an HBM budget."""
+    import threading
+
+    arrivals = scenes.serving_arrivals(args.rate, args.duration)
+    print(f"generating {len(arrivals)} requests", file=sys.stderr, flush=True)
+    reqs = [scenes.serving_request(i) for i in range(len(arrivals))]
+    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    srv = taccel.Server(hbm_budget_bytes=args.budget_gb * 1e9, max_cohort=args.max_cohort,
+                        max_cohorts=args.max_cohorts, coalesce_ms=2.0)
+    ids = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def feeder():
+        for i, (ta, sp) in enumerate(zip(arrivals, reqs)):
+            delay = ta - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = srv.submit(sp, precision=prec)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    done = {}
+    last_print = time.perf_counter()
+    while len(done) < len(reqs):
+        for c in srv.poll(cap=256, wait_ms=100):
+            done[c["req_id"]] = c
+        if time.perf_counter() - last_print > 5:
+            inf = srv.info()
+            print(f"{time.perf_counter() - t0:.1f} s: {len(done)}/{len(reqs)} done, "
+                  f"queued {inf['queued']}, cohorts {inf['running_cohorts']}, "
+                  f"{inf['used_bytes'] / 1e9:.2f} GB", file=sys.stderr, flush=True)
+            last_print = time.perf_counter()
+    dt = time.perf_counter() - t0
+    th.join()
+    ok_steps = 0
+    lat = []
+    n_ok = 0
+    for rid in ids:
+        c = done[rid]
+        good = c["steps_done"] - (0 if c["status"] == taccel.OK else 1)
+        ok_steps += good
+        n_ok += c["status"] == taccel.OK
+        lat.extend(srv.step_latencies(rid).tolist())
+    info = srv.info()
+    srv.close()
+    waits = [done[r]["wait_ms"] for r in ids]
+    return dict(
+        metric=METRIC, value=ok_steps / dt, unit="env-steps/s", n_gpus=1, steps=len(reqs),
+        warmup=0, ms_per_step=float(np.mean(lat)), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        config=dict(workload=f"serving stream: Poisson {args.rate}/s for {args.duration} s, "
+                             "50-step rollouts of pads {16x12x4, 32x24x6, 48x36x8} with 1-3 "
+                             "hull indenters of 200-8000 tris",
+                    requests=len(reqs), budget_gb=args.budget_gb, precision=args.precision,
+                    max_cohort=args.max_cohort, max_cohorts=args.max_cohorts),
+        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+        requests_ok=n_ok, wall_s=dt, peak_device_gb=info["peak_bytes"] / 1e9,
+        wait_p50_ms=float(np.percentile(waits, 50)), wait_p99_ms=float(np.percentile(waits, 99)),
+        roofline=None,
+    )
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["single", "batch", "serving"], default="single")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--scenes", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--duration", type=float, default=1.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-cohort", type=int, default=64)
+    ap.add_argument("--max-cohorts", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (scenes shard across GPUs without "
+              "communication; no multi-GPU run is part of it)", file=sys.stderr)
+        sys.exit(1)
+    import numpy as np
+
+    from paper_2504_12908_amd import scenes, taccel
+
+    run = dict(single=run_single, batch=run_batch, serving=run_serving)[args.workload]
+    out = run(args, taccel, scenes, np)
     print(json.dumps(out), flush=True)
 
 

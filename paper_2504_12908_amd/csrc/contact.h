@@ -239,96 +239,184 @@ TC_HD void barrier_d(double d, double dhat, double* b, double* b1, double* b2) {
   *b2 = -2.0 * L - 4.0 * t / d + t * t / (d * d);
 }
 
-// Energy kappa * m * b(d) of one pair with its 12-gradient and (unprojected) 12x12 Hessian,
-// the Hessian written at H[(i*12+j)*stride].  Returns the distance type; *e = +inf when
-// s <= 0 and 0 (with zero derivatives) when d >= dhat.  work: kBarrierWork doubles of
-// scratch (on the GPU a slice of LDS, so the temporaries never go to private memory).
-constexpr int kBarrierWork = 160;
-TC_HD int barrier_pair(int kind, const double* x12, double meps, double dhat, double kappa,
-                       double* e, double* g12, double* H, int stride, double* work) {
-  const int type = classify(kind, x12);
-  const DistForm f = dist_form(kind, type);
-  for (int k = 0; k < 12; ++k) g12[k] = 0.0;
-  for (int k = 0; k < 144; ++k) H[k * stride] = 0.0;
-  double* gr = work;         // 9
-  double* Hr = work + 9;     // 81
-  double* gc12 = work + 90;  // 12
-  double* Hc = work + 102;   // 36
-  double* gs = work + 138;   // 12
-  const double s = sqdist_reduced(f, x12, gr, Hr);
-  if (!(s > 0.0)) { *e = INFINITY; return type; }
+// Entry (i, j) of the Hessian of |u x v|^2 in (u, v); bu, bv pick the blocks (0: u, 1: v).
+TC_HD double cross_sq_hess(const d3& u, const d3& v, int bu, int bv, int i, int j) {
+  const double dij = i == j ? 1.0 : 0.0;
+  if (bu == 0 && bv == 0) return 2.0 * (dot(v, v) * dij - at(v, i) * at(v, j));
+  if (bu == 1 && bv == 1) return 2.0 * (dot(u, u) * dij - at(u, i) * at(u, j));
+  if (bu == 1) {  // (v, u) block is the transpose of the (u, v) block
+    const int t = i; i = j; j = t;
+  }
+  return 4.0 * at(u, i) * at(v, j) - 2.0 * dot(u, v) * dij - 2.0 * at(v, i) * at(u, j);
+}
+
+// ([v]x)_ij, the cross-product matrix of v.
+TC_HD double skew_entry(const d3& v, int i, int j) {
+  if (i == j) return 0.0;
+  const int k = 3 - i - j;
+  const double sg = ((j - i + 3) % 3 == 1) ? -1.0 : 1.0;
+  return sg * at(v, k);
+}
+
+// Everything one pair's barrier derivatives need besides per-entry arithmetic: the distance
+// type, the reduced vectors and their first derivatives, and the chain-rule coefficients.
+// Every lane of a wavefront evaluates it (it is a few hundred flops), then each lane forms
+// its own Hessian entries with barrier_hess_entry.
+struct BarrierCore {
+  int kind, type, regime;  // regime 0: 0 < d < dhat; 1: s <= 0 (e = +inf); 2: d >= dhat (0)
+  DistForm f;
+  double e;         // kappa m b(d)
+  double cs;        // kappa m b'(d) / (2d)           (multiplies Hess s)
+  double cr;        // kappa m (b'' - b'/d) / (4s)    (multiplies grad s grad s^T)
+  double cc;        // kappa m' b                     (multiplies Hess c)
+  double cx;        // kappa m' b'(d) / (2d)          (grad s grad c^T + grad c grad s^T)
+  double cm;        // kappa m'' b                    (grad c grad c^T)
+  d3 r, e1, e2;     // reduced vectors
+  d3 u, v;          // edge vectors (EE mollifier)
+  double iB, A2, gA[6];         // nred 2: s = A2 iB, A2 = |r x e1|^2, B = |e1|^2
+  double q, iN, gq[9], gN[9];   // nred 3: s = q^2 iN, q = r.(e1 x e2), N = |e1 x e2|^2
+  double gs[12], gc12[12];      // grad s, grad c in the 12 local coordinates
+};
+
+TC_HD void barrier_core(int kind, const double* x12, double meps, double dhat, double kappa,
+                        BarrierCore& B) {
+  B.kind = kind;
+  B.type = classify(kind, x12);
+  const DistForm& f = B.f = dist_form(kind, B.type);
+  B.r = reduced(f, 0, x12);
+  B.e1 = f.nred > 1 ? reduced(f, 1, x12) : mk(0, 0, 0);
+  B.e2 = f.nred > 2 ? reduced(f, 2, x12) : mk(0, 0, 0);
+  double gr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double s;
+  if (f.nred == 1) {
+    st(gr, 2.0 * B.r);
+    s = dot(B.r, B.r);
+  } else if (f.nred == 2) {
+    double HA[36];
+    B.A2 = cross_sq(B.r, B.e1, B.gA, HA);
+    B.iB = 1.0 / dot(B.e1, B.e1);
+    const double gB[6] = {0, 0, 0, 2 * B.e1.x, 2 * B.e1.y, 2 * B.e1.z};
+    for (int k = 0; k < 6; ++k) gr[k] = B.gA[k] * B.iB - B.A2 * gB[k] * B.iB * B.iB;
+    s = B.A2 * B.iB;
+  } else {
+    const d3 n = cross(B.e1, B.e2);
+    B.q = dot(B.r, n);
+    st(B.gq, n);
+    st(B.gq + 3, cross(B.e2, B.r));
+    st(B.gq + 6, cross(B.r, B.e1));
+    double gN6[6], HN[36];
+    const double N = cross_sq(B.e1, B.e2, gN6, HN);
+    B.gN[0] = B.gN[1] = B.gN[2] = 0.0;
+    for (int k = 0; k < 6; ++k) B.gN[3 + k] = gN6[k];
+    B.iN = 1.0 / N;
+    for (int k = 0; k < 9; ++k) gr[k] = 2.0 * B.q * B.gq[k] * B.iN - B.q * B.q * B.gN[k] * B.iN * B.iN;
+    s = B.q * B.q * B.iN;
+  }
+  for (int k = 0; k < 12; ++k) B.gs[k] = B.gc12[k] = 0.0;
+  B.e = B.cs = B.cr = B.cc = B.cx = B.cm = 0.0;
+  if (!(s > 0.0)) { B.regime = 1; B.e = INFINITY; return; }
   const double d = sqrt(s);
-  if (d >= dhat) { *e = 0.0; return type; }
+  if (d >= dhat) { B.regime = 2; return; }
+  B.regime = 0;
   double b, b1, b2;
   barrier_d(d, dhat, &b, &b1, &b2);
   const double Bs = b1 / (2.0 * d), Bss = (b2 - b1 / d) / (4.0 * s);
   double m = 1.0, m1 = 0.0, m2 = 0.0;
-  for (int k = 0; k < 12; ++k) gc12[k] = 0.0;
   if (kind == KIND_EE) {
-    const d3 u = ld(x12 + 3) - ld(x12), v = ld(x12 + 9) - ld(x12 + 6);
-    double gc[6];
-    const double c = cross_sq(u, v, gc, Hc);
+    B.u = ld(x12 + 3) - ld(x12);
+    B.v = ld(x12 + 9) - ld(x12 + 6);
+    double gc[6], Hc[36];
+    const double c = cross_sq(B.u, B.v, gc, Hc);
     if (c < meps) {
       m = 2.0 * c / meps - c * c / (meps * meps);
       m1 = 2.0 / meps - 2.0 * c / (meps * meps);
       m2 = -2.0 / (meps * meps);
     }
     for (int i = 0; i < 3; ++i) {
-      gc12[i] = -gc[i];
-      gc12[3 + i] = gc[i];
-      gc12[6 + i] = -gc[3 + i];
-      gc12[9 + i] = gc[3 + i];
+      B.gc12[i] = -gc[i];
+      B.gc12[3 + i] = gc[i];
+      B.gc12[6 + i] = -gc[3 + i];
+      B.gc12[9 + i] = gc[3 + i];
     }
   }
-  // grad of s in 12-space
-  for (int k = 0; k < 12; ++k) gs[k] = 0.0;
   for (int j = 0; j < f.nred; ++j)
     for (int v = 0; v < 4; ++v)
       if (f.C[j][v])
-        for (int i = 0; i < 3; ++i) gs[3 * v + i] += f.C[j][v] * gr[3 * j + i];
-  *e = kappa * m * b;
-  for (int k = 0; k < 12; ++k) g12[k] = kappa * (m * Bs * gs[k] + m1 * b * gc12[k]);
-  // kappa * m * Bs * Hess(s), pulled back from reduced space
-  const double cs = kappa * m * Bs;
-  for (int j = 0; j < f.nred; ++j)
-    for (int k = 0; k < f.nred; ++k)
-      for (int v = 0; v < 4; ++v) {
-        if (!f.C[j][v]) continue;
-        for (int w = 0; w < 4; ++w) {
-          if (!f.C[k][w]) continue;
-          const double cf = cs * f.C[j][v] * f.C[k][w];
-          for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c)
-              H[((3 * v + a) * 12 + 3 * w + c) * stride] += cf * Hr[(j * f.nred + k) * 9 + 3 * a + c];
-        }
-      }
-  if (kind == KIND_EE && m1 != 0.0) {
-    // kappa * m1 * b * Hess(c); c depends on u = x1 - x0 (block 0) and v = x3 - x2 (block 1)
-    const signed char Cc[2][4] = {{-1, 1, 0, 0}, {0, 0, -1, 1}};
-    const double cc = kappa * m1 * b;
-    for (int j = 0; j < 2; ++j)
-      for (int k = 0; k < 2; ++k)
-        for (int v = 0; v < 4; ++v) {
-          if (!Cc[j][v]) continue;
-          for (int w = 0; w < 4; ++w) {
-            if (!Cc[k][w]) continue;
-            const double cf = cc * Cc[j][v] * Cc[k][w];
-            for (int a = 0; a < 3; ++a)
-              for (int c = 0; c < 3; ++c)
-                H[((3 * v + a) * 12 + 3 * w + c) * stride] += cf * Hc[(2 * j + k) * 9 + 3 * a + c];
-          }
-        }
+        for (int i = 0; i < 3; ++i) B.gs[3 * v + i] += f.C[j][v] * gr[3 * j + i];
+  B.e = kappa * m * b;
+  B.cs = kappa * m * Bs;
+  B.cr = kappa * m * Bss;
+  B.cc = kappa * m1 * b;
+  B.cx = kappa * m1 * Bs;
+  B.cm = kappa * m2 * b;
+}
+
+// Entry (a, c) of block (j, k) of the Hessian of s in reduced space.
+TC_HD double sqdist_reduced_hess(const BarrierCore& B, int j, int k, int a, int c) {
+  const int nred = B.f.nred;
+  if (nred == 1) return a == c ? 2.0 : 0.0;
+  if (nred == 2) {
+    const int ia = 3 * j + a, ic = 3 * k + c;
+    const double gBa = j == 1 ? 2.0 * at(B.e1, a) : 0.0, gBc = k == 1 ? 2.0 * at(B.e1, c) : 0.0;
+    double v = cross_sq_hess(B.r, B.e1, j, k, a, c) * B.iB;
+    v -= (B.gA[ia] * gBc + gBa * B.gA[ic]) * B.iB * B.iB;
+    if (j == 1 && k == 1 && a == c) v -= B.A2 * 2.0 * B.iB * B.iB;
+    v += 2.0 * B.A2 * gBa * gBc * B.iB * B.iB * B.iB;
+    return v;
   }
-  for (int a = 0; a < 12; ++a)
-    for (int c = 0; c < 12; ++c) {
-      double v = kappa * m * Bss * gs[a] * gs[c];
-      if (kind == KIND_EE) {
-        v += kappa * m1 * Bs * (gs[a] * gc12[c] + gc12[a] * gs[c]);
-        v += kappa * m2 * b * gc12[a] * gc12[c];
-      }
-      H[(a * 12 + c) * stride] += v;
+  // Hessian of q: (r,e1) = -[e2]x, (r,e2) = [e1]x, (e1,e2) = -[r]x (and transposes)
+  double hq = 0.0;
+  if (j == 0 && k == 1) hq = -skew_entry(B.e2, a, c);
+  else if (j == 1 && k == 0) hq = -skew_entry(B.e2, c, a);
+  else if (j == 0 && k == 2) hq = skew_entry(B.e1, a, c);
+  else if (j == 2 && k == 0) hq = skew_entry(B.e1, c, a);
+  else if (j == 1 && k == 2) hq = -skew_entry(B.r, a, c);
+  else if (j == 2 && k == 1) hq = -skew_entry(B.r, c, a);
+  const double hN = (j > 0 && k > 0) ? cross_sq_hess(B.e1, B.e2, j - 1, k - 1, a, c) : 0.0;
+  const int ia = 3 * j + a, ic = 3 * k + c;
+  const double q = B.q, iN = B.iN;
+  double v = 2.0 * B.gq[ia] * B.gq[ic] * iN + 2.0 * q * hq * iN;
+  v -= 2.0 * q * (B.gq[ia] * B.gN[ic] + B.gN[ia] * B.gq[ic]) * iN * iN;
+  v -= q * q * hN * iN * iN;
+  v += 2.0 * q * q * B.gN[ia] * B.gN[ic] * iN * iN * iN;
+  return v;
+}
+
+// Gradient entry A (0..11) of kappa m b(d).
+TC_HD double barrier_grad_entry(const BarrierCore& B, int A) {
+  return B.cs * B.gs[A] + B.cc * B.gc12[A];
+}
+
+// Unprojected Hessian entry (A, C) of kappa m b(d) in the 12 local coordinates.
+TC_HD double barrier_hess_entry(const BarrierCore& B, int A, int C) {
+  if (B.regime != 0) return 0.0;
+  const int va = A / 3, a = A % 3, vc = C / 3, c = C % 3;
+  const DistForm& f = B.f;
+  double h = 0.0;
+  for (int j = 0; j < f.nred; ++j) {
+    if (!f.C[j][va]) continue;
+    for (int k = 0; k < f.nred; ++k) {
+      if (!f.C[k][vc]) continue;
+      h += B.cs * f.C[j][va] * f.C[k][vc] * sqdist_reduced_hess(B, j, k, a, c);
     }
-  return type;
+  }
+  if (B.kind == KIND_EE && B.cc != 0.0) {
+    // c depends on u = x1 - x0 (block 0) and v = x3 - x2 (block 1)
+    const signed char Cc[2][4] = {{-1, 1, 0, 0}, {0, 0, -1, 1}};
+    for (int j = 0; j < 2; ++j) {
+      if (!Cc[j][va]) continue;
+      for (int k = 0; k < 2; ++k) {
+        if (!Cc[k][vc]) continue;
+        h += B.cc * Cc[j][va] * Cc[k][vc] * cross_sq_hess(B.u, B.v, j, k, a, c);
+      }
+    }
+  }
+  h += B.cr * B.gs[A] * B.gs[C];
+  if (B.kind == KIND_EE) {
+    h += B.cx * (B.gs[A] * B.gc12[C] + B.gc12[A] * B.gs[C]);
+    h += B.cm * B.gc12[A] * B.gc12[C];
+  }
+  return h;
 }
 
 // Barrier energy only (line search).  +inf if s <= 0, 0 if d >= dhat.

@@ -489,72 +489,74 @@ __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
 // parallel cyclic Jacobi with the round-robin ("tournament") ordering, 6 disjoint rotations
 // per round applied together as A <- J^T A J, V <- V J.  A and V live in LDS (double
 // buffered); on return A holds the projected matrix.  All 64 lanes of the workgroup call it.
-struct WaveJacobiLds {
-  double A[2][144];
-  double V[2][144];
-  double c[6], s[6];
-  double red[1];
-};
+// Frobenius-nearest PSD projection of a symmetric N x N matrix (N even) held in LDS by one
+// wavefront: cyclic Jacobi in round-robin (tournament) order, N/2 disjoint rotations per
+// round applied to A and to the eigenvector matrix V, ping-pong buffers, until the
+// off-diagonal mass is below 1e-30 of the total; then V max(w, 0) V^T.  Result in A[0].
+template <int N>
 __device__ __forceinline__ int tour_index(int pos, int r) {  // index at a tournament position
-  return pos == 0 ? 0 : 1 + (pos - 1 + r) % 11;
+  return pos == 0 ? 0 : 1 + (pos - 1 + r) % (N - 1);
 }
+template <int N>
 __device__ __forceinline__ int tour_pos(int idx, int r) {
-  return idx == 0 ? 0 : 1 + ((idx - 1 - r) % 11 + 11) % 11;
+  return idx == 0 ? 0 : 1 + ((idx - 1 - r) % (N - 1) + (N - 1)) % (N - 1);
 }
-__device__ void wave_psd12(WaveJacobiLds& L) {
+template <int N>
+__device__ void wave_psd(double (&A)[2][N * N], double (&Vm)[2][N * N], double* cs, double* sn) {
+  constexpr int NN = N * N, H = N / 2;
   const int lane = threadIdx.x;
   int cur = 0;
-  for (int e = lane; e < 144; e += 64) L.V[0][e] = (e / 12 == e % 12) ? 1.0 : 0.0;
+  for (int e = lane; e < NN; e += 64) Vm[0][e] = (e / N == e % N) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int e = lane; e < 144; e += 64) {
-      const double a = L.A[cur][e];
+    for (int e = lane; e < NN; e += 64) {
+      const double a = A[cur][e];
       tot += a * a;
-      if (e / 12 != e % 12) off += a * a;
+      if (e / N != e % N) off += a * a;
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_xor(off, o, 64);
       tot += __shfl_xor(tot, o, 64);
     }
     if (off <= 1e-30 * tot) break;
-    for (int r = 0; r < 11; ++r) {
-      if (lane < 6) {
-        int p = tour_index(lane, r), q = tour_index(11 - lane, r);
+    for (int r = 0; r < N - 1; ++r) {
+      if (lane < H) {
+        int p = tour_index<N>(lane, r), q = tour_index<N>(N - 1 - lane, r);
         if (p > q) { const int t = p; p = q; q = t; }
-        const double apq = L.A[cur][12 * p + q];
-        double c = 1.0, sn = 0.0;
+        const double apq = A[cur][N * p + q];
+        double c = 1.0, sg = 0.0;
         if (apq != 0.0) {
-          const double theta = (L.A[cur][12 * q + q] - L.A[cur][12 * p + p]) / (2.0 * apq);
+          const double theta = (A[cur][N * q + q] - A[cur][N * p + p]) / (2.0 * apq);
           const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
-          sn = t * c;
+          sg = t * c;
         }
-        L.c[lane] = c;
-        L.s[lane] = sn;
+        cs[lane] = c;
+        sn[lane] = sg;
       }
       __syncthreads();
       const int nxt = cur ^ 1;
-      for (int e = lane; e < 288; e += 64) {
-        const bool isV = e >= 144;
-        const int ee = isV ? e - 144 : e;
-        const int i = ee / 12, j = ee % 12;
+      for (int e = lane; e < 2 * NN; e += 64) {
+        const bool isV = e >= NN;
+        const int ee = isV ? e - NN : e;
+        const int i = ee / N, j = ee % N;
         // rotation acting on column j: partner index and coefficients
-        const int pj = tour_pos(j, r), kj = pj < 6 ? pj : 11 - pj;
-        const int oj = tour_index(11 - pj, r);
-        const double cj = L.c[kj], sj = L.s[kj];
+        const int pj = tour_pos<N>(j, r), kj = pj < H ? pj : N - 1 - pj;
+        const int oj = tour_index<N>(N - 1 - pj, r);
+        const double cj = cs[kj], sj = sn[kj];
         // J[j][j] = c; J[oj][j] = -s if j is the smaller index of its pair, else +s
         const double jjj = cj, joj = j < oj ? -sj : sj;
         if (isV) {
-          L.V[nxt][ee] = L.V[cur][12 * i + j] * jjj + L.V[cur][12 * i + oj] * joj;
+          Vm[nxt][ee] = Vm[cur][N * i + j] * jjj + Vm[cur][N * i + oj] * joj;
         } else {
-          const int pi = tour_pos(i, r), ki = pi < 6 ? pi : 11 - pi;
-          const int oi = tour_index(11 - pi, r);
-          const double ci = L.c[ki], si = L.s[ki];
+          const int pi = tour_pos<N>(i, r), ki = pi < H ? pi : N - 1 - pi;
+          const int oi = tour_index<N>(N - 1 - pi, r);
+          const double ci = cs[ki], si = sn[ki];
           const double jii = ci, joi = i < oi ? -si : si;
-          const double a_ij = L.A[cur][12 * i + j], a_ioj = L.A[cur][12 * i + oj];
-          const double a_oij = L.A[cur][12 * oi + j], a_oioj = L.A[cur][12 * oi + oj];
-          L.A[nxt][ee] = jii * (a_ij * jjj + a_ioj * joj) + joi * (a_oij * jjj + a_oioj * joj);
+          const double a_ij = A[cur][N * i + j], a_ioj = A[cur][N * i + oj];
+          const double a_oij = A[cur][N * oi + j], a_oioj = A[cur][N * oi + oj];
+          A[nxt][ee] = jii * (a_ij * jjj + a_ioj * joj) + joi * (a_oij * jjj + a_oioj * joj);
         }
       }
       __syncthreads();
@@ -563,41 +565,108 @@ __device__ void wave_psd12(WaveJacobiLds& L) {
   }
   // rebuild with clamped eigenvalues: out_ij = sum_k V_ik max(w_k, 0) V_jk
   const int nxt = cur ^ 1;
-  for (int e = lane; e < 144; e += 64) {
-    const int i = e / 12, j = e % 12;
+  for (int e = lane; e < NN; e += 64) {
+    const int i = e / N, j = e % N;
     double acc = 0.0;
-    for (int k = 0; k < 12; ++k) {
-      const double w = L.A[cur][13 * k];
-      if (w > 0.0) acc += L.V[cur][12 * i + k] * w * L.V[cur][12 * j + k];
+    for (int k = 0; k < N; ++k) {
+      const double w = A[cur][(N + 1) * k];
+      if (w > 0.0) acc += Vm[cur][N * i + k] * w * Vm[cur][N * j + k];
     }
-    L.A[nxt][e] = acc;
+    A[nxt][e] = acc;
   }
   __syncthreads();
-  for (int e = lane; e < 144; e += 64) L.A[0][e] = L.A[nxt][e];
+  if (nxt != 0)
+    for (int e = lane; e < NN; e += 64) A[0][e] = A[nxt][e];
   __syncthreads();
 }
 
 // ------------------------------------------------------------------ barrier (1 wave per pair)
+// A pair's energy depends on vertex differences only, so its 12x12 Hessian vanishes on the
+// three translations and is Q^T M Q for the 9x9 M = Q H Q^T, where Q = C (x) I3 and the rows
+// of C (3x4) are orthonormal and orthogonal to (1,1,1,1).  Projecting M (padded to 10x10 with
+// a zero row/column so the tournament has an even size) gives the projection of H.
+__constant__ double kContrast[3][4] = {
+    {0.70710678118654752440, -0.70710678118654752440, 0.0, 0.0},
+    {0.40824829046386301637, 0.40824829046386301637, -0.81649658092772603273, 0.0},
+    {0.28867513459481288225, 0.28867513459481288225, 0.28867513459481288225, -0.86602540378443864676}};
+
+struct WaveBarrierLds {
+  BarrierCore core;  // shared scalars of the pair (one lane computes them)
+  double H[144];     // 12x12 Hessian, row-major; projected in place by wave_barrier_project
+  double M[2][100];  // reduced 10x10
+  double V[2][100];
+  double c[5], s[5];
+  double g[12];
+};
+
+// All 64 lanes: derivatives of one pair into L.H / L.g (entries spread over lanes).
+__device__ void wave_barrier_derivs(int kind, const double* x12, double meps, double dhat,
+                                    double kappa, WaveBarrierLds& L, double* e_out, int* type_out) {
+  const int lane = threadIdx.x;
+  if (lane == 0) barrier_core(kind, x12, meps, dhat, kappa, L.core);
+  __syncthreads();
+  const BarrierCore& B = L.core;
+  if (lane < 12) L.g[lane] = barrier_grad_entry(B, lane);
+  for (int e = lane; e < 144; e += 64) L.H[e] = barrier_hess_entry(B, e / 12, e % 12);
+  *e_out = B.e;
+  *type_out = B.type;
+  __syncthreads();
+}
+
+__device__ void wave_barrier_project(WaveBarrierLds& L) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < 100; e += 64) {
+    const int i = e / 10, j = e % 10;
+    double acc = 0.0;
+    if (i < 9 && j < 9) {
+      const int al = i / 3, a = i % 3, be = j / 3, c = j % 3;
+      for (int v = 0; v < 4; ++v) {
+        const double cv = kContrast[al][v];
+        if (cv == 0.0) continue;
+        for (int w = 0; w < 4; ++w) {
+          const double cw = kContrast[be][w];
+          if (cw == 0.0) continue;
+          acc += cv * cw * L.H[12 * (3 * v + a) + 3 * w + c];
+        }
+      }
+    }
+    L.M[0][e] = acc;
+  }
+  __syncthreads();
+  wave_psd<10>(L.M, L.V, L.c, L.s);
+  for (int e = lane; e < 144; e += 64) {
+    const int va = e / 12 / 3, a = (e / 12) % 3, vc = (e % 12) / 3, c = e % 3;
+    double acc = 0.0;
+    for (int al = 0; al < 3; ++al) {
+      const double cv = kContrast[al][va];
+      if (cv == 0.0) continue;
+      for (int be = 0; be < 3; ++be) {
+        const double cw = kContrast[be][vc];
+        if (cw == 0.0) continue;
+        acc += cv * cw * L.M[0][10 * (3 * al + a) + 3 * be + c];
+      }
+    }
+    L.H[e] = acc;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(64) k_barrier_hess(View V, int np, const int* pkind,
                                                      const int* pv, const double* pmeps, double* pg,
                                                      double* ph) {
-  __shared__ WaveJacobiLds L;
-  __shared__ double g_s[12];
-  __shared__ double work[kBarrierWork];
+  __shared__ WaveBarrierLds L;
   const int k = blockIdx.x;
   if (k >= np) return;
-  if (threadIdx.x == 0) {
-    int ids[4];
-    for (int v = 0; v < 4; ++v) ids[v] = pv[4 * k + v];
-    const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
-    double x12[12], e;
-    gather12(V.cpos, ids, x12);
-    barrier_pair(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, &e, g_s, L.A[0], 1, work);
-  }
-  __syncthreads();
-  wave_psd12(L);
-  if (threadIdx.x < 12) pg[12 * (size_t)k + threadIdx.x] = g_s[threadIdx.x];
-  for (int e = threadIdx.x; e < 144; e += 64) ph[144 * (size_t)k + e] = L.A[0][e];
+  int ids[4];
+  for (int v = 0; v < 4; ++v) ids[v] = pv[4 * k + v];
+  const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
+  double x12[12], e;
+  int type;
+  gather12(V.cpos, ids, x12);
+  wave_barrier_derivs(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, L, &e, &type);
+  wave_barrier_project(L);
+  if (threadIdx.x < 12) pg[12 * (size_t)k + threadIdx.x] = L.g[threadIdx.x];
+  for (int i = threadIdx.x; i < 144; i += 64) ph[144 * (size_t)k + i] = L.H[i];
 }
 
 // ------------------------------------------------------------------ affine bodies
@@ -1466,24 +1535,23 @@ __global__ void __launch_bounds__(64) k_debug_barrier(int n, const int* kinds, c
                                                       const double* meps, double dhat, double kappa,
                                                       double* e, double* g, double* H, double* Hp,
                                                       int* types) {
-  __shared__ WaveJacobiLds L;
-  __shared__ double work[kBarrierWork];
+  __shared__ WaveBarrierLds L;
   const int k = blockIdx.x;
   if (k >= n) return;
+  double ee;
+  int type;
+  wave_barrier_derivs(kinds[k], x + 12 * k, meps[k], dhat, kappa, L, &ee, &type);
   if (threadIdx.x == 0) {
-    double ee, gg[12];
-    const int type = barrier_pair(kinds[k], x + 12 * k, meps[k], dhat, kappa, &ee, gg, L.A[0], 1, work);
     if (e) e[k] = ee;
     if (types) types[k] = type;
-    if (g)
-      for (int i = 0; i < 12; ++i) g[12 * k + i] = gg[i];
   }
-  __syncthreads();
+  if (g && threadIdx.x < 12) g[12 * k + threadIdx.x] = L.g[threadIdx.x];
   if (H)
-    for (int i = threadIdx.x; i < 144; i += 64) H[144 * (size_t)k + i] = L.A[0][i];
-  wave_psd12(L);
+    for (int i = threadIdx.x; i < 144; i += 64) H[144 * (size_t)k + i] = L.H[i];
+  __syncthreads();
+  wave_barrier_project(L);
   if (Hp)
-    for (int i = threadIdx.x; i < 144; i += 64) Hp[144 * (size_t)k + i] = L.A[0][i];
+    for (int i = threadIdx.x; i < 144; i += 64) Hp[144 * (size_t)k + i] = L.H[i];
 }
 
 __global__ void k_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,

@@ -29,6 +29,13 @@ Workloads (all lengths in mm in the descriptions, metres in the arrays):
 * ``uniform_batch(n)``: n copies of the 8x8x2 pad, scene i from ``default_rng(1000+i)`` with
   an 8-point hull (12 tris) of 10 mm extent, xy offset U(-3,3) mm, press depth
   U(0.3,1.2) mm reached over 10 steps after closing the 0.05 mm gap.
+* ``serving_request(i)`` / ``serving_arrivals(rate, duration)``: a stream of rollout requests.
+  Request i (from ``default_rng([7, i])``) is the 32x24x6 mm pad on a grid drawn from
+  {16x12x4, 32x24x6, 48x36x8}, with 1-3 rigid hull indenters of 8 mm extent whose triangle
+  counts are log-uniform in [200, 8000] (even; n = tris/2 + 2 hull points), placed at
+  non-overlapping xy positions 0.05 mm above the pad; each is pressed U(0.3,1.2) mm over 25
+  steps, then all slide together U(0,2) mm in one random tangent direction over 25 steps,
+  h = 0.005 s.  Arrival times are Poisson (exponential gaps from ``default_rng(seed)``).
 """
 from __future__ import annotations
 
@@ -86,7 +93,19 @@ def default_params(h: float) -> dict:
 
 
 # ----------------------------------------------------------------------------- meshes
+_KUHN_CACHE = {}
+
+
 def kuhn_box(lo, hi, cells):
+    """Cached front of ``_kuhn_box`` (returns fresh copies)."""
+    key = (tuple(float(v) for v in lo), tuple(float(v) for v in hi), tuple(int(c) for c in cells))
+    if key not in _KUHN_CACHE:
+        _KUHN_CACHE[key] = _kuhn_box(lo, hi, cells)
+    v, t = _KUHN_CACHE[key]
+    return v.copy(), t.copy()
+
+
+def _kuhn_box(lo, hi, cells):
     """Box [lo,hi] on an (nx,ny,nz) hex grid, each hex split into the 6 Kuhn tetrahedra.
 
     Vertex id = i + (nx+1)*(j + (ny+1)*k).  Cells are visited with i fastest, then j, k;
@@ -152,11 +171,10 @@ def _random_rotation(rng):
 def _orient_outward(verts, tris):
     c = verts.mean(axis=0)
     out = tris.copy()
-    for f in range(len(out)):
-        a, b, d = verts[out[f]]
-        n = np.cross(b - a, d - a)
-        if np.dot(n, (a + b + d) / 3.0 - c) < 0:
-            out[f, 1], out[f, 2] = out[f, 2], out[f, 1]
+    a, b, d = verts[out[:, 0]], verts[out[:, 1]], verts[out[:, 2]]
+    n = np.cross(b - a, d - a)
+    flip = np.einsum("ij,ij->i", n, (a + b + d) / 3.0 - c) < 0
+    out[flip, 1], out[flip, 2] = tris[flip, 2], tris[flip, 1]
     return out
 
 
@@ -251,6 +269,57 @@ def batch_member(i: int, n_steps: int = 10) -> SceneSpec:
     return _pad_scene(f"uniform_batch[{i}]", pad_lo, pad_hi, (8, 8, 2),
                       [BodySpec(hv, ht)], tg[:, None, :], 0.01,
                       dict(index=i, offset=(ox, oy), depth=depth))
+
+
+SERVING_GRIDS = ((16, 12, 4), (32, 24, 6), (48, 36, 8))
+
+
+def serving_request(i: int, n_press: int = 25, n_slide: int = 25) -> SceneSpec:
+    rng = np.random.default_rng([7, i])
+    pad_lo = (-16 * MM, -12 * MM, 0.0)
+    pad_hi = (16 * MM, 12 * MM, 6 * MM)
+    gap = 0.05 * MM
+    cells = SERVING_GRIDS[int(rng.integers(len(SERVING_GRIDS)))]
+    n_bodies = int(rng.integers(1, 4))
+    # xy centres at least 9 mm apart along some axis (the 8 mm hull boxes never overlap,
+    # and they slide together)
+    centres = []
+    for _ in range(1000):
+        if len(centres) == n_bodies:
+            break
+        c = rng.uniform((-10 * MM, -6 * MM), (10 * MM, 6 * MM))
+        if all(max(abs(c[0] - o[0]), abs(c[1] - o[1])) >= 9 * MM for o in centres):
+            centres.append(c)
+    n_steps = n_press + n_slide
+    ang = rng.uniform(0.0, 2.0 * np.pi)
+    slide = rng.uniform(0.0, 2.0) * MM * np.array([np.cos(ang), np.sin(ang)])
+    bodies, targets = [], []
+    for c in centres:
+        tris = 2 * int(round(0.5 * np.exp(rng.uniform(np.log(200.0), np.log(8000.0)))))
+        hv, ht = random_hull(rng, tris // 2 + 2, 8 * MM)
+        hv = hv + np.array([c[0], c[1], pad_hi[2] + gap - hv[:, 2].min()])
+        depth = rng.uniform(0.3, 1.2) * MM
+        off = np.zeros((n_steps, 3))
+        for s in range(1, n_steps + 1):
+            off[s - 1, 2] = -(depth + gap) * min(s, n_press) / n_press
+            off[s - 1, :2] = slide * max(0, s - n_press) / n_slide
+        bodies.append(BodySpec(hv, ht))
+        targets.append(translation_targets(off))
+    return _pad_scene(f"serving_request[{i}]", pad_lo, pad_hi, cells, bodies,
+                      np.stack(targets, axis=1), 0.005,
+                      dict(index=i, cells=cells, n_bodies=len(bodies),
+                           tris=[len(b.tris) for b in bodies]))
+
+
+def serving_arrivals(rate: float, duration: float, seed: int = 7) -> np.ndarray:
+    """Poisson arrival times (s) in [0, duration) at the given rate (1/s)."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return np.array(out)
+        out.append(t)
 
 
 def uniform_batch(n: int = 256, n_steps: int = 10):
