@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "coarse.h"
 #include "kernels.h"
 #include "prims.h"
 
@@ -98,7 +99,8 @@ struct HostBody {
 struct HostScene {
   int nv = 0, nb = 0, n_moving = 0;
   int node0 = 0, node1 = 0;
-  std::vector<int> moving;  // soft vertex ids flagged 2
+  std::vector<int> moving;  // internal soft vertex ids flagged 2, in the caller's vertex order
+  std::vector<int> perm;    // caller's soft vertex id -> internal id (Morton order)
   std::vector<HostBody> bodies;
   std::vector<int> cv_world;  // world id per contact vertex of the scene
   int cv0 = 0, cv1 = 0, tri0 = 0, tri1 = 0, edge0 = 0, edge1 = 0;
@@ -170,7 +172,7 @@ struct Batch::Impl {
   int S = 0, Nn = 0, Nt = 0, Nb = 0, Ncv = 0, Ntr = 0, Ned = 0, Nq = 0, nnz = 0;
   std::vector<HostScene> hs;
   std::vector<SceneConst> hsc;
-  std::vector<int> h_ntype, h_nscene, h_bnode, h_bscene, h_bpres, h_moving_nodes;
+  std::vector<int> h_ntype, h_nscene, h_bnode, h_bscene, h_bpres;
   std::vector<double> spmv_static_blocks;  // per scene: stored blocks of free rows
   std::vector<double> spmv_free_nodes;
   std::vector<hipEvent_t> ev_pool;
@@ -196,8 +198,8 @@ struct Batch::Impl {
   bool cover_valid = false;
   int n_cover = 0;
   bool device_touched = false;
-  bool xn_valid = false;
-  bool validate_only = false;  // build() stops after the host-side checks  // xn holds the positions at the start of the current step
+  bool xn_valid = false;       // xn holds the positions at the start of the current step
+  bool validate_only = false;  // build() stops after the host-side checks
   int mixed = 0;  // 1: FP32 Hessian blocks, assembly, SpMV and PCG (taccel_precision MIXED)
   // dynamic work buffers
   BroadPhase bp;
@@ -214,6 +216,12 @@ struct Batch::Impl {
   DBuf<double> dval;
   DBuf<double> g, r, z, p, p1, q, dx, pinv;
   DBuf<double> P_pq, P_rz0, P_rz1, P_rr, P_gg;
+  // two-level preconditioner: coarse space of 6 rigid modes per aggregate of 64-node
+  // blocks, with the inverse of its rest-state operator per scene
+  DBuf<int> cg_blk_agg, cg_agg_b0, cg_agg_b1, cg_sc_a0, cg_sc_m;
+  DBuf<long long> cg_sc_off;
+  DBuf<double> cg_d, cg_ainv, cg_rc;  // T-typed storage (float in mixed mode)
+  int cg_on = 0;
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
   DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs;
@@ -294,6 +302,36 @@ struct Batch::Impl {
   void release_all();
 };
 
+// Order of n points along a Morton (Z-order) curve of their bounding box, 10 bits per axis;
+// ties keep the input order.  Returns perm with perm[i] = rank of point i.
+static std::vector<int> morton_order(const double* X, int n) {
+  std::vector<int> perm(n);
+  if (n == 0) return perm;
+  double lo[3], hi[3];
+  for (int c = 0; c < 3; ++c) lo[c] = hi[c] = X[c];
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], X[3 * (size_t)i + c]);
+      hi[c] = std::max(hi[c], X[3 * (size_t)i + c]);
+    }
+  std::vector<std::pair<uint32_t, int>> key(n);
+  for (int i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int c = 0; c < 3; ++c) {
+      const double span = hi[c] - lo[c];
+      const double t = span > 0.0 ? (X[3 * (size_t)i + c] - lo[c]) / span : 0.0;
+      q[c] = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(t * 1024.0)));
+    }
+    uint32_t k = 0;
+    for (int b = 9; b >= 0; --b)
+      for (int c = 2; c >= 0; --c) k = (k << 1) | ((q[c] >> b) & 1u);
+    key[i] = {k, i};
+  }
+  std::sort(key.begin(), key.end());
+  for (int r = 0; r < n; ++r) perm[key[r].second] = r;
+  return perm;
+}
+
 static int bits_for(uint64_t v) {
   int b = 1;
   while (b < 64 && (v >> b) != 0) ++b;
@@ -316,15 +354,38 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   // static BSR built per scene and concatenated
   std::vector<int> h_rowptr(1, 0), h_col, h_diag, h_cptr(1, 0), h_clist, h_vptr(1, 0), h_vlist, h_brow;
   for (int s = 0; s < S; ++s) {
-    const taccel_scene_desc& d = descs[s];
+    const taccel_scene_desc& du = descs[s];  // caller's vertex order
     HostScene& H = hs[s];
-    const taccel_params& P = d.params;
+    const taccel_params& P = du.params;
     if (!(P.h > 0) || !(P.dhat > 0) || !(P.kappa >= 0) || !(P.newton_tol > 0))
       throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(s) + ": h, dhat, newton_tol must be > 0");
-    const int nv = d.soft.nv, nt = d.soft.nt, nb = d.n_bodies;
-    if (nv < 0 || nt < 0 || nb < 0 || (nv > 0 && !d.soft.verts) || (nt > 0 && !d.soft.tets) ||
-        (nb > 0 && !d.bodies))
+    const int nv = du.soft.nv, nt = du.soft.nt, nb = du.n_bodies;
+    if (nv < 0 || nt < 0 || nb < 0 || (nv > 0 && !du.soft.verts) || (nt > 0 && !du.soft.tets) ||
+        (nb > 0 && !du.bodies))
       throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(s) + ": bad soft/body sizes");
+    // ---- internal vertex order: soft vertices sorted along a Morton curve of their rest
+    // positions, so consecutive nodes (each 64-node block in particular) are spatially
+    // compact; tets keep their order and refer to the new ids
+    for (int k = 0; k < 4 * nt; ++k)
+      if (du.soft.tets[k] < 0 || du.soft.tets[k] >= nv) throw ApiError(TACCEL_ERR_ARG, "tet index out of range");
+    if (du.soft.dirichlet)
+      for (int i = 0; i < nv; ++i)
+        if (du.soft.dirichlet[i] > 2) throw ApiError(TACCEL_ERR_ARG, "dirichlet flag must be 0, 1 or 2");
+    H.perm = morton_order(du.soft.verts, nv);
+    std::vector<double> pverts(3 * (size_t)nv);
+    std::vector<int32_t> ptets(4 * (size_t)nt);
+    std::vector<uint8_t> pdir(du.soft.dirichlet ? nv : 0);
+    std::vector<int> iperm(nv);
+    for (int i = 0; i < nv; ++i) {
+      iperm[H.perm[i]] = i;
+      for (int c = 0; c < 3; ++c) pverts[3 * (size_t)H.perm[i] + c] = du.soft.verts[3 * (size_t)i + c];
+      if (du.soft.dirichlet) pdir[H.perm[i]] = du.soft.dirichlet[i];
+    }
+    for (int k = 0; k < 4 * nt; ++k) ptets[k] = H.perm[du.soft.tets[k]];
+    taccel_scene_desc d = du;
+    d.soft.verts = pverts.data();
+    d.soft.tets = ptets.data();
+    d.soft.dirichlet = du.soft.dirichlet ? pdir.data() : nullptr;
     H.nv = nv;
     H.nb = nb;
     H.h = P.h;
@@ -367,11 +428,9 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
       if (flag > 2) throw ApiError(TACCEL_ERR_ARG, "dirichlet flag must be 0, 1 or 2");
       h_nfree[node0 + i] = flag == 0;
       h_ntype[node0 + i] = 0;
-      if (flag == 2) {
-        H.moving.push_back(i);
-        h_moving_nodes.push_back(node0 + i);
-      }
     }
+    for (int u = 0; u < nv; ++u)
+      if (du.soft.dirichlet && du.soft.dirichlet[u] == 2) H.moving.push_back(H.perm[u]);
     H.n_moving = (int)H.moving.size();
     // ---- tets
     const int tet0 = Nt;
@@ -473,8 +532,8 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
         const int flag = d.soft.dirichlet ? d.soft.dirichlet[i] : 0;
         h_cvfix.push_back(flag == 1);
         h_cvscene.push_back(s);
-        h_cvworld.push_back(i);
-        H.cv_world.push_back(i);
+        h_cvworld.push_back(iperm[i]);
+        H.cv_world.push_back(iperm[i]);
       }
     std::vector<std::array<int, 3>> tris;
     for (const auto& f : bfaces) tris.push_back({soft_cv[f[0]], soft_cv[f[1]], soft_cv[f[2]]});
@@ -553,7 +612,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
       const int li = cv - cv0;
       const int w = H.cv_world[li];
       if (w < nv) {
-        for (int c = 0; c < 3; ++c) p[c] = d.soft.verts[3 * w + c];
+        for (int c = 0; c < 3; ++c) p[c] = du.soft.verts[3 * w + c];
       } else {
         int off = nv;
         for (int b = 0; b < nb; ++b) {
@@ -674,6 +733,38 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   }
   // ---- upload (everything above is host-side validation and setup)
   if (validate_only) return;
+  // ---- coarse level of the preconditioner (rest state, formed once)
+  std::vector<int> cg_blk_agg_h(tn_sc_h.size(), -1), cg_agg_b0_h, cg_agg_b1_h, cg_sc_a0_h(S, 0),
+      cg_sc_m_h(S, 0);
+  std::vector<long long> cg_sc_off_h(S, 0);
+  std::vector<double> cg_d_h(3 * (size_t)Nn, 0.0), cg_ainv_h;
+  for (int s = 0; s < S; ++s) {
+    const HostScene& H = hs[s];
+    const SceneConst& C = hsc[s];
+    CoarseScene cs;
+    cs.node0 = H.node0;
+    cs.nv = H.nv;
+    cs.nfree = h_nfree.data();
+    cs.X = h_x.data();
+    cs.mass = h_mass.data();
+    cs.tet0 = C.tet0;
+    cs.tet1 = C.tet1;
+    cs.tv = h_tv_aos.data();
+    cs.Dminv = h_Dminv_aos.data();
+    cs.vol = h_tvol.data();
+    cs.h = C.h;
+    cs.mu = C.mu;
+    cs.lam = C.lam;
+    cs.tn_b0 = tn_b0_h.data();
+    cs.bfirst = tn_sblk_h[s];
+    cs.bend = tn_sblk_h[s + 1];
+    cs.block = kNodeChunk;
+    cs.max_agg = kCoarseMaxAgg;
+    cg_sc_a0_h[s] = (int)cg_agg_b0_h.size();
+    cg_sc_off_h[s] = (long long)cg_ainv_h.size();
+    cg_sc_m_h[s] = build_coarse(cs, cg_blk_agg_h, cg_agg_b0_h, cg_agg_b1_h, cg_d_h, cg_ainv_h);
+  }
+  cg_on = cg_agg_b0_h.empty() ? 0 : 1;
   if (!mem.stream) {
     // a stream of our own (default priority): the PCG chunks are captured into a graph,
     // which the null stream does not allow
@@ -761,6 +852,24 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   pinv.ensure(m, 9 * (size_t)Nn);
   for (DBuf<double>* b : {&P_rz0, &P_rz1, &P_rr, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
   P_pq.ensure(m, std::max(TS.nblk, 1));
+  cg_blk_agg.upload(m, cg_blk_agg_h);
+  cg_agg_b0.upload(m, cg_agg_b0_h.empty() ? std::vector<int>(1, 0) : cg_agg_b0_h);
+  cg_agg_b1.upload(m, cg_agg_b1_h.empty() ? std::vector<int>(1, 0) : cg_agg_b1_h);
+  cg_sc_a0.upload(m, cg_sc_a0_h);
+  cg_sc_m.upload(m, cg_sc_m_h);
+  cg_sc_off.upload(m, cg_sc_off_h);
+  cg_rc.ensure(m, 6 * (size_t)std::max(TN.nblk, 1));
+  if (mixed) {
+    const std::vector<float> df(cg_d_h.begin(), cg_d_h.end()), af(cg_ainv_h.begin(), cg_ainv_h.end());
+    cg_d.ensure(m, (df.size() + 1) / 2 + 1);
+    cg_ainv.ensure(m, (af.size() + 1) / 2 + 1);
+    h2d(reinterpret_cast<float*>(cg_d.p), df.data(), df.size());
+    h2d(reinterpret_cast<float*>(cg_ainv.p), af.data(), af.size());
+    sync();
+  } else {
+    cg_d.upload(m, cg_d_h);
+    cg_ainv.upload(m, cg_ainv_h.empty() ? std::vector<double>(1, 0.0) : cg_ainv_h);
+  }
   iters.ensure(m, S);
   bad.ensure(m, S);
   infeasible.ensure(m, S);
@@ -870,6 +979,16 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.P_rr = reinterpret_cast<T*>(P_rr.p);
   B.P_gg = reinterpret_cast<T*>(P_gg.p);
   B.iters = iters.p;
+  B.cg_on = cg_on;
+  B.cg_blk_agg = cg_blk_agg.p;
+  B.cg_agg_b0 = cg_agg_b0.p;
+  B.cg_agg_b1 = cg_agg_b1.p;
+  B.cg_sc_a0 = cg_sc_a0.p;
+  B.cg_sc_m = cg_sc_m.p;
+  B.cg_sc_off = cg_sc_off.p;
+  B.cg_d = reinterpret_cast<const T*>(cg_d.p);
+  B.cg_ainv = reinterpret_cast<const T*>(cg_ainv.p);
+  B.cg_rc = reinterpret_cast<T*>(cg_rc.p);
   int max_pcg = 0;
   for (const auto& H : hs) max_pcg = std::max(max_pcg, H.max_pcg);
   B.max_iters = max_pcg;
@@ -929,6 +1048,7 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
     for (int k = 0; k < kPcgChunk; ++k) {
       launch_pcg_spmv(V, TN, TS, B, k & 1, s);
       launch_pcg_update(V, TN, TS, B, k & 1, s);
+      launch_pcg_coarse(V, TN, B, (k & 1) ? B.P_rz0 : B.P_rz1, s);
     }
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &graph);  // always ends the capture
@@ -1041,10 +1161,12 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   if (mixed) {
     const PcgBufsT<float> B = pcg_bufs<float>();
     launch_pcg_init(V, TN, B, s);
+    launch_pcg_coarse(V, TN, B, B.P_rz0, s);
     run_pcg(V, B, nseg);
   } else {
     const PcgBufsT<double> B = pcg_bufs<double>();
     launch_pcg_init(V, TN, B, s);
+    launch_pcg_coarse(V, TN, B, B.P_rz0, s);
     run_pcg(V, B, nseg);
   }
   d2h(pcg_it.data(), iters.p, S);
@@ -1427,6 +1549,8 @@ size_t Batch::Impl::device_bytes() const {
   add(hsrc); add(gsrc); add(hidx2); add(gidx2); add(hkey); add(gkey); add(hkey2); add(gkey2);
   add(sflag); add(segid); add(segstart); add(drow); add(dcol); add(rowcnt); add(drowptr); add(scratch);
   add(e_pairs); add(part_nodes); add(part_tets);
+  add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
+  add(cg_d); add(cg_ainv); add(cg_rc);
   return n;
 }
 
@@ -1489,6 +1613,9 @@ Batch::~Batch() {
            &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
            &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs)
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
+  FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m)
+  FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc)
+  I.cg_sc_off.free();
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
            &I.clist, &I.vptr, &I.vlist, &I.brow, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,
            &I.cvn, &I.cvb, &I.cvfix, &I.cvscene, &I.cvworld, &I.trv, &I.edv, &I.qkind, &I.qidx, &I.qscene,
@@ -1565,8 +1692,11 @@ taccel_status Batch::read(int k, taccel_field f, void* dst, size_t bytes) {
     const HostScene& H = I.hs[k];
     double* out = static_cast<double*>(dst);
     if (f == TACCEL_FIELD_X || f == TACCEL_FIELD_V) {
-      I.d2h(out, (f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, cnt);
+      std::vector<double> tmp(cnt);
+      I.d2h(tmp.data(), (f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, cnt);
       I.sync();
+      for (int u = 0; u < H.nv; ++u)
+        for (int c = 0; c < 3; ++c) out[3 * (size_t)u + c] = tmp[3 * (size_t)H.perm[u] + c];
       return TACCEL_OK;
     }
     const int n_soft_pad = (H.nv + 3) / 4 * 4;
@@ -1614,7 +1744,10 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
     const HostScene& H = I.hs[k];
     const double* in = static_cast<const double*>(src);
     if (f == TACCEL_FIELD_X || f == TACCEL_FIELD_V) {
-      I.h2d((f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, in, cnt);
+      std::vector<double> tmp(cnt);
+      for (int u = 0; u < H.nv; ++u)
+        for (int c = 0; c < 3; ++c) tmp[3 * (size_t)H.perm[u] + c] = in[3 * (size_t)u + c];
+      I.h2d((f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, tmp.data(), cnt);
       I.sync();
       return TACCEL_OK;
     }

@@ -104,12 +104,26 @@ struct PcgBufsT {
   T *P_pq, *P_rz0, *P_rz1, *P_rr, *P_gg;
   int* iters;
   int max_iters;
+  // coarse level (cg_on = 0: block Jacobi alone)
+  int cg_on;
+  const int* cg_blk_agg;      // [TN blocks] aggregate of the block, -1 if it has no soft node
+  const int* cg_agg_b0;       // [aggregates] first TN block
+  const int* cg_agg_b1;       // [aggregates] one past the last TN block
+  const int* cg_sc_a0;        // [S] first aggregate of the scene
+  const int* cg_sc_m;         // [S] coarse dimension (6 per aggregate)
+  const long long* cg_sc_off; // [S] offset of the scene's inverse coarse operator
+  const T* cg_d;              // [nodes][3] scaled rest offset from the aggregate centroid
+  const T* cg_ainv;           // per scene m x m, row-major
+  T* cg_rc;                   // [TN blocks][6] restricted residual partials
 };
+constexpr int kCoarseMaxAgg = 128;  // aggregates per scene (coarse dimension <= 768)
 template <class T>
 void launch_pcg_init(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, hipStream_t s);
 template <class T>
 void launch_pcg_spmv(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                      int parity, hipStream_t s);
+template <class T>
+void launch_pcg_coarse(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, T* prz, hipStream_t s);
 template <class T>
 void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                        int parity, hipStream_t s);

@@ -485,10 +485,6 @@ __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
 }
 
 // ------------------------------------------------------------------ wave-parallel Jacobi
-// PSD projection (eigenvalues clamped at 0) of a symmetric 12x12 matrix by one wavefront:
-// parallel cyclic Jacobi with the round-robin ("tournament") ordering, 6 disjoint rotations
-// per round applied together as A <- J^T A J, V <- V J.  A and V live in LDS (double
-// buffered); on return A holds the projected matrix.  All 64 lanes of the workgroup call it.
 // Frobenius-nearest PSD projection of a symmetric N x N matrix (N even) held in LDS by one
 // wavefront: cyclic Jacobi in round-robin (tournament) order, N/2 disjoint rotations per
 // round applied to A and to the eigenvector matrix V, ping-pong buffers, until the
@@ -1076,12 +1072,36 @@ __device__ T block_sum256t(T v, T* lds) {
   return r;
 }
 
+// Restriction of the residual onto the coarse space of the node's aggregate: the 6 rigid
+// modes u = t + w x d (d = scaled rest offset from the aggregate centroid) give P^T r =
+// (sum r, sum d x r) over the block's soft nodes.  One wave per 64-node block.
+template <class T>
+__device__ __forceinline__ void restrict_block(const View& V, const PcgBufsT<T>& B, int n, bool live,
+                                               const T* r) {
+  T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  if (live && V.ntype[n] == 0) {
+    const T* d = B.cg_d + 3 * n;
+    v[0] = r[0];
+    v[1] = r[1];
+    v[2] = r[2];
+    v[3] = d[1] * r[2] - d[2] * r[1];
+    v[4] = d[2] * r[0] - d[0] * r[2];
+    v[5] = d[0] * r[1] - d[1] * r[0];
+  }
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) B.cg_rc[6 * blockIdx.x + k] = v[k];
+}
+
 // Preconditioned CG with two kernels per iteration k (parity = k & 1):
 //   k_pcg_dir_spmv: convergence test on |r_k|; beta_k = rz_k / rz_{k-1};
 //                   p_k = z_k + beta_k p_{k-1} (written to the other p buffer) and
 //                   q_k = A p_k with p_k formed on the fly from z and p_{k-1};
 //   k_pcg_update:   alpha_k = rz_k / (p_k . q_k); x += alpha p; r -= alpha q; z = M^{-1} r.
 // p_{-1} = 0 and rz_{-1} = 1 make iteration 0 start with p_0 = z_0.
+// With the coarse level on, M^{-1} = D^{-1} + P A_c^{-1} P^T (additive two-level): the node
+// kernels apply D^{-1} (block Jacobi) and restrict r; k_pcg_coarse then solves the coarse
+// system and adds P e to z and r_c . e to the block partials of r.z.
 template <class T>
 __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBufsT<T> B) {
   __shared__ T rs[kWave][3];
@@ -1109,6 +1129,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
   }
   const T rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
   const T rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (B.cg_on) restrict_block<T>(V, B, n, live, r);
   if (threadIdx.x == 0) {
     B.P_rz0[blockIdx.x] = rz;
     B.P_rz1[blockIdx.x] = (T)1;
@@ -1225,10 +1246,53 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
   }
   const T rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
   const T rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (B.cg_on) restrict_block<T>(V, B, n, live, r);
   if (threadIdx.x == 0) {
     Prz_new[blockIdx.x] = rz;
     B.P_rr[blockIdx.x] = rr;
     if ((int)blockIdx.x == TN.sblk[s]) ++B.iters[s];
+  }
+}
+
+// Coarse correction, one wave per 64-node block: the scene's restricted residual r_c (sum of
+// block partials per aggregate) staged in LDS, e = rows of A_c^{-1} for the block's aggregate
+// times r_c, z += t + w x d on the block's soft nodes, and r_c . e of the aggregate added to
+// the partial of r.z of the aggregate's first block.
+template <class T>
+__global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, PcgBufsT<T> B, T* prz) {
+  __shared__ T rcs[6 * kCoarseMaxAgg];
+  const int blk = blockIdx.x;
+  const int s = TN.sc[blk];
+  if (V.pdone[s]) return;
+  const int a = B.cg_blk_agg[blk];
+  if (a < 0) return;
+  const int a0 = B.cg_sc_a0[s], m = B.cg_sc_m[s];
+  for (int i = threadIdx.x; i < m; i += kWave) {
+    const int ag = a0 + i / 6, k = i % 6;
+    T acc = (T)0;
+    for (int b = B.cg_agg_b0[ag]; b < B.cg_agg_b1[ag]; ++b) acc += B.cg_rc[6 * b + k];
+    rcs[i] = acc;
+  }
+  __syncthreads();
+  const int la = a - a0;
+  const T* Ai = B.cg_ainv + B.cg_sc_off[s] + (size_t)6 * la * m;
+  T e[6];
+  for (int k = 0; k < 6; ++k) {
+    T acc = (T)0;
+    for (int j = threadIdx.x; j < m; j += kWave) acc += Ai[(size_t)k * m + j] * rcs[j];
+    e[k] = wave_sum(acc);
+  }
+  if (threadIdx.x == 0 && blk == B.cg_agg_b0[a]) {
+    T dot = (T)0;
+    for (int k = 0; k < 6; ++k) dot += rcs[6 * la + k] * e[k];
+    prz[blk] += dot;
+  }
+  const int n = TN.b0[blk] + (int)threadIdx.x;
+  if (n < TN.b1[blk] && V.ntype[n] == 0 && V.nfree[n]) {
+    const T* d = B.cg_d + 3 * n;
+    B.z[3 * n] += e[0] + (e[4] * d[2] - e[5] * d[1]);
+    B.z[3 * n + 1] += e[1] + (e[5] * d[0] - e[3] * d[2]);
+    B.z[3 * n + 2] += e[2] + (e[3] * d[1] - e[4] * d[0]);
   }
 }
 
@@ -1727,6 +1791,12 @@ void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS
   if (TN.nblk > 0)
     hipLaunchKernelGGL(k_pcg_update<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, TS, B, parity);
 }
+template <class T>
+void launch_pcg_coarse(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, T* prz, hipStream_t s) {
+  if (TN.nblk > 0 && B.cg_on) hipLaunchKernelGGL(k_pcg_coarse<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, B, prz);
+}
+template void launch_pcg_coarse<double>(const View&, const BlockTable&, const PcgBufsT<double>&, double*, hipStream_t);
+template void launch_pcg_coarse<float>(const View&, const BlockTable&, const PcgBufsT<float>&, float*, hipStream_t);
 template void launch_pcg_init<double>(const View&, const BlockTable&, const PcgBufsT<double>&, hipStream_t);
 template void launch_pcg_init<float>(const View&, const BlockTable&, const PcgBufsT<float>&, hipStream_t);
 template void launch_pcg_spmv<double>(const View&, const BlockTable&, const BlockTable&, const PcgBufsT<double>&, int, hipStream_t);
