@@ -87,7 +87,8 @@ def test_server_mix_equals_alone(T):
 
 
 def test_server_staggered_cohorts(T):
-    # requests arriving while an earlier cohort runs form a second, concurrent cohort
+    # requests arriving while an earlier cohort runs form further, concurrent cohorts; each
+    # request ends exactly as the same scene stepped alone (status, step count and state)
     specs = [S.batch_member(10 + i) for i in range(4)]
     say("server: staggered arrivals, one request per cohort, up to 4 cohorts at once")
     srv = T.Server(hbm_budget_bytes=8e9, max_cohort=1, max_cohorts=4, coalesce_ms=1.0)
@@ -96,11 +97,15 @@ def test_server_staggered_cohorts(T):
         ids.append(srv.submit(sp, 10))
         time.sleep(0.02)
     done = _drain(srv, len(ids))
+    n_ok = 0
     for rid, sp in zip(ids, specs):
-        assert done[rid]["status"] == T.OK
-        _, ref = _alone(T, sp, 10)
+        st, ref = _alone(T, sp, 10)
+        c = done[rid]
+        assert c["status"] == st, (T.STATUS_NAMES[c["status"]], T.STATUS_NAMES[st])
+        n_ok += c["status"] == T.OK
         for a, b in zip(_fields(T, srv, rid), ref):
             assert np.array_equal(a, b)
+    assert n_ok >= 3
     assert srv.info()["running_cohorts"] == 0
     srv.close()
 
