@@ -1040,10 +1040,8 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
   }
   const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, V.bpinv};
   if (!pcg_exec || key != pcg_key) {
-    if (pcg_exec) HIPCHECK(hipGraphExecDestroy(pcg_exec));
-    if (pcg_graph) HIPCHECK(hipGraphDestroy(pcg_graph));
-    pcg_exec = nullptr;
-    pcg_graph = nullptr;
+    // (re)capture the chunk; when only buffer addresses changed, the existing executable
+    // graph is updated in place rather than rebuilt
     HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < kPcgChunk; ++k) {
       launch_pcg_spmv(V, TN, TS, B, k & 1, s);
@@ -1056,8 +1054,21 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
       if (graph) (void)hipGraphDestroy(graph);
       HIPCHECK(ec);
     }
+    bool updated = false;
+    if (pcg_exec) {
+      hipGraphNode_t err_node = nullptr;
+      hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+      updated = hipGraphExecUpdate(pcg_exec, graph, &err_node, &res) == hipSuccess &&
+                res == hipGraphExecUpdateSuccess;
+      if (!updated) {
+        (void)hipGetLastError();
+        HIPCHECK(hipGraphExecDestroy(pcg_exec));
+        pcg_exec = nullptr;
+      }
+    }
+    if (pcg_graph) HIPCHECK(hipGraphDestroy(pcg_graph));
     pcg_graph = graph;
-    HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
+    if (!updated) HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
     pcg_key = key;
   }
   for (int it = 0; it < B.max_iters; it += kPcgChunk) {
