@@ -220,7 +220,7 @@ struct Batch::Impl {
   // blocks, with the inverse of its rest-state operator per scene
   DBuf<int> cg_blk_agg, cg_agg_b0, cg_agg_b1, cg_sc_a0, cg_sc_m;
   DBuf<long long> cg_sc_off;
-  DBuf<double> cg_d, cg_ainv, cg_rc;  // T-typed storage (float in mixed mode)
+  DBuf<double> cg_d, cg_ainv, cg_rc;  // cg_d, cg_rc: T-typed storage; cg_ainv: float
   int cg_on = 0;
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
@@ -859,17 +859,19 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   cg_sc_m.upload(m, cg_sc_m_h);
   cg_sc_off.upload(m, cg_sc_off_h);
   cg_rc.ensure(m, 6 * (size_t)std::max(TN.nblk, 1));
-  if (mixed) {
-    const std::vector<float> df(cg_d_h.begin(), cg_d_h.end()), af(cg_ainv_h.begin(), cg_ainv_h.end());
-    cg_d.ensure(m, (df.size() + 1) / 2 + 1);
-    cg_ainv.ensure(m, (af.size() + 1) / 2 + 1);
-    h2d(reinterpret_cast<float*>(cg_d.p), df.data(), df.size());
+  {
+    const std::vector<float> af(cg_ainv_h.begin(), cg_ainv_h.end());
+    cg_ainv.ensure(m, af.size() / 2 + 1);
     h2d(reinterpret_cast<float*>(cg_ainv.p), af.data(), af.size());
-    sync();
+  }
+  if (mixed) {
+    const std::vector<float> df(cg_d_h.begin(), cg_d_h.end());
+    cg_d.ensure(m, df.size() / 2 + 1);
+    h2d(reinterpret_cast<float*>(cg_d.p), df.data(), df.size());
   } else {
     cg_d.upload(m, cg_d_h);
-    cg_ainv.upload(m, cg_ainv_h.empty() ? std::vector<double>(1, 0.0) : cg_ainv_h);
   }
+  sync();
   iters.ensure(m, S);
   bad.ensure(m, S);
   infeasible.ensure(m, S);
@@ -987,7 +989,7 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.cg_sc_m = cg_sc_m.p;
   B.cg_sc_off = cg_sc_off.p;
   B.cg_d = reinterpret_cast<const T*>(cg_d.p);
-  B.cg_ainv = reinterpret_cast<const T*>(cg_ainv.p);
+  B.cg_ainv = reinterpret_cast<const float*>(cg_ainv.p);
   B.cg_rc = reinterpret_cast<T*>(cg_rc.p);
   int max_pcg = 0;
   for (const auto& H : hs) max_pcg = std::max(max_pcg, H.max_pcg);

@@ -113,7 +113,7 @@ struct PcgBufsT {
   const int* cg_sc_m;         // [S] coarse dimension (6 per aggregate)
   const long long* cg_sc_off; // [S] offset of the scene's inverse coarse operator
   const T* cg_d;              // [nodes][3] scaled rest offset from the aggregate centroid
-  const T* cg_ainv;           // per scene m x m, row-major
+  const float* cg_ainv;       // per scene m x m, row-major (FP32: preconditioner only)
   T* cg_rc;                   // [TN blocks][6] restricted residual partials
 };
 constexpr int kCoarseMaxAgg = 128;  // aggregates per scene (coarse dimension <= 768)

@@ -1054,6 +1054,13 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+// N independent wavefront sums, interleaved so their shuffles overlap.
+template <class T, int N>
+__device__ __forceinline__ void wave_sum_n(T (&v)[N]) {
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], off, 64);
+}
 // Sum of a scene's block partials by one wavefront (fixed assignment and fixed tree).
 template <class T>
 __device__ __forceinline__ T scene_sum_wave(const T* P, const int* sblk, int s) {
@@ -1072,25 +1079,36 @@ __device__ T block_sum256t(T v, T* lds) {
   return r;
 }
 
-// Restriction of the residual onto the coarse space of the node's aggregate: the 6 rigid
-// modes u = t + w x d (d = scaled rest offset from the aggregate centroid) give P^T r =
-// (sum r, sum d x r) over the block's soft nodes.  One wave per 64-node block.
+// Block partials of r.z and r.r and, with the coarse level on, the restriction of the
+// residual onto the rigid modes u = t + w x d of the block's aggregate (d = scaled rest offset
+// from the aggregate centroid): P^T r = (sum r, sum d x r) over the block's soft nodes.  One
+// wave per 64-node block; lane 0 returns the sums.
 template <class T>
-__device__ __forceinline__ void restrict_block(const View& V, const PcgBufsT<T>& B, int n, bool live,
-                                               const T* r) {
-  T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-  if (live && V.ntype[n] == 0) {
-    const T* d = B.cg_d + 3 * n;
-    v[0] = r[0];
-    v[1] = r[1];
-    v[2] = r[2];
-    v[3] = d[1] * r[2] - d[2] * r[1];
-    v[4] = d[2] * r[0] - d[0] * r[2];
-    v[5] = d[0] * r[1] - d[1] * r[0];
+__device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>& B, int n, bool live,
+                                               const T* r, const T* z, T& rz, T& rr) {
+  T v[8] = {r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
+            (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  if (B.cg_on) {
+    if (live && V.ntype[n] == 0) {
+      const T* d = B.cg_d + 3 * n;
+      v[2] = r[0];
+      v[3] = r[1];
+      v[4] = r[2];
+      v[5] = d[1] * r[2] - d[2] * r[1];
+      v[6] = d[2] * r[0] - d[0] * r[2];
+      v[7] = d[0] * r[1] - d[1] * r[0];
+    }
+    wave_sum_n(v);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 6; ++k) B.cg_rc[6 * blockIdx.x + k] = v[2 + k];
+  } else {
+    T w[2] = {v[0], v[1]};
+    wave_sum_n(w);
+    v[0] = w[0];
+    v[1] = w[1];
   }
-  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 6; ++k) B.cg_rc[6 * blockIdx.x + k] = v[k];
+  rz = v[0];
+  rr = v[1];
 }
 
 // Preconditioned CG with two kernels per iteration k (parity = k & 1):
@@ -1127,9 +1145,8 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
     precond_apply<T>(V, B.pinv, n, n0, rs, z);
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
-  const T rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
-  const T rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-  if (B.cg_on) restrict_block<T>(V, B, n, live, r);
+  T rz, rr;
+  block_partials<T>(V, B, n, live, r, z, rz, rr);
   if (threadIdx.x == 0) {
     B.P_rz0[blockIdx.x] = rz;
     B.P_rz1[blockIdx.x] = (T)1;
@@ -1244,9 +1261,8 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
     precond_apply<T>(V, B.pinv, n, n0, rs, z);
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
-  const T rz = wave_sum(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
-  const T rr = wave_sum(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-  if (B.cg_on) restrict_block<T>(V, B, n, live, r);
+  T rz, rr;
+  block_partials<T>(V, B, n, live, r, z, rz, rr);
   if (threadIdx.x == 0) {
     Prz_new[blockIdx.x] = rz;
     B.P_rr[blockIdx.x] = rr;
@@ -1275,13 +1291,14 @@ __global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, Pcg
   }
   __syncthreads();
   const int la = a - a0;
-  const T* Ai = B.cg_ainv + B.cg_sc_off[s] + (size_t)6 * la * m;
-  T e[6];
-  for (int k = 0; k < 6; ++k) {
-    T acc = (T)0;
-    for (int j = threadIdx.x; j < m; j += kWave) acc += Ai[(size_t)k * m + j] * rcs[j];
-    e[k] = wave_sum(acc);
+  const float* Ai = B.cg_ainv + B.cg_sc_off[s] + (size_t)6 * la * m;
+  T e[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  for (int j = threadIdx.x; j < m; j += kWave) {
+    const T rj = rcs[j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] += (T)Ai[(size_t)k * m + j] * rj;
   }
+  wave_sum_n(e);
   if (threadIdx.x == 0 && blk == B.cg_agg_b0[a]) {
     T dot = (T)0;
     for (int k = 0; k < 6; ++k) dot += rcs[6 * la + k] * e[k];
