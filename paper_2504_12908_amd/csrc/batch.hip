@@ -58,6 +58,8 @@ struct Mem {
   }
   void release(void* p) {
     if (!p) return;
+    // work queued on the stream may still read the buffer
+    if (stream) (void)hipStreamSynchronize(stream);
     if (rt.free) rt.free(p, rt.ctx);
     else (void)hipFree(p);
   }
@@ -199,6 +201,8 @@ struct Batch::Impl {
   int n_cover = 0;
   bool device_touched = false;
   bool xn_valid = false;       // xn holds the positions at the start of the current step
+  std::vector<int> act_host;   // host copy of act for the current Newton iteration
+  int pcg_last_max = 0;        // largest PCG iteration count of the previous solve
   bool validate_only = false;  // build() stops after the host-side checks
   int mixed = 0;  // 1: FP32 Hessian blocks, assembly, SpMV and PCG (taccel_precision MIXED)
   // dynamic work buffers
@@ -273,9 +277,13 @@ struct Batch::Impl {
   }
   void ensure_scratch(size_t bytes) { scratch.ensure(&mem, bytes); }
   int scan(const int* in, int* out, int n) {
-    ensure_scratch(scan_scratch_bytes(n));
-    HIPCHECK(exclusive_scan(in, out, n, scalars.p, scratch.p, mem.stream));
+    scan_async(in, out, n, scalars.p);
     return read_int(scalars.p);
+  }
+  // exclusive scan whose total stays on the device
+  void scan_async(const int* in, int* out, int n, int* total) {
+    ensure_scratch(scan_scratch_bytes(n));
+    HIPCHECK(exclusive_scan(in, out, n, total, scratch.p, mem.stream));
   }
   void sort(uint64_t* keys, int* vals, uint64_t* tk, int* tv_, int n, int bits) {
     ensure_scratch(sort_scratch_bytes(n));
@@ -948,16 +956,20 @@ int Batch::Impl::broad_phase(const double* P0, const double* P1, int all, DBuf<i
   zero(bp.bcount, sizeof(int) * table);
   zero(bp.bfill, sizeof(int) * table);
   launch_bp_count(V, bp, s);
-  scan(bp.bcount, bp.bstart, table);
+  scan_async(bp.bcount, bp.bstart, table, scalars.p + 2);
   launch_bp_fill(V, bp, s);
   launch_bp_query(V, P0, P1, bp, all, 0, nullptr, nullptr, s);
-  const int ncand = scan(bp.qcount, bp.qoff, Nq);
+  scan_async(bp.qcount, bp.qoff, Nq, scalars.p);
+  int tot[2];  // candidates, overflow flag
+  d2h(tot, scalars.p, 2);
+  sync();
+  if (tot[1])
+    throw ApiError(TACCEL_NAN, "broad phase: a primitive box spans more than 64 cells per axis "
+                               "(positions exploded or non-finite)");
+  const int ncand = tot[0];
   oq.ensure(&mem, std::max(ncand, 1));
   ot.ensure(&mem, std::max(ncand, 1));
   launch_bp_query(V, P0, P1, bp, all, 1, oq.p, ot.p, s);
-  if (read_int(bp.overflow))
-    throw ApiError(TACCEL_NAN, "broad phase: a primitive box spans more than 64 cells per axis "
-                               "(positions exploded or non-finite)");
   return ncand;
 }
 
@@ -1073,7 +1085,13 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
     if (!updated) HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
     pcg_key = key;
   }
+  // chunks launched before the first convergence check: about 3/4 of the previous solve's
+  // iteration count (chunks after convergence return at once)
+  const int nfirst = std::max(1, std::min(8, (3 * pcg_last_max / 4) / kPcgChunk));
   for (int it = 0; it < B.max_iters; it += kPcgChunk) {
+    if (it == 0)
+      for (int c = 1; c < nfirst && (c + 1) * kPcgChunk <= B.max_iters; ++c, it += kPcgChunk)
+        HIPCHECK(hipGraphLaunch(pcg_exec, s));
     HIPCHECK(hipGraphLaunch(pcg_exec, s));
     d2h(hd.data(), pdone.p, S);
     sync();
@@ -1114,6 +1132,8 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   pg.ensure(&mem, 12 * (size_t)std::max(np, 1));
   ph.ensure(&mem, 144 * (size_t)std::max(np, 1));
   launch_compact_pairs(V, ncand, cqp, ctp, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
+  zero(scnt.p, sizeof(int) * (S + 1));
+  launch_count_scene(np, pscene.p, scnt.p, s);
   // ---- element derivatives
   launch_fem_hess(V, mixed, s);
   launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, s);
@@ -1127,8 +1147,12 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   hoff.ensure(&mem, std::max(nitems, 1));
   goff.ensure(&mem, std::max(nitems, 1));
   launch_contrib_count(V, np, pv.p, hcnt.p, gcnt.p, s);
-  const int nh = scan(hcnt.p, hoff.p, nitems);
-  const int ng = scan(gcnt.p, goff.p, nitems);
+  scan_async(hcnt.p, hoff.p, nitems, scalars.p + 3);
+  scan_async(gcnt.p, goff.p, nitems, scalars.p + 4);
+  int hg[2];
+  d2h(hg, scalars.p + 3, 2);
+  sync();
+  const int nh = hg[0], ng = hg[1];
   for (DBuf<uint64_t>* b : {&hkey, &hkey2}) b->ensure(&mem, std::max(nh, 1));
   for (DBuf<int>* b : {&hidx, &hidx2, &hsrc}) b->ensure(&mem, std::max(nh, 1));
   hcoef.ensure(&mem, std::max(nh, 1));
@@ -1153,7 +1177,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   zero(rowcnt.p, sizeof(int) * (Nn + 1));
   launch_reduce_blocks(V, nseg, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p, dcol.p,
                        dval.p, rowcnt.p, mixed, s);
-  scan(rowcnt.p, drowptr.p, Nn + 1);
+  scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
   // gradient entries
   launch_seg_flags(ng, gkey.p, sflag.p, s);
   const int ngseg = scan(sflag.p, segid.p, ng);
@@ -1165,9 +1189,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   {
     // pdone = !act
     std::vector<int> ha(S);
-    d2h(ha.data(), act.p, S);
-    sync();
-    for (int& a : ha) a = !a;
+    for (int k = 0; k < S; ++k) ha[k] = !act_host[k];
     h2d(pdone.p, ha.data(), S);
   }
   zero(iters.p, sizeof(int) * S);
@@ -1191,11 +1213,16 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   zero(pmax, sizeof(unsigned long long) * S);
   launch_pmax(V, dx.p, pmax, s);
   std::vector<unsigned long long> hp(S);
+  std::vector<int> hcount(S);
   d2h(hp.data(), pmax, S);
+  d2h(hcount.data(), scnt.p, S);
   sync();
-  std::vector<int> hact(S);
-  d2h(hact.data(), act.p, S);
-  sync();
+  const std::vector<int>& hact = act_host;
+  pcg_last_max = 0;
+  for (int k = 0; k < S; ++k) {
+    n_active[k] = hcount[k];
+    if (hact[k]) pcg_last_max = std::max(pcg_last_max, pcg_it[k]);
+  }
   for (int k = 0; k < S; ++k) {
     double pm;
     std::memcpy(&pm, &hp[k], sizeof(double));
@@ -1288,12 +1315,6 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   }
   h2d(alpha.p, alpha_h.data(), S);
   launch_update(V, dx.p, alpha.p, s);
-  // active pairs per scene (stats)
-  std::vector<int> hps(std::max(np, 1));
-  d2h(hps.data(), pscene.p, np);
-  sync();
-  std::fill(n_active.begin(), n_active.end(), 0);
-  for (int k = 0; k < np; ++k) n_active[hps[k]]++;
 }
 
 taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
@@ -1419,6 +1440,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
     if (nactive == 0) break;
     if (++guard > 1000000) throw ApiError(TACCEL_ERR_HIP, "internal: step state machine did not terminate");
     h2d(act.p, hact.data(), S);
+    act_host = hact;
     newton_iteration(last, lsf, nanf, pcg_it, nact, halv);
     std::vector<int> al_scene(S, 0);
     bool any_al = false;

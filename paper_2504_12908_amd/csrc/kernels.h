@@ -64,6 +64,7 @@ void launch_compact_pairs(const View& V, int n, const int* cand_q, const int* ca
                           int* pscene, hipStream_t s);
 
 // element derivatives
+void launch_count_scene(int n, const int* pscene, int* cnt, hipStream_t s);
 void launch_fem_hess(const View& V, int mixed, hipStream_t s);
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
                          const double* pmeps, double* pg, double* ph, hipStream_t s);

@@ -1313,6 +1313,12 @@ __global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, Pcg
   }
 }
 
+// Number of active pairs per scene (statistics).
+__global__ void k_count_scene(int n, const int* pscene, int* cnt) {
+  const int k = gid();
+  if (k < n) atomicAdd(cnt + pscene[k], 1);
+}
+
 // ------------------------------------------------------------------ convergence & CCD
 // Largest displacement component of the Newton direction per scene: free soft vertices and
 // affine-body vertices (J p).  Lanes of a wave that share a scene combine before the atomic.
@@ -1727,6 +1733,9 @@ void launch_compact_pairs(const View& V, int n, const int* cq, const int* ct, co
                           const int* pos, int* pkind, int* pv, double* pmeps, int* pscene,
                           hipStream_t s) {
   LAUNCH(k_compact_pairs, n, TPB, s, V, n, cq, ct, flag, pos, pkind, pv, pmeps, pscene);
+}
+void launch_count_scene(int n, const int* pscene, int* cnt, hipStream_t s) {
+  LAUNCH(k_count_scene, n, TPB, s, n, pscene, cnt);
 }
 void launch_fem_hess(const View& V, int mixed, hipStream_t s) {
   if (mixed) LAUNCH(k_fem_hess<float>, 4 * V.Nt, TPB, s, V);
