@@ -102,6 +102,9 @@ def run_single(args, taccel, scenes, np):
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
         roofline=_spmv_roofline(taccel),
     )
+    pcg = taccel.profile_query("pcg")
+    if pcg["launches"]:
+        out["pcg_us_per_iter"] = pcg["total_ms"] * 1e3 / pcg["launches"]
     sc.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, 1, 1)

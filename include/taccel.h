@@ -250,10 +250,14 @@ taccel_status taccel_debug_candidates(taccel_scene* s, const double* P0, const d
                                       int32_t* out, int32_t cap, int32_t* n);
 
 /* ---- Measurement --------------------------------------------------------------------
- * Process-wide HIP-event timing of the PCG sparse matrix-vector kernel ("spmv"), off by
- * default.  While enabled, every SpMV launch is bracketed by two events on the scene's
- * stream; query returns the summed kernel milliseconds, the number of launches and the
- * summed algorithmic bytes (values, indices and vectors the product must move once). */
+ * Process-wide HIP-event timing, off by default (it adds synchronisations).  While enabled:
+ *   "spmv": on every Newton iteration, 16 back-to-back launches of the PCG sparse-product
+ *     kernel on that iteration's matrix are timed between two events on the object's stream
+ *     (their outputs are recomputed by the solve); query returns the summed milliseconds, the
+ *     number of launches and the summed algorithmic bytes (values, indices and vectors the
+ *     product must move once);
+ *   "pcg": the PCG iterations of every solve (after initialisation) between two events;
+ *     query returns the summed milliseconds and iterations (largest count per solve). */
 void taccel_profile_enable(int32_t on);
 void taccel_profile_reset(void);
 taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t* launches,

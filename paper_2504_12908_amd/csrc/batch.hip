@@ -1088,6 +1088,7 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
   // chunks launched before the first convergence check: about 3/4 of the previous solve's
   // iteration count (chunks after convergence return at once)
   const int nfirst = std::max(1, std::min(8, (3 * pcg_last_max / 4) / kPcgChunk));
+  if (prof.on) HIPCHECK(hipEventRecord(ev_pool[2], s));
   for (int it = 0; it < B.max_iters; it += kPcgChunk) {
     if (it == 0)
       for (int c = 1; c < nfirst && (c + 1) * kPcgChunk <= B.max_iters; ++c, it += kPcgChunk)
@@ -1098,6 +1099,19 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
     bool all = true;
     for (int k = 0; k < S; ++k) all = all && hd[k];
     if (all) break;
+  }
+  if (prof.on) {
+    HIPCHECK(hipEventRecord(ev_pool[3], s));
+    HIPCHECK(hipEventSynchronize(ev_pool[3]));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, ev_pool[2], ev_pool[3]));
+    std::vector<int> it(S);
+    d2h(it.data(), iters.p, S);
+    sync();
+    int mx = 0;
+    for (int v : it) mx = std::max(mx, v);
+    prof.pcg_ms += ms;
+    prof.pcg_iters += mx;
   }
 }
 

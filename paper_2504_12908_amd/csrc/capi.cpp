@@ -259,17 +259,26 @@ void taccel_profile_reset(void) {
   p.spmv_ms = 0.0;
   p.spmv_launches = 0;
   p.spmv_bytes = 0.0;
+  p.pcg_ms = 0.0;
+  p.pcg_iters = 0;
 }
 
 taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t* launches,
                                    double* algorithmic_bytes) {
-  if (!kernel || std::strcmp(kernel, "spmv") != 0)
-    return fail(TACCEL_ERR_ARG, "profile_query: only \"spmv\" is instrumented");
   const tc::Profiler& p = tc::profiler();
-  if (total_ms) *total_ms = p.spmv_ms;
-  if (launches) *launches = p.spmv_launches;
-  if (algorithmic_bytes) *algorithmic_bytes = p.spmv_bytes;
-  return TACCEL_OK;
+  if (kernel && std::strcmp(kernel, "spmv") == 0) {
+    if (total_ms) *total_ms = p.spmv_ms;
+    if (launches) *launches = p.spmv_launches;
+    if (algorithmic_bytes) *algorithmic_bytes = p.spmv_bytes;
+    return TACCEL_OK;
+  }
+  if (kernel && std::strcmp(kernel, "pcg") == 0) {
+    if (total_ms) *total_ms = p.pcg_ms;
+    if (launches) *launches = p.pcg_iters;
+    if (algorithmic_bytes) *algorithmic_bytes = 0.0;
+    return TACCEL_OK;
+  }
+  return fail(TACCEL_ERR_ARG, "profile_query: \"spmv\" or \"pcg\"");
 }
 
 taccel_status taccel_device_synchronize(void) {

@@ -135,6 +135,8 @@ struct Profiler {
   double spmv_ms = 0.0;
   long long spmv_launches = 0;
   double spmv_bytes = 0.0;
+  double pcg_ms = 0.0;        // wall time of the PCG chunk replays (after initialisation)
+  long long pcg_iters = 0;    // iterations of those solves (largest per solve)
 };
 Profiler& profiler();
 
