@@ -1155,61 +1155,68 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
   }
 }
 
+// One wave covers 4 block-rows (16 lanes each); every wave computes the scene scalars
+// itself, so the row loads are not held back behind a workgroup barrier (the only barrier
+// is in the closing p.q reduction).
 template <class T>
 __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, BlockTable TS, PcgBufsT<T> B,
                                                       int parity) {
-  __shared__ T red[4];
-  __shared__ T beta_s;
-  __shared__ int conv_s;
   const int s = TS.sc[blockIdx.x];
   if (V.pdone[s]) return;
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   const T* Prz_old = parity ? B.P_rz0 : B.P_rz1;
   const T* pold = parity ? B.p1 : B.p0;
   T* pnew = parity ? B.p0 : B.p1;
-  if (threadIdx.x < kWave) {
-    const T rzc = scene_sum_wave(Prz_cur, TN.sblk, s), rzo = scene_sum_wave(Prz_old, TN.sblk, s);
-    const T rr = scene_sum_wave(B.P_rr, TN.sblk, s), gg = scene_sum_wave(B.P_gg, TN.sblk, s);
-    if (threadIdx.x == 0) {
-      const T eta = (T)V.sc[s].pcg_eta;
-      // iters[s] is only written by k_pcg_update, so every block sees the same count here
-      conv_s = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters;
-      beta_s = conv_s ? (T)0 : rzc / rzo;
-    }
-  }
-  __syncthreads();
-  const bool first = (int)blockIdx.x == TS.sblk[s];
-  if (conv_s) {
-    if (first && threadIdx.x == 0) V.pdone[s] = 1;
-    return;
-  }
-  const T beta = beta_s;
   const int sub = threadIdx.x & (kRowLanes - 1);
   const int row = TS.b0[blockIdx.x] + (int)(threadIdx.x / kRowLanes);
   const bool inrange = row < TS.b1[blockIdx.x];
   const bool live = inrange && V.nfree[row];
+  const int k0 = live ? V.rowptr[row] : 0, k1 = live ? V.rowptr[row + 1] : 0;
+  const int d0 = live ? B.drowptr[row] : 0, d1 = live ? B.drowptr[row + 1] : 0;
+  T rzc, rzo, rr, gg;
+  {
+    T v[4] = {(T)0, (T)0, (T)0, (T)0};
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int k = TN.sblk[s] + lane; k < TN.sblk[s + 1]; k += kWave) {
+      v[0] += Prz_cur[k];
+      v[1] += Prz_old[k];
+      v[2] += B.P_rr[k];
+      v[3] += B.P_gg[k];
+    }
+    wave_sum_n(v);
+    rzc = v[0];
+    rzo = v[1];
+    rr = v[2];
+    gg = v[3];
+  }
+  const T eta = (T)V.sc[s].pcg_eta;
+  // iters[s] is only written by k_pcg_update, so every wave sees the same count here
+  const bool conv = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters;
+  if (conv) {
+    if ((int)blockIdx.x == TS.sblk[s] && threadIdx.x == 0) V.pdone[s] = 1;
+    return;
+  }
+  const T beta = rzc / rzo;
   T q0 = (T)0, q1 = (T)0, q2 = (T)0;
-  if (live) {
-    for (int k = V.rowptr[row] + sub; k < V.rowptr[row + 1]; k += kRowLanes) {
-      const T* A = reinterpret_cast<const T*>(V.val) + 9 * (size_t)k;
-      const int c = V.col[k];
-      const T p0 = B.z[3 * c] + beta * pold[3 * c];
-      const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
-      const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
-      q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
-      q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
-      q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
-    }
-    for (int k = B.drowptr[row] + sub; k < B.drowptr[row + 1]; k += kRowLanes) {
-      const T* A = B.dval + 9 * (size_t)k;
-      const int c = B.dcol[k];
-      const T p0 = B.z[3 * c] + beta * pold[3 * c];
-      const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
-      const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
-      q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
-      q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
-      q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
-    }
+  for (int k = k0 + sub; k < k1; k += kRowLanes) {
+    const T* A = reinterpret_cast<const T*>(V.val) + 9 * (size_t)k;
+    const int c = V.col[k];
+    const T p0 = B.z[3 * c] + beta * pold[3 * c];
+    const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
+    const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
+    q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
+    q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
+    q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
+  }
+  for (int k = d0 + sub; k < d1; k += kRowLanes) {
+    const T* A = B.dval + 9 * (size_t)k;
+    const int c = B.dcol[k];
+    const T p0 = B.z[3 * c] + beta * pold[3 * c];
+    const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
+    const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
+    q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
+    q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
+    q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
   }
   for (int off = kRowLanes / 2; off > 0; off >>= 1) {
     q0 += __shfl_xor(q0, off, kRowLanes);
@@ -1228,6 +1235,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
     B.q[3 * row + 2] = q2;
     if (live) pq = pn[0] * q0 + pn[1] * q1 + pn[2] * q2;
   }
+  __shared__ T red[TPB / kWave];
   pq = block_sum256t(pq, red);
   if (threadIdx.x == 0) B.P_pq[blockIdx.x] = pq;
 }
@@ -1241,7 +1249,11 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   T* Prz_new = parity ? B.P_rz0 : B.P_rz1;
   const T* pk = parity ? B.p0 : B.p1;
-  const T rzs = scene_sum_wave(Prz_cur, TN.sblk, s), pqs = scene_sum_wave(B.P_pq, TS.sblk, s);
+  T tot[2] = {(T)0, (T)0};
+  for (int k = TN.sblk[s] + (int)threadIdx.x; k < TN.sblk[s + 1]; k += kWave) tot[0] += Prz_cur[k];
+  for (int k = TS.sblk[s] + (int)threadIdx.x; k < TS.sblk[s + 1]; k += kWave) tot[1] += B.P_pq[k];
+  wave_sum_n(tot);
+  const T rzs = tot[0], pqs = tot[1];
   const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
   const int n0 = TN.b0[blockIdx.x], n1 = TN.b1[blockIdx.x];
   const int n = n0 + threadIdx.x;
@@ -1276,40 +1288,52 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
 // the partial of r.z of the aggregate's first block.
 template <class T>
 __global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, PcgBufsT<T> B, T* prz) {
-  __shared__ T rcs[6 * kCoarseMaxAgg];
+  constexpr int kPerLane = 6 * kCoarseMaxAgg / kWave;  // coarse entries per lane (at most)
   const int blk = blockIdx.x;
   const int s = TN.sc[blk];
   if (V.pdone[s]) return;
   const int a = B.cg_blk_agg[blk];
   if (a < 0) return;
-  const int a0 = B.cg_sc_a0[s], m = B.cg_sc_m[s];
-  for (int i = threadIdx.x; i < m; i += kWave) {
-    const int ag = a0 + i / 6, k = i % 6;
-    T acc = (T)0;
-    for (int b = B.cg_agg_b0[ag]; b < B.cg_agg_b1[ag]; ++b) acc += B.cg_rc[6 * b + k];
-    rcs[i] = acc;
-  }
-  __syncthreads();
-  const int la = a - a0;
+  const int a0 = B.cg_sc_a0[s], m = B.cg_sc_m[s], la = a - a0;
+  const int lane = threadIdx.x;
+  // the block's own node (issued early: independent of the coarse solve)
+  const int n = TN.b0[blk] + lane;
+  const bool mine = n < TN.b1[blk] && V.ntype[n] == 0 && V.nfree[n];
+  T dn[3] = {(T)0, (T)0, (T)0};
+  if (mine)
+    for (int c = 0; c < 3; ++c) dn[c] = B.cg_d[3 * n + c];
+  // e = rows 6 la .. 6 la + 5 of A_c^{-1} times r_c; lane j-slices of r_c summed from the
+  // block partials of their aggregates
   const float* Ai = B.cg_ainv + B.cg_sc_off[s] + (size_t)6 * la * m;
+  // aggregates are runs of grp consecutive blocks from the scene's first block sb (the last
+  // run may be shorter), so a lane's block indices are plain arithmetic
+  const int sb = B.cg_agg_b0[a0], grp = B.cg_agg_b1[a0] - sb, send = B.cg_agg_b1[a0 + m / 6 - 1];
   T e[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-  for (int j = threadIdx.x; j < m; j += kWave) {
-    const T rj = rcs[j];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) e[k] += (T)Ai[(size_t)k * m + j] * rj;
+  for (int t = 0; t < kPerLane; ++t) {
+    const int j = lane + kWave * t;
+    if (j < m) {
+      const int b0 = sb + (j / 6) * grp, b1 = min(b0 + grp, send), k = j % 6;
+      T rj = B.cg_rc[6 * b0 + k];
+      for (int b = b0 + 1; b < b1; ++b) rj += B.cg_rc[6 * b + k];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) e[r] += (T)Ai[(size_t)r * m + j] * rj;
+    }
   }
   wave_sum_n(e);
-  if (threadIdx.x == 0 && blk == B.cg_agg_b0[a]) {
+  if (lane == 0 && blk == B.cg_agg_b0[a]) {
     T dot = (T)0;
-    for (int k = 0; k < 6; ++k) dot += rcs[6 * la + k] * e[k];
+    for (int k = 0; k < 6; ++k) {
+      T rk = (T)0;
+      for (int b = B.cg_agg_b0[a]; b < B.cg_agg_b1[a]; ++b) rk += B.cg_rc[6 * b + k];
+      dot += rk * e[k];
+    }
     prz[blk] += dot;
   }
-  const int n = TN.b0[blk] + (int)threadIdx.x;
-  if (n < TN.b1[blk] && V.ntype[n] == 0 && V.nfree[n]) {
-    const T* d = B.cg_d + 3 * n;
-    B.z[3 * n] += e[0] + (e[4] * d[2] - e[5] * d[1]);
-    B.z[3 * n + 1] += e[1] + (e[5] * d[0] - e[3] * d[2]);
-    B.z[3 * n + 2] += e[2] + (e[3] * d[1] - e[4] * d[0]);
+  if (mine) {
+    B.z[3 * n] += e[0] + (e[4] * dn[2] - e[5] * dn[1]);
+    B.z[3 * n + 1] += e[1] + (e[5] * dn[0] - e[3] * dn[2]);
+    B.z[3 * n + 2] += e[2] + (e[3] * dn[1] - e[4] * dn[0]);
   }
 }
 
