@@ -895,7 +895,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   dE.ensure(m, kTrials * (size_t)S);
   part_nodes.ensure(m, kTrials * (size_t)std::max(TN.nblk, 1));
   part_tets.ensure(m, kTrials * (size_t)std::max(TT.nblk, 1));
-  e_bodies.ensure(m, kTrials * (size_t)std::max(Nb, 1));
+  e_bodies.ensure(m, (kTrials + 1) * (size_t)std::max(Nb, 1));
   scalars.ensure(m, 16);
   rowcnt.ensure(m, Nn + 1);
   drowptr.ensure(m, Nn + 1);
@@ -1265,7 +1265,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   std::vector<double> amax(S), alpha_h(S, 0.0);
   for (int k = 0; k < S; ++k) std::memcpy(&amax[k], &ha[k], sizeof(double));
   // ---- line search (8 step sizes per launch)
-  e_pairs.ensure(&mem, kTrials * (size_t)std::max(nsw, 1));
+  e_pairs.ensure(&mem, (kTrials + 1) * (size_t)std::max(nsw, 1));
   LsBufs L;
   L.p = dx.p;
   L.abase = abase.p;

@@ -442,7 +442,11 @@ TC_HD double barrier_energy(int kind, const double* x12, double meps, double dha
 // on the other).  Advance by a fraction of distance / lp; stop before the distance falls
 // below gap_ratio * d(0), return 1 once the whole step is covered.  max_iter bounds the
 // loop (the time reached so far is returned, which is still safe).
-TC_HD double accd(int kind, const double* x12, const double* p12, double gap_ratio, int max_iter) {
+// stop_at (nullable): the running minimum over other pairs (a double's bits, non-negative);
+// once t reaches it, this pair cannot lower the minimum and the loop ends early (the
+// minimum over all pairs is unchanged).
+TC_HD double accd(int kind, const double* x12, const double* p12, double gap_ratio, int max_iter,
+                  const unsigned long long* stop_at = nullptr) {
   double q[12];
   for (int c = 0; c < 3; ++c) {
     const double mean = 0.25 * (p12[c] + p12[3 + c] + p12[6 + c] + p12[9 + c]);
@@ -466,6 +470,12 @@ TC_HD double accd(int kind, const double* x12, const double* p12, double gap_rat
     t = tn;
     if (t > 1.0) return 1.0;
     step = 0.9 * d / lp;
+    if (stop_at && (it & 15) == 15) {
+      const unsigned long long bits = *(volatile const unsigned long long*)stop_at;
+      double m;
+      __builtin_memcpy(&m, &bits, sizeof(double));
+      if (t >= m) return t;
+    }
   }
   return t;
 }

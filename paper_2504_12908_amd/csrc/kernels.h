@@ -150,8 +150,8 @@ struct LsBufs {
   const double* abase;    // [S] largest trial step of this launch
   double* part_nodes;     // [node blocks][8]
   double* part_tets;      // [tet blocks][8]
-  double* e_bodies;       // [Nb][8]
-  double* e_pairs;        // [ncand][8]
+  double* e_bodies;       // [Nb][9] energy at the current point, then at the 8 trials
+  double* e_pairs;        // [ncand][9] same layout
   int* infeasible;        // [S] bit k: trial k hits J <= 0 or d <= 0
   const int* cand_off;    // [S+1]
   double* dE;             // [S][8]

@@ -1385,8 +1385,9 @@ __global__ void k_ccd(View V, int n, const int* cq, const int* ct, unsigned long
   double x12[12], p12[12];
   gather12(V.cpos, ids, x12);
   gather12(V.cdisp, ids, p12);
-  const double t = accd(kind, x12, p12, 0.1, 100000);
-  atomic_min_pos(amin + V.qscene[cq[k]], t);
+  unsigned long long* am = amin + V.qscene[cq[k]];
+  const double t = accd(kind, x12, p12, 0.1, 100000, am);
+  atomic_min_pos(am, t);
 }
 
 // off[s] = first candidate of scene s (candidates are sorted by scene); off[S] = n.
@@ -1491,26 +1492,31 @@ __device__ double body_energy(const View& V, int b, const double* y, const Scene
   return e;
 }
 
+// Bodies and contact pairs: one thread per (element, trial) with trial index 0 for the
+// current point and 1 + k for step size k; the energy differences are formed by the
+// reduction (the current point's energy is finite by construction).
+constexpr int kLsSlots = kTrials + 1;
 __global__ void k_ls_bodies(View V, LsBufs L) {
-  const int b = gid();
+  const int g = gid();
+  const int b = g / kLsSlots, slot = g % kLsSlots;
   if (b >= V.Nb) return;
   const int s = V.bscene[b];
-  for (int k = 0; k < kTrials; ++k) L.e_bodies[kTrials * b + k] = 0.0;
-  if (!V.act[s] || V.bsnap[b]) return;
+  if (!V.act[s] || V.bsnap[b]) {
+    L.e_bodies[kLsSlots * b + slot] = 0.0;
+    return;
+  }
   const SceneConst& sc = V.sc[s];
   const double* y = V.x + 3 * V.bnode[b];
   const double* p = L.p + 3 * V.bnode[b];
-  const double e0 = body_energy(V, b, y, sc);
-  for (int k = 0; k < kTrials; ++k) {
-    const double a = trial_alpha(L.abase, s, k);
-    double yt[12];
-    for (int i = 0; i < 12; ++i) yt[i] = y[i] + a * p[i];
-    L.e_bodies[kTrials * b + k] = body_energy(V, b, yt, sc) - e0;
-  }
+  const double a = slot == 0 ? 0.0 : trial_alpha(L.abase, s, slot - 1);
+  double yt[12];
+  for (int i = 0; i < 12; ++i) yt[i] = slot == 0 ? y[i] : y[i] + a * p[i];
+  L.e_bodies[kLsSlots * b + slot] = body_energy(V, b, yt, sc);
 }
 
 __global__ void k_ls_pairs(View V, int n, const int* cq, const int* ct, LsBufs L) {
-  const int k = gid();
+  const int g = gid();
+  const int k = g / kLsSlots, slot = g % kLsSlots;
   if (k >= n) return;
   const int s = V.qscene[cq[k]];
   const SceneConst& sc = V.sc[s];
@@ -1521,36 +1527,45 @@ __global__ void k_ls_pairs(View V, int n, const int* cq, const int* ct, LsBufs L
   gather12(V.cdisp, ids, p12);
   const double meps = kind == 1 ? 1e-3 * V.elen2[V.qidx[cq[k]]] * V.elen2[ct[k]] : 0.0;
   const double kap = sc.h * sc.h * sc.kappa;
-  const double e0 = barrier_energy(kind, x12, meps, sc.dhat, kap);
-  int bad = 0;
-  for (int j = 0; j < kTrials; ++j) {
-    const double a = trial_alpha(L.abase, s, j);
+  double e;
+  if (slot == 0) {
+    e = barrier_energy(kind, x12, meps, sc.dhat, kap);
+  } else {
+    const double a = trial_alpha(L.abase, s, slot - 1);
     double xt[12];
     for (int i = 0; i < 12; ++i) xt[i] = x12[i] + a * p12[i];
-    const double e = barrier_energy(kind, xt, meps, sc.dhat, kap);
-    double d = 0.0;
-    if (isinf(e)) bad |= 1 << j;
-    else d = e - e0;
-    L.e_pairs[kTrials * (size_t)k + j] = d;
+    e = barrier_energy(kind, xt, meps, sc.dhat, kap);
+    if (isinf(e)) atomicOr(L.infeasible + s, 1 << (slot - 1));
   }
-  if (bad) atomicOr(L.infeasible + s, bad);
+  L.e_pairs[kLsSlots * (size_t)k + slot] = e;
 }
 
+// Per scene: dE[k] = sum over the scene's node and tet partials, bodies and pairs, all 8
+// trials in one pass (fixed assignment and order, so the sums are deterministic).
 __global__ void __launch_bounds__(TPB) k_ls_reduce(View V, BlockTable TN, BlockTable TT, LsBufs L) {
-  __shared__ double red[4];
+  __shared__ double red[TPB / kWave][kTrials];
   const int s = blockIdx.x;
   if (!V.act[s]) return;
   const int t = threadIdx.x;
-  for (int k = 0; k < kTrials; ++k) {
-    double acc = 0.0;
-    for (int b = TN.sblk[s] + t; b < TN.sblk[s + 1]; b += TPB) acc += L.part_nodes[kTrials * b + k];
-    for (int b = TT.sblk[s] + t; b < TT.sblk[s + 1]; b += TPB) acc += L.part_tets[kTrials * b + k];
-    for (int b = V.sc[s].body0 + t; b < V.sc[s].body1; b += TPB) acc += L.e_bodies[kTrials * b + k];
-    for (int c = L.cand_off[s] + t; c < L.cand_off[s + 1]; c += TPB)
-      acc += L.e_pairs[kTrials * (size_t)c + k];
-    acc = block_sum256(acc, red);
-    if (t == 0) L.dE[kTrials * s + k] = acc;
+  double acc[kTrials];
+  for (int k = 0; k < kTrials; ++k) acc[k] = 0.0;
+  for (int b = TN.sblk[s] + t; b < TN.sblk[s + 1]; b += TPB)
+    for (int k = 0; k < kTrials; ++k) acc[k] += L.part_nodes[kTrials * b + k];
+  for (int b = TT.sblk[s] + t; b < TT.sblk[s + 1]; b += TPB)
+    for (int k = 0; k < kTrials; ++k) acc[k] += L.part_tets[kTrials * b + k];
+  for (int b = V.sc[s].body0 + t; b < V.sc[s].body1; b += TPB) {
+    const double* e = L.e_bodies + kLsSlots * b;
+    for (int k = 0; k < kTrials; ++k) acc[k] += e[1 + k] - e[0];
   }
+  for (int c = L.cand_off[s] + t; c < L.cand_off[s + 1]; c += TPB) {
+    const double* e = L.e_pairs + kLsSlots * (size_t)c;
+    for (int k = 0; k < kTrials; ++k) acc[k] += isinf(e[1 + k]) ? 0.0 : e[1 + k] - e[0];
+  }
+  wave_sum_n(acc);
+  if ((t & (kWave - 1)) == 0)
+    for (int k = 0; k < kTrials; ++k) red[t / kWave][k] = acc[k];
+  __syncthreads();
+  if (t < kTrials) L.dE[kTrials * s + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
 __global__ void k_update(View V, const double* p, const double* alpha) {
@@ -1867,8 +1882,8 @@ void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& T
                         const int* cq, const int* ct, const LsBufs& L, hipStream_t s) {
   if (TN.nblk > 0) hipLaunchKernelGGL(k_ls_nodes, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, L);
   if (TT.nblk > 0) hipLaunchKernelGGL(k_ls_tets, dim3(TT.nblk), dim3(TPB), 0, s, V, TT, L);
-  LAUNCH(k_ls_bodies, V.Nb, 64, s, V, L);
-  LAUNCH(k_ls_pairs, ncand, 64, s, V, ncand, cq, ct, L);
+  LAUNCH(k_ls_bodies, kLsSlots * V.Nb, 64, s, V, L);
+  LAUNCH(k_ls_pairs, kLsSlots * ncand, 64, s, V, ncand, cq, ct, L);
   hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(TPB), 0, s, V, TN, TT, L);
 }
 void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s) {
