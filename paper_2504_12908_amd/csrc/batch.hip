@@ -228,7 +228,12 @@ struct Batch::Impl {
   int cg_on = 0;
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
-  DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs;
+  DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs, part_pairs;
+  // swept candidates in blocks of one scene (line-search partial sums), rebuilt per iteration
+  static constexpr int kPairChunk = 1024;
+  std::vector<int> tp_sc_h, tp_c0_h, tp_c1_h, tp_sblk_h;
+  DBuf<int> tp_sc, tp_b0, tp_b1, tp_sblk;
+  BlockTable TP;
   DBuf<int> scalars;  // device scalars for scan totals
   DBuf<char> scratch;
   DBuf<int> mv_nodes;
@@ -1261,9 +1266,36 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   std::vector<unsigned long long> ha(S);
   d2h(ha.data(), amin, S);
   launch_scene_offsets(V, nsw, sq.p, cand_off.p, s);
+  std::vector<int> hoffs(S + 1);
+  d2h(hoffs.data(), cand_off.p, S + 1);
   sync();
   std::vector<double> amax(S), alpha_h(S, 0.0);
   for (int k = 0; k < S; ++k) std::memcpy(&amax[k], &ha[k], sizeof(double));
+  // blocks of at most kPairChunk swept candidates of one scene (line-search partial sums)
+  {
+    tp_sc_h.clear();
+    tp_c0_h.clear();
+    tp_c1_h.clear();
+    tp_sblk_h.assign(1, 0);
+    for (int k = 0; k < S; ++k) {
+      for (int c0 = hoffs[k]; c0 < hoffs[k + 1]; c0 += kPairChunk) {
+        tp_sc_h.push_back(k);
+        tp_c0_h.push_back(c0);
+        tp_c1_h.push_back(std::min(c0 + kPairChunk, hoffs[k + 1]));
+      }
+      tp_sblk_h.push_back((int)tp_sc_h.size());
+    }
+    tp_sc.upload(&mem, tp_sc_h);
+    tp_b0.upload(&mem, tp_c0_h);
+    tp_b1.upload(&mem, tp_c1_h);
+    tp_sblk.upload(&mem, tp_sblk_h);
+    TP.nblk = (int)tp_sc_h.size();
+    TP.sc = tp_sc.p;
+    TP.b0 = tp_b0.p;
+    TP.b1 = tp_b1.p;
+    TP.sblk = tp_sblk.p;
+    part_pairs.ensure(&mem, kTrials * (size_t)std::max(TP.nblk, 1));
+  }
   // ---- line search (8 step sizes per launch)
   e_pairs.ensure(&mem, (kTrials + 1) * (size_t)std::max(nsw, 1));
   LsBufs L;
@@ -1275,6 +1307,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   L.e_pairs = e_pairs.p;
   L.infeasible = infeasible.p;
   L.cand_off = cand_off.p;
+  L.part_pairs = part_pairs.p;
   L.dE = dE.p;
   std::vector<int> pending(S, 0);
   std::vector<double> base(S);
@@ -1296,7 +1329,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   for (int round = 0; npending > 0; ++round) {
     h2d(abase.p, base.data(), S);
     zero(infeasible.p, sizeof(int) * S);
-    launch_line_search(V, TN, TT, nsw, sq.p, st.p, L, s);
+    launch_line_search(V, TN, TT, TP, nsw, sq.p, st.p, L, s);
     d2h(hdE.data(), dE.p, hdE.size());
     d2h(hinf.data(), infeasible.p, S);
     sync();
@@ -1597,7 +1630,8 @@ size_t Batch::Impl::device_bytes() const {
   add(pkind); add(pv); add(pscene); add(hcnt); add(gcnt); add(hoff); add(goff); add(hidx); add(gidx);
   add(hsrc); add(gsrc); add(hidx2); add(gidx2); add(hkey); add(gkey); add(hkey2); add(gkey2);
   add(sflag); add(segid); add(segstart); add(drow); add(dcol); add(rowcnt); add(drowptr); add(scratch);
-  add(e_pairs); add(part_nodes); add(part_tets);
+  add(e_pairs); add(part_nodes); add(part_tets); add(part_pairs);
+  add(tp_sc); add(tp_b0); add(tp_b1); add(tp_sblk);
   add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
   add(cg_d); add(cg_ainv); add(cg_rc);
   return n;
@@ -1660,7 +1694,8 @@ Batch::~Batch() {
            &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,
            &I.cend, &I.elen2, &I.bp_tbox, &I.pmeps, &I.pg, &I.ph, &I.hcoef, &I.gcoef, &I.dval, &I.g, &I.r,
            &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
-           &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs)
+           &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs, &I.part_pairs)
+  FREE_ALL(&I.tp_sc, &I.tp_b0, &I.tp_b1, &I.tp_sblk)
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m)
   FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc)

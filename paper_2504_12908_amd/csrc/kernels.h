@@ -154,10 +154,11 @@ struct LsBufs {
   double* e_pairs;        // [ncand][9] same layout
   int* infeasible;        // [S] bit k: trial k hits J <= 0 or d <= 0
   const int* cand_off;    // [S+1]
+  double* part_pairs;     // [pair blocks][8] sums of the pair energy differences
   double* dE;             // [S][8]
 };
-void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, int ncand,
-                        const int* cand_q, const int* cand_t, const LsBufs& L, hipStream_t s);
+void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, const BlockTable& TP,
+                        int ncand, const int* cand_q, const int* cand_t, const LsBufs& L, hipStream_t s);
 void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s);
 void launch_al_apply(const View& V, const int* action, hipStream_t s);
 void launch_body_reset(const View& V, double kappa0, hipStream_t s);

@@ -501,6 +501,14 @@ template <int N>
 __device__ void wave_psd(double (&A)[2][N * N], double (&Vm)[2][N * N], double* cs, double* sn) {
   constexpr int NN = N * N, H = N / 2;
   const int lane = threadIdx.x;
+  // round-robin schedule: partner of index i in round r and the slot of that pair
+  __shared__ signed char partner[N - 1][N], slot[N - 1][N];
+  for (int e = lane; e < (N - 1) * N; e += 64) {
+    const int r = e / N, i = e % N;
+    const int pi = tour_pos<N>(i, r);
+    partner[r][i] = (signed char)tour_index<N>(N - 1 - pi, r);
+    slot[r][i] = (signed char)(pi < H ? pi : N - 1 - pi);
+  }
   int cur = 0;
   for (int e = lane; e < NN; e += 64) Vm[0][e] = (e / N == e % N) ? 1.0 : 0.0;
   __syncthreads();
@@ -537,19 +545,15 @@ __device__ void wave_psd(double (&A)[2][N * N], double (&Vm)[2][N * N], double* 
         const bool isV = e >= NN;
         const int ee = isV ? e - NN : e;
         const int i = ee / N, j = ee % N;
-        // rotation acting on column j: partner index and coefficients
-        const int pj = tour_pos<N>(j, r), kj = pj < H ? pj : N - 1 - pj;
-        const int oj = tour_index<N>(N - 1 - pj, r);
-        const double cj = cs[kj], sj = sn[kj];
-        // J[j][j] = c; J[oj][j] = -s if j is the smaller index of its pair, else +s
-        const double jjj = cj, joj = j < oj ? -sj : sj;
+        // rotation acting on column j: J[j][j] = c; J[oj][j] = -s if j is the smaller index
+        // of its pair, else +s
+        const int oj = partner[r][j], kj = slot[r][j];
+        const double jjj = cs[kj], joj = j < oj ? -sn[kj] : sn[kj];
         if (isV) {
           Vm[nxt][ee] = Vm[cur][N * i + j] * jjj + Vm[cur][N * i + oj] * joj;
         } else {
-          const int pi = tour_pos<N>(i, r), ki = pi < H ? pi : N - 1 - pi;
-          const int oi = tour_index<N>(N - 1 - pi, r);
-          const double ci = cs[ki], si = sn[ki];
-          const double jii = ci, joi = i < oi ? -si : si;
+          const int oi = partner[r][i], ki = slot[r][i];
+          const double jii = cs[ki], joi = i < oi ? -sn[ki] : sn[ki];
           const double a_ij = A[cur][N * i + j], a_ioj = A[cur][N * i + oj];
           const double a_oij = A[cur][N * oi + j], a_oioj = A[cur][N * oi + oj];
           A[nxt][ee] = jii * (a_ij * jjj + a_ioj * joj) + joi * (a_oij * jjj + a_oioj * joj);
@@ -1540,9 +1544,30 @@ __global__ void k_ls_pairs(View V, int n, const int* cq, const int* ct, LsBufs L
   L.e_pairs[kLsSlots * (size_t)k + slot] = e;
 }
 
-// Per scene: dE[k] = sum over the scene's node and tet partials, bodies and pairs, all 8
-// trials in one pass (fixed assignment and order, so the sums are deterministic).
-__global__ void __launch_bounds__(TPB) k_ls_reduce(View V, BlockTable TN, BlockTable TT, LsBufs L) {
+// Energy differences of the swept pairs summed per block of one scene's candidates.
+__global__ void __launch_bounds__(TPB) k_ls_pair_sums(View V, BlockTable TP, LsBufs L) {
+  __shared__ double red[TPB / kWave][kTrials];
+  const int s = TP.sc[blockIdx.x];
+  if (!V.act[s]) return;
+  const int t = threadIdx.x;
+  double acc[kTrials];
+  for (int k = 0; k < kTrials; ++k) acc[k] = 0.0;
+  for (int c = TP.b0[blockIdx.x] + t; c < TP.b1[blockIdx.x]; c += TPB) {
+    const double* e = L.e_pairs + kLsSlots * (size_t)c;
+    for (int k = 0; k < kTrials; ++k) acc[k] += isinf(e[1 + k]) ? 0.0 : e[1 + k] - e[0];
+  }
+  wave_sum_n(acc);
+  if ((t & (kWave - 1)) == 0)
+    for (int k = 0; k < kTrials; ++k) red[t / kWave][k] = acc[k];
+  __syncthreads();
+  if (t < kTrials)
+    L.part_pairs[kTrials * blockIdx.x + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
+// Per scene: dE[k] = sum over the scene's node, tet and pair-block partials and its bodies,
+// all 8 trials in one pass (fixed assignment and order, so the sums are deterministic).
+__global__ void __launch_bounds__(TPB) k_ls_reduce(View V, BlockTable TN, BlockTable TT, BlockTable TP,
+                                                   LsBufs L) {
   __shared__ double red[TPB / kWave][kTrials];
   const int s = blockIdx.x;
   if (!V.act[s]) return;
@@ -1557,10 +1582,8 @@ __global__ void __launch_bounds__(TPB) k_ls_reduce(View V, BlockTable TN, BlockT
     const double* e = L.e_bodies + kLsSlots * b;
     for (int k = 0; k < kTrials; ++k) acc[k] += e[1 + k] - e[0];
   }
-  for (int c = L.cand_off[s] + t; c < L.cand_off[s + 1]; c += TPB) {
-    const double* e = L.e_pairs + kLsSlots * (size_t)c;
-    for (int k = 0; k < kTrials; ++k) acc[k] += isinf(e[1 + k]) ? 0.0 : e[1 + k] - e[0];
-  }
+  for (int b = TP.sblk[s] + t; b < TP.sblk[s + 1]; b += TPB)
+    for (int k = 0; k < kTrials; ++k) acc[k] += L.part_pairs[kTrials * b + k];
   wave_sum_n(acc);
   if ((t & (kWave - 1)) == 0)
     for (int k = 0; k < kTrials; ++k) red[t / kWave][k] = acc[k];
@@ -1878,13 +1901,14 @@ void launch_ccd(const View& V, int n, const int* cq, const int* ct, unsigned lon
 void launch_scene_offsets(const View& V, int n, const int* cq, int* off, hipStream_t s) {
   LAUNCH(k_scene_offsets, n + 1, TPB, s, V, n, cq, off);
 }
-void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, int ncand,
-                        const int* cq, const int* ct, const LsBufs& L, hipStream_t s) {
+void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, const BlockTable& TP,
+                        int ncand, const int* cq, const int* ct, const LsBufs& L, hipStream_t s) {
   if (TN.nblk > 0) hipLaunchKernelGGL(k_ls_nodes, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, L);
   if (TT.nblk > 0) hipLaunchKernelGGL(k_ls_tets, dim3(TT.nblk), dim3(TPB), 0, s, V, TT, L);
   LAUNCH(k_ls_bodies, kLsSlots * V.Nb, 64, s, V, L);
   LAUNCH(k_ls_pairs, kLsSlots * ncand, 64, s, V, ncand, cq, ct, L);
-  hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(TPB), 0, s, V, TN, TT, L);
+  if (TP.nblk > 0) hipLaunchKernelGGL(k_ls_pair_sums, dim3(TP.nblk), dim3(TPB), 0, s, V, TP, L);
+  hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(TPB), 0, s, V, TN, TT, TP, L);
 }
 void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s) {
   LAUNCH(k_update, V.Nn, TPB, s, V, p, alpha);
