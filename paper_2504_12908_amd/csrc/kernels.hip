@@ -1050,6 +1050,16 @@ __device__ __forceinline__ void precond_apply(const View& V, const T* pinv, int 
 
 // Node-parallel PCG kernels run one wavefront (64 nodes) per block of the table T; the
 // sparse product runs 16 lanes per block-row over the table TS (16 rows per block).
+// Workgroups are dealt to the 8 XCDs round-robin in launch order; the PCG kernels remap the
+// launch index so that each XCD takes one contiguous run of table blocks (with the Morton
+// node order, a compact part of the mesh whose vector entries stay in that XCD's L2).
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int xcd_grid(int nblk) { return (nblk + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_block(int nblk) {
+  const int per = (nblk + kXcds - 1) / kXcds;
+  const int logical = ((int)blockIdx.x % kXcds) * per + (int)blockIdx.x / kXcds;
+  return logical < nblk ? logical : -1;
+}
 constexpr int kWave = 64;
 constexpr int kRowLanes = 16;
 
@@ -1088,7 +1098,7 @@ __device__ T block_sum256t(T v, T* lds) {
 // from the aggregate centroid): P^T r = (sum r, sum d x r) over the block's soft nodes.  One
 // wave per 64-node block; lane 0 returns the sums.
 template <class T>
-__device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>& B, int n, bool live,
+__device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>& B, int blk, int n, bool live,
                                                const T* r, const T* z, T& rz, T& rr) {
   T v[8] = {r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
             (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
@@ -1104,7 +1114,7 @@ __device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>&
     }
     wave_sum_n(v);
     if (threadIdx.x == 0)
-      for (int k = 0; k < 6; ++k) B.cg_rc[6 * blockIdx.x + k] = v[2 + k];
+      for (int k = 0; k < 6; ++k) B.cg_rc[6 * blk + k] = v[2 + k];
   } else {
     T w[2] = {v[0], v[1]};
     wave_sum_n(w);
@@ -1126,10 +1136,12 @@ __device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>&
 // system and adds P e to z and r_c . e to the block partials of r.z.
 template <class T>
 __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBufsT<T> B) {
+  const int blk = xcd_block(TN.nblk);
+  if (blk < 0) return;
   __shared__ T rs[kWave][3];
-  const int s = TN.sc[blockIdx.x];
+  const int s = TN.sc[blk];
   if (V.pdone[s]) return;
-  const int n0 = TN.b0[blockIdx.x], n1 = TN.b1[blockIdx.x];
+  const int n0 = TN.b0[blk], n1 = TN.b1[blk];
   const int n = n0 + threadIdx.x;
   const bool live = n < n1;
   T r[3] = {(T)0, (T)0, (T)0};
@@ -1150,12 +1162,12 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
   T rz, rr;
-  block_partials<T>(V, B, n, live, r, z, rz, rr);
+  block_partials<T>(V, B, blk, n, live, r, z, rz, rr);
   if (threadIdx.x == 0) {
-    B.P_rz0[blockIdx.x] = rz;
-    B.P_rz1[blockIdx.x] = (T)1;
-    B.P_gg[blockIdx.x] = rr;
-    B.P_rr[blockIdx.x] = rr;
+    B.P_rz0[blk] = rz;
+    B.P_rz1[blk] = (T)1;
+    B.P_gg[blk] = rr;
+    B.P_rr[blk] = rr;
   }
 }
 
@@ -1165,15 +1177,17 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
 template <class T>
 __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, BlockTable TS, PcgBufsT<T> B,
                                                       int parity) {
-  const int s = TS.sc[blockIdx.x];
+  const int blk = xcd_block(TS.nblk);
+  if (blk < 0) return;
+  const int s = TS.sc[blk];
   if (V.pdone[s]) return;
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   const T* Prz_old = parity ? B.P_rz0 : B.P_rz1;
   const T* pold = parity ? B.p1 : B.p0;
   T* pnew = parity ? B.p0 : B.p1;
   const int sub = threadIdx.x & (kRowLanes - 1);
-  const int row = TS.b0[blockIdx.x] + (int)(threadIdx.x / kRowLanes);
-  const bool inrange = row < TS.b1[blockIdx.x];
+  const int row = TS.b0[blk] + (int)(threadIdx.x / kRowLanes);
+  const bool inrange = row < TS.b1[blk];
   const bool live = inrange && V.nfree[row];
   const int k0 = live ? V.rowptr[row] : 0, k1 = live ? V.rowptr[row + 1] : 0;
   const int d0 = live ? B.drowptr[row] : 0, d1 = live ? B.drowptr[row + 1] : 0;
@@ -1197,7 +1211,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   // iters[s] is only written by k_pcg_update, so every wave sees the same count here
   const bool conv = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters;
   if (conv) {
-    if ((int)blockIdx.x == TS.sblk[s] && threadIdx.x == 0) V.pdone[s] = 1;
+    if (blk == TS.sblk[s] && threadIdx.x == 0) V.pdone[s] = 1;
     return;
   }
   const T beta = rzc / rzo;
@@ -1241,14 +1255,16 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   }
   __shared__ T red[TPB / kWave];
   pq = block_sum256t(pq, red);
-  if (threadIdx.x == 0) B.P_pq[blockIdx.x] = pq;
+  if (threadIdx.x == 0) B.P_pq[blk] = pq;
 }
 
 template <class T>
 __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, BlockTable TS,
                                                       PcgBufsT<T> B, int parity) {
+  const int blk = xcd_block(TN.nblk);
+  if (blk < 0) return;
   __shared__ T rs[kWave][3];
-  const int s = TN.sc[blockIdx.x];
+  const int s = TN.sc[blk];
   if (V.pdone[s]) return;
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   T* Prz_new = parity ? B.P_rz0 : B.P_rz1;
@@ -1259,7 +1275,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
   wave_sum_n(tot);
   const T rzs = tot[0], pqs = tot[1];
   const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
-  const int n0 = TN.b0[blockIdx.x], n1 = TN.b1[blockIdx.x];
+  const int n0 = TN.b0[blk], n1 = TN.b1[blk];
   const int n = n0 + threadIdx.x;
   const bool live = n < n1;
   T r[3] = {(T)0, (T)0, (T)0};
@@ -1278,11 +1294,11 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
   T rz, rr;
-  block_partials<T>(V, B, n, live, r, z, rz, rr);
+  block_partials<T>(V, B, blk, n, live, r, z, rz, rr);
   if (threadIdx.x == 0) {
-    Prz_new[blockIdx.x] = rz;
-    B.P_rr[blockIdx.x] = rr;
-    if ((int)blockIdx.x == TN.sblk[s]) ++B.iters[s];
+    Prz_new[blk] = rz;
+    B.P_rr[blk] = rr;
+    if (blk == TN.sblk[s]) ++B.iters[s];
   }
 }
 
@@ -1293,7 +1309,8 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
 template <class T>
 __global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, PcgBufsT<T> B, T* prz) {
   constexpr int kPerLane = 6 * kCoarseMaxAgg / kWave;  // coarse entries per lane (at most)
-  const int blk = blockIdx.x;
+  const int blk = xcd_block(TN.nblk);
+  if (blk < 0) return;
   const int s = TN.sc[blk];
   if (V.pdone[s]) return;
   const int a = B.cg_blk_agg[blk];
@@ -1865,23 +1882,23 @@ void launch_precond(const View& V, const int* drowptr, const int* dcol, const vo
 }
 template <class T>
 void launch_pcg_init(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, hipStream_t s) {
-  if (TN.nblk > 0) hipLaunchKernelGGL(k_pcg_init<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, B);
+  if (TN.nblk > 0) hipLaunchKernelGGL(k_pcg_init<T>, dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, B);
 }
 template <class T>
 void launch_pcg_spmv(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                      int parity, hipStream_t s) {
   if (TS.nblk > 0)
-    hipLaunchKernelGGL(k_pcg_dir_spmv<T>, dim3(TS.nblk), dim3(TPB), 0, s, V, TN, TS, B, parity);
+    hipLaunchKernelGGL(k_pcg_dir_spmv<T>, dim3(xcd_grid(TS.nblk)), dim3(TPB), 0, s, V, TN, TS, B, parity);
 }
 template <class T>
 void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                        int parity, hipStream_t s) {
   if (TN.nblk > 0)
-    hipLaunchKernelGGL(k_pcg_update<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, TS, B, parity);
+    hipLaunchKernelGGL(k_pcg_update<T>, dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, TS, B, parity);
 }
 template <class T>
 void launch_pcg_coarse(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, T* prz, hipStream_t s) {
-  if (TN.nblk > 0 && B.cg_on) hipLaunchKernelGGL(k_pcg_coarse<T>, dim3(TN.nblk), dim3(kWave), 0, s, V, TN, B, prz);
+  if (TN.nblk > 0 && B.cg_on) hipLaunchKernelGGL(k_pcg_coarse<T>, dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, B, prz);
 }
 template void launch_pcg_coarse<double>(const View&, const BlockTable&, const PcgBufsT<double>&, double*, hipStream_t);
 template void launch_pcg_coarse<float>(const View&, const BlockTable&, const PcgBufsT<float>&, float*, hipStream_t);
