@@ -45,6 +45,35 @@ def cpu_baseline(spec, k_warm, k_timed):
                        f"{k_warm} warm-up step(s); one scene on one host core; {dt:.1f} s")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pcg_dir_spmv_pad32x24x6_hull796_fp64_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2504_12908_amd", "csrc", f) for f in ("kernels.hip", "kernels.h")]
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def _measured_traffic():
+    """HBM bytes per launch of the sparse product from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the factor a plain device copy of
+    known size gives), or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != _kernel_source_hash():
+        return None
+    return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
+            float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+
+
 def _spmv_roofline(taccel):
     prof = taccel.profile_query("spmv")
     n_l = max(prof["launches"], 1)
@@ -102,6 +131,8 @@ def run_single(args, taccel, scenes, np):
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
         roofline=_spmv_roofline(taccel),
     )
+    if prec == taccel.FP64:
+        out["roofline"]["traffic"] = _measured_traffic()
     pcg = taccel.profile_query("pcg")
     if pcg["launches"]:
         out["pcg_us_per_iter"] = pcg["total_ms"] * 1e3 / pcg["launches"]
@@ -221,13 +252,40 @@ def run_serving(args, taccel, scenes, np):
     )
 
 
+def run_copy(args, taccel, scenes, np):
+    """Counter calibration: three device-to-device copies of 256 MiB (a plain copy kernel of
+    known size) through the HIP runtime."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    n = 256 << 20
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    for ptr in (a, b):
+        if hip.hipMalloc(ctypes.byref(ptr), ctypes.c_size_t(n)) != 0:
+            sys.exit("hipMalloc failed")
+    if hip.hipMemset(a, 1, ctypes.c_size_t(n)) != 0:
+        sys.exit("hipMemset failed")
+    t0 = time.perf_counter()
+    for _ in range(3):
+        if hip.hipMemcpy(b, a, ctypes.c_size_t(n), 3) != 0:  # device to device
+            sys.exit("hipMemcpy failed")
+    hip.hipDeviceSynchronize()
+    dt = time.perf_counter() - t0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    return dict(metric="device copy bandwidth (counter calibration)", value=3 * 2 * n / dt / 1e9,
+                unit="GB/s", n_gpus=1, steps=3, warmup=0, ms_per_step=dt * 1e3 / 3,
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="u8",
+                data="synthetic", config=dict(workload="copy 256 MiB device to device x3",
+                                              bytes_per_copy=n))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "serving"], default="single")
+    ap.add_argument("--workload", choices=["single", "batch", "serving", "copy"], default="single")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--scenes", type=int, default=256)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -244,7 +302,7 @@ def main():
 
     from paper_2504_12908_amd import scenes, taccel
 
-    run = dict(single=run_single, batch=run_batch, serving=run_serving)[args.workload]
+    run = dict(single=run_single, batch=run_batch, serving=run_serving, copy=run_copy)[args.workload]
     out = run(args, taccel, scenes, np)
     print(json.dumps(out), flush=True)
 
