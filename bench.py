@@ -153,6 +153,8 @@ def run_batch(args, taccel, scenes, np):
     if W + K > specs[0].n_steps:
         sys.exit(f"warmup + steps must be <= {specs[0].n_steps}")
     prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    if prec == taccel.MIXED and n > 1:
+        sys.exit("bench.py: mixed precision runs one scene per batch (see include/taccel.h)")
     b = taccel.Batch(specs, precision=prec)
     for k in range(W):
         rc, per, st = b.step(k)

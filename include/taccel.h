@@ -37,6 +37,8 @@ typedef enum {
   TACCEL_CANCELLED = 10            /* server request dropped by taccel_server_destroy */
 } taccel_status;
 
+/* MIXED: FP32 Hessian blocks, assembly, SpMV and PCG; FP64 positions, gradient, contact,
+ * CCD and convergence test.  A batch with more than one scene must use FP64 (ERR_ARG). */
 typedef enum { TACCEL_FP64 = 0, TACCEL_MIXED = 1 } taccel_precision;
 
 /* Soft body (the gel pad): nv rest vertices, nt tets of positive orientation.

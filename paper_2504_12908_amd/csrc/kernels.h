@@ -33,7 +33,7 @@ struct BroadPhase {
   BpEntry* entries = nullptr;
   int* qcount = nullptr;    // [Nq]
   int* qoff = nullptr;      // [Nq]
-  int* overflow = nullptr;  // set when a box spans too many cells (exploded positions)
+  int* overflow = nullptr;  // [S] set when a box of the scene spans too many cells
 };
 
 void launch_predict(const View& V, hipStream_t s);

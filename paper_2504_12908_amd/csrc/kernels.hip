@@ -155,21 +155,29 @@ __device__ void prim_box(const double* P0, const double* P1, const int* ids, int
       }
     }
 }
-// Cell range of a box grown by dhat.  A range longer than kMaxSpan cells per axis only
-// arises from exploded positions; it is clamped (keeping every loop bounded) and flagged so
-// the host can fail the step instead of using an incomplete candidate set.
+// Cell range of a box grown by dhat.  A box longer than kMaxSpan cells on an axis, or
+// covering more than kMaxCells cells, only arises from exploded positions or a runaway
+// Newton direction: it is collapsed to its first cell (keeping every loop and every entry
+// count bounded) and its scene is flagged, so the host fails that scene instead of using an
+// incomplete candidate set.
 constexpr int kMaxSpan = 64;
+constexpr int kMaxCells = 4096;
 __device__ void cell_range(const SceneConst& sc, const double* lo, const double* hi, int* cl,
-                           int* overflow) {
+                           int* overflow_s) {
   const double inv = 1.0 / sc.cell;
+  bool bad = false;
+  long long cells = 1;
   for (int c = 0; c < 3; ++c) {
     cl[c] = cell_of(lo[c] - sc.dhat, sc.org[c], inv);
     cl[3 + c] = cell_of(hi[c] + sc.dhat, sc.org[c], inv);
     if (cl[3 + c] < cl[c]) cl[3 + c] = cl[c];
-    if (cl[3 + c] - cl[c] >= kMaxSpan) {
-      cl[3 + c] = cl[c] + kMaxSpan - 1;
-      atomicOr(overflow, 1);
-    }
+    const int span = cl[3 + c] - cl[c] + 1;
+    bad = bad || span > kMaxSpan;
+    cells *= span > kMaxSpan ? kMaxSpan : span;
+  }
+  if (bad || cells > kMaxCells) {
+    for (int c = 0; c < 3; ++c) cl[3 + c] = cl[c];
+    atomicOr(overflow_s, 1);
   }
 }
 __device__ __forceinline__ int target_ids(const View& V, int t, int* ids) {
@@ -198,7 +206,7 @@ __global__ void k_bp_targets(View V, const double* P0, const double* P1, BroadPh
   double lo[3], hi[3];
   prim_box(P0, P1, ids, n, lo, hi);
   int cl[6];
-  cell_range(V.sc[s], lo, hi, cl, bp.overflow);
+  cell_range(V.sc[s], lo, hi, cl, bp.overflow + s);
   for (int c = 0; c < 3; ++c) {
     bp.tbox[6 * t + c] = lo[c];
     bp.tbox[6 * t + 3 + c] = hi[c];
@@ -287,7 +295,7 @@ __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, cons
   double qb[6];
   prim_box(P0, P1, qids, nq, qb, qb + 3);
   int ql[6];
-  cell_range(sc, qb, qb + 3, ql, bp.overflow);
+  cell_range(sc, qb, qb + 3, ql, bp.overflow + s);
   const int off = emit ? bp.qoff[q] : 0;
   int cnt = 0;  // matches of this lane (count pass) / of the group so far (emit pass)
   const int qb0 = V.cvb[qids[0]];
@@ -1375,6 +1383,7 @@ __global__ void k_pmax(View V, const double* p, unsigned long long* pmax) {
     const int n = k;
     if (V.ntype[n] == 0 && V.nfree[n] && V.act[V.nscene[n]]) {
       m = fmax(fabs(p[3 * n]), fmax(fabs(p[3 * n + 1]), fabs(p[3 * n + 2])));
+      if (isnan(p[3 * n]) || isnan(p[3 * n + 1]) || isnan(p[3 * n + 2])) m = INFINITY;
       s = V.nscene[n];
     }
   } else if (k - V.Nn < V.Ncv) {
@@ -1384,6 +1393,7 @@ __global__ void k_pmax(View V, const double* p, unsigned long long* pmax) {
       double d[3];
       body_point(V, p + 3 * V.bnode[b], cv, d);
       m = fmax(fabs(d[0]), fmax(fabs(d[1]), fabs(d[2])));
+      if (isnan(d[0]) || isnan(d[1]) || isnan(d[2])) m = INFINITY;
       s = V.bscene[b];
     }
   }

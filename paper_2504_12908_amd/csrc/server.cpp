@@ -213,8 +213,9 @@ struct Server {
       size_t bytes = 0;
       while (!pending.empty() && (int)take.size() < max_cohort) {
         Request* r = pending.front();
-        // a batch computes in one precision
+        // a batch computes in one precision; mixed precision runs one scene per batch
         if (!take.empty() && r->scene->desc.params.precision != take[0]->scene->desc.params.precision) break;
+        if (!take.empty() && take[0]->scene->desc.params.precision == TACCEL_MIXED) break;
         if ((double)r->footprint > budget) {  // can never fit: fail it
           pending.pop_front();
           r->status = TACCEL_ERR_OOM;

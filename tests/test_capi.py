@@ -139,3 +139,12 @@ def test_server_submit_validates_on_host():
     assert srv.info()["queued"] == 0
     assert srv.poll(wait_ms=0) == []
     srv.close()
+
+
+def test_mixed_batch_of_several_scenes_is_refused():
+    T = _lib_or_skip()
+    from paper_2504_12908_amd import scenes
+    with pytest.raises(T.TaccelError) as ei:
+        T.Batch([scenes.pad_press_cube(0), scenes.pad_press_cube(1)], precision=T.MIXED)
+    assert ei.value.status == T.ERR_ARG
+    assert "one scene per batch" in str(ei.value)
