@@ -164,10 +164,9 @@ void taccel_batch_destroy(taccel_batch* b);
  * A request is one scene plus a script of n_steps per-step targets (a rollout, e.g. one
  * tactile press-and-slide episode, Sec. 5).  Requests are admitted in arrival order into
  * cohorts: a cohort is one resident batch (as taccel_batch_*) with its own stream and host
- * thread; every Newton iteration is one set of launches over all its requests, and each
- * request moves on to its next step as soon as its current one converges, so a request never
- * waits for slower ones.  A request that finishes or fails leaves the iteration while the
- * others go on, and the cohort's device memory is released with its last request.  A new cohort is formed whenever requests are
+ * thread that advances all its unfinished requests by one step per call; a request that
+ * finishes or fails stops being stepped while the others go on, and the cohort's device
+ * memory is released with its last request.  A new cohort is formed whenever requests are
  * waiting, fewer than max_cohorts run, and the estimated footprint of the requests taken fits
  * hbm_budget_bytes minus what running cohorts hold, so cohorts formed at different times
  * run concurrently.  A request's results are bitwise the same as stepping its scene alone
@@ -188,7 +187,7 @@ typedef struct {
   int32_t steps_done;  /* steps attempted (the last one failed if status != OK) */
   double wait_ms;      /* submit -> admission into a cohort */
   double run_ms;       /* admission -> completion */
-  double mean_step_ms; /* per-step latency: start to end of each of this request's steps */
+  double mean_step_ms; /* per-step latency of the cohort calls that stepped this request */
   double max_step_ms;
 } taccel_completion;
 

@@ -5,7 +5,6 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
-#include <functional>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -316,25 +315,6 @@ struct Batch::Impl {
                         std::vector<int>& pcg_it, std::vector<int>& n_active, std::vector<int>& halvings);
   taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st,
                      const int* mask);
-  // per-scene state of the step in progress
-  enum { kPhaseIdle = 0, kPhaseNewton = 1, kPhaseDone = 2, kPhaseFailed = 3 };
-  struct StepCtl {
-    int phase = kPhaseIdle, status = TACCEL_OK, nit = 0, tot_nit = 0, rounds = 1, tot_pcg = 0;
-    int nact_last = 0, tot_halv = 0;
-    double ms = 0.0;
-    std::chrono::steady_clock::time_point t0;
-  };
-  std::vector<StepCtl> ctl;        // [S]
-  std::vector<char> snapped_host;  // [Nb] body snapped onto its target in the current step
-  std::vector<double> hstar_all;   // [Nb][12] current targets y* (host copy)
-  DBuf<int> smask;                 // [S] scenes starting a step
-  void begin_steps(const std::vector<int>& in, const taccel_targets* tg);
-  int iterate();
-  void finish_steps(const std::vector<int>& out);
-  void fill_stats(int k, taccel_step_stats& st) const;
-  taccel_status run_sequences(const std::vector<int>& steps,
-                              const std::function<const taccel_targets*(int, int)>& targets_of,
-                              const std::function<bool(int, int, const taccel_step_stats&)>& on_step);
   size_t device_bytes() const;
   void release_all();
 };
@@ -931,10 +911,6 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   e_bodies.ensure(m, (kTrials + 1) * (size_t)std::max(Nb, 1));
   scalars.ensure(m, 16);
   bp_ovf.ensure(m, std::max(S, 1));
-  smask.ensure(m, std::max(S, 1));
-  ctl.assign(S, StepCtl());
-  snapped_host.assign(std::max(Nb, 1), 0);
-  hstar_all.assign(12 * (size_t)Nb, 0.0);
   rowcnt.ensure(m, Nn + 1);
   drowptr.ensure(m, Nn + 1);
   bp.ntarget = Ntr + Ned;
@@ -1425,17 +1401,19 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_update(V, dx.p, alpha.p, s);
 }
 
-// Start a step for every scene with in[k] set: kinematic targets, masked predictor, moving
-// Dirichlet targets (with their feasibility check), body multipliers reset, start residuals.
-void Batch::Impl::begin_steps(const std::vector<int>& in, const taccel_targets* tg) {
+taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
+                                taccel_step_stats* stats, const int* mask) {
+  const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = stream();
   View V = view();
+  // ---- targets: body y* (host conversion of the public affine maps), moving vertices
+  std::vector<double> hstar(12 * (size_t)Nb, 0.0);
   std::vector<double> hmove;
   std::vector<int> hmove_nodes;
   int bglob = 0;
   for (int k = 0; k < S; ++k) {
     const HostScene& H = hs[k];
-    if (!in[k]) {
+    if (mask && !mask[k]) {  // scene not stepped this call
       bglob += H.nb;
       continue;
     }
@@ -1446,7 +1424,7 @@ void Batch::Impl::begin_steps(const std::vector<int>& in, const taccel_targets* 
         throw ApiError(TACCEL_ERR_ARG, "scene " + std::to_string(k) + " has a prescribed body but no body_targets");
       const double* q = tg[k].body_targets + 12 * b;
       const double* A = q + 3;
-      double* y = hstar_all.data() + 12 * (size_t)bglob;
+      double* y = hstar.data() + 12 * (size_t)bglob;
       for (int i = 0; i < 3; ++i) {
         double acc = q[i];
         for (int j = 0; j < 3; ++j) acc += A[3 * i + j] * hb.com0[j];
@@ -1462,9 +1440,10 @@ void Batch::Impl::begin_steps(const std::vector<int>& in, const taccel_targets* 
       for (int v : H.moving) hmove_nodes.push_back(H.node0 + v);
     }
   }
-  h2d(bstar.p, hstar_all.data(), hstar_all.size());
-  h2d(smask.p, in.data(), S);
-  launch_predict(V, smask.p, s);
+  xn_valid = false;
+  h2d(bstar.p, hstar.data(), hstar.size());
+  launch_predict(V, s);
+  xn_valid = true;
   std::vector<int> infeasible_target(S, 0);
   if (!hmove_nodes.empty()) {
     mv_nodes.upload(&mem, hmove_nodes);
@@ -1478,7 +1457,7 @@ void Batch::Impl::begin_steps(const std::vector<int>& in, const taccel_targets* 
     launch_cmap(V, r.p, cend.p, s);
     launch_diff3(3 * Ncv, cend.p, cpos.p, cdisp.p, s);
     std::vector<int> all_on(S, 1);
-    for (int k = 0; k < S; ++k) all_on[k] = in[k] && hs[k].n_moving > 0;
+    for (int k = 0; k < S; ++k) all_on[k] = (!mask || mask[k]) && hs[k].n_moving > 0;
     h2d(act.p, all_on.data(), S);
     const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
     unsigned long long* amin = u64s.p + S;
@@ -1501,13 +1480,13 @@ void Batch::Impl::begin_steps(const std::vector<int>& in, const taccel_targets* 
     for (int k = 0; k < S; ++k) {
       double a;
       std::memcpy(&a, &ha[k], sizeof(double));
-      infeasible_target[k] = in[k] && hs[k].n_moving > 0 && (a < 1.0 || hb[k]);
+      infeasible_target[k] = hs[k].n_moving > 0 && (a < 1.0 || hb[k]);
     }
     launch_set_moving(x.p, (int)hmove_nodes.size(), mv_nodes.p, mv_tgt.p, s);
   }
-  launch_body_reset(V, 1e6, smask.p, s);
+  launch_body_reset(V, 1e6, s);
   cover_valid = false;
-  // start residual of every prescribed body of the scenes starting
+  // initial residual of every prescribed body
   unsigned long long* bres = u64s.p + 2 * S;
   zero(bres, sizeof(unsigned long long) * (Nb + 1));
   launch_body_resid(V, bres, s);
@@ -1515,266 +1494,162 @@ void Batch::Impl::begin_steps(const std::vector<int>& in, const taccel_targets* 
   d2h(hres.data(), bres, Nb);
   sync();
   bglob = 0;
-  for (int k = 0; k < S; ++k)
-    for (auto& hb : hs[k].bodies) {
-      if (in[k]) {
-        double r;
-        std::memcpy(&r, &hres[bglob], sizeof(double));
-        hb.r0 = hb.rprev = r;
-        snapped_host[bglob] = 0;
-      }
-      ++bglob;
+  for (auto& H : hs)
+    for (auto& hb : H.bodies) {
+      double r;
+      std::memcpy(&r, &hres[bglob++], sizeof(double));
+      hb.r0 = hb.rprev = r;
     }
-  const auto now = std::chrono::steady_clock::now();
+  // ---- per-scene state machine
+  enum { kNewton = 0, kDone = 1, kFailed = 2 };
+  std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
   for (int k = 0; k < S; ++k) {
-    if (!in[k]) continue;
-    StepCtl& c = ctl[k];
-    c = StepCtl();
-    c.t0 = now;
-    c.phase = kPhaseNewton;
     if (infeasible_target[k]) {
-      c.phase = kPhaseFailed;
-      c.status = TACCEL_INFEASIBLE_TARGET;
+      phase[k] = kFailed;
+      status[k] = TACCEL_INFEASIBLE_TARGET;
     }
+    if (mask && !mask[k]) phase[k] = kDone;
   }
-}
-
-// One Newton iteration for every scene in its Newton phase, then the augmented-Lagrangian
-// bookkeeping of the scenes whose Newton loop converged.  Returns the number of scenes that
-// took part.
-int Batch::Impl::iterate() {
-  hipStream_t s = stream();
-  View V = view();
-  std::vector<int> hact(S);
-  int nactive = 0;
-  for (int k = 0; k < S; ++k) {
-    hact[k] = ctl[k].phase == kPhaseNewton;
-    nactive += hact[k];
-  }
-  if (nactive == 0) return 0;
+  std::vector<int> tot_pcg(S, 0), nact_last(S, 0), tot_halv(S, 0);
   std::vector<int> last(S), lsf(S), nanf(S), pcg_it(S), nact(S), halv(S);
-  h2d(act.p, hact.data(), S);
-  act_host = hact;
-  newton_iteration(last, lsf, nanf, pcg_it, nact, halv);
-  std::vector<int> al_scene(S, 0);
-  bool any_al = false;
-  for (int k = 0; k < S; ++k) {
-    if (!hact[k]) continue;
-    StepCtl& c = ctl[k];
-    ++c.nit;
-    ++c.tot_nit;
-    c.tot_pcg += pcg_it[k];
-    c.tot_halv += halv[k];
-    c.nact_last = nact[k];
-    if (nanf[k]) { c.phase = kPhaseFailed; c.status = TACCEL_NAN; continue; }
-    if (lsf[k]) { c.phase = kPhaseFailed; c.status = TACCEL_LINESEARCH_FAILED; continue; }
-    if (last[k]) {
-      al_scene[k] = 1;
-      any_al = true;
-    } else if (c.nit >= hs[k].max_newton) {
-      c.phase = kPhaseFailed;
-      c.status = TACCEL_NOT_CONVERGED;
+  std::vector<int> hact(S);
+  std::vector<char> snapped_host(Nb, 0);
+  int guard = 0;
+  for (;;) {
+    int nactive = 0;
+    for (int k = 0; k < S; ++k) {
+      hact[k] = phase[k] == kNewton;
+      nactive += hact[k];
     }
-  }
-  if (!any_al) return nactive;
-  // ---- augmented Lagrangian round for the scenes whose Newton loop converged
-  std::vector<int> pending_scene(S, 0);
-  std::vector<int> candidates(Nb, 0), actions(Nb, 0);
-  bool any_cand = false;
-  unsigned long long* bres = u64s.p + 2 * S;
-  zero(bres, sizeof(unsigned long long) * (Nb + 1));
-  launch_body_resid(V, bres, s);
-  std::vector<unsigned long long> hres(Nb + 1);
-  d2h(hres.data(), bres, Nb);
-  sync();
-  int bglob = 0;
-  for (int k = 0; k < S; ++k)
-    for (int b = 0; b < hs[k].nb; ++b, ++bglob) {
-      HostBody& hb = hs[k].bodies[b];
-      if (!al_scene[k] || !hb.prescribed || snapped_host[bglob]) continue;
-      pending_scene[k] = 1;
-      double rr;
-      std::memcpy(&rr, &hres[bglob], sizeof(double));
-      if (rr <= 1e-3 * hb.r0) {
-        candidates[bglob] = 1;
-        any_cand = true;
+    if (nactive == 0) break;
+    if (++guard > 1000000) throw ApiError(TACCEL_ERR_HIP, "internal: step state machine did not terminate");
+    h2d(act.p, hact.data(), S);
+    act_host = hact;
+    newton_iteration(last, lsf, nanf, pcg_it, nact, halv);
+    std::vector<int> al_scene(S, 0);
+    bool any_al = false;
+    for (int k = 0; k < S; ++k) {
+      if (!hact[k]) continue;
+      ++nit[k];
+      ++tot_nit[k];
+      tot_pcg[k] += pcg_it[k];
+      tot_halv[k] += halv[k];
+      nact_last[k] = nact[k];
+      if (nanf[k]) { phase[k] = kFailed; status[k] = TACCEL_NAN; continue; }
+      if (lsf[k]) { phase[k] = kFailed; status[k] = TACCEL_LINESEARCH_FAILED; continue; }
+      if (last[k]) {
+        al_scene[k] = 1;
+        any_al = true;
+      } else if (nit[k] >= hs[k].max_newton) {
+        phase[k] = kFailed;
+        status[k] = TACCEL_NOT_CONVERGED;
       }
-      actions[bglob] = rr > 0.5 * hb.rprev ? 3 : 2;
-      hb.rprev = rr;
     }
-  if (any_cand) {
-    // collision-free snap test: move the candidate bodies onto their targets
-    std::vector<int> snap_act(S, 0);
-    bglob = 0;
-    for (int k = 0; k < S; ++k)
-      for (int b = 0; b < hs[k].nb; ++b, ++bglob)
-        if (candidates[bglob]) snap_act[k] = 1;
-    h2d(act.p, snap_act.data(), S);
-    h2d(snapcand.p, candidates.data(), Nb);
-    launch_cpos(V, s);
-    launch_snap_disp(V, snapcand.p, s);
-    launch_cend(V, cend.p, s);
-    const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
-    cover_valid = false;
-    unsigned long long* amin = u64s.p + S;
-    std::vector<unsigned long long> one(S);
-    const double d1 = 1.0;
-    unsigned long long b1;
-    std::memcpy(&b1, &d1, sizeof(double));
-    std::fill(one.begin(), one.end(), b1);
-    h2d(amin, one.data(), S);
-    launch_ccd(V, nsw, sq.p, st.p, amin, s);
-    std::vector<unsigned long long> ha(S);
-    d2h(ha.data(), amin, S);
+    if (!any_al) continue;
+    // ---- augmented Lagrangian round for the scenes whose Newton loop converged
+    std::vector<int> pending_scene(S, 0);
+    std::vector<int> candidates(Nb, 0), actions(Nb, 0);
+    bool any_cand = false;
+    zero(bres, sizeof(unsigned long long) * (Nb + 1));
+    launch_body_resid(V, bres, s);
+    d2h(hres.data(), bres, Nb);
     sync();
     bglob = 0;
-    for (int k = 0; k < S; ++k) {
-      double a;
-      std::memcpy(&a, &ha[k], sizeof(double));
-      for (int b = 0; b < hs[k].nb; ++b, ++bglob)
-        if (candidates[bglob] && a >= 1.0) {
-          actions[bglob] = 1;
-          snapped_host[bglob] = 1;
+    for (int k = 0; k < S; ++k)
+      for (int b = 0; b < hs[k].nb; ++b, ++bglob) {
+        HostBody& hb = hs[k].bodies[b];
+        if (!al_scene[k] || !hb.prescribed || snapped_host[bglob]) continue;
+        pending_scene[k] = 1;
+        double rr;
+        std::memcpy(&rr, &hres[bglob], sizeof(double));
+        if (rr <= 1e-3 * hb.r0) {
+          candidates[bglob] = 1;
+          any_cand = true;
         }
+        actions[bglob] = rr > 0.5 * hb.rprev ? 3 : 2;
+        hb.rprev = rr;
+      }
+    if (any_cand) {
+      // collision-free snap test: move the candidate bodies onto their targets
+      std::vector<int> snap_act(S, 0);
+      bglob = 0;
+      for (int k = 0; k < S; ++k)
+        for (int b = 0; b < hs[k].nb; ++b, ++bglob)
+          if (candidates[bglob]) snap_act[k] = 1;
+      h2d(act.p, snap_act.data(), S);
+      h2d(snapcand.p, candidates.data(), Nb);
+      launch_cpos(V, s);
+      launch_snap_disp(V, snapcand.p, s);
+      launch_cend(V, cend.p, s);
+      const int nsw = broad_phase(cpos.p, cend.p, 0, sq, st);
+      cover_valid = false;
+      unsigned long long* amin = u64s.p + S;
+      std::vector<unsigned long long> one(S);
+      const double d1 = 1.0;
+      unsigned long long b1;
+      std::memcpy(&b1, &d1, sizeof(double));
+      std::fill(one.begin(), one.end(), b1);
+      h2d(amin, one.data(), S);
+      launch_ccd(V, nsw, sq.p, st.p, amin, s);
+      std::vector<unsigned long long> ha(S);
+      d2h(ha.data(), amin, S);
+      sync();
+      bglob = 0;
+      for (int k = 0; k < S; ++k) {
+        double a;
+        std::memcpy(&a, &ha[k], sizeof(double));
+        for (int b = 0; b < hs[k].nb; ++b, ++bglob)
+          if (candidates[bglob] && a >= 1.0) {
+            actions[bglob] = 1;
+            snapped_host[bglob] = 1;
+          }
+      }
+    }
+    h2d(action.p, actions.data(), Nb);
+    launch_al_apply(V, action.p, s);
+    for (int k = 0; k < S; ++k) {
+      if (!al_scene[k]) continue;
+      if (!pending_scene[k]) {
+        phase[k] = kDone;
+        continue;
+      }
+      if (rounds[k] >= hs[k].max_al) {
+        phase[k] = kFailed;
+        status[k] = TACCEL_AL_FAILED;
+        continue;
+      }
+      ++rounds[k];
+      nit[k] = 0;
     }
   }
-  h2d(action.p, actions.data(), Nb);
-  launch_al_apply(V, action.p, s);
-  for (int k = 0; k < S; ++k) {
-    if (!al_scene[k]) continue;
-    StepCtl& c = ctl[k];
-    if (!pending_scene[k]) {
-      c.phase = kPhaseDone;
-      continue;
-    }
-    if (c.rounds >= hs[k].max_al) {
-      c.phase = kPhaseFailed;
-      c.status = TACCEL_AL_FAILED;
-      continue;
-    }
-    ++c.rounds;
-    c.nit = 0;
-  }
-  return nactive;
-}
-
-// End the steps of the scenes with out[k] set: velocities of the converged ones (and their
-// new start positions), roll-back of the failed ones.
-void Batch::Impl::finish_steps(const std::vector<int>& out) {
-  hipStream_t s = stream();
-  View V = view();
+  // ---- finish: velocities for converged scenes, roll back failed ones
   std::vector<int> ok(S), failed(S);
   for (int k = 0; k < S; ++k) {
-    ok[k] = out[k] && ctl[k].status == TACCEL_OK;
-    failed[k] = out[k] && ctl[k].status != TACCEL_OK;
+    const bool stepped = !mask || mask[k];
+    ok[k] = stepped && status[k] == TACCEL_OK;
+    failed[k] = stepped && status[k] != TACCEL_OK;
   }
   h2d(okflag.p, ok.data(), S);
   h2d(failflag.p, failed.data(), S);
   launch_velocity(V, okflag.p, s);
   launch_rollback(V, failflag.p, s);
   sync();
-  const auto now = std::chrono::steady_clock::now();
-  for (int k = 0; k < S; ++k)
-    if (out[k]) {
-      ctl[k].ms = std::chrono::duration<double, std::milli>(now - ctl[k].t0).count();
-      ctl[k].phase = kPhaseIdle;
-    }
-}
-
-void Batch::Impl::fill_stats(int k, taccel_step_stats& st) const {
-  const StepCtl& c = ctl[k];
-  st.status = c.status;
-  st.newton_iters = c.tot_nit;
-  st.al_rounds = c.rounds;
-  st.pcg_iters = c.tot_pcg;
-  st.n_active = c.nact_last;
-  st.ls_halvings = c.tot_halv;
-  st.step_ms = c.ms;
-}
-
-taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
-                                taccel_step_stats* stats, const int* mask) {
-  std::vector<int> in(S);
-  for (int k = 0; k < S; ++k) in[k] = !mask || mask[k];
-  xn_valid = false;
-  begin_steps(in, tg);
-  xn_valid = true;
-  int guard = 0;
-  while (iterate() > 0)
-    if (++guard > 1000000) throw ApiError(TACCEL_ERR_HIP, "internal: step state machine did not terminate");
-  finish_steps(in);
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   taccel_status first_bad = TACCEL_OK;
   for (int k = 0; k < S; ++k) {
-    if (!in[k]) {
-      if (per_scene) per_scene[k] = TACCEL_OK;
-      if (stats) {
-        std::memset(&stats[k], 0, sizeof(stats[k]));
-      }
-      continue;
+    if (per_scene) per_scene[k] = (taccel_status)status[k];
+    if (stats) {
+      stats[k].status = status[k];
+      stats[k].newton_iters = tot_nit[k];
+      stats[k].al_rounds = rounds[k];
+      stats[k].pcg_iters = tot_pcg[k];
+      stats[k].n_active = nact_last[k];
+      stats[k].ls_halvings = tot_halv[k];
+      stats[k].step_ms = ms;
     }
-    if (per_scene) per_scene[k] = (taccel_status)ctl[k].status;
-    if (stats) fill_stats(k, stats[k]);
-    if (ctl[k].status != TACCEL_OK && first_bad == TACCEL_OK) first_bad = (taccel_status)ctl[k].status;
+    if (status[k] != TACCEL_OK && first_bad == TACCEL_OK) first_bad = (taccel_status)status[k];
   }
   return first_bad;
-}
-
-// Scenes advancing through their own step sequences: every scene with steps[k] > 0 runs that
-// many steps (targets from targets_of(k, j) for its j-th step); a scene that finishes a step
-// starts its next one at once, so scenes with fewer Newton iterations per step never wait for
-// slower ones.  on_step(k, j, stats) reports each finished step and returns whether the
-// scene goes on; a failed step ends the scene's sequence.
-taccel_status Batch::Impl::run_sequences(const std::vector<int>& steps,
-                                         const std::function<const taccel_targets*(int, int)>& targets_of,
-                                         const std::function<bool(int, int, const taccel_step_stats&)>& on_step) {
-  std::vector<int> done(S, 0), left(steps);
-  std::vector<taccel_targets> tg(S);
-  std::vector<int> start(S, 0);
-  auto launch = [&](std::vector<int>& in) {
-    bool any = false;
-    for (int k = 0; k < S; ++k)
-      if (in[k]) {
-        const taccel_targets* t = targets_of(k, done[k]);
-        tg[k] = t ? *t : taccel_targets{nullptr, nullptr};
-        any = true;
-      }
-    if (any) begin_steps(in, tg.data());
-  };
-  for (int k = 0; k < S; ++k) start[k] = left[k] > 0;
-  xn_valid = false;
-  launch(start);
-  xn_valid = true;
-  int guard = 0;
-  for (;;) {
-    const int nactive = iterate();
-    // scenes whose step just ended (or failed before any iteration)
-    std::vector<int> out(S, 0);
-    bool any_out = false;
-    for (int k = 0; k < S; ++k)
-      if (left[k] > 0 && (ctl[k].phase == kPhaseDone || ctl[k].phase == kPhaseFailed)) {
-        out[k] = 1;
-        any_out = true;
-      }
-    if (any_out) {
-      finish_steps(out);
-      std::vector<int> next(S, 0);
-      for (int k = 0; k < S; ++k) {
-        if (!out[k]) continue;
-        taccel_step_stats st;
-        fill_stats(k, st);
-        const bool more = on_step(k, done[k], st);
-        ++done[k];
-        --left[k];
-        if (st.status != TACCEL_OK || !more) left[k] = 0;
-        next[k] = left[k] > 0;
-      }
-      launch(next);
-    } else if (nactive == 0) {
-      break;
-    }
-    if (++guard > 100000000) throw ApiError(TACCEL_ERR_HIP, "internal: sequence loop did not terminate");
-  }
-  return TACCEL_OK;
 }
 
 size_t Batch::Impl::device_bytes() const {
@@ -1879,7 +1754,6 @@ Batch::~Batch() {
   I.u64s.free();
   I.bp_entries.free();
   I.bp_ovf.free();
-  I.smask.free();
   I.scratch.free();
   I.mv_nodes.free();
   I.mv_tgt.free();
@@ -1910,24 +1784,6 @@ taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, tac
         std::memset(&st[k], 0, sizeof(st[k]));
         st[k].status = e.st;
       }
-    return e.st;
-  }
-}
-
-taccel_status Batch::run_sequences(const std::vector<int>& steps,
-                                   const std::function<const taccel_targets*(int, int)>& targets_of,
-                                   const std::function<bool(int, int, const taccel_step_stats&)>& on_step) {
-  try {
-    return impl_->run_sequences(steps, targets_of, on_step);
-  } catch (const ApiError& e) {
-    set_last_error(e.what());
-    // every scene back to the start of its current step (idle scenes have xn == x)
-    Impl& I = *impl_;
-    (void)hipStreamSynchronize(I.mem.stream);
-    if (I.xn_valid)
-      (void)hipMemcpyAsync(I.x.p, I.xn.p, sizeof(double) * 3 * (size_t)I.Nn, hipMemcpyDeviceToDevice,
-                           I.mem.stream);
-    (void)hipStreamSynchronize(I.mem.stream);
     return e.st;
   }
 }
@@ -2014,7 +1870,6 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
       for (int u = 0; u < H.nv; ++u)
         for (int c = 0; c < 3; ++c) tmp[3 * (size_t)H.perm[u] + c] = in[3 * (size_t)u + c];
       I.h2d((f == TACCEL_FIELD_X ? I.x.p : I.v.p) + 3 * (size_t)H.node0, tmp.data(), cnt);
-      if (f == TACCEL_FIELD_X) I.h2d(I.xn.p + 3 * (size_t)H.node0, tmp.data(), cnt);
       I.sync();
       return TACCEL_OK;
     }
@@ -2034,7 +1889,6 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
         for (int j = 0; j < 3; ++j) yb[3 + 3 * j + i] = A[3 * i + j];
     }
     I.h2d((f == TACCEL_FIELD_QDOT ? I.v.p : I.x.p) + 3 * (size_t)(H.node0 + n_soft_pad), y.data(), y.size());
-    if (f == TACCEL_FIELD_Q) I.h2d(I.xn.p + 3 * (size_t)(H.node0 + n_soft_pad), y.data(), y.size());
     I.sync();
     return TACCEL_OK;
   } catch (const ApiError& e) {

@@ -36,7 +36,7 @@ struct BroadPhase {
   int* overflow = nullptr;  // [S] set when a box of the scene spans too many cells
 };
 
-void launch_predict(const View& V, const int* mask, hipStream_t s);
+void launch_predict(const View& V, hipStream_t s);
 void launch_set_moving(double* x, int n, const int* nodes, const double* tgt, hipStream_t s);
 void launch_touching(const View& V, int n, const int* cand_q, const int* cand_t, int* bad, hipStream_t s);
 void launch_diff3(int n3, const double* a, const double* b, double* out, hipStream_t s);
@@ -161,7 +161,7 @@ void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& T
                         int ncand, const int* cand_q, const int* cand_t, const LsBufs& L, hipStream_t s);
 void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s);
 void launch_al_apply(const View& V, const int* action, hipStream_t s);
-void launch_body_reset(const View& V, double kappa0, const int* mask, hipStream_t s);
+void launch_body_reset(const View& V, double kappa0, hipStream_t s);
 void launch_velocity(const View& V, const int* ok, hipStream_t s);
 void launch_rollback(const View& V, const int* failed, hipStream_t s);
 

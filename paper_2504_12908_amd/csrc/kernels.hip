@@ -41,10 +41,9 @@ __device__ __forceinline__ void atomic_min_pos(unsigned long long* a, double v) 
 }
 
 // ------------------------------------------------------------------ predict & positions
-__global__ void k_predict(View V, const int* mask) {
+__global__ void k_predict(View V) {
   const int n = gid();
   if (n >= V.Nn) return;
-  if (!mask[V.nscene[n]]) return;
   const SceneConst& sc = V.sc[V.nscene[n]];
   const int type = V.ntype[n];
   const double h = sc.h;
@@ -1648,10 +1647,9 @@ __global__ void k_al_apply(View V, const int* action) {
 
 // Start of a step: multipliers cleared, penalty reset, every body unsnapped (its 4
 // pseudo-nodes become unknowns again).
-__global__ void k_body_reset(View V, double kappa0, const int* mask) {
+__global__ void k_body_reset(View V, double kappa0) {
   const int b = gid();
   if (b >= V.Nb) return;
-  if (!mask[V.bscene[b]]) return;
   for (int k = 0; k < 12; ++k) V.blam[12 * b + k] = 0.0;
   V.bkap[b] = kappa0;
   V.bsnap[b] = 0;
@@ -1664,10 +1662,7 @@ __global__ void k_velocity(View V, const int* ok) {
   const int s = V.nscene[n];
   if (!ok[s]) return;
   const double inv = 1.0 / V.sc[s].h;
-  for (int c = 0; c < 3; ++c) {
-    V.v[3 * n + c] = (V.x[3 * n + c] - V.xn[3 * n + c]) * inv;
-    V.xn[3 * n + c] = V.x[3 * n + c];  // the accepted state is the next step's start
-  }
+  for (int c = 0; c < 3; ++c) V.v[3 * n + c] = (V.x[3 * n + c] - V.xn[3 * n + c]) * inv;
 }
 
 __global__ void k_rollback(View V, const int* failed) {
@@ -1775,7 +1770,7 @@ __global__ void k_debug_arap(int n, const double* A, double* e, double* g, doubl
     if (_nb > 0) hipLaunchKernelGGL(kern, dim3(_nb), dim3(tpb), 0, s, __VA_ARGS__); \
   } while (0)
 
-void launch_predict(const View& V, const int* mask, hipStream_t s) { LAUNCH(k_predict, V.Nn, TPB, s, V, mask); }
+void launch_predict(const View& V, hipStream_t s) { LAUNCH(k_predict, V.Nn, TPB, s, V); }
 void launch_set_moving(double* x, int n, const int* nodes, const double* tgt, hipStream_t s) {
   LAUNCH(k_set_moving, n, TPB, s, x, n, nodes, tgt);
 }
@@ -1948,8 +1943,8 @@ void launch_update(const View& V, const double* p, const double* alpha, hipStrea
 void launch_al_apply(const View& V, const int* action, hipStream_t s) {
   LAUNCH(k_al_apply, V.Nb, 64, s, V, action);
 }
-void launch_body_reset(const View& V, double kappa0, const int* mask, hipStream_t s) {
-  LAUNCH(k_body_reset, V.Nb, 64, s, V, kappa0, mask);
+void launch_body_reset(const View& V, double kappa0, hipStream_t s) {
+  LAUNCH(k_body_reset, V.Nb, 64, s, V, kappa0);
 }
 void launch_velocity(const View& V, const int* ok, hipStream_t s) {
   LAUNCH(k_velocity, V.Nn, TPB, s, V, ok);

@@ -5,9 +5,8 @@
 // new cohort as soon as their estimated device footprint fits the remaining HBM budget and
 // fewer than max_cohorts cohorts are running.  A cohort is one resident Batch (all its
 // scenes concatenated on the device, one launch per stage) with its own stream and host
-// thread; its requests advance through their own step sequences (each starts its next step
-// as soon as its current one converges, so none waits for a slower one) and the cohort's
-// memory is released when the last one finishes.  Cohorts admitted at different times run
+// thread; it advances all its unfinished requests by one step per call and releases its
+// memory when the last one finishes.  Cohorts admitted at different times therefore run
 // concurrently on the device.  Per scene the numerics are independent of what else is in
 // the batch, so a request's results do not depend on the mix it was served in.
 #include <algorithm>
@@ -123,55 +122,57 @@ struct Server {
     cv_done.notify_all();
   }
 
-  // Host thread of one cohort.  The cohort's requests advance through their own step
-  // sequences (a request that needs fewer Newton iterations per step never waits for a slower
-  // one).  Only this thread touches a running request's step data; the request becomes
-  // visible to poll/read/release once finish() has run under the lock, after which this thread
-  // no longer dereferences it (it may be released at any time).
+  // Host thread of one cohort.  Only this thread touches a running request's step data; the
+  // request becomes visible to poll/read/release once finish() has run under the lock, after
+  // which this thread no longer dereferences it (it may be released at any time).
   void run_cohort(std::vector<Request*> reqs, Batch* batch, size_t bytes) {
     const int n = (int)reqs.size();
-    std::vector<int> steps(n), done(n, 0);
+    std::vector<int> mask(n, 1), done(n, 0);
     std::vector<taccel_targets> tg(n);
-    for (int i = 0; i < n; ++i) steps[i] = reqs[i]->n_steps;
-    auto targets_of = [&](int i, int k) -> const taccel_targets* {
-      const Request* r = reqs[i];
-      const int nb = r->scene->desc.n_bodies, nm = r->scene->n_moving;
-      tg[i].body_targets = nb ? r->body_targets.data() + (size_t)k * nb * 12 : nullptr;
-      tg[i].dirichlet_targets = nm ? r->dir_targets.data() + (size_t)k * nm * 3 : nullptr;
-      return &tg[i];
-    };
-    auto complete = [&](int i) {
-      Request* r = reqs[i];
-      HostFields f = read_fields(batch, i, r);
-      std::lock_guard<std::mutex> lk(mu);
-      r->fields = std::move(f.fields);
-      done[i] = 1;
-      finish(r);
-    };
-    auto on_step = [&](int i, int k, const taccel_step_stats& st) -> bool {
-      Request* r = reqs[i];
-      r->step_ms.push_back(st.step_ms);
-      r->steps_done = k + 1;
-      bool end = st.status != TACCEL_OK || r->steps_done >= r->n_steps;
-      if (st.status != TACCEL_OK) r->status = st.status;
-      bool stopping;
+    std::vector<taccel_status> per(n);
+    std::vector<taccel_step_stats> st(n);
+    for (;;) {
       {
         std::lock_guard<std::mutex> lk(mu);
-        stopping = stop;
+        if (stop)
+          for (int i = 0; i < n; ++i)
+            if (!done[i]) {
+              reqs[i]->status = TACCEL_CANCELLED;
+              done[i] = 1;
+              finish(reqs[i]);
+            }
       }
-      if (stopping && !end) {
-        r->status = TACCEL_CANCELLED;
-        end = true;
+      bool any = false;
+      for (int i = 0; i < n; ++i) {
+        mask[i] = !done[i];
+        any = any || mask[i];
+        if (!mask[i]) continue;
+        Request* r = reqs[i];
+        const int k = r->steps_done;
+        const int nb = r->scene->desc.n_bodies, nm = r->scene->n_moving;
+        tg[i].body_targets = nb ? r->body_targets.data() + (size_t)k * nb * 12 : nullptr;
+        tg[i].dirichlet_targets = nm ? r->dir_targets.data() + (size_t)k * nm * 3 : nullptr;
       }
-      if (end) complete(i);
-      return !end;
-    };
-    const taccel_status st = batch->run_sequences(steps, targets_of, on_step);
-    for (int i = 0; i < n; ++i)
-      if (!done[i]) {  // an internal error ended the cohort
-        reqs[i]->status = st != TACCEL_OK ? st : TACCEL_ERR_HIP;
-        complete(i);
+      if (!any) break;
+      const auto t0 = Clock::now();
+      batch->step(tg.data(), per.data(), st.data(), mask.data());
+      const double dt = ms_since(t0, Clock::now());
+      for (int i = 0; i < n; ++i) {
+        if (!mask[i]) continue;
+        Request* r = reqs[i];
+        r->step_ms.push_back(dt);
+        r->steps_done += 1;
+        const bool failed = per[i] != TACCEL_OK;
+        if (failed || r->steps_done >= r->n_steps) {
+          if (failed) r->status = per[i];
+          HostFields f = read_fields(batch, i, r);
+          std::lock_guard<std::mutex> lk(mu);
+          r->fields = std::move(f.fields);
+          done[i] = 1;
+          finish(r);
+        }
       }
+    }
     delete batch;
     std::lock_guard<std::mutex> lk(mu);
     used_bytes -= bytes;

@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <functional>
 #include <string>
 #include <vector>
 
@@ -98,11 +97,6 @@ class Batch {
   // mask (nullable): scenes with mask[k] == 0 are left untouched by this call
   taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st,
                      const int* mask = nullptr);
-  // Scenes advancing through their own step sequences (see Impl::run_sequences); on an
-  // internal error every scene is returned to the start of its current step.
-  taccel_status run_sequences(const std::vector<int>& steps,
-                              const std::function<const taccel_targets*(int, int)>& targets_of,
-                              const std::function<bool(int, int, const taccel_step_stats&)>& on_step);
   size_t device_bytes() const;
   taccel_status read(int scene, taccel_field f, void* dst, size_t bytes);
   taccel_status write(int scene, taccel_field f, const void* src, size_t bytes);
