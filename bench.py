@@ -136,6 +136,17 @@ def run_single(args, taccel, scenes, np):
     pcg = taccel.profile_query("pcg")
     if pcg["launches"]:
         out["pcg_us_per_iter"] = pcg["total_ms"] * 1e3 / pcg["launches"]
+    if args.phases > 0 and W + K + args.phases <= spec.n_steps:
+        # after the timed region: host wall time per Newton-iteration phase (every phase ends
+        # with a synchronisation here, so the sum exceeds an unprofiled iteration)
+        taccel.profile_reset()
+        taccel.profile_enable(False, phases=True)
+        for k in range(W + K, W + K + args.phases):
+            sc.step(k)
+        taccel.profile_enable(False)
+        ph = {name: taccel.profile_query(name) for name in taccel.PHASES}
+        n_it = max(ph["solve"]["launches"], 1)
+        out["phase_ms_per_newton_iter"] = {name: v["total_ms"] / n_it for name, v in ph.items()}
     sc.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, 1, 1)
@@ -290,6 +301,8 @@ def main():
     ap.add_argument("--workload", choices=["single", "batch", "serving", "copy"], default="single")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--scenes", type=int, default=256)
+    ap.add_argument("--phases", type=int, default=0,
+                    help="extra steps after the timed region with per-phase host timing")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=1.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)

@@ -252,14 +252,20 @@ taccel_status taccel_debug_candidates(taccel_scene* s, const double* P0, const d
                                       int32_t* out, int32_t cap, int32_t* n);
 
 /* ---- Measurement --------------------------------------------------------------------
- * Process-wide HIP-event timing, off by default (it adds synchronisations).  While enabled:
+ * Process-wide timing, off by default (it adds synchronisations).  taccel_profile_enable(flags):
+ * bit 0 turns on the kernel timings "spmv" and "pcg", bit 1 the phase timings.  While enabled:
  *   "spmv": on every Newton iteration, 16 back-to-back launches of the PCG sparse-product
  *     kernel on that iteration's matrix are timed between two events on the object's stream
  *     (their outputs are recomputed by the solve); query returns the summed milliseconds, the
  *     number of launches and the summed algorithmic bytes (values, indices and vectors the
  *     product must move once);
  *   "pcg": the PCG iterations of every solve (after initialisation) between two events;
- *     query returns the summed milliseconds and iterations (largest count per solve). */
+ *     query returns the summed milliseconds and iterations (largest count per solve);
+ *   "candidates", "derivatives", "solve", "check", "ccd", "line_search": host wall time of
+ *     each phase of a Newton iteration (static candidates and narrow phase; element
+ *     derivatives, assembly and preconditioner; PCG; convergence test; swept candidates and
+ *     CCD; line search and update), each ended by a stream synchronisation; query returns
+ *     the summed milliseconds and the number of Newton iterations. */
 void taccel_profile_enable(int32_t on);
 void taccel_profile_reset(void);
 taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t* launches,

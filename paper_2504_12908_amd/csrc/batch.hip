@@ -22,6 +22,8 @@ Profiler& profiler() {
   static Profiler p;
   return p;
 }
+const char* const kPhaseNames[Profiler::kPhases] = {"candidates", "derivatives", "solve",
+                                                    "check", "ccd", "line_search"};
 
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -880,13 +882,13 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   cg_sc_m.upload(m, cg_sc_m_h);
   cg_sc_off.upload(m, cg_sc_off_h);
   cg_rc.ensure(m, 6 * (size_t)std::max(TN.nblk, 1));
-  {
-    const std::vector<float> af(cg_ainv_h.begin(), cg_ainv_h.end());
-    cg_ainv.ensure(m, af.size() / 2 + 1);
-    h2d(reinterpret_cast<float*>(cg_ainv.p), af.data(), af.size());
-  }
+  // FP32 staging copies stay alive until the stream synchronisation below
+  const std::vector<float> af(cg_ainv_h.begin(), cg_ainv_h.end());
+  cg_ainv.ensure(m, af.size() / 2 + 1);
+  h2d(reinterpret_cast<float*>(cg_ainv.p), af.data(), af.size());
+  std::vector<float> df;
   if (mixed) {
-    const std::vector<float> df(cg_d_h.begin(), cg_d_h.end());
+    df.assign(cg_d_h.begin(), cg_d_h.end());
     cg_d.ensure(m, df.size() / 2 + 1);
     h2d(reinterpret_cast<float*>(cg_d.p), df.data(), df.size());
   } else {
@@ -1148,6 +1150,16 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
                                    std::vector<int>& n_active, std::vector<int>& halvings) {
   hipStream_t s = stream();
   View V = view();
+  Profiler& prof = profiler();
+  auto t_mark = std::chrono::steady_clock::now();
+  auto phase_end = [&](int ph) {  // profiling only: attribute the wall time since the last mark
+    if (!prof.phases) return;
+    sync();
+    const auto now = std::chrono::steady_clock::now();
+    prof.phase_ms[ph] += std::chrono::duration<double, std::milli>(now - t_mark).count();
+    t_mark = now;
+  };
+  if (prof.phases) ++prof.phase_calls;
   std::vector<int> bp_bad(S, 0), bp_bad2(S, 0);  // scenes whose boxes overflowed the grid
   launch_cpos(V, s);
   // ---- active pairs at the current point: from the covering set of the previous
@@ -1177,6 +1189,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_compact_pairs(V, ncand, cqp, ctp, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
   zero(scnt.p, sizeof(int) * (S + 1));
   launch_count_scene(np, pscene.p, scnt.p, s);
+  phase_end(0);
   // ---- element derivatives
   launch_fem_hess(V, mixed, s);
   launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, s);
@@ -1236,6 +1249,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     h2d(pdone.p, ha.data(), S);
   }
   zero(iters.p, sizeof(int) * S);
+  phase_end(1);
   if (mixed) {
     const PcgBufsT<float> B = pcg_bufs<float>();
     launch_pcg_init(V, TN, B, s);
@@ -1247,6 +1261,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     launch_pcg_coarse(V, TN, B, B.P_rz0, s);
     run_pcg(V, B, nseg);
   }
+  phase_end(2);
   d2h(pcg_it.data(), iters.p, S);
   std::vector<int> hbad(S);
   d2h(hbad.data(), bad.p, S);
@@ -1284,6 +1299,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
       }
     if (any) h2d(act.p, a2.data(), S);
   }
+  phase_end(3);
   // ---- CCD over the swept candidates
   launch_cdisp(V, dx.p, s);
   launch_cend(V, cend.p, s);
@@ -1333,6 +1349,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     TP.sblk = tp_sblk.p;
     part_pairs.ensure(&mem, kTrials * (size_t)std::max(TP.nblk, 1));
   }
+  phase_end(4);
   // ---- line search (8 step sizes per launch)
   e_pairs.ensure(&mem, (kTrials + 1) * (size_t)std::max(nsw, 1));
   LsBufs L;
@@ -1399,6 +1416,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   }
   h2d(alpha.p, alpha_h.data(), S);
   launch_update(V, dx.p, alpha.p, s);
+  phase_end(5);
 }
 
 taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,

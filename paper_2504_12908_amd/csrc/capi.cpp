@@ -252,7 +252,10 @@ taccel_status taccel_debug_arap(int32_t n, const double* A, double* e, double* g
   return fetch(Hp, dHp, 81 * (size_t)n);
 }
 
-void taccel_profile_enable(int32_t on) { tc::profiler().on = on != 0; }
+void taccel_profile_enable(int32_t on) {
+  tc::profiler().on = (on & 1) != 0;
+  tc::profiler().phases = (on & 2) != 0;
+}
 
 void taccel_profile_reset(void) {
   tc::Profiler& p = tc::profiler();
@@ -261,6 +264,8 @@ void taccel_profile_reset(void) {
   p.spmv_bytes = 0.0;
   p.pcg_ms = 0.0;
   p.pcg_iters = 0;
+  for (double& v : p.phase_ms) v = 0.0;
+  p.phase_calls = 0;
 }
 
 taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t* launches,
@@ -278,7 +283,14 @@ taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t
     if (algorithmic_bytes) *algorithmic_bytes = 0.0;
     return TACCEL_OK;
   }
-  return fail(TACCEL_ERR_ARG, "profile_query: \"spmv\" or \"pcg\"");
+  for (int k = 0; kernel && k < tc::Profiler::kPhases; ++k)
+    if (std::strcmp(kernel, tc::kPhaseNames[k]) == 0) {
+      if (total_ms) *total_ms = p.phase_ms[k];
+      if (launches) *launches = p.phase_calls;
+      if (algorithmic_bytes) *algorithmic_bytes = 0.0;
+      return TACCEL_OK;
+    }
+  return fail(TACCEL_ERR_ARG, "profile_query: \"spmv\", \"pcg\" or a Newton-iteration phase name");
 }
 
 taccel_status taccel_device_synchronize(void) {

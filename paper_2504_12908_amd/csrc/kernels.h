@@ -131,13 +131,21 @@ void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS
 
 // Process-wide kernel timing with HIP events (off by default).
 struct Profiler {
-  bool on = false;
+  bool on = false;      // kernel timing with HIP events
+  bool phases = false;  // host wall time per Newton-iteration phase
   double spmv_ms = 0.0;
   long long spmv_launches = 0;
   double spmv_bytes = 0.0;
   double pcg_ms = 0.0;        // wall time of the PCG chunk replays (after initialisation)
   long long pcg_iters = 0;    // iterations of those solves (largest per solve)
+  // host wall time per Newton-iteration phase (each phase ends with a stream synchronisation
+  // while profiling): candidates, derivatives + assembly, linear solve, convergence check,
+  // swept candidates + CCD, line search + update
+  static constexpr int kPhases = 6;
+  double phase_ms[kPhases] = {0, 0, 0, 0, 0, 0};
+  long long phase_calls = 0;
 };
+extern const char* const kPhaseNames[Profiler::kPhases];
 Profiler& profiler();
 
 // convergence, CCD, line search, update

@@ -400,8 +400,12 @@ class Server:
 
 
 # ------------------------------------------------------------------ measurement
-def profile_enable(on=True):
-    lib().taccel_profile_enable(1 if on else 0)
+PHASES = ("candidates", "derivatives", "solve", "check", "ccd", "line_search")
+
+
+def profile_enable(on=True, phases=False):
+    """Kernel timing (spmv, pcg) when on; host wall time per Newton phase when phases."""
+    lib().taccel_profile_enable((1 if on else 0) | (2 if phases else 0))
 
 
 def profile_reset():
