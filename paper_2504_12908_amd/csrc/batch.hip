@@ -227,6 +227,8 @@ struct Batch::Impl {
   DBuf<int> cg_blk_agg, cg_agg_b0, cg_agg_b1, cg_sc_a0, cg_sc_m;
   DBuf<long long> cg_sc_off;
   DBuf<double> cg_d, cg_ainv, cg_rc;  // cg_d, cg_rc: T-typed storage; cg_ainv: float
+  DBuf<double> P_qc, cg_rca0, cg_rca1, cg_dw;  // T-typed storage
+  DBuf<int> cg_sc_ts0, cg_sc_tsn, cg_sc_tsend;
   int cg_on = 0;
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
@@ -788,6 +790,35 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     cg_sc_m_h[s] = build_coarse(cs, cg_blk_agg_h, cg_agg_b0_h, cg_agg_b1_h, cg_d_h, cg_ainv_h);
   }
   cg_on = cg_agg_b0_h.empty() ? 0 : 1;
+  // TS blocks (16 rows) of each aggregate: both tables start at the scene's first node and
+  // 64 is a multiple of 16, so the rows of a TN block are the TS blocks 4j .. 4j + 3
+  static_assert(kNodeChunk % kRowChunk == 0, "TN blocks must hold whole TS blocks");
+  constexpr int kTsPerTn = kNodeChunk / kRowChunk;
+  // Per scene: the TS blocks of its j-th aggregate are [ts0 + j tsn, min(ts0 + (j + 1) tsn, tsend)).
+  std::vector<int> cg_sc_ts0_h(S, 0), cg_sc_tsn_h(S, 0), cg_sc_tsend_h(S, 0);
+  for (int sc = 0; sc < S; ++sc) {
+    const int na = cg_sc_m_h[sc] / 6;
+    if (na == 0) continue;
+    const int a0 = cg_sc_a0_h[sc];
+    const int grp = cg_agg_b1_h[a0] - cg_agg_b0_h[a0];
+    cg_sc_ts0_h[sc] = ts_sblk_h[sc] + kTsPerTn * (cg_agg_b0_h[a0] - tn_sblk_h[sc]);
+    cg_sc_tsn_h[sc] = kTsPerTn * grp;
+    cg_sc_tsend_h[sc] = std::min(ts_sblk_h[sc] + kTsPerTn * (cg_agg_b1_h[a0 + na - 1] - tn_sblk_h[sc]),
+                                 ts_sblk_h[sc + 1]);
+    for (int j = 0; j < na; ++j) {
+      const int a = a0 + j;
+      const int t0 = cg_sc_ts0_h[sc] + cg_sc_tsn_h[sc] * j;
+      const int t1 = std::min(t0 + cg_sc_tsn_h[sc], cg_sc_tsend_h[sc]);
+      if (t0 >= t1 || t0 < ts_sblk_h[sc] || t1 > ts_sblk_h[sc + 1])
+        throw ApiError(TACCEL_ERR_HIP, "internal: empty or foreign row-block range of an aggregate");
+      for (int t = t0; t < t1; ++t)
+        if (ts_sc_h[t] != sc || ts_b0_h[t] < tn_b0_h[cg_agg_b0_h[a]] || ts_b1_h[t] > tn_b1_h[cg_agg_b1_h[a] - 1])
+          throw ApiError(TACCEL_ERR_HIP, "internal: row blocks do not nest in node blocks");
+      // every row of the aggregate's node blocks is in one of its row blocks
+      if (ts_b0_h[t0] != tn_b0_h[cg_agg_b0_h[a]] || ts_b1_h[t1 - 1] != tn_b1_h[cg_agg_b1_h[a] - 1])
+        throw ApiError(TACCEL_ERR_HIP, "internal: row blocks do not cover an aggregate");
+    }
+  }
   if (!mem.stream) {
     // a stream of our own (default priority): the PCG chunks are captured into a graph,
     // which the null stream does not allow
@@ -882,17 +913,39 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   cg_sc_m.upload(m, cg_sc_m_h);
   cg_sc_off.upload(m, cg_sc_off_h);
   cg_rc.ensure(m, 6 * (size_t)std::max(TN.nblk, 1));
+  P_qc.ensure(m, 6 * (size_t)std::max(TS.nblk, 1));
+  cg_rca0.ensure(m, 6 * (size_t)std::max<size_t>(cg_agg_b0_h.size(), 1));
+  cg_rca1.ensure(m, 6 * (size_t)std::max<size_t>(cg_agg_b0_h.size(), 1));
+  cg_sc_ts0.upload(m, cg_sc_ts0_h);
+  cg_sc_tsn.upload(m, cg_sc_tsn_h);
+  cg_sc_tsend.upload(m, cg_sc_tsend_h);
   // FP32 staging copies stay alive until the stream synchronisation below
   const std::vector<float> af(cg_ainv_h.begin(), cg_ainv_h.end());
   cg_ainv.ensure(m, af.size() / 2 + 1);
   h2d(reinterpret_cast<float*>(cg_ainv.p), af.data(), af.size());
-  std::vector<float> df;
+  // (d, w) per node for the restriction inside the sparse product: w = 1 where the coarse
+  // offset is defined (free soft nodes of an aggregate)
+  std::vector<double> dw_h(4 * (size_t)Nn, 0.0);
+  for (int s2 = 0; s2 < S; ++s2) {
+    if (cg_sc_m_h[s2] == 0) continue;
+    const HostScene& H = hs[s2];
+    for (int n = H.node0; n < H.node0 + H.nv; ++n) {
+      if (!h_nfree[n] || cg_blk_agg_h[tn_sblk_h[s2] + (n - H.node0) / kNodeChunk] < 0) continue;
+      for (int c = 0; c < 3; ++c) dw_h[4 * (size_t)n + c] = cg_d_h[3 * (size_t)n + c];
+      dw_h[4 * (size_t)n + 3] = 1.0;
+    }
+  }
+  std::vector<float> df, dwf;
   if (mixed) {
     df.assign(cg_d_h.begin(), cg_d_h.end());
     cg_d.ensure(m, df.size() / 2 + 1);
     h2d(reinterpret_cast<float*>(cg_d.p), df.data(), df.size());
+    dwf.assign(dw_h.begin(), dw_h.end());
+    cg_dw.ensure(m, dwf.size() / 2 + 1);
+    h2d(reinterpret_cast<float*>(cg_dw.p), dwf.data(), dwf.size());
   } else {
     cg_d.upload(m, cg_d_h);
+    cg_dw.upload(m, dw_h);
   }
   sync();
   iters.ensure(m, S);
@@ -1031,8 +1084,15 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.cg_sc_m = cg_sc_m.p;
   B.cg_sc_off = cg_sc_off.p;
   B.cg_d = reinterpret_cast<const T*>(cg_d.p);
+  B.cg_dw = reinterpret_cast<const T*>(cg_dw.p);
   B.cg_ainv = reinterpret_cast<const float*>(cg_ainv.p);
   B.cg_rc = reinterpret_cast<T*>(cg_rc.p);
+  B.cg_sc_ts0 = cg_sc_ts0.p;
+  B.cg_sc_tsn = cg_sc_tsn.p;
+  B.cg_sc_tsend = cg_sc_tsend.p;
+  B.P_qc = reinterpret_cast<T*>(P_qc.p);
+  B.cg_rca0 = reinterpret_cast<T*>(cg_rca0.p);
+  B.cg_rca1 = reinterpret_cast<T*>(cg_rca1.p);
   int max_pcg = 0;
   for (const auto& H : hs) max_pcg = std::max(max_pcg, H.max_pcg);
   B.max_iters = max_pcg;
@@ -1090,7 +1150,6 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
     for (int k = 0; k < kPcgChunk; ++k) {
       launch_pcg_spmv(V, TN, TS, B, k & 1, s);
       launch_pcg_update(V, TN, TS, B, k & 1, s);
-      launch_pcg_coarse(V, TN, B, (k & 1) ? B.P_rz0 : B.P_rz1, s);
     }
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &graph);  // always ends the capture
@@ -1688,7 +1747,8 @@ size_t Batch::Impl::device_bytes() const {
   add(e_pairs); add(part_nodes); add(part_tets); add(part_pairs);
   add(tp_sc); add(tp_b0); add(tp_b1); add(tp_sblk);
   add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
-  add(cg_d); add(cg_ainv); add(cg_rc);
+  add(cg_d); add(cg_ainv); add(cg_rc); add(P_qc); add(cg_rca0); add(cg_rca1); add(cg_dw); add(cg_sc_ts0);
+  add(cg_sc_tsn); add(cg_sc_tsend);
   return n;
 }
 
@@ -1752,8 +1812,9 @@ Batch::~Batch() {
            &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs, &I.part_pairs)
   FREE_ALL(&I.tp_sc, &I.tp_b0, &I.tp_b1, &I.tp_sblk)
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
-  FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m)
-  FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc)
+  FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m, &I.cg_sc_ts0,
+           &I.cg_sc_tsn, &I.cg_sc_tsend)
+  FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc, &I.P_qc, &I.cg_rca0, &I.cg_rca1, &I.cg_dw)
   I.cg_sc_off.free();
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
            &I.clist, &I.vptr, &I.vlist, &I.brow, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,

@@ -114,8 +114,15 @@ struct PcgBufsT {
   const int* cg_sc_m;         // [S] coarse dimension (6 per aggregate)
   const long long* cg_sc_off; // [S] offset of the scene's inverse coarse operator
   const T* cg_d;              // [nodes][3] scaled rest offset from the aggregate centroid
+  const T* cg_dw;             // [nodes][4] the same offset and a weight: 1 on the free soft
+                              // nodes of an aggregate (whose offset is defined), else 0
   const float* cg_ainv;       // per scene m x m, row-major (FP32: preconditioner only)
-  T* cg_rc;                   // [TN blocks][6] restricted residual partials
+  T* cg_rc;                   // [TN blocks][6] restricted residual partials (initial residual)
+  const int* cg_sc_ts0;       // [S] first TS block of the scene's first aggregate
+  const int* cg_sc_tsn;       // [S] TS blocks per aggregate (the last one may have fewer)
+  const int* cg_sc_tsend;     // [S] one past the last TS block of the scene's aggregates
+  T* P_qc;                    // [TS blocks][6] restriction of q = A p onto the rigid modes
+  T *cg_rca0, *cg_rca1;       // [aggregates][6] restricted residual P^T r_k (by parity of k)
 };
 constexpr int kCoarseMaxAgg = 128;  // aggregates per scene (coarse dimension <= 768)
 template <class T>

@@ -1083,12 +1083,74 @@ __device__ __forceinline__ void wave_sum_n(T (&v)[N]) {
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], off, 64);
 }
+// Wavefront totals by DPP lane moves (VALU only, no LDS crossbar traffic), for code where all
+// 64 lanes are active: an inclusive scan within each row of 16 lanes (shifts by 1, 2, 4, 8),
+// then the row totals carried across rows (row broadcasts of lanes 15 and 31), so lane 63
+// ends with the total, which every lane then reads.  The order of the additions is fixed.
+template <int Ctrl, int RowMask, int BankMask, bool Bound>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), Ctrl, RowMask, BankMask, Bound);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), Ctrl, RowMask, BankMask, Bound);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int Ctrl, int RowMask, int BankMask, bool Bound>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, RowMask, BankMask, Bound));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <class T>
+__device__ __forceinline__ T wave_total(T x) {
+  x += dpp_move<0x111, 0xf, 0xf, true>(x);   // row_shr:1
+  x += dpp_move<0x112, 0xf, 0xf, true>(x);   // row_shr:2
+  x += dpp_move<0x114, 0xf, 0xf, true>(x);   // row_shr:4
+  x += dpp_move<0x118, 0xf, 0xf, true>(x);   // row_shr:8
+  x += dpp_move<0x142, 0xa, 0xf, false>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc, 0xf, false>(x);  // row_bcast:31 into rows 2 and 3
+  return lane63(x);
+}
+template <class T, int N>
+__device__ __forceinline__ void wave_total_n(T (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_total(v[k]);
+}
+// N sums over a 256-thread workgroup by DPP wavefront totals; lds holds 4 x N values.
+template <class T, int N>
+__device__ void block_total256_n(T (&v)[N], T* lds) {
+  wave_total_n(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) lds[N * wid + k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) v[k] = (lds[k] + lds[N + k]) + (lds[2 * N + k] + lds[3 * N + k]);
+  __syncthreads();
+}
+
 // Sum of a scene's block partials by one wavefront (fixed assignment and fixed tree).
 template <class T>
 __device__ __forceinline__ T scene_sum_wave(const T* P, const int* sblk, int s) {
   T acc = (T)0;
   for (int k = sblk[s] + (int)threadIdx.x; k < sblk[s + 1]; k += kWave) acc += P[k];
   return wave_sum(acc);
+}
+// N sums over a 256-thread workgroup; lds holds 4 x N values.  Every thread gets the totals.
+template <class T, int N>
+__device__ void block_sum256t_n(T (&v)[N], T* lds) {
+  wave_sum_n(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) lds[N * wid + k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) v[k] = (lds[k] + lds[N + k]) + (lds[2 * N + k] + lds[3 * N + k]);
+  __syncthreads();
 }
 template <class T>
 __device__ T block_sum256t(T v, T* lds) {
@@ -1120,12 +1182,12 @@ __device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>&
       v[6] = d[2] * r[0] - d[0] * r[2];
       v[7] = d[0] * r[1] - d[1] * r[0];
     }
-    wave_sum_n(v);
+    wave_total_n(v);
     if (threadIdx.x == 0)
       for (int k = 0; k < 6; ++k) B.cg_rc[6 * blk + k] = v[2 + k];
   } else {
     T w[2] = {v[0], v[1]};
-    wave_sum_n(w);
+    wave_total_n(w);
     v[0] = w[0];
     v[1] = w[1];
   }
@@ -1139,9 +1201,13 @@ __device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>&
 //                   q_k = A p_k with p_k formed on the fly from z and p_{k-1};
 //   k_pcg_update:   alpha_k = rz_k / (p_k . q_k); x += alpha p; r -= alpha q; z = M^{-1} r.
 // p_{-1} = 0 and rz_{-1} = 1 make iteration 0 start with p_0 = z_0.
-// With the coarse level on, M^{-1} = D^{-1} + P A_c^{-1} P^T (additive two-level): the node
-// kernels apply D^{-1} (block Jacobi) and restrict r; k_pcg_coarse then solves the coarse
-// system and adds P e to z and r_c . e to the block partials of r.z.
+// With the coarse level on, M^{-1} = D^{-1} + P A_c^{-1} P^T (additive two-level).  The
+// restricted residual r_c = P^T r follows the same recurrence as r: the sparse product also
+// restricts q_k (block partials), and k_pcg_update forms r_c,k+1 = r_c,k - alpha_k P^T q_k for
+// the whole scene, solves the coarse system for its aggregate (e = rows of A_c^{-1} times
+// r_c,k+1) and adds P e to z and r_c . e to the block partials of r.z, so one kernel boundary
+// per half-iteration suffices.  At the start, k_pcg_init restricts r_0 directly and
+// k_pcg_coarse applies the coarse correction to z_0.
 template <class T>
 __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBufsT<T> B) {
   const int blk = xcd_block(TN.nblk);
@@ -1199,6 +1265,11 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   const bool live = inrange && V.nfree[row];
   const int k0 = live ? V.rowptr[row] : 0, k1 = live ? V.rowptr[row + 1] : 0;
   const int d0 = live ? B.drowptr[row] : 0, d1 = live ? B.drowptr[row + 1] : 0;
+  // rest offset and weight of the row for the restriction of q (one load that depends on
+  // nothing but the row, issued first; used at the end)
+  T dr[4] = {(T)0, (T)0, (T)0, (T)0};
+  if (B.cg_on && inrange && sub == 0)
+    for (int c = 0; c < 4; ++c) dr[c] = B.cg_dw[4 * row + c];
   T rzc, rzo, rr, gg;
   {
     T v[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -1209,7 +1280,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
       v[2] += B.P_rr[k];
       v[3] += B.P_gg[k];
     }
-    wave_sum_n(v);
+    wave_total_n(v);
     rzc = v[0];
     rzo = v[1];
     rr = v[2];
@@ -1261,31 +1332,90 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
     B.q[3 * row + 2] = q2;
     if (live) pq = pn[0] * q0 + pn[1] * q1 + pn[2] * q2;
   }
-  __shared__ T red[TPB / kWave];
-  pq = block_sum256t(pq, red);
-  if (threadIdx.x == 0) B.P_pq[blk] = pq;
+  if (!B.cg_on) {
+    __shared__ T red[TPB / kWave];
+    {
+      T one[1] = {pq};
+      block_total256_n(one, red);
+      pq = one[0];
+    }
+    if (threadIdx.x == 0) B.P_pq[blk] = pq;
+    return;
+  }
+  // restriction of q onto the rigid modes of the rows' aggregate: (sum q, sum d x q)
+  T v[7] = {pq, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  if (inrange && sub == 0) {
+    v[1] = dr[3] * q0;
+    v[2] = dr[3] * q1;
+    v[3] = dr[3] * q2;
+    v[4] = dr[1] * q2 - dr[2] * q1;
+    v[5] = dr[2] * q0 - dr[0] * q2;
+    v[6] = dr[0] * q1 - dr[1] * q0;
+  }
+  __shared__ T red7[7 * (TPB / kWave)];
+  block_total256_n(v, red7);
+  if (threadIdx.x == 0) {
+    B.P_pq[blk] = v[0];
+    for (int k = 0; k < 6; ++k) B.P_qc[6 * blk + k] = v[1 + k];
+  }
 }
 
 template <class T>
-__global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, BlockTable TS,
-                                                      PcgBufsT<T> B, int parity) {
+__global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, BlockTable TS,
+                                                    PcgBufsT<T> B, int parity) {
   const int blk = xcd_block(TN.nblk);
   if (blk < 0) return;
   __shared__ T rs[kWave][3];
+  __shared__ T red[TPB / kWave][6];
   const int s = TN.sc[blk];
   if (V.pdone[s]) return;
+  const int wid = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   T* Prz_new = parity ? B.P_rz0 : B.P_rz1;
   const T* pk = parity ? B.p0 : B.p1;
+  // ---- coarse operands first: they do not depend on alpha, so their loads overlap the
+  // scalar reductions and the node update (4 waves share the scene's coarse entries)
+  constexpr int kPerThread = 6 * kCoarseMaxAgg / TPB;
+  const int a = B.cg_on ? B.cg_blk_agg[blk] : -1;
+  int m = 0, la = 0;
+  T rcj[kPerThread], qsj[kPerThread];
+  float Aij[kPerThread][6];
+  T* rc_next = nullptr;
+  if (a >= 0) {
+    const int a0 = B.cg_sc_a0[s];
+    m = B.cg_sc_m[s];
+    la = a - a0;
+    const T* rc_cur = (parity ? B.cg_rca1 : B.cg_rca0) + 6 * (size_t)a0;
+    rc_next = (parity ? B.cg_rca0 : B.cg_rca1) + 6 * (size_t)a0;
+    const float* Ai = B.cg_ainv + B.cg_sc_off[s] + (size_t)6 * la * m;
+    // TS blocks of aggregate j / 6: runs of tsn blocks from the scene's first one
+    const int ts0 = B.cg_sc_ts0[s], tsn = B.cg_sc_tsn[s], tsend = B.cg_sc_tsend[s];
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = (int)threadIdx.x + TPB * t;
+      rcj[t] = qsj[t] = (T)0;
+      for (int q = 0; q < 6; ++q) Aij[t][q] = 0.f;
+      if (j < m) {
+        const int k = j % 6, i0 = ts0 + tsn * (j / 6), i1 = min(i0 + tsn, tsend);
+        rcj[t] = rc_cur[j];
+        T qs = (T)0;
+        for (int i = i0; i < i1; ++i) qs += B.P_qc[6 * i + k];
+        qsj[t] = qs;
+        for (int q = 0; q < 6; ++q) Aij[t][q] = Ai[(size_t)q * m + j];
+      }
+    }
+  }
+  // ---- scene scalars (every wave computes them itself)
   T tot[2] = {(T)0, (T)0};
-  for (int k = TN.sblk[s] + (int)threadIdx.x; k < TN.sblk[s + 1]; k += kWave) tot[0] += Prz_cur[k];
-  for (int k = TS.sblk[s] + (int)threadIdx.x; k < TS.sblk[s + 1]; k += kWave) tot[1] += B.P_pq[k];
-  wave_sum_n(tot);
+  for (int k = TN.sblk[s] + lane; k < TN.sblk[s + 1]; k += kWave) tot[0] += Prz_cur[k];
+  for (int k = TS.sblk[s] + lane; k < TS.sblk[s + 1]; k += kWave) tot[1] += B.P_pq[k];
+  wave_total_n(tot);
   const T rzs = tot[0], pqs = tot[1];
   const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
+  // ---- node update on wave 0: x += alpha p, r -= alpha q, z = D^{-1} r
   const int n0 = TN.b0[blk], n1 = TN.b1[blk];
-  const int n = n0 + threadIdx.x;
-  const bool live = n < n1;
+  const int n = n0 + lane;
+  const bool live = wid == 0 && n < n1;
   T r[3] = {(T)0, (T)0, (T)0};
   if (live) {
     for (int c = 0; c < 3; ++c) {
@@ -1294,24 +1424,50 @@ __global__ void __launch_bounds__(kWave) k_pcg_update(View V, BlockTable TN, Blo
       B.r[3 * n + c] = r[c];
     }
   }
-  for (int c = 0; c < 3; ++c) rs[threadIdx.x][c] = r[c];
+  if (wid == 0)
+    for (int c = 0; c < 3; ++c) rs[lane][c] = r[c];
   __syncthreads();
   T z[3] = {(T)0, (T)0, (T)0};
-  if (live) {
-    precond_apply<T>(V, B.pinv, n, n0, rs, z);
-    for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
+  if (live) precond_apply<T>(V, B.pinv, n, n0, rs, z);
+  if (a >= 0) {
+    // r_c,k+1 = r_c,k - alpha P^T q_k; e = rows of A_c^{-1} for the block's aggregate times it
+    const bool first = blk == B.cg_agg_b0[a];  // writes the aggregate's entries of r_c,k+1
+    T e[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const T rj = rcj[t] - alpha * qsj[t];
+      const int j = (int)threadIdx.x + TPB * t;
+      if (first && j < m && j / 6 == la) rc_next[j] = rj;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) e[q] += (T)Aij[t][q] * rj;
+    }
+    wave_total_n(e);
+    if (lane == 0)
+      for (int q = 0; q < 6; ++q) red[wid][q] = e[q];
+    __syncthreads();
+    for (int q = 0; q < 6; ++q) e[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    if (live && V.ntype[n] == 0 && V.nfree[n]) {
+      const T* d = B.cg_d + 3 * n;
+      z[0] += e[0] + (e[4] * d[2] - e[5] * d[1]);
+      z[1] += e[1] + (e[5] * d[0] - e[3] * d[2]);
+      z[2] += e[2] + (e[3] * d[1] - e[4] * d[0]);
+    }
   }
-  T rz, rr;
-  block_partials<T>(V, B, blk, n, live, r, z, rz, rr);
-  if (threadIdx.x == 0) {
-    Prz_new[blk] = rz;
-    B.P_rr[blk] = rr;
+  if (wid != 0) return;
+  if (live)
+    for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
+  // block partials of r.z (z with its coarse part) and r.r
+  T sums[2] = {r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
+  wave_total_n(sums);
+  if (lane == 0) {
+    Prz_new[blk] = sums[0];
+    B.P_rr[blk] = sums[1];
     if (blk == TN.sblk[s]) ++B.iters[s];
   }
 }
 
-// Coarse correction, one wave per 64-node block: the scene's restricted residual r_c (sum of
-// block partials per aggregate) staged in LDS, e = rows of A_c^{-1} for the block's aggregate
+// Coarse correction of z_0, one wave per 64-node block: the scene's restricted residual r_c
+// (sum of block partials per aggregate), e = rows of A_c^{-1} for the block's aggregate
 // times r_c, z += t + w x d on the block's soft nodes, and r_c . e of the aggregate added to
 // the partial of r.z of the aggregate's first block.
 template <class T>
@@ -1349,13 +1505,14 @@ __global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, Pcg
       for (int r = 0; r < 6; ++r) e[r] += (T)Ai[(size_t)r * m + j] * rj;
     }
   }
-  wave_sum_n(e);
+  wave_total_n(e);
   if (lane == 0 && blk == B.cg_agg_b0[a]) {
     T dot = (T)0;
     for (int k = 0; k < 6; ++k) {
       T rk = (T)0;
       for (int b = B.cg_agg_b0[a]; b < B.cg_agg_b1[a]; ++b) rk += B.cg_rc[6 * b + k];
       dot += rk * e[k];
+      B.cg_rca0[6 * (size_t)a + k] = rk;  // r_c,0 for the recurrence of the iterations
     }
     prz[blk] += dot;
   }
@@ -1904,7 +2061,7 @@ template <class T>
 void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                        int parity, hipStream_t s) {
   if (TN.nblk > 0)
-    hipLaunchKernelGGL(k_pcg_update<T>, dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, TS, B, parity);
+    hipLaunchKernelGGL(k_pcg_update<T>, dim3(xcd_grid(TN.nblk)), dim3(TPB), 0, s, V, TN, TS, B, parity);
 }
 template <class T>
 void launch_pcg_coarse(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, T* prz, hipStream_t s) {
