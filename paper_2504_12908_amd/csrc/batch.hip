@@ -229,6 +229,7 @@ struct Batch::Impl {
   DBuf<double> cg_d, cg_ainv, cg_rc;  // cg_d, cg_rc: T-typed storage; cg_ainv: float
   DBuf<double> P_qc, cg_rca0, cg_rca1, cg_dw;  // T-typed storage
   DBuf<int> cg_sc_ts0, cg_sc_tsn, cg_sc_tsend;
+  DBuf<int> bp_tmp;  // broad phase: candidates in emitted order before the per-query sort
   int cg_on = 0;
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
@@ -1043,7 +1044,7 @@ int Batch::Impl::broad_phase(const double* P0, const double* P1, int all, DBuf<i
   launch_bp_count(V, bp, s);
   scan_async(bp.bcount, bp.bstart, (int)table, scalars.p + 2);
   launch_bp_fill(V, bp, s);
-  launch_bp_query(V, P0, P1, bp, all, 0, nullptr, nullptr, s);
+  launch_bp_query(V, P0, P1, bp, all, 0, nullptr, nullptr, nullptr, s);
   scan_async(bp.qcount, bp.qoff, Nq, scalars.p);
   int ncand = 0;
   d2h(&ncand, scalars.p, 1);
@@ -1052,7 +1053,8 @@ int Batch::Impl::broad_phase(const double* P0, const double* P1, int all, DBuf<i
   check();
   oq.ensure(&mem, std::max(ncand, 1));
   ot.ensure(&mem, std::max(ncand, 1));
-  launch_bp_query(V, P0, P1, bp, all, 1, oq.p, ot.p, s);
+  bp_tmp.ensure(&mem, std::max(ncand, 1));
+  launch_bp_query(V, P0, P1, bp, all, 1, oq.p, ot.p, bp_tmp.p, s);
   return ncand;
 }
 
@@ -1747,7 +1749,7 @@ size_t Batch::Impl::device_bytes() const {
   add(e_pairs); add(part_nodes); add(part_tets); add(part_pairs);
   add(tp_sc); add(tp_b0); add(tp_b1); add(tp_sblk);
   add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
-  add(cg_d); add(cg_ainv); add(cg_rc); add(P_qc); add(cg_rca0); add(cg_rca1); add(cg_dw); add(cg_sc_ts0);
+  add(cg_d); add(cg_ainv); add(cg_rc); add(P_qc); add(cg_rca0); add(cg_rca1); add(cg_dw); add(bp_tmp); add(cg_sc_ts0);
   add(cg_sc_tsn); add(cg_sc_tsend);
   return n;
 }
@@ -1813,7 +1815,7 @@ Batch::~Batch() {
   FREE_ALL(&I.tp_sc, &I.tp_b0, &I.tp_b1, &I.tp_sblk)
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m, &I.cg_sc_ts0,
-           &I.cg_sc_tsn, &I.cg_sc_tsend)
+           &I.cg_sc_tsn, &I.cg_sc_tsend, &I.bp_tmp)
   FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc, &I.P_qc, &I.cg_rca0, &I.cg_rca1, &I.cg_dw)
   I.cg_sc_off.free();
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,

@@ -53,8 +53,8 @@ void launch_bp_targets(const View& V, const double* P0, const double* P1, BroadP
                        int all_scenes, hipStream_t s);
 void launch_bp_count(const View& V, BroadPhase& bp, hipStream_t s);
 void launch_bp_fill(const View& V, BroadPhase& bp, hipStream_t s);
-void launch_bp_query(const View& V, const double* P0, const double* P1, BroadPhase& bp,
-                     int all_scenes, int emit, int* cand_q, int* cand_t, hipStream_t s);
+void launch_bp_query(const View& V, const double* P0, const double* P1, BroadPhase& bp, int all,
+                     int emit, int* cand_q, int* cand_t, int* tmp_t, hipStream_t s);
 
 // narrow phase: flag candidates with d < dhat at cpos
 void launch_narrow(const View& V, int n, const int* cand_q, const int* cand_t, int* flag,

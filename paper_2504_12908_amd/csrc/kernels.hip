@@ -357,19 +357,23 @@ __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, cons
   }
 }
 
-// Canonical order inside each query's segment: ascending target.
-__global__ void k_bp_sort_queries(View V, BroadPhase bp, int* cand_t) {
-  const int q = gid();
+// Canonical order inside each query's segment: ascending target.  One group of 16 lanes per
+// query places every candidate at its stable rank (targets smaller than it, plus equal ones
+// before it), reading the emitted order from tmp_t and writing the sorted one to cand_t.
+__global__ void __launch_bounds__(TPB) k_bp_sort_queries(View V, BroadPhase bp, const int* tmp_t,
+                                                         int* cand_t) {
+  const int sub = threadIdx.x & (kQueryLanes - 1);
+  const int q = blockIdx.x * (TPB / kQueryLanes) + (int)(threadIdx.x / kQueryLanes);
   if (q >= V.Nq) return;
   const int off = bp.qoff[q], cnt = bp.qcount[q];
-  for (int a = 1; a < cnt; ++a) {
-    const int key = cand_t[off + a];
-    int b = a - 1;
-    while (b >= 0 && cand_t[off + b] > key) {
-      cand_t[off + b + 1] = cand_t[off + b];
-      --b;
+  for (int i = sub; i < cnt; i += kQueryLanes) {
+    const int ti = tmp_t[off + i];
+    int rank = 0;
+    for (int j = 0; j < cnt; ++j) {
+      const int tj = tmp_t[off + j];
+      rank += (tj < ti) || (tj == ti && j < i);
     }
-    cand_t[off + b + 1] = key;
+    cand_t[off + rank] = ti;
   }
 }
 
@@ -1575,7 +1579,8 @@ __global__ void k_ccd(View V, int n, const int* cq, const int* ct, unsigned long
   gather12(V.cdisp, ids, p12);
   unsigned long long* am = amin + V.qscene[cq[k]];
   const double t = accd(kind, x12, p12, 0.1, 100000, am);
-  atomic_min_pos(am, t);
+  // the minimum starts at 1 and most pairs return 1: only smaller bounds contend for it
+  if (t < 1.0) atomic_min_pos(am, t);
 }
 
 // off[s] = first candidate of scene s (candidates are sorted by scene); off[S] = n.
@@ -1967,10 +1972,12 @@ void launch_bp_fill(const View& V, BroadPhase& bp, hipStream_t s) {
   LAUNCH(k_bp_fill, bp.ntarget, TPB, s, V, bp);
 }
 void launch_bp_query(const View& V, const double* P0, const double* P1, BroadPhase& bp, int all,
-                     int emit, int* cand_q, int* cand_t, hipStream_t s) {
+                     int emit, int* cand_q, int* cand_t, int* tmp_t, hipStream_t s) {
   const int nb = nblk(V.Nq, TPB / kQueryLanes);
-  if (nb > 0) hipLaunchKernelGGL(k_bp_query, dim3(nb), dim3(TPB), 0, s, V, P0, P1, bp, all, emit, cand_q, cand_t);
-  if (emit) LAUNCH(k_bp_sort_queries, V.Nq, TPB, s, V, bp, cand_t);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_bp_query, dim3(nb), dim3(TPB), 0, s, V, P0, P1, bp, all, emit, cand_q,
+                       emit ? tmp_t : cand_t);
+  if (emit && nb > 0) hipLaunchKernelGGL(k_bp_sort_queries, dim3(nb), dim3(TPB), 0, s, V, bp, tmp_t, cand_t);
 }
 void launch_narrow(const View& V, int n, const int* cq, const int* ct, int* flag, hipStream_t s) {
   LAUNCH(k_narrow, n, TPB, s, V, n, cq, ct, flag);
