@@ -46,6 +46,7 @@ struct ApiError : std::runtime_error {
 struct Mem {
   taccel_runtime rt{};
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // second stream (contact Hessians beside the assembly chain)
   bool own_stream = false;
   void* alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -60,8 +61,9 @@ struct Mem {
   }
   void release(void* p) {
     if (!p) return;
-    // work queued on the stream may still read the buffer
+    // work queued on either stream may still read the buffer
     if (stream) (void)hipStreamSynchronize(stream);
+    if (side) (void)hipStreamSynchronize(side);
     if (rt.free) rt.free(p, rt.ctx);
     else (void)hipFree(p);
   }
@@ -180,6 +182,7 @@ struct Batch::Impl {
   std::vector<double> spmv_static_blocks;  // per scene: stored blocks of free rows
   std::vector<double> spmv_free_nodes;
   std::vector<hipEvent_t> ev_pool;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // static device data
   DBuf<SceneConst> d_sc;
   DBuf<double> x, xn, xhat, v, mass;
@@ -826,6 +829,10 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     HIPCHECK(hipStreamCreateWithFlags(&mem.stream, hipStreamNonBlocking));
     mem.own_stream = true;
   }
+  // second stream (default priority) and the events that fork work onto it and join it back
+  HIPCHECK(hipStreamCreateWithFlags(&mem.side, hipStreamNonBlocking));
+  HIPCHECK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
   device_touched = true;
   Mem* m = &mem;
   d_sc.upload(m, hsc);
@@ -1253,7 +1260,13 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   phase_end(0);
   // ---- element derivatives
   launch_fem_hess(V, mixed, s);
-  launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, s);
+  // contact Hessians (one wavefront per pair: long, narrow) on the second stream, beside the
+  // FEM assembly and the emission and sort of the contact blocks; joined before the blocks
+  // are reduced
+  HIPCHECK(hipEventRecord(ev_fork, s));
+  HIPCHECK(hipStreamWaitEvent(mem.side, ev_fork, 0));
+  launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
+  HIPCHECK(hipEventRecord(ev_join, mem.side));
   launch_body_hess(V, s);
   launch_assemble_bsr(V, nnz, brow.p, mixed, s);
   launch_assemble_grad(V, g.p, s);
@@ -1292,6 +1305,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   dcol.ensure(&mem, std::max(nseg, 1));
   dval.ensure(&mem, 9 * (size_t)std::max(nseg, 1));
   zero(rowcnt.p, sizeof(int) * (Nn + 1));
+  HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
   launch_reduce_blocks(V, nseg, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p, dcol.p,
                        dval.p, rowcnt.p, mixed, s);
   scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
@@ -1802,8 +1816,11 @@ Batch::~Batch() {
     return;
   }
   (void)hipStreamSynchronize(I.mem.stream);
+  if (I.mem.side) (void)hipStreamSynchronize(I.mem.side);
   I.release_all();
   for (hipEvent_t e : I.ev_pool) (void)hipEventDestroy(e);
+  if (I.ev_fork) (void)hipEventDestroy(I.ev_fork);
+  if (I.ev_join) (void)hipEventDestroy(I.ev_join);
   if (I.pcg_exec) (void)hipGraphExecDestroy(I.pcg_exec);
   if (I.pcg_graph) (void)hipGraphDestroy(I.pcg_graph);
 #define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
@@ -1841,6 +1858,8 @@ Batch::~Batch() {
   I.d_sc.free();
 #undef FREE_ALL
   if (I.mem.own_stream) (void)hipStreamDestroy(I.mem.stream);
+  if (I.mem.side) (void)hipStreamDestroy(I.mem.side);
+  I.mem.side = nullptr;
   delete impl_;
 }
 
@@ -1854,6 +1873,7 @@ taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, tac
     Impl& I = *impl_;
     // (when the error came before the predictor, nothing has been moved yet)
     (void)hipStreamSynchronize(I.mem.stream);
+    if (I.mem.side) (void)hipStreamSynchronize(I.mem.side);
     if (I.xn_valid)
       (void)hipMemcpyAsync(I.x.p, I.xn.p, sizeof(double) * 3 * (size_t)I.Nn, hipMemcpyDeviceToDevice,
                            I.mem.stream);
