@@ -1121,6 +1121,16 @@ __device__ __forceinline__ T wave_total(T x) {
   x += dpp_move<0x143, 0xc, 0xf, false>(x);  // row_bcast:31 into rows 2 and 3
   return lane63(x);
 }
+// Sum over each row of 16 lanes (an inclusive DPP scan within the row): the total is valid
+// in the row's last lane (lane & 15 == 15).  All lanes of the wave must be active.
+template <class T>
+__device__ __forceinline__ T row16_total(T x) {
+  x += dpp_move<0x111, 0xf, 0xf, true>(x);  // row_shr:1
+  x += dpp_move<0x112, 0xf, 0xf, true>(x);  // row_shr:2
+  x += dpp_move<0x114, 0xf, 0xf, true>(x);  // row_shr:4
+  x += dpp_move<0x118, 0xf, 0xf, true>(x);  // row_shr:8
+  return x;
+}
 template <class T, int N>
 __device__ __forceinline__ void wave_total_n(T (&v)[N]) {
 #pragma unroll
@@ -1269,11 +1279,19 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   const bool live = inrange && V.nfree[row];
   const int k0 = live ? V.rowptr[row] : 0, k1 = live ? V.rowptr[row + 1] : 0;
   const int d0 = live ? B.drowptr[row] : 0, d1 = live ? B.drowptr[row + 1] : 0;
-  // rest offset and weight of the row for the restriction of q (one load that depends on
-  // nothing but the row, issued first; used at the end)
+  // the row's last lane owns its results; its own entries of z and p_{k-1}, and the rest
+  // offset and weight for the restriction of q, depend on nothing but the row: loaded first
+  const bool owner = inrange && sub == kRowLanes - 1;
   T dr[4] = {(T)0, (T)0, (T)0, (T)0};
-  if (B.cg_on && inrange && sub == 0)
-    for (int c = 0; c < 4; ++c) dr[c] = B.cg_dw[4 * row + c];
+  T zr[3] = {(T)0, (T)0, (T)0}, por[3] = {(T)0, (T)0, (T)0};
+  if (owner) {
+    if (B.cg_on)
+      for (int c = 0; c < 4; ++c) dr[c] = B.cg_dw[4 * row + c];
+    for (int c = 0; c < 3; ++c) {
+      zr[c] = B.z[3 * row + c];
+      por[c] = pold[3 * row + c];
+    }
+  }
   T rzc, rzo, rr, gg;
   {
     T v[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -1319,16 +1337,14 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
     q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
     q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
   }
-  for (int off = kRowLanes / 2; off > 0; off >>= 1) {
-    q0 += __shfl_xor(q0, off, kRowLanes);
-    q1 += __shfl_xor(q1, off, kRowLanes);
-    q2 += __shfl_xor(q2, off, kRowLanes);
-  }
+  q0 = row16_total(q0);
+  q1 = row16_total(q1);
+  q2 = row16_total(q2);
   T pq = (T)0;
-  if (inrange && sub == 0) {
+  if (owner) {
     T pn[3];
     for (int c = 0; c < 3; ++c) {
-      pn[c] = B.z[3 * row + c] + beta * pold[3 * row + c];
+      pn[c] = zr[c] + beta * por[c];
       pnew[3 * row + c] = pn[c];
     }
     B.q[3 * row] = q0;
@@ -1348,7 +1364,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   }
   // restriction of q onto the rigid modes of the rows' aggregate: (sum q, sum d x q)
   T v[7] = {pq, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-  if (inrange && sub == 0) {
+  if (owner) {
     v[1] = dr[3] * q0;
     v[2] = dr[3] * q1;
     v[3] = dr[3] * q2;
