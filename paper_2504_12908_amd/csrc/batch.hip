@@ -46,7 +46,8 @@ struct ApiError : std::runtime_error {
 struct Mem {
   taccel_runtime rt{};
   hipStream_t stream = nullptr;
-  hipStream_t side = nullptr;  // second stream (contact Hessians beside the assembly chain)
+  hipStream_t side = nullptr;   // second stream: contact Hessians
+  hipStream_t side2 = nullptr;  // third stream: FEM and affine-body terms and their assembly
   bool own_stream = false;
   void* alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -64,6 +65,7 @@ struct Mem {
     // work queued on either stream may still read the buffer
     if (stream) (void)hipStreamSynchronize(stream);
     if (side) (void)hipStreamSynchronize(side);
+    if (side2) (void)hipStreamSynchronize(side2);
     if (rt.free) rt.free(p, rt.ctx);
     else (void)hipFree(p);
   }
@@ -182,7 +184,7 @@ struct Batch::Impl {
   std::vector<double> spmv_static_blocks;  // per scene: stored blocks of free rows
   std::vector<double> spmv_free_nodes;
   std::vector<hipEvent_t> ev_pool;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   // static device data
   DBuf<SceneConst> d_sc;
   DBuf<double> x, xn, xhat, v, mass;
@@ -829,10 +831,12 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     HIPCHECK(hipStreamCreateWithFlags(&mem.stream, hipStreamNonBlocking));
     mem.own_stream = true;
   }
-  // second stream (default priority) and the events that fork work onto it and join it back
+  // two more streams (default priority) and the events that fork work onto them and join it back
   HIPCHECK(hipStreamCreateWithFlags(&mem.side, hipStreamNonBlocking));
+  HIPCHECK(hipStreamCreateWithFlags(&mem.side2, hipStreamNonBlocking));
   HIPCHECK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&ev_join2, hipEventDisableTiming));
   device_touched = true;
   Mem* m = &mem;
   d_sc.upload(m, hsc);
@@ -1259,17 +1263,20 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_count_scene(np, pscene.p, scnt.p, s);
   phase_end(0);
   // ---- element derivatives
-  launch_fem_hess(V, mixed, s);
-  // contact Hessians (one wavefront per pair: long, narrow) on the second stream, beside the
-  // FEM assembly and the emission and sort of the contact blocks; joined before the blocks
-  // are reduced
+  // Three independent chains, joined before the contact blocks are reduced: the contact
+  // Hessians (one wavefront per pair: long and narrow) on the second stream, the FEM and
+  // affine-body terms with the static assembly on the third, and the emission and sort of the
+  // contact blocks here.
   HIPCHECK(hipEventRecord(ev_fork, s));
   HIPCHECK(hipStreamWaitEvent(mem.side, ev_fork, 0));
+  HIPCHECK(hipStreamWaitEvent(mem.side2, ev_fork, 0));
   launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
   HIPCHECK(hipEventRecord(ev_join, mem.side));
-  launch_body_hess(V, s);
-  launch_assemble_bsr(V, nnz, brow.p, mixed, s);
-  launch_assemble_grad(V, g.p, s);
+  launch_fem_hess(V, mixed, mem.side2);
+  launch_body_hess(V, mem.side2);
+  launch_assemble_bsr(V, nnz, brow.p, mixed, mem.side2);
+  launch_assemble_grad(V, g.p, mem.side2);
+  HIPCHECK(hipEventRecord(ev_join2, mem.side2));
   // ---- contact and body blocks: emit, sort by (row, col), reduce
   const int nitems = np + Nb;
   hcnt.ensure(&mem, std::max(nitems, 1));
@@ -1306,6 +1313,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   dval.ensure(&mem, 9 * (size_t)std::max(nseg, 1));
   zero(rowcnt.p, sizeof(int) * (Nn + 1));
   HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
+  HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
   launch_reduce_blocks(V, nseg, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p, dcol.p,
                        dval.p, rowcnt.p, mixed, s);
   scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
@@ -1817,10 +1825,12 @@ Batch::~Batch() {
   }
   (void)hipStreamSynchronize(I.mem.stream);
   if (I.mem.side) (void)hipStreamSynchronize(I.mem.side);
+  if (I.mem.side2) (void)hipStreamSynchronize(I.mem.side2);
   I.release_all();
   for (hipEvent_t e : I.ev_pool) (void)hipEventDestroy(e);
   if (I.ev_fork) (void)hipEventDestroy(I.ev_fork);
   if (I.ev_join) (void)hipEventDestroy(I.ev_join);
+  if (I.ev_join2) (void)hipEventDestroy(I.ev_join2);
   if (I.pcg_exec) (void)hipGraphExecDestroy(I.pcg_exec);
   if (I.pcg_graph) (void)hipGraphDestroy(I.pcg_graph);
 #define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
@@ -1859,7 +1869,8 @@ Batch::~Batch() {
 #undef FREE_ALL
   if (I.mem.own_stream) (void)hipStreamDestroy(I.mem.stream);
   if (I.mem.side) (void)hipStreamDestroy(I.mem.side);
-  I.mem.side = nullptr;
+  if (I.mem.side2) (void)hipStreamDestroy(I.mem.side2);
+  I.mem.side = I.mem.side2 = nullptr;
   delete impl_;
 }
 
@@ -1874,6 +1885,7 @@ taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, tac
     // (when the error came before the predictor, nothing has been moved yet)
     (void)hipStreamSynchronize(I.mem.stream);
     if (I.mem.side) (void)hipStreamSynchronize(I.mem.side);
+    if (I.mem.side2) (void)hipStreamSynchronize(I.mem.side2);
     if (I.xn_valid)
       (void)hipMemcpyAsync(I.x.p, I.xn.p, sizeof(double) * 3 * (size_t)I.Nn, hipMemcpyDeviceToDevice,
                            I.mem.stream);
