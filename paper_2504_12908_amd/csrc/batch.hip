@@ -248,9 +248,31 @@ struct Batch::Impl {
   DBuf<char> scratch;
   DBuf<int> mv_nodes;
   DBuf<double> mv_tgt;
-  // pinned host staging
-  int* h_pin = nullptr;
-  size_t h_pin_bytes = 0;
+  // Pinned host staging for small transfers.  A readback is copied into it asynchronously
+  // and reaches its destination in sync(); an upload is copied into it and read by the device
+  // before the next sync(), which makes the whole area free again.  Transfers that do not
+  // fit go through pageable memory (synchronous).
+  char* h_pin = nullptr;
+  size_t h_pin_bytes = 0, h_pin_used = 0;
+  struct Readback {
+    void* dst;
+    const void* staged;
+    size_t bytes;
+  };
+  std::vector<Readback> readbacks;
+  static constexpr size_t kStageBytes = 4u << 20, kStageMaxCopy = 256u << 10;
+  void* stage_take(size_t bytes) {
+    if (!h_pin || bytes > kStageMaxCopy) return nullptr;
+    const size_t at = (h_pin_used + 255) & ~size_t(255);
+    if (at + bytes > h_pin_bytes) return nullptr;
+    h_pin_used = at + bytes;
+    return h_pin + at;
+  }
+  // readbacks whose destinations may no longer exist (an error unwound their callers)
+  void discard_pending() {
+    readbacks.clear();
+    h_pin_used = 0;
+  }
 
   View view() const {
     View V;
@@ -272,14 +294,35 @@ struct Batch::Impl {
   }
 
   hipStream_t stream() const { return mem.stream; }
-  void sync() { HIPCHECK(hipStreamSynchronize(mem.stream)); }
+  void sync() {
+    const hipError_t e = hipStreamSynchronize(mem.stream);
+    // the destinations are alive here (their owners are waiting in this call)
+    for (const Readback& r : readbacks) std::memcpy(r.dst, r.staged, r.bytes);
+    readbacks.clear();
+    h_pin_used = 0;
+    HIPCHECK(e);
+  }
   template <class T>
   void d2h(T* dst, const T* src, size_t n) {
-    if (n) HIPCHECK(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyDeviceToHost, mem.stream));
+    if (!n) return;
+    const size_t bytes = sizeof(T) * n;
+    if (void* st = stage_take(bytes)) {
+      HIPCHECK(hipMemcpyAsync(st, src, bytes, hipMemcpyDeviceToHost, mem.stream));
+      readbacks.push_back({dst, st, bytes});
+    } else {
+      HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, mem.stream));
+    }
   }
   template <class T>
   void h2d(T* dst, const T* src, size_t n) {
-    if (n) HIPCHECK(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyHostToDevice, mem.stream));
+    if (!n) return;
+    const size_t bytes = sizeof(T) * n;
+    if (void* st = stage_take(bytes)) {
+      std::memcpy(st, src, bytes);
+      HIPCHECK(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, mem.stream));
+    } else {
+      HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, mem.stream));
+    }
   }
   void zero(void* p, size_t bytes) {
     if (bytes) HIPCHECK(hipMemsetAsync(p, 0, bytes, mem.stream));
@@ -987,8 +1030,9 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   bp_toff.ensure(m, std::max(bp.ntarget, 1));
   bp_qcount.ensure(m, std::max(Nq, 1));
   bp_qoff.ensure(m, std::max(Nq, 1));
-  HIPCHECK(hipHostMalloc((void**)&h_pin, 4096, hipHostMallocDefault));
-  h_pin_bytes = 4096;
+  HIPCHECK(hipHostMalloc((void**)&h_pin, kStageBytes, hipHostMallocDefault));
+  h_pin_bytes = kStageBytes;
+  h_pin_used = 0;
   // The initial state must have every admissible pair at positive distance (the barrier is
   // infinite at contact); tets were checked on the host.
   {
@@ -1880,6 +1924,7 @@ taccel_status Batch::step(const taccel_targets* t, taccel_status* per_scene, tac
     return impl_->step(t, per_scene, st, mask);
   } catch (const ApiError& e) {
     set_last_error(e.what());
+    impl_->discard_pending();
     // roll every scene back to the start of the step (positions saved by the predictor)
     Impl& I = *impl_;
     // (when the error came before the predictor, nothing has been moved yet)
@@ -1965,6 +2010,7 @@ taccel_status Batch::read(int k, taccel_field f, void* dst, size_t bytes) {
     return TACCEL_OK;
   } catch (const ApiError& e) {
     set_last_error(e.what());
+    impl_->discard_pending();
     return e.st;
   }
 }
@@ -2006,6 +2052,7 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
     return TACCEL_OK;
   } catch (const ApiError& e) {
     set_last_error(e.what());
+    impl_->discard_pending();
     return e.st;
   }
 }
@@ -2063,6 +2110,7 @@ taccel_status Batch::debug_candidates(const double* P0, const double* P1, int32_
     return TACCEL_OK;
   } catch (const ApiError& e) {
     set_last_error(e.what());
+    impl_->discard_pending();
     return e.st;
   }
 }
