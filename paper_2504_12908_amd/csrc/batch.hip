@@ -1176,6 +1176,14 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
     launch_bytes += (9 * w + 4.0) * nseg + 4.0 * Nn;
     for (int k = 0; k < S; ++k)
       if (ha[k]) launch_bytes += 9.0 * w * spmv_free_nodes[k];
+    // with the coarse level: the rest offset and weight of every row (4 values) read and the
+    // restriction of q (6 values per 16-row block) written; p.q partials (1 value per block)
+    for (int k = 0; k < S; ++k)
+      if (ha[k]) {
+        const int nrow = hs[k].node1 - hs[k].node0;
+        const double rows = nrow, blocks = (nrow + kRowChunk - 1) / kRowChunk;
+        launch_bytes += w * blocks + (B.cg_on ? 4.0 * w * rows + 6.0 * w * blocks : 0.0);
+      }
   }
   if (prof.on)
     while (ev_pool.size() < 2 * (size_t)kPcgChunk) {
