@@ -90,9 +90,12 @@ typedef struct {
 } taccel_scene_desc;
 
 /* Device memory and stream.  alloc/free may be NULL (then hipMalloc/hipFree).  stream NULL:
- * the library creates a non-blocking stream of default priority for the object.  All device
- * work of a scene/batch is enqueued on that one stream (the PCG loop is replayed from a HIP
- * graph captured on it, so it must not be the legacy null stream). */
+ * the library creates a non-blocking stream of default priority for the object.  The device
+ * work of a scene/batch is ordered on that stream (the PCG loop is replayed from a HIP graph
+ * captured on it, so it must not be the legacy null stream); inside a Newton iteration two
+ * more streams of the object's own (default priority) take part of the derivative work and
+ * are joined back to it by events before anything later depends on them, so every call still
+ * returns with its work complete. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
