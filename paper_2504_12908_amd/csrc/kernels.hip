@@ -1148,6 +1148,24 @@ __device__ void block_total256_n(T (&v)[N], T* lds) {
   __syncthreads();
 }
 
+// Lane-strided partial sum P[b0 + lane], P[b0 + lane + 64], ... < P[b1], with U loads in
+// flight per lane (added in the same order as a plain strided loop).
+template <int U, class T>
+__device__ __forceinline__ T strided_sum(const T* P, int b0, int b1, int lane) {
+  T acc = (T)0;
+  for (int k0 = b0 + lane; k0 < b1; k0 += kWave * U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + kWave * u;
+      v[u] = k < b1 ? P[k] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
+  }
+  return acc;
+}
+
 // Sum of a scene's block partials by one wavefront (fixed assignment and fixed tree).
 template <class T>
 __device__ __forceinline__ T scene_sum_wave(const T* P, const int* sblk, int s) {
@@ -1268,7 +1286,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   const int blk = xcd_block(TS.nblk);
   if (blk < 0) return;
   const int s = TS.sc[blk];
-  if (V.pdone[s]) return;
+  if (V.pdone[s]) return;  // one uniform load: the blocks of converged scenes stay cheap
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   const T* Prz_old = parity ? B.P_rz0 : B.P_rz1;
   const T* pold = parity ? B.p1 : B.p0;
@@ -1276,9 +1294,18 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   const int sub = threadIdx.x & (kRowLanes - 1);
   const int row = TS.b0[blk] + (int)(threadIdx.x / kRowLanes);
   const bool inrange = row < TS.b1[blk];
-  const bool live = inrange && V.nfree[row];
-  const int k0 = live ? V.rowptr[row] : 0, k1 = live ? V.rowptr[row + 1] : 0;
-  const int d0 = live ? B.drowptr[row] : 0, d1 = live ? B.drowptr[row + 1] : 0;
+  // row data first, none of it behind another load (the free flag only masks the ranges)
+  int fr = 0, rp0 = 0, rp1 = 0, dp0 = 0, dp1 = 0;
+  if (inrange) {
+    fr = V.nfree[row];
+    rp0 = V.rowptr[row];
+    rp1 = V.rowptr[row + 1];
+    dp0 = B.drowptr[row];
+    dp1 = B.drowptr[row + 1];
+  }
+  const bool live = inrange && fr;
+  const int k0 = live ? rp0 : 0, k1 = live ? rp1 : 0;
+  const int d0 = live ? dp0 : 0, d1 = live ? dp1 : 0;
   // the row's last lane owns its results; its own entries of z and p_{k-1}, and the rest
   // offset and weight for the restriction of q, depend on nothing but the row: loaded first
   const bool owner = inrange && sub == kRowLanes - 1;
@@ -1294,14 +1321,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   }
   T rzc, rzo, rr, gg;
   {
-    T v[4] = {(T)0, (T)0, (T)0, (T)0};
     const int lane = threadIdx.x & (kWave - 1);
-    for (int k = TN.sblk[s] + lane; k < TN.sblk[s + 1]; k += kWave) {
-      v[0] += Prz_cur[k];
-      v[1] += Prz_old[k];
-      v[2] += B.P_rr[k];
-      v[3] += B.P_gg[k];
-    }
+    const int b0 = TN.sblk[s], b1 = TN.sblk[s + 1];
+    T v[4] = {strided_sum<2>(Prz_cur, b0, b1, lane), strided_sum<2>(Prz_old, b0, b1, lane),
+              strided_sum<2>(B.P_rr, b0, b1, lane), strided_sum<2>(B.P_gg, b0, b1, lane)};
     wave_total_n(v);
     rzc = v[0];
     rzo = v[1];
@@ -1388,18 +1411,39 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
   __shared__ T rs[kWave][3];
   __shared__ T red[TPB / kWave][6];
   const int s = TN.sc[blk];
-  if (V.pdone[s]) return;
+  if (V.pdone[s]) return;  // one uniform load: the blocks of converged scenes stay cheap
   const int wid = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   T* Prz_new = parity ? B.P_rz0 : B.P_rz1;
   const T* pk = parity ? B.p0 : B.p1;
-  // ---- coarse operands first: they do not depend on alpha, so their loads overlap the
-  // scalar reductions and the node update (4 waves share the scene's coarse entries)
+  // Every load that does not depend on alpha is issued first, so their latencies overlap
+  // instead of adding up.
+  // ---- node operands (wave 0: one node per lane)
+  const int n0 = TN.b0[blk], n1 = TN.b1[blk];
+  const int n = n0 + lane;
+  const bool live = wid == 0 && n < n1;
+  T pkn[3] = {(T)0, (T)0, (T)0}, qn[3] = {(T)0, (T)0, (T)0}, rn[3] = {(T)0, (T)0, (T)0};
+  T P9[9] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+  double dxn[3] = {0.0, 0.0, 0.0};
+  int ntn = 0, nfn = 0;
+  if (live) {
+    ntn = V.ntype[n];
+    nfn = V.nfree[n];
+    for (int c = 0; c < 3; ++c) {
+      pkn[c] = pk[3 * n + c];
+      qn[c] = B.q[3 * n + c];
+      rn[c] = B.r[3 * n + c];
+      dxn[c] = B.dx[3 * n + c];
+    }
+    for (int i = 0; i < 9; ++i) P9[i] = B.pinv[9 * (size_t)n + i];
+  }
+  // ---- coarse operands (4 waves share the scene's coarse entries)
   constexpr int kPerThread = 6 * kCoarseMaxAgg / TPB;
   const int a = B.cg_on ? B.cg_blk_agg[blk] : -1;
   int m = 0, la = 0;
   T rcj[kPerThread], qsj[kPerThread];
   float Aij[kPerThread][6];
+  T dn[3] = {(T)0, (T)0, (T)0};
   T* rc_next = nullptr;
   if (a >= 0) {
     const int a0 = B.cg_sc_a0[s];
@@ -1410,37 +1454,66 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
     const float* Ai = B.cg_ainv + B.cg_sc_off[s] + (size_t)6 * la * m;
     // TS blocks of aggregate j / 6: runs of tsn blocks from the scene's first one
     const int ts0 = B.cg_sc_ts0[s], tsn = B.cg_sc_tsn[s], tsend = B.cg_sc_tsend[s];
+    // Loads without branches: entries past m read entry 0 (in range) and are weighted 0, and
+    // the 4 partials of an aggregate of one block are read at once, so nothing waits until
+    // every operand of the thread is in flight.
+    T qv[kPerThread][4];
+    bool on[kPerThread];
 #pragma unroll
     for (int t = 0; t < kPerThread; ++t) {
       const int j = (int)threadIdx.x + TPB * t;
-      rcj[t] = qsj[t] = (T)0;
-      for (int q = 0; q < 6; ++q) Aij[t][q] = 0.f;
-      if (j < m) {
-        const int k = j % 6, i0 = ts0 + tsn * (j / 6), i1 = min(i0 + tsn, tsend);
-        rcj[t] = rc_cur[j];
-        T qs = (T)0;
-        for (int i = i0; i < i1; ++i) qs += B.P_qc[6 * i + k];
-        qsj[t] = qs;
-        for (int q = 0; q < 6; ++q) Aij[t][q] = Ai[(size_t)q * m + j];
+      on[t] = j < m;
+      const int jj = on[t] ? j : 0;
+      const int k = jj % 6, i0 = ts0 + tsn * (jj / 6), i1 = min(i0 + tsn, tsend);
+      rcj[t] = rc_cur[jj];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) qv[t][u] = B.P_qc[6 * min(i0 + u, i1 - 1) + k];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) Aij[t][q] = Ai[(size_t)q * m + jj];
+      // aggregates of more than one block: the remaining partials, four at a time
+      T extra = (T)0;
+      for (int ib = i0 + 4; ib < i1; ib += 4) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = ib + u < i1 ? B.P_qc[6 * (ib + u) + k] : (T)0;
+        extra += v[0];
+        extra += v[1];
+        extra += v[2];
+        extra += v[3];
+      }
+      qsj[t] = extra;
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u >= i1) qv[t][u] = (T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      // same order as one pass over the aggregate's partials
+      T qs = (T)0;
+      qs += qv[t][0];
+      qs += qv[t][1];
+      qs += qv[t][2];
+      qs += qv[t][3];
+      qsj[t] = qs + qsj[t];
+      if (!on[t]) {
+        rcj[t] = qsj[t] = (T)0;
+        for (int q = 0; q < 6; ++q) Aij[t][q] = 0.f;
       }
     }
+    if (live)
+      for (int c = 0; c < 3; ++c) dn[c] = B.cg_d[3 * n + c];
   }
   // ---- scene scalars (every wave computes them itself)
-  T tot[2] = {(T)0, (T)0};
-  for (int k = TN.sblk[s] + lane; k < TN.sblk[s + 1]; k += kWave) tot[0] += Prz_cur[k];
-  for (int k = TS.sblk[s] + lane; k < TS.sblk[s + 1]; k += kWave) tot[1] += B.P_pq[k];
+  T tot[2] = {strided_sum<2>(Prz_cur, TN.sblk[s], TN.sblk[s + 1], lane),
+              strided_sum<8>(B.P_pq, TS.sblk[s], TS.sblk[s + 1], lane)};
   wave_total_n(tot);
   const T rzs = tot[0], pqs = tot[1];
   const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
-  // ---- node update on wave 0: x += alpha p, r -= alpha q, z = D^{-1} r
-  const int n0 = TN.b0[blk], n1 = TN.b1[blk];
-  const int n = n0 + lane;
-  const bool live = wid == 0 && n < n1;
+  // ---- node update: x += alpha p, r -= alpha q, z = D^{-1} r
   T r[3] = {(T)0, (T)0, (T)0};
   if (live) {
+    for (int c = 0; c < 3; ++c) r[c] = rn[c] - alpha * qn[c];
     for (int c = 0; c < 3; ++c) {
-      B.dx[3 * n + c] += (double)(alpha * pk[3 * n + c]);
-      r[c] = B.r[3 * n + c] - alpha * B.q[3 * n + c];
+      B.dx[3 * n + c] = dxn[c] + (double)(alpha * pkn[c]);
       B.r[3 * n + c] = r[c];
     }
   }
@@ -1448,7 +1521,13 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
     for (int c = 0; c < 3; ++c) rs[lane][c] = r[c];
   __syncthreads();
   T z[3] = {(T)0, (T)0, (T)0};
-  if (live) precond_apply<T>(V, B.pinv, n, n0, rs, z);
+  if (live && nfn) {
+    if (ntn == 0) {
+      for (int i = 0; i < 3; ++i) z[i] = P9[3 * i] * r[0] + P9[3 * i + 1] * r[1] + P9[3 * i + 2] * r[2];
+    } else {
+      precond_apply<T>(V, B.pinv, n, n0, rs, z);
+    }
+  }
   if (a >= 0) {
     // r_c,k+1 = r_c,k - alpha P^T q_k; e = rows of A_c^{-1} for the block's aggregate times it
     const bool first = blk == B.cg_agg_b0[a];  // writes the aggregate's entries of r_c,k+1
@@ -1466,11 +1545,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
       for (int q = 0; q < 6; ++q) red[wid][q] = e[q];
     __syncthreads();
     for (int q = 0; q < 6; ++q) e[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-    if (live && V.ntype[n] == 0 && V.nfree[n]) {
-      const T* d = B.cg_d + 3 * n;
-      z[0] += e[0] + (e[4] * d[2] - e[5] * d[1]);
-      z[1] += e[1] + (e[5] * d[0] - e[3] * d[2]);
-      z[2] += e[2] + (e[3] * d[1] - e[4] * d[0]);
+    if (live && ntn == 0 && nfn) {
+      z[0] += e[0] + (e[4] * dn[2] - e[5] * dn[1]);
+      z[1] += e[1] + (e[5] * dn[0] - e[3] * dn[2]);
+      z[2] += e[2] + (e[3] * dn[1] - e[4] * dn[0]);
     }
   }
   if (wid != 0) return;
