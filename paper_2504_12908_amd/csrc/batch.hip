@@ -355,7 +355,7 @@ struct Batch::Impl {
   std::vector<const void*> pcg_key;
   static constexpr int kPcgChunk = 16;
   template <class T>
-  void run_pcg(const View& V, const PcgBufsT<T>& B, int nseg);
+  void run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d);
   template <class T>
   PcgBufsT<T> pcg_bufs();
   void build(const taccel_scene_desc* d, int n);
@@ -1157,11 +1157,12 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
 }
 
 template <class T>
-void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, int nseg) {
+void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d) {
   hipStream_t s = stream();
   Profiler& prof = profiler();
   double launch_bytes = 0.0;
   if (prof.on) {
+    const int nseg = read_int(nseg_d);  // dynamic blocks of this matrix
     std::vector<int> ha(S);
     d2h(ha.data(), act.p, S);
     sync();
@@ -1356,24 +1357,28 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   sflag.ensure(&mem, std::max(nmax, 1));
   segid.ensure(&mem, std::max(nmax, 1));
   segstart.ensure(&mem, std::max(nmax, 1) + 1);
-  // Hessian blocks
+  // Hessian blocks.  The segment counts stay on the device (scalars 6 and 7): the records
+  // bound them, so buffers and grids are sized by the record counts and the reductions read
+  // the exact counts themselves.
+  int* nseg_d = scalars.p + 6;
+  int* ngseg_d = scalars.p + 7;
   launch_seg_flags(nh, hkey.p, sflag.p, s);
-  const int nseg = scan(sflag.p, segid.p, nh);
+  scan_async(sflag.p, segid.p, nh, nseg_d);
   launch_seg_start(nh, sflag.p, segid.p, segstart.p, s);
-  drow.ensure(&mem, std::max(nseg, 1));
-  dcol.ensure(&mem, std::max(nseg, 1));
-  dval.ensure(&mem, 9 * (size_t)std::max(nseg, 1));
+  drow.ensure(&mem, std::max(nh, 1));
+  dcol.ensure(&mem, std::max(nh, 1));
+  dval.ensure(&mem, 9 * (size_t)std::max(nh, 1));
   zero(rowcnt.p, sizeof(int) * (Nn + 1));
   HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
   HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
-  launch_reduce_blocks(V, nseg, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p, dcol.p,
-                       dval.p, rowcnt.p, mixed, s);
+  launch_reduce_blocks(V, nh, nseg_d, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p,
+                       dcol.p, dval.p, rowcnt.p, mixed, s);
   scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
   // gradient entries
   launch_seg_flags(ng, gkey.p, sflag.p, s);
-  const int ngseg = scan(sflag.p, segid.p, ng);
+  scan_async(sflag.p, segid.p, ng, ngseg_d);
   launch_seg_start(ng, sflag.p, segid.p, segstart.p, s);
-  launch_reduce_grad(V, ngseg, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
+  launch_reduce_grad(V, ng, ngseg_d, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
   // ---- preconditioner and PCG
   zero(bad.p, sizeof(int) * S);
   launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, mixed, s);
@@ -1389,12 +1394,12 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     const PcgBufsT<float> B = pcg_bufs<float>();
     launch_pcg_init(V, TN, B, s);
     launch_pcg_coarse(V, TN, B, B.P_rz0, s);
-    run_pcg(V, B, nseg);
+    run_pcg(V, B, nseg_d);
   } else {
     const PcgBufsT<double> B = pcg_bufs<double>();
     launch_pcg_init(V, TN, B, s);
     launch_pcg_coarse(V, TN, B, B.P_rz0, s);
-    run_pcg(V, B, nseg);
+    run_pcg(V, B, nseg_d);
   }
   phase_end(2);
   d2h(pcg_it.data(), iters.p, S);

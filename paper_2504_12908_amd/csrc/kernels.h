@@ -80,11 +80,11 @@ void launch_contrib_emit(const View& V, int np, const int* pv, const int* hoff, 
                          int* gidx, int* gsrc, double* gcoef, hipStream_t s);
 void launch_seg_flags(int n, const uint64_t* keys, int* flags, hipStream_t s);
 void launch_seg_start(int n, const int* flags, const int* segid, int* segstart, hipStream_t s);
-void launch_reduce_blocks(const View& V, int nseg, const uint64_t* keys, const int* idx,
+void launch_reduce_blocks(const View& V, int nmax, const int* nseg, const uint64_t* keys, const int* idx,
                           const int* segstart, const int* src, const double* coef,
                           const double* ph, int* drow, int* dcol, void* dval, int* rowcnt,
                           int mixed, hipStream_t s);
-void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int* idx,
+void launch_reduce_grad(const View& V, int nmax, const int* nseg, const uint64_t* keys, const int* idx,
                         const int* segstart, const int* src, const double* coef,
                         const double* pg, double* g, hipStream_t s);
 void launch_precond(const View& V, const int* drowptr, const int* dcol, const void* dval,

@@ -888,11 +888,11 @@ __global__ void k_seg_start(int n, const int* flags, const int* segid, int* segs
 }
 
 template <class T>
-__global__ void k_reduce_blocks(View V, int nseg, const uint64_t* keys, const int* idx,
+__global__ void k_reduce_blocks(View V, int nmax, const int* nseg, const uint64_t* keys, const int* idx,
                                 const int* segstart, const int* src, const double* coef,
                                 const double* ph, int* drow, int* dcol, T* dval, int* rowcnt) {
   const int k = gid();
-  if (k >= nseg) return;
+  if (k >= nmax || k >= *nseg) return;
   const int i0 = segstart[k], i1 = segstart[k + 1];
   const uint64_t key = keys[i0];
   const int row = (int)(key / (uint64_t)V.Nn), col = (int)(key % (uint64_t)V.Nn);
@@ -923,11 +923,11 @@ __global__ void k_reduce_blocks(View V, int nseg, const uint64_t* keys, const in
   atomicAdd(rowcnt + row, 1);
 }
 
-__global__ void k_reduce_grad(View V, int nseg, const uint64_t* keys, const int* idx,
+__global__ void k_reduce_grad(View V, int nmax, const int* nseg, const uint64_t* keys, const int* idx,
                               const int* segstart, const int* src, const double* coef,
                               const double* pg, double* g) {
   const int k = gid();
-  if (k >= nseg) return;
+  if (k >= nmax || k >= *nseg) return;
   const int i0 = segstart[k], i1 = segstart[k + 1];
   const int node = (int)keys[i0];
   double acc[3] = {0, 0, 0};
@@ -2116,21 +2116,21 @@ void launch_seg_flags(int n, const uint64_t* keys, int* flags, hipStream_t s) {
 void launch_seg_start(int n, const int* flags, const int* segid, int* segstart, hipStream_t s) {
   LAUNCH(k_seg_start, n, TPB, s, n, flags, segid, segstart);
 }
-void launch_reduce_blocks(const View& V, int nseg, const uint64_t* keys, const int* idx,
+void launch_reduce_blocks(const View& V, int nmax, const int* nseg, const uint64_t* keys, const int* idx,
                           const int* segstart, const int* src, const double* coef,
                           const double* ph, int* drow, int* dcol, void* dval, int* rowcnt,
                           int mixed, hipStream_t s) {
   if (mixed)
-    LAUNCH(k_reduce_blocks<float>, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, ph, drow,
+    LAUNCH(k_reduce_blocks<float>, nmax, TPB, s, V, nmax, nseg, keys, idx, segstart, src, coef, ph, drow,
            dcol, static_cast<float*>(dval), rowcnt);
   else
-    LAUNCH(k_reduce_blocks<double>, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, ph, drow,
+    LAUNCH(k_reduce_blocks<double>, nmax, TPB, s, V, nmax, nseg, keys, idx, segstart, src, coef, ph, drow,
            dcol, static_cast<double*>(dval), rowcnt);
 }
-void launch_reduce_grad(const View& V, int nseg, const uint64_t* keys, const int* idx,
+void launch_reduce_grad(const View& V, int nmax, const int* nseg, const uint64_t* keys, const int* idx,
                         const int* segstart, const int* src, const double* coef,
                         const double* pg, double* g, hipStream_t s) {
-  LAUNCH(k_reduce_grad, nseg, TPB, s, V, nseg, keys, idx, segstart, src, coef, pg, g);
+  LAUNCH(k_reduce_grad, nmax, TPB, s, V, nmax, nseg, keys, idx, segstart, src, coef, pg, g);
 }
 void launch_precond(const View& V, const int* drowptr, const int* dcol, const void* dval,
                     void* pinv, int* bad, int mixed, hipStream_t s) {
