@@ -264,15 +264,28 @@ __device__ __forceinline__ bool boxes_close_lohi(const double* a, const double* 
   return true;
 }
 
-// One query primitive per group of 16 lanes: the lanes walk the query's cells together and
-// scan each bucket's entries in parallel.  Count pass: matches per query.  Emit pass: the
-// matches are compacted in lane order with a ballot; k_bp_sort_queries then sorts each
+// One query primitive per group of 16 lanes.  The lanes take 16 of the query's cells at a time
+// and fetch their buckets' entry ranges together; an inclusive scan of the entry counts over
+// the group (DPP, one row = one group) flattens those entries, and the lanes then test 16
+// entries at a time, each finding its cell from the scan.  So the dependent loads of a query
+// are paid once per 16 cells and once per 16 entries rather than once per cell.  Count pass:
+// matches per query.  Emit pass: matches compacted in lane order with a ballot (the same tests
+// in the same order, so each query emits exactly its count); k_bp_sort_queries then sorts each
 // query's segment by target so the candidate list has the canonical order.
 constexpr int kQueryLanes = 16;
+__device__ __forceinline__ int row16_scan_int(int x) {  // inclusive scan within each DPP row
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  return x;
+}
 __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, const double* P1,
                                                   BroadPhase bp, int all, int emit, int* cand_q,
                                                   int* cand_t) {
+  __shared__ int sh_incl[TPB], sh_e0[TPB], sh_cell[TPB];
   const int sub = threadIdx.x & (kQueryLanes - 1);
+  const int gbase = (int)threadIdx.x - sub;  // first thread of this lane's group
   const int q = blockIdx.x * (TPB / kQueryLanes) + (int)(threadIdx.x / kQueryLanes);
   if (q >= V.Nq) return;  // whole 16-lane group leaves together
   const int s = V.qscene[q];
@@ -302,55 +315,75 @@ __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, cons
   const double inv = 1.0 / sc.cell;
   const int gshift = (threadIdx.x & 63) & ~(kQueryLanes - 1);
   const unsigned long long lt = (1ull << (threadIdx.x & 63)) - 1ull;
-  for (int z = ql[2]; z <= ql[5]; ++z)
-    for (int y = ql[1]; y <= ql[4]; ++y)
-      for (int x = ql[0]; x <= ql[3]; ++x) {
-        const int b = bucket_of(s, x, y, z, kind, bp.table_mask);
-        const int e0 = bp.bstart[b], e1 = e0 + bp.bcount[b];
-        for (int base = e0; base < e1; base += kQueryLanes) {
-          const int e = base + sub;
-          bool hit = false;
-          int tgt = 0;
-          if (e < e1) {
-            const BpEntry& E = bp.entries[e];
-            const int t = E.t;
-            hit = E.cx == x && E.cy == y && E.cz == z && !(kind == 1 && t - V.Ntr <= i) &&
-                  max(ql[0], cell_of(E.lo[0] - sc.dhat, sc.org[0], inv)) == x &&
-                  max(ql[1], cell_of(E.lo[1] - sc.dhat, sc.org[1], inv)) == y &&
-                  max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) == z &&
-                  boxes_close_lohi(qb, E.lo, E.hi, sc.dhat);
-            if (hit) {
-              int tid[3];
-              target_ids(V, t, tid);
-              if (kind == 0) {
-                tgt = t;
-                const int v = qids[0];
-                hit = V.cvscene[tid[0]] == s && v != tid[0] && v != tid[1] && v != tid[2] &&
-                      !(qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) &&
-                      !(V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]);
-              } else {
-                tgt = t - V.Ntr;
-                hit = V.cvscene[tid[0]] == s && qids[0] != tid[0] && qids[0] != tid[1] &&
-                      qids[1] != tid[0] && qids[1] != tid[1] &&
-                      !(qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) &&
-                      !(V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]);
-              }
-            }
-          }
-          if (!emit) {
-            cnt += hit;
+  // the cell box has at most kMaxCells cells (cell_range collapses larger ones)
+  const int nx = ql[3] - ql[0] + 1, ny = ql[4] - ql[1] + 1, nz = ql[5] - ql[2] + 1;
+  const int ncell = nx * ny * nz;
+  for (int c0 = 0; c0 < ncell; c0 += kQueryLanes) {  // uniform over the group
+    const int c = c0 + sub;
+    int e0 = 0, ne = 0;
+    if (c < ncell) {
+      const int x = ql[0] + c % nx, y = ql[1] + (c / nx) % ny, z = ql[2] + c / (nx * ny);
+      const int b = bucket_of(s, x, y, z, kind, bp.table_mask);
+      e0 = bp.bstart[b];
+      ne = bp.bcount[b];
+    }
+    const int incl = row16_scan_int(ne);
+    const int total = __shfl(incl, kQueryLanes - 1, kQueryLanes);
+    sh_incl[threadIdx.x] = incl;
+    sh_e0[threadIdx.x] = e0;
+    sh_cell[threadIdx.x] = c;
+    __builtin_amdgcn_wave_barrier();
+    for (int t0 = 0; t0 < total; t0 += kQueryLanes) {  // uniform over the group
+      const int t = t0 + sub;
+      bool hit = false;
+      int tgt = 0;
+      if (t < total) {
+        int j = 0;  // the lane whose cell holds flattened entry t
+        while (sh_incl[gbase + j] <= t) ++j;
+        const int before = j > 0 ? sh_incl[gbase + j - 1] : 0;
+        const int e = sh_e0[gbase + j] + (t - before);
+        const int cc = sh_cell[gbase + j];
+        const int x = ql[0] + cc % nx, y = ql[1] + (cc / nx) % ny, z = ql[2] + cc / (nx * ny);
+        const BpEntry& E = bp.entries[e];
+        const int tt = E.t;
+        hit = E.cx == x && E.cy == y && E.cz == z && !(kind == 1 && tt - V.Ntr <= i) &&
+              max(ql[0], cell_of(E.lo[0] - sc.dhat, sc.org[0], inv)) == x &&
+              max(ql[1], cell_of(E.lo[1] - sc.dhat, sc.org[1], inv)) == y &&
+              max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) == z &&
+              boxes_close_lohi(qb, E.lo, E.hi, sc.dhat);
+        if (hit) {
+          int tid[3];
+          target_ids(V, tt, tid);
+          if (kind == 0) {
+            tgt = tt;
+            const int v = qids[0];
+            hit = V.cvscene[tid[0]] == s && v != tid[0] && v != tid[1] && v != tid[2] &&
+                  !(qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) &&
+                  !(V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]);
           } else {
-            const unsigned long long m = __ballot(hit);
-            const unsigned long long mine = (m >> gshift) & 0xFFFFull;
-            if (hit) {
-              const int pos = off + cnt + __popcll(m & lt & (0xFFFFull << gshift));
-              cand_q[pos] = q;
-              cand_t[pos] = tgt;
-            }
-            cnt += __popcll(mine);
+            tgt = tt - V.Ntr;
+            hit = V.cvscene[tid[0]] == s && qids[0] != tid[0] && qids[0] != tid[1] &&
+                  qids[1] != tid[0] && qids[1] != tid[1] &&
+                  !(qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) &&
+                  !(V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]);
           }
         }
       }
+      if (!emit) {
+        cnt += hit;
+      } else {
+        const unsigned long long m = __ballot(hit);
+        const unsigned long long mine = (m >> gshift) & 0xFFFFull;
+        if (hit) {
+          const int pos = off + cnt + __popcll(m & lt & (0xFFFFull << gshift));
+          cand_q[pos] = q;
+          cand_t[pos] = tgt;
+        }
+        cnt += __popcll(mine);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // this round's LDS entries are read before the next round
+  }
   if (!emit) {
     for (int o = kQueryLanes / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kQueryLanes);
     if (sub == 0) bp.qcount[q] = cnt;
