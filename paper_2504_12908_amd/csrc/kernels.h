@@ -17,6 +17,12 @@ struct BlockTable {
 struct BpEntry {
   int t, cx, cy, cz;
   double lo[3], hi[3];
+  // target attributes the query tests need, copied at fill time so a test costs one load:
+  int v[3];    // contact vertices (v[2] = -1 for an edge)
+  int scene;
+  int body;    // the affine body all its vertices belong to, else -1
+  int fixed;   // 1 when all its vertices are permanently fixed
+  int pad[2];
 };
 
 // Broad-phase working set.

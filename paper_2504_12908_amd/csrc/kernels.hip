@@ -245,6 +245,19 @@ __global__ void k_bp_fill(View V, BroadPhase bp) {
     E.lo[c] = bp.tbox[6 * t + c];
     E.hi[c] = bp.tbox[6 * t + 3 + c];
   }
+  const int nv = type == 0 ? 3 : 2;
+  E.v[0] = ids[0];
+  E.v[1] = ids[1];
+  E.v[2] = nv == 3 ? ids[2] : -1;
+  E.scene = s;
+  int body = V.cvb[ids[0]], fixed = V.cvfix[ids[0]] ? 1 : 0;
+  for (int k = 1; k < nv; ++k) {
+    if (V.cvb[ids[k]] != body) body = -1;
+    if (!V.cvfix[ids[k]]) fixed = 0;
+  }
+  E.body = body;
+  E.fixed = fixed;
+  E.pad[0] = E.pad[1] = 0;
   for (int z = cl[2]; z <= cl[5]; ++z)
     for (int y = cl[1]; y <= cl[4]; ++y)
       for (int x = cl[0]; x <= cl[3]; ++x) {
@@ -312,6 +325,10 @@ __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, cons
   const int off = emit ? bp.qoff[q] : 0;
   int cnt = 0;  // matches of this lane (count pass) / of the group so far (emit pass)
   const int qb0 = V.cvb[qids[0]];
+  // query side of the admissibility tests: an edge query lies in body qb0 only if both its
+  // vertices do; it is fixed only if all its vertices are
+  const bool qbody = kind == 0 || V.cvb[qids[1]] == qb0;
+  const bool qfix = V.cvfix[qids[0]] && (kind == 0 || V.cvfix[qids[1]]);
   const double inv = 1.0 / sc.cell;
   const int gshift = (threadIdx.x & 63) & ~(kQueryLanes - 1);
   const unsigned long long lt = (1ull << (threadIdx.x & 63)) - 1ull;
@@ -352,20 +369,16 @@ __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, cons
               max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) == z &&
               boxes_close_lohi(qb, E.lo, E.hi, sc.dhat);
         if (hit) {
-          int tid[3];
-          target_ids(V, tt, tid);
+          // admissibility: same scene, no shared vertex, not inside one body, not all fixed
           if (kind == 0) {
             tgt = tt;
             const int v = qids[0];
-            hit = V.cvscene[tid[0]] == s && v != tid[0] && v != tid[1] && v != tid[2] &&
-                  !(qb0 >= 0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0 && V.cvb[tid[2]] == qb0) &&
-                  !(V.cvfix[v] && V.cvfix[tid[0]] && V.cvfix[tid[1]] && V.cvfix[tid[2]]);
+            hit = E.scene == s && v != E.v[0] && v != E.v[1] && v != E.v[2] &&
+                  !(qb0 >= 0 && E.body == qb0) && !(qfix && E.fixed);
           } else {
             tgt = tt - V.Ntr;
-            hit = V.cvscene[tid[0]] == s && qids[0] != tid[0] && qids[0] != tid[1] &&
-                  qids[1] != tid[0] && qids[1] != tid[1] &&
-                  !(qb0 >= 0 && V.cvb[qids[1]] == qb0 && V.cvb[tid[0]] == qb0 && V.cvb[tid[1]] == qb0) &&
-                  !(V.cvfix[qids[0]] && V.cvfix[qids[1]] && V.cvfix[tid[0]] && V.cvfix[tid[1]]);
+            hit = E.scene == s && qids[0] != E.v[0] && qids[0] != E.v[1] && qids[1] != E.v[0] &&
+                  qids[1] != E.v[1] && !(qb0 >= 0 && qbody && E.body == qb0) && !(qfix && E.fixed);
           }
         }
       }
