@@ -1791,6 +1791,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   h2d(failflag.p, failed.data(), S);
   launch_velocity(V, okflag.p, s);
   launch_rollback(V, failflag.p, s);
+  launch_body_clear_lambda(V, failflag.p, s);
   sync();
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   taccel_status first_bad = TACCEL_OK;
@@ -2061,6 +2062,11 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
         for (int j = 0; j < 3; ++j) yb[3 + 3 * j + i] = A[3 * i + j];
     }
     I.h2d((f == TACCEL_FIELD_QDOT ? I.v.p : I.x.p) + 3 * (size_t)(H.node0 + n_soft_pad), y.data(), y.size());
+    if (f == TACCEL_FIELD_Q && H.nb > 0) {
+      // a new body state: the multipliers carried over from the last step no longer apply
+      const std::vector<double> zeros(12 * (size_t)H.nb, 0.0);
+      I.h2d(I.blam.p + 12 * (size_t)I.hsc[k].body0, zeros.data(), zeros.size());
+    }
     I.sync();
     return TACCEL_OK;
   } catch (const ApiError& e) {

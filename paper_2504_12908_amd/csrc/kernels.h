@@ -185,6 +185,7 @@ void launch_al_apply(const View& V, const int* action, hipStream_t s);
 void launch_body_reset(const View& V, double kappa0, hipStream_t s);
 void launch_velocity(const View& V, const int* ok, hipStream_t s);
 void launch_rollback(const View& V, const int* failed, hipStream_t s);
+void launch_body_clear_lambda(const View& V, const int* flag, hipStream_t s);
 
 // debug evaluators
 void launch_debug_fem(int n, const double* x, const double* Dminv, const double* vol, double mu,

@@ -1947,15 +1947,23 @@ __global__ void k_al_apply(View V, const int* action) {
   if (act == 3) V.bkap[b] = 2.0 * kap;
 }
 
-// Start of a step: multipliers cleared, penalty reset, every body unsnapped (its 4
-// pseudo-nodes become unknowns again).
+// Start of a step: penalty reset, every body unsnapped (its 4 pseudo-nodes become unknowns
+// again).  The multipliers carry over from the previous accepted step (they approximate the
+// constraint force, which changes little from one step to the next); they start at zero, and
+// a failed step or a state write clears them (k_body_clear_lambda).
 __global__ void k_body_reset(View V, double kappa0) {
   const int b = gid();
   if (b >= V.Nb) return;
-  for (int k = 0; k < 12; ++k) V.blam[12 * b + k] = 0.0;
   V.bkap[b] = kappa0;
   V.bsnap[b] = 0;
   for (int u = 0; u < 4; ++u) V.nfree[V.bnode[b] + u] = 1;
+}
+
+// Multipliers of the bodies of the flagged scenes back to zero.
+__global__ void k_body_clear_lambda(View V, const int* flag) {
+  const int b = gid();
+  if (b >= V.Nb || !flag[V.bscene[b]]) return;
+  for (int k = 0; k < 12; ++k) V.blam[12 * b + k] = 0.0;
 }
 
 __global__ void k_velocity(View V, const int* ok) {
@@ -2249,6 +2257,9 @@ void launch_al_apply(const View& V, const int* action, hipStream_t s) {
 }
 void launch_body_reset(const View& V, double kappa0, hipStream_t s) {
   LAUNCH(k_body_reset, V.Nb, 64, s, V, kappa0);
+}
+void launch_body_clear_lambda(const View& V, const int* flag, hipStream_t s) {
+  LAUNCH(k_body_clear_lambda, V.Nb, 64, s, V, flag);
 }
 void launch_velocity(const View& V, const int* ok, hipStream_t s) {
   LAUNCH(k_velocity, V.Nn, TPB, s, V, ok);
