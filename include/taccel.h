@@ -145,7 +145,9 @@ taccel_status taccel_scene_create(const taccel_scene_desc* d, const taccel_runti
 taccel_status taccel_step(taccel_scene* s, const taccel_targets* targets, taccel_step_stats* stats);
 /* Copy a field to caller-owned host memory; bytes must equal the field size (else ARG). */
 taccel_status taccel_state_read(const taccel_scene* s, taccel_field f, void* dst, size_t bytes);
-/* Overwrite X, V, Q or QDOT (reset / resume). */
+/* Overwrite X, V, Q or QDOT (reset / resume).  The augmented-Lagrangian multipliers of the
+ * prescribed bodies (Sec. 3.4, App. A.5), which otherwise carry over from one accepted step to
+ * the next as a starting guess, are cleared by a write of Q and by a failed step. */
 taccel_status taccel_state_write(taccel_scene* s, taccel_field f, const void* src, size_t bytes);
 void taccel_scene_destroy(taccel_scene* s);
 
