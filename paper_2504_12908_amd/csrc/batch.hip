@@ -84,10 +84,14 @@ struct DBuf {
     p = static_cast<T*>(m->alloc(sizeof(T) * std::max<size_t>(c, 1)));
     cap = c;
   }
+  // Copies h and waits for the copy: callers may pass temporaries.  (An asynchronous copy
+  // from pageable memory may still be reading it after the call returns.)
   void upload(Mem* mem, const std::vector<T>& h) {
     ensure(mem, h.size());
-    if (!h.empty())
+    if (!h.empty()) {
       HIPCHECK(hipMemcpyAsync(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, m->stream));
+      HIPCHECK(hipStreamSynchronize(m->stream));
+    }
   }
   void free() {
     if (p && m) m->release(p);
@@ -321,7 +325,9 @@ struct Batch::Impl {
       std::memcpy(st, src, bytes);
       HIPCHECK(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, mem.stream));
     } else {
+      // pageable source: wait for the copy, so the caller may release it at once
       HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, mem.stream));
+      HIPCHECK(hipStreamSynchronize(mem.stream));
     }
   }
   void zero(void* p, size_t bytes) {
@@ -1478,10 +1484,12 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
       }
       tp_sblk_h.push_back((int)tp_sc_h.size());
     }
-    tp_sc.upload(&mem, tp_sc_h);
-    tp_b0.upload(&mem, tp_c0_h);
-    tp_b1.upload(&mem, tp_c1_h);
-    tp_sblk.upload(&mem, tp_sblk_h);
+    // through the pinned staging area (no wait; large tables wait for their copy)
+    for (const auto& pr : {std::make_pair(&tp_sc, &tp_sc_h), std::make_pair(&tp_b0, &tp_c0_h),
+                     std::make_pair(&tp_b1, &tp_c1_h), std::make_pair(&tp_sblk, &tp_sblk_h)}) {
+      pr.first->ensure(&mem, std::max<size_t>(pr.second->size(), 1));
+      h2d(pr.first->p, pr.second->data(), pr.second->size());
+    }
     TP.nblk = (int)tp_sc_h.size();
     TP.sc = tp_sc.p;
     TP.b0 = tp_b0.p;
