@@ -27,11 +27,6 @@ __device__ double block_sum256(double v, double* lds) {
   return r;
 }
 
-__device__ double scene_sum(const double* P, const int* sblk, int s) {
-  double acc = 0.0;
-  for (int k = sblk[s]; k < sblk[s + 1]; ++k) acc += P[k];
-  return acc;
-}
 
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
   atomicMax(a, (unsigned long long)__double_as_longlong(v));
@@ -1210,35 +1205,6 @@ __device__ __forceinline__ T strided_sum(const T* P, int b0, int b1, int lane) {
     for (int u = 0; u < U; ++u) acc += v[u];
   }
   return acc;
-}
-
-// Sum of a scene's block partials by one wavefront (fixed assignment and fixed tree).
-template <class T>
-__device__ __forceinline__ T scene_sum_wave(const T* P, const int* sblk, int s) {
-  T acc = (T)0;
-  for (int k = sblk[s] + (int)threadIdx.x; k < sblk[s + 1]; k += kWave) acc += P[k];
-  return wave_sum(acc);
-}
-// N sums over a 256-thread workgroup; lds holds 4 x N values.  Every thread gets the totals.
-template <class T, int N>
-__device__ void block_sum256t_n(T (&v)[N], T* lds) {
-  wave_sum_n(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
-    for (int k = 0; k < N; ++k) lds[N * wid + k] = v[k];
-  __syncthreads();
-  for (int k = 0; k < N; ++k) v[k] = (lds[k] + lds[N + k]) + (lds[2 * N + k] + lds[3 * N + k]);
-  __syncthreads();
-}
-template <class T>
-__device__ T block_sum256t(T v, T* lds) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) lds[wid] = v;
-  __syncthreads();
-  const T r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
-  __syncthreads();
-  return r;
 }
 
 // Block partials of r.z and r.r and, with the coarse level on, the restriction of the
