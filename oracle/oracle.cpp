@@ -1238,6 +1238,10 @@ static int step(Scene& S, const double* body_targets, const double* dir_targets,
       b.kappaA = 1e6;
       b.r0 = body_residual(b);
       b.rprev = b.r0;
+      // A body that starts the step on its target (a held indenter) satisfies its constraint
+      // already: its DOFs are fixed from the start, as a Dirichlet DOF is.  The relative snap
+      // test below could never pass for it (its start-of-step residual is zero).
+      if (b.r0 == 0.0) b.snapped = true;
     }
   }
   // Moving Dirichlet vertices jump to their targets; the move must be collision-free.

@@ -1666,6 +1666,27 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       std::memcpy(&r, &hres[bglob++], sizeof(double));
       hb.r0 = hb.rprev = r;
     }
+  // a prescribed body already on its target (zero residual) is snapped before the first Newton
+  // iteration: its constraint holds, and the relative snap test could never accept it
+  std::vector<char> snapped_host(Nb, 0);
+  {
+    std::vector<int> held(Nb, 0);
+    bool any_held = false;
+    bglob = 0;
+    for (int k = 0; k < S; ++k)
+      for (int b = 0; b < hs[k].nb; ++b, ++bglob) {
+        const HostBody& hb = hs[k].bodies[b];
+        if (hb.prescribed && hb.r0 == 0.0 && (!mask || mask[k])) {
+          held[bglob] = 1;
+          snapped_host[bglob] = 1;
+          any_held = true;
+        }
+      }
+    if (any_held) {
+      h2d(action.p, held.data(), Nb);
+      launch_al_apply(V, action.p, s);
+    }
+  }
   // ---- per-scene state machine
   enum { kNewton = 0, kDone = 1, kFailed = 2 };
   std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
@@ -1679,7 +1700,6 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   std::vector<int> tot_pcg(S, 0), nact_last(S, 0), tot_halv(S, 0);
   std::vector<int> last(S), lsf(S), nanf(S), pcg_it(S), nact(S), halv(S);
   std::vector<int> hact(S);
-  std::vector<char> snapped_host(Nb, 0);
   int guard = 0;
   for (;;) {
     int nactive = 0;

@@ -254,6 +254,26 @@ def pad_press_slide_hull(seed: int = 0, n_steps: int = 100, cells=(32, 24, 6),
                       dict(seed=seed))
 
 
+def pad_push_moving(seed: int = 0, n_steps: int = 10, rise: float = 0.04 * MM) -> SceneSpec:
+    """The 8x8x2 pad with its bottom face prescribed (moving Dirichlet vertices) and raised
+    by `rise` per step against a cube held in place 0.05 mm above the pad."""
+    rng = np.random.default_rng(seed)
+    ox, oy = rng.uniform(-2.0, 2.0, size=2) * MM
+    pad_lo = (-10 * MM, -10 * MM, 0.0)
+    pad_hi = (10 * MM, 10 * MM, 4 * MM)
+    gap = 0.05 * MM
+    cube_v, cube_t = box_mesh((ox, oy, pad_hi[2] + gap + 5 * MM), (10 * MM,) * 3)
+    spec = _pad_scene(f"pad_push_moving(seed={seed})", pad_lo, pad_hi, (8, 8, 2),
+                      [BodySpec(cube_v, cube_t)], translation_targets(np.zeros((n_steps, 3)))[:, None, :],
+                      0.01, dict(seed=seed, offset=(ox, oy), rise=rise))
+    bottom = spec.dirichlet == 1
+    spec.dirichlet[bottom] = 2
+    base = spec.verts[bottom]
+    steps = np.arange(1, n_steps + 1)
+    spec.dirichlet_targets = base[None, :, :] + np.array([0.0, 0.0, 1.0])[None, None, :] * (rise * steps)[:, None, None]
+    return spec
+
+
 def batch_member(i: int, n_steps: int = 10) -> SceneSpec:
     rng = np.random.default_rng(1000 + i)
     pad_lo = (-10 * MM, -10 * MM, 0.0)

@@ -185,6 +185,31 @@ def test_c1_step_teacher_forced(T, oracle_lib, seed):
     g.close()
 
 
+def test_moving_dirichlet_teacher_forced(T, oracle_lib):
+    """Moving Dirichlet vertices (flag 2, bottom face raised 0.04 mm per step into a held
+    cube): teacher-forced steps within 1e-8 * L of the oracle, moving vertices exact."""
+    spec = S.pad_push_moving(0, n_steps=6)
+    say(f"teacher-forced steps: {spec.name}")
+    mov = np.flatnonzero(spec.dirichlet == 2)
+    o = oracle_lib.OracleScene(spec)
+    g = T.Scene(spec)
+    L = o.scale
+    for k in range(spec.n_steps):
+        x, v, q, qd = o.get_state()
+        g.set_state(x, v, q, qd)
+        rc_o, st_o = o.step(k)
+        rc_g, st_g = g.step(k)
+        assert rc_o == 0 and rc_g == T.OK, (k, rc_o, T.STATUS_NAMES[rc_g], st_g)
+        xo = o.get_state()[0]
+        xg = g.get_state()[0]
+        assert np.array_equal(xg[mov], spec.dirichlet_targets[k])
+        err = np.abs(xg - xo).max()
+        say(f"  step {k}: newton gpu {st_g['newton_iters']} oracle {st_o['newton_iters']} "
+            f"active {st_g['n_active']} err {err:.3e} (tol {1e-8 * L:.3e})")
+        assert err <= 1e-8 * L
+    g.close()
+
+
 @pytest.mark.parametrize("seed", [1])
 def test_c1_mixed_precision_teacher_forced(T, oracle_lib, seed):
     """Mixed precision (FP32 Hessian/SpMV/PCG, FP64 gradient, contact and CCD): every
