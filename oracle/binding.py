@@ -38,7 +38,8 @@ class _Desc(C.Structure):
                 ("body_density", _dp), ("body_prescribed", _ip), ("h", C.c_double),
                 ("dhat", C.c_double), ("kappa", C.c_double), ("kappa_s", C.c_double),
                 ("newton_tol", C.c_double), ("gravity", C.c_double * 3),
-                ("max_newton", C.c_int32), ("max_al", C.c_int32)]
+                ("max_newton", C.c_int32), ("max_al", C.c_int32), ("friction", C.c_double),
+                ("eps_v", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -80,6 +81,9 @@ def lib():
         L.orc_arap.argtypes = [_dp, _dp, _dp, _dp]
         L.orc_arap.restype = C.c_double
         L.orc_psd_project.argtypes = [C.c_int32, _dp, _dp]
+        L.orc_pair_friction.argtypes = [C.c_int32, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, _dp, _dp, _dp]
+        L.orc_pair_friction.restype = C.c_double
         _lib = L
     return _lib
 
@@ -133,6 +137,8 @@ class OracleScene:
         d.gravity = (C.c_double * 3)(*p["gravity"])
         d.max_newton = max_newton or p.get("max_newton", 100)
         d.max_al = max_al or p.get("max_al", 30)
+        d.friction = p.get("friction", 0.0)
+        d.eps_v = p.get("eps_v", 0.0)
         err = C.create_string_buffer(256)
         self.h = lib().orc_create(C.byref(d), err, 256)
         if not self.h:
@@ -223,6 +229,18 @@ def pair_barrier(kind, x, meps, dhat, kappa):
     Hp = np.zeros(144)
     t = lib().orc_pair_barrier(kind, _d(x), meps, dhat, kappa, _d(e), _d(g), _d(H), _d(Hp))
     return e[0], g, H.reshape(12, 12), Hp.reshape(12, 12), t
+
+
+def pair_friction(kind, xn, x, meps, dhat, kappa, mu, eps_v_h):
+    """Friction potential of one pair lagged at xn, at x: (lambda, e, g, H)."""
+    xn = _f64(xn).reshape(12)
+    x = _f64(x).reshape(12)
+    e = np.zeros(1)
+    g = np.zeros(12)
+    H = np.zeros(144)
+    lam = lib().orc_pair_friction(kind, _d(xn), _d(x), meps, dhat, kappa, mu, eps_v_h, _d(e),
+                                  _d(g), _d(H))
+    return lam, e[0], g, H.reshape(12, 12)
 
 
 def pair_sqdist(kind, x):

@@ -448,6 +448,139 @@ static int pair_eval(int kind, const double* x, double meps, double dhat, double
   return type;
 }
 
+// ============================================================ friction (App. A.3)
+// A friction pair with the data lagged at the start of the step: four world vertex ids, the
+// weights of the closest-point difference c = sum_v gam_v X_v, its value c0 at the start of
+// the step, the unit normal c0/|c0| and mu * lambda.
+struct FPair {
+  int w[4];
+  double gam[4];
+  V3 c0, n;
+  double mul;
+};
+// Weights gam of the closest-point difference c = sum_v gam_v x_v of the closest features of
+// a pair of the given distance type (the same types closest_type returns): c is the vector
+// from the closest point of the second primitive to that of the first, |c| the distance.
+static void closest_weights(int kind, int type, const double* x, double* gam) {
+  const double* P[4] = {x, x + 3, x + 6, x + 9};
+  for (int v = 0; v < 4; ++v) gam[v] = 0.0;
+  if (kind == 0) {
+    gam[0] = 1.0;
+    if (type <= 2) {
+      gam[1 + type] = -1.0;
+    } else if (type <= 5) {
+      const int ea[3] = {1, 2, 3}, eb[3] = {2, 3, 1};
+      const int k = type - 3;
+      const double u = seg_param(P[0], P[ea[k]], P[eb[k]]);
+      gam[ea[k]] = -(1.0 - u);
+      gam[eb[k]] = -u;
+    } else {
+      // barycentric coordinates of the projection of p onto the triangle's plane
+      double e1[3], e2[3], r[3];
+      tsub(P[2], P[1], e1);
+      tsub(P[3], P[1], e2);
+      tsub(P[0], P[1], r);
+      const double a11 = tdot(e1, e1), a12 = tdot(e1, e2), a22 = tdot(e2, e2);
+      const double b1 = tdot(r, e1), b2 = tdot(r, e2);
+      const double det = a11 * a22 - a12 * a12;
+      const double l1 = (b1 * a22 - b2 * a12) / det, l2 = (a11 * b2 - a12 * b1) / det;
+      gam[1] = -(1.0 - l1 - l2);
+      gam[2] = -l1;
+      gam[3] = -l2;
+    }
+    return;
+  }
+  if (type <= 3) {
+    const int a = type < 2 ? 0 : 1, b = (type & 1) ? 3 : 2;
+    gam[a] = 1.0;
+    gam[b] = -1.0;
+  } else if (type <= 5) {  // a0 or a1 against edge b
+    const double t = seg_param(P[type - 4], P[2], P[3]);
+    gam[type - 4] = 1.0;
+    gam[2] = -(1.0 - t);
+    gam[3] = -t;
+  } else if (type <= 7) {  // b0 or b1 against edge a
+    const double t = seg_param(P[type - 4], P[0], P[1]);
+    gam[0] = 1.0 - t;
+    gam[1] = t;
+    gam[type - 4] = -1.0;
+  } else {  // closest points of the two lines
+    double u[3], v[3], w[3];
+    tsub(P[1], P[0], u);
+    tsub(P[3], P[2], v);
+    tsub(P[0], P[2], w);
+    const double A = tdot(u, u), B = tdot(u, v), C = tdot(v, v), D = tdot(u, w), E = tdot(v, w);
+    const double den = A * C - B * B;
+    const double sa = (B * E - C * D) / den, sb = (A * E - B * D) / den;
+    gam[0] = 1.0 - sa;
+    gam[1] = sa;
+    gam[2] = -(1.0 - sb);
+    gam[3] = -sb;
+  }
+}
+
+// Lagged data of one pair at the start-of-step configuration xn: weights, c0, normal and
+// mu * lambda, lambda = -kappa m d b/dd the magnitude of the pair's normal force (the
+// mollifier value m of an edge-edge pair held fixed).  Returns false for a pair not closer
+// than dhat (or at zero distance).
+static bool friction_lag(int kind, const double* xn, double meps, double dhat, double kappa,
+                         double mu, FPair& f) {
+  double s;
+  const int type = closest_type(kind, xn, &s);
+  if (!(s > 0.0) || !(s < dhat * dhat)) return false;
+  closest_weights(kind, type, xn, f.gam);
+  f.c0 = {0, 0, 0};
+  for (int v = 0; v < 4; ++v) f.c0 = f.c0 + f.gam[v] * ld3(xn + 3 * v);
+  f.n = (1.0 / norm(f.c0)) * f.c0;
+  Jet<1> d = Jet<1>::variable(std::sqrt(s), 0);
+  const double db = barrier_of_d(d, dhat).g[0];
+  const double m = kind == 1 ? mollifier(edge_cross_sq(xn), meps) : 1.0;
+  f.mul = mu * (-kappa * m * db);
+  return true;
+}
+
+// f0 of the friction mollifier with eh = eps_v h, as a function of s = |u|^2: the closed form
+// -|u|^3/(3 eh^2) + |u|^2/eh + eh/3 below eh and |u| above.  At s = 0 exactly the cubic term,
+// whose first and second derivatives vanish there, is dropped (its jet would divide by 0).
+template <class T>
+static T friction_f0(const T& s, double eh) {
+  using std::sqrt;
+  if (value_of(s) == 0.0) return s * (1.0 / eh) + eh / 3.0;
+  const T y = sqrt(s);
+  if (value_of(y) < eh) return -(s * y) * (1.0 / (3.0 * eh * eh)) + s * (1.0 / eh) + eh / 3.0;
+  return y;
+}
+
+// Friction energy mu lambda f0(|u|) of a lagged pair at the configuration x (12 values), with
+// u the tangential part of c(x) - c0; gradient and Hessian by jets when g is given.
+static double friction_eval(const FPair& f, const double* x, double eh, double* g, double* H) {
+  if (!g) {
+    V3 dl = {0, 0, 0};
+    for (int v = 0; v < 4; ++v) dl = dl + f.gam[v] * ld3(x + 3 * v);
+    dl = dl - f.c0;
+    const V3 u = dl - dot(f.n, dl) * f.n;
+    return f.mul * friction_f0(dot(u, u), eh);
+  }
+  Jet<12> X[12];
+  for (int k = 0; k < 12; ++k) X[k] = Jet<12>::variable(x[k], k);
+  Jet<12> dl[3];
+  for (int c = 0; c < 3; ++c) {
+    dl[c] = Jet<12>(-f.c0[c]);
+    for (int v = 0; v < 4; ++v) dl[c] = dl[c] + f.gam[v] * X[3 * v + c];
+  }
+  const Jet<12> nd = f.n[0] * dl[0] + f.n[1] * dl[1] + f.n[2] * dl[2];
+  Jet<12> ss(0.0);
+  for (int c = 0; c < 3; ++c) {
+    const Jet<12> uc = dl[c] - f.n[c] * nd;
+    ss = ss + uc * uc;
+  }
+  const Jet<12> E = f.mul * friction_f0(ss, eh);
+  for (int k = 0; k < 12; ++k) g[k] = E.g[k];
+  for (int a = 0; a < 12; ++a)
+    for (int b = 0; b < 12; ++b) H[12 * a + b] = E.h[a][b];
+  return E.v;
+}
+
 // ============================================================ additive CCD
 // Conservative advancement: with the common mean displacement removed, the distance can
 // shrink at most at rate l_p (sum of the largest displacement on each side).  Advance by
@@ -685,6 +818,7 @@ struct Pair {
 struct Scene {
   // parameters
   double h, dhat, kappa, kappa_s, tol, grav[3], mu, lam, rho;
+  double fmu = 0.0, epsv = 0.0;  // friction coefficient and velocity threshold
   int max_newton, max_al;
   // soft body
   int nv = 0;
@@ -704,6 +838,8 @@ struct Scene {
   vector<array<int, 2>> cedges;
   vector<double> edge_len2;  // rest squared length per contact edge
   double L = 0;
+  // friction pairs of the current step (lagged at its start)
+  vector<FPair> fric;
   // diagnostics
   vector<double> ls_log;
 };
@@ -909,6 +1045,11 @@ static double total_energy(const Scene& S, const vector<Pair>& pairs) {
     if (std::isinf(pe)) return kInf;
     Eb += pe;
   }
+  for (const FPair& f : S.fric) {
+    double x12[12];
+    gather12(P, f.w, x12);
+    Eb += friction_eval(f, x12, S.epsv * S.h, nullptr, nullptr);
+  }
   E += h2 * Eb;
   return E;
 }
@@ -984,12 +1125,23 @@ static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
   }
   vector<V3> P;
   world_positions(S, P);
-  for (const Pair& pr : active) {
+  const size_t npair = active.size();
+  for (size_t k = 0; k < npair + S.fric.size(); ++k) {
     int w[4];
-    pair_verts(S, pr, w);
     double x12[12], e, g[12], Hp[144];
-    gather12(P, w, x12);
-    pair_eval(pr.kind, x12, pair_meps(S, pr), S.dhat, S.kappa, &e, g, nullptr, Hp);
+    if (k < npair) {
+      const Pair& pr = active[k];
+      pair_verts(S, pr, w);
+      gather12(P, w, x12);
+      pair_eval(pr.kind, x12, pair_meps(S, pr), S.dhat, S.kappa, &e, g, nullptr, Hp);
+    } else {
+      // friction: the exact Hessian, positive semidefinite by construction (the lagged normal
+      // and weights make u linear in x, and f0 is convex in |u| with f1 >= 0)
+      const FPair& f = S.fric[k - npair];
+      for (int v = 0; v < 4; ++v) w[v] = f.w[v];
+      gather12(P, w, x12);
+      friction_eval(f, x12, S.epsv * S.h, g, Hp);
+    }
     int nodes[4][4];
     double wts[4][4];
     int cnt[4];
@@ -1244,6 +1396,21 @@ static int step(Scene& S, const double* body_targets, const double* dir_targets,
       if (b.r0 == 0.0) b.snapped = true;
     }
   }
+  // Friction pairs and their lagged data at the start-of-step configuration.
+  S.fric.clear();
+  if (S.fmu > 0.0) {
+    vector<V3> P;
+    world_positions(S, P);
+    vector<Pair> cand;
+    brute_candidates(S, P, nullptr, cand);
+    for (const Pair& pr : cand) {
+      FPair f;
+      pair_verts(S, pr, f.w);
+      double x12[12];
+      gather12(P, f.w, x12);
+      if (friction_lag(pr.kind, x12, pair_meps(S, pr), S.dhat, S.kappa, S.fmu, f)) S.fric.push_back(f);
+    }
+  }
   // Moving Dirichlet vertices jump to their targets; the move must be collision-free.
   if (!S.moving.empty()) {
     vector<V3> P, disp(S.nw, V3{0, 0, 0}), P1;
@@ -1326,6 +1493,13 @@ static Scene* create(const orc_desc* d, std::string& err) {
   for (int c = 0; c < 3; ++c) S->grav[c] = d->gravity[c];
   S->max_newton = d->max_newton > 0 ? d->max_newton : 100;
   S->max_al = d->max_al > 0 ? d->max_al : 30;
+  S->fmu = d->friction;
+  S->epsv = d->eps_v;
+  if (S->fmu < 0.0 || (S->fmu > 0.0 && !(S->epsv > 0.0))) {
+    err = "friction needs mu >= 0 and, when mu > 0, eps_v > 0";
+    delete S;
+    return nullptr;
+  }
   S->mu = d->youngs / (2.0 * (1.0 + d->poisson));
   S->lam = d->youngs * d->poisson / ((1.0 + d->poisson) * (1.0 - 2.0 * d->poisson));
   S->rho = d->density;
@@ -1576,5 +1750,19 @@ double orc_arap(const double A[9], double g[9], double H[81], double Hp[81]) {
   return arap_eval(A, g, H, Hp);
 }
 void orc_psd_project(int32_t n, const double* A, double* out) { psd_project(n, A, out); }
+double orc_pair_friction(int32_t kind, const double xn[12], const double x[12], double meps,
+                         double dhat, double kappa, double mu, double eps_v_h, double* e,
+                         double g[12], double H[144]) {
+  FPair f;
+  for (int v = 0; v < 4; ++v) f.w[v] = v;
+  if (!friction_lag(kind, xn, meps, dhat, kappa, mu, f)) {
+    *e = 0.0;
+    std::memset(g, 0, sizeof(double) * 12);
+    std::memset(H, 0, sizeof(double) * 144);
+    return 0.0;
+  }
+  *e = friction_eval(f, x, eps_v_h, g, H);
+  return mu > 0.0 ? f.mul / mu : 0.0;
+}
 
 }  // extern "C"

@@ -38,6 +38,8 @@ typedef struct {
   double h, dhat, kappa, kappa_s, newton_tol;
   double gravity[3];
   int32_t max_newton, max_al;
+  double friction; /* Coulomb coefficient mu of the lagged friction potential; 0: frictionless */
+  double eps_v;    /* static/dynamic velocity threshold of the friction mollifier (m/s) */
 } orc_desc;
 
 typedef struct {
@@ -90,6 +92,12 @@ double orc_barrier(double d, double dhat, double* d1, double* d2);
 void orc_abd_mass(int32_t nv, const double* verts, int32_t nf, const int32_t* tris,
                   double rho, double out[14]); /* m, volume, com[3], Q[9] */
 double orc_arap(const double A[9], double g[9], double H[81], double Hp[81]);
+/* Friction potential of one pair (App. A.3): the lagged data (closest-point weights, normal,
+ * normal-force magnitude lambda) are taken at xn[12]; returns lambda and writes the energy
+ * mu*lambda*f0(|u|) of the configuration x[12] and its gradient and Hessian (no h^2 factor). */
+double orc_pair_friction(int32_t kind, const double xn[12], const double x[12], double mollifier_eps,
+                         double dhat, double kappa, double mu, double eps_v_h, double* e,
+                         double g[12], double H[144]);
 void orc_psd_project(int32_t n, const double* A, double* out);
 
 #ifdef __cplusplus

@@ -89,7 +89,7 @@ class SceneSpec:
 def default_params(h: float) -> dict:
     return dict(h=h, dhat=DHAT, kappa=KAPPA, kappa_s=KAPPA_S, newton_tol=NEWTON_TOL,
                 gravity=(0.0, 0.0, -9.81), max_newton=100, max_al=30, max_pcg=10000,
-                pcg_eta=1e-4)
+                pcg_eta=1e-4, friction=0.0, eps_v=1e-3)
 
 
 # ----------------------------------------------------------------------------- meshes
@@ -271,6 +271,28 @@ def pad_push_moving(seed: int = 0, n_steps: int = 10, rise: float = 0.04 * MM) -
     base = spec.verts[bottom]
     steps = np.arange(1, n_steps + 1)
     spec.dirichlet_targets = base[None, :, :] + np.array([0.0, 0.0, 1.0])[None, None, :] * (rise * steps)[:, None, None]
+    return spec
+
+
+def pad_press_slide_friction(seed: int = 0, n_steps: int = 8, mu: float = 0.5,
+                             eps_v: float = 1e-3) -> SceneSpec:
+    """The 8x8x2 pad and the 10 mm cube with friction: the cube closes the 0.05 mm gap and
+    presses 0.15 mm over the first half of the steps, then slides 0.1 mm per step in x."""
+    rng = np.random.default_rng(seed)
+    ox, oy = rng.uniform(-2.0, 2.0, size=2) * MM
+    pad_lo = (-10 * MM, -10 * MM, 0.0)
+    pad_hi = (10 * MM, 10 * MM, 4 * MM)
+    cube_v, cube_t = box_mesh((ox, oy, pad_hi[2] + 0.05 * MM + 5 * MM), (10 * MM,) * 3)
+    half = n_steps // 2
+    k = np.arange(1, n_steps + 1)
+    dz = -0.05 * MM * np.minimum(k, half)
+    dx = 0.1 * MM * np.maximum(k - half, 0)
+    tg = translation_targets(np.stack([dx, 0 * dx, dz], axis=1))
+    spec = _pad_scene(f"pad_press_slide_friction(seed={seed})", pad_lo, pad_hi, (8, 8, 2),
+                      [BodySpec(cube_v, cube_t)], tg[:, None, :], 0.01,
+                      dict(seed=seed, offset=(ox, oy), mu=mu, eps_v=eps_v))
+    spec.params["friction"] = mu
+    spec.params["eps_v"] = eps_v
     return spec
 
 

@@ -293,6 +293,132 @@ def test_barrier_pair_closed_form_energy(oracle_lib):
     assert oracle_lib.pair_barrier(0, x, 0.0, DHAT, 1e3)[0] == 0.0
 
 
+# ----------------------------------------------------------------------------- friction
+MU_F = 0.5
+EH = 1e-5  # eps_v * h
+
+
+def _bprime(d):
+    return -2.0 * (d - DHAT) * math.log(d / DHAT) - (d - DHAT) ** 2 / d
+
+
+def _f0(y):
+    # f0(y) = int_{EH}^{y} f1 + EH with f1(y) = -y^2/EH^2 + 2y/EH below EH, 1 above
+    return -y ** 3 / (3 * EH ** 2) + y ** 2 / EH + EH / 3 if y < EH else y
+
+
+def test_friction_closed_forms(oracle_lib):
+    """Point over a triangle's interior, moved tangentially by |u|: energy mu lambda f0(|u|)
+    with lambda = -kappa b'(d) and f0 in closed form (App. A.3); f0 joins C1 at EH."""
+    rng = np.random.default_rng(31)
+    for d in (0.2 * DHAT, 0.6 * DHAT):
+        R = _rand_rot(rng)
+        tri = np.array([[0, 0, 0], [1.5e-3, 0, 0], [0, 1.5e-3, 0]])
+        p = np.array([4e-4, 4e-4, d])
+        xn = (np.vstack([p, tri]) @ R.T).ravel()
+        for y in (0.0, 0.3 * EH, EH, 4 * EH):
+            x = xn.copy()
+            x[:3] += y * (R @ np.array([0.6, 0.8, 0.0]))
+            lam, e, g, H = oracle_lib.pair_friction(0, xn, x, 0.0, DHAT, 1e3, MU_F, EH)
+            assert lam == pytest.approx(-1e3 * _bprime(d), rel=1e-10)
+            assert e == pytest.approx(MU_F * lam * _f0(y), rel=1e-10)
+    assert _f0(EH * (1 - 1e-9)) == pytest.approx(EH, rel=1e-8)
+    # beyond dhat there is no friction pair
+    xn = _pt_config(rng, "face", 1.2 * DHAT)
+    assert oracle_lib.pair_friction(0, xn, xn, 0.0, DHAT, 1e3, MU_F, EH)[:2] == (0.0, 0.0)
+
+
+def test_friction_weights_follow_closest_points(oracle_lib):
+    """Moving one vertex of the second primitive by D (sliding regime) gives |u| = w |D| with
+    w its weight in the closest point: the barycentric coordinate for a point over a face,
+    the edge parameter for crossing edges."""
+    rng = np.random.default_rng(37)
+    R = _rand_rot(rng)
+    D = 50 * EH * (R @ np.array([1.0, 0.0, 0.0]))
+    d = 0.5 * DHAT
+    # point over a face: barycentric of (4e-4, 4e-4) in the triangle is (7/15, 4/15, 4/15)
+    tri = np.array([[0, 0, 0], [1.5e-3, 0, 0], [0, 1.5e-3, 0]])
+    xn = (np.vstack([[4e-4, 4e-4, d], tri]) @ R.T).ravel()
+    for v, w in ((1, 7 / 15), (2, 4 / 15), (3, 4 / 15)):
+        x = xn.copy()
+        x[3 * v:3 * v + 3] += D
+        lam, e, _, _ = oracle_lib.pair_friction(0, xn, x, 0.0, DHAT, 1e3, MU_F, EH)
+        assert e == pytest.approx(MU_F * lam * w * np.linalg.norm(D), rel=1e-9)
+    # crossing edges: a at parameter 0.525, b at 0.5
+    ea = np.array([[-1e-3, 0, 0], [1e-3, 0, 0]])
+    eb = np.array([[0.2e-3, -1e-3, d], [-0.1e-3, 1e-3, d]])
+    xn = (np.vstack([ea, eb]) @ R.T).ravel()
+    meps = 1e-12
+    for v, w in ((0, 0.475), (1, 0.525), (2, 0.5), (3, 0.5)):
+        x = xn.copy()
+        x[3 * v:3 * v + 3] += D
+        lam, e, _, _ = oracle_lib.pair_friction(1, xn, x, meps, DHAT, 1e3, MU_F, EH)
+        assert e == pytest.approx(MU_F * lam * w * np.linalg.norm(D), rel=1e-9)
+
+
+@pytest.mark.parametrize("kind,where", [(0, "face"), (0, "edge"), (0, "vertex"),
+                                        (1, "cross"), (1, "end")])
+def test_friction_invariances_and_coulomb(oracle_lib, kind, where):
+    """No friction from a rigid translation of the pair or from motion along the lagged
+    normal; in the sliding regime the force on the first primitive has magnitude mu lambda,
+    opposes the tangential motion, and the pair's forces sum to zero."""
+    rng = np.random.default_rng(41)
+    d = 0.5 * DHAT
+    xn = _pt_config(rng, where, d) if kind == 0 else _ee_config(rng, where, d)
+    meps = 1e-3 * (2e-3) ** 2 * (1.6e-3) ** 2 if kind == 1 else 0.0
+    lam, e0, g0, _ = oracle_lib.pair_friction(kind, xn, xn, meps, DHAT, 1e3, MU_F, EH)
+    assert lam > 0 and e0 == pytest.approx(MU_F * lam * EH / 3, rel=1e-12)
+    assert np.abs(g0).max() <= 1e-9 * MU_F * lam
+    shift = np.tile(rng.normal(size=3) * 1e-4, 4)
+    assert oracle_lib.pair_friction(kind, xn, xn + shift, meps, DHAT, 1e3, MU_F, EH)[1] == \
+        pytest.approx(e0, rel=1e-6)
+    # translate the whole first primitive (its weights sum to 1, so u is the tangential part
+    # of the translation)
+    nf = 3 if kind == 0 else 6
+    dirn = rng.normal(size=3)
+    dirn /= np.linalg.norm(dirn)
+    x1 = xn.copy()
+    x1[:nf] += np.tile(100 * EH * dirn, nf // 3)
+    _, e1, g1, _ = oracle_lib.pair_friction(kind, xn, x1, meps, DHAT, 1e3, MU_F, EH)
+    assert e1 > MU_F * lam * EH  # sliding regime
+    # Coulomb: forces on the two primitives are equal and opposite, the one on the first has
+    # magnitude mu lambda and points along the motion's tangential part (the gradient is
+    # minus the force)
+    G = g1.reshape(4, 3)
+    first = G[0] if kind == 0 else G[0] + G[1]
+    assert np.abs(G.sum(axis=0)).max() <= 1e-9 * MU_F * lam
+    assert np.linalg.norm(first) == pytest.approx(MU_F * lam, rel=1e-9)
+    assert np.dot(first, dirn) > 0
+    n = dirn - first / np.linalg.norm(first) * np.dot(first / np.linalg.norm(first), dirn)
+    n /= np.linalg.norm(n)
+    x2 = xn.copy()
+    x2[:nf] += np.tile(3 * EH * n, nf // 3)
+    assert oracle_lib.pair_friction(kind, xn, x2, meps, DHAT, 1e3, MU_F, EH)[1] == \
+        pytest.approx(e0, rel=1e-6)
+
+
+@pytest.mark.parametrize("kind,where", [(0, "face"), (0, "edge"), (0, "vertex"),
+                                        (1, "cross"), (1, "parallel"), (1, "end")])
+def test_friction_finite_differences(oracle_lib, kind, where):
+    """Gradient and Hessian of the friction potential against central differences, in the
+    static (|u| < eps_v h) and sliding regimes; the Hessian is positive semidefinite."""
+    rng = np.random.default_rng(43)
+    d = 0.5 * DHAT
+    xn = _pt_config(rng, where, d) if kind == 0 else _ee_config(rng, where, d)
+    meps = 1e-3 * (2e-3) ** 2 * (1.6e-3) ** 2 if kind == 1 else 0.0
+    for scale in (0.3 * EH, 5 * EH):
+        x = xn + rng.normal(size=12) * scale / 2
+
+        def f(xx):
+            _, e, g, _ = oracle_lib.pair_friction(kind, xn, xx, meps, DHAT, 1e3, MU_F, EH)
+            return e, g
+
+        _, e, g, H = oracle_lib.pair_friction(kind, xn, x, meps, DHAT, 1e3, MU_F, EH)
+        _fd_check(f, x, g, H, 1e-6, 1e-5, 1e-4 * scale)
+        w = np.linalg.eigvalsh(0.5 * (H + H.T))
+        assert w.min() >= -1e-9 * np.abs(w).max()
+
+
 # ----------------------------------------------------------------------------- CCD
 def test_accd_guarantee(oracle_lib):
     rng = np.random.default_rng(19)
@@ -485,6 +611,30 @@ def test_moving_dirichlet_steps(oracle_lib):
     assert under.sum() >= 9
     assert x[under, 2].max() < cv[:, 2].min()
     assert x[top & ~under, 2].max() > cv[:, 2].min()
+
+
+def test_friction_drags_the_pad(oracle_lib):
+    """A cube pressed into the pad and then slid 0.1 mm per step: with friction (mu = 0.5)
+    the top face under it follows the slide (it sticks), without friction it barely moves;
+    the steps stay feasible either way."""
+    moved = {}
+    for mu in (0.0, 0.5):
+        spec = S.pad_press_slide_friction(0, n_steps=6, mu=mu)
+        o = oracle_lib.OracleScene(spec)
+        for k in range(spec.n_steps):
+            rc, st = o.step(k)
+            assert rc == 0, (mu, k, st)
+            dmin, jmin, nact = o.diagnostics()
+            assert dmin > 0.0 and jmin > 0.0 and nact > 0
+        x = o.get_state()[0]
+        cv = spec.bodies[0].verts
+        top = spec.verts[:, 2] == spec.verts[:, 2].max()
+        under = top & np.all((spec.verts[:, :2] > cv[:, :2].min(0)) &
+                             (spec.verts[:, :2] < cv[:, :2].max(0)), axis=1)
+        moved[mu] = (x[under, 0] - spec.verts[under, 0]).mean()
+    slide = 0.3 * S.MM
+    assert moved[0.5] >= 0.5 * slide
+    assert abs(moved[0.0]) <= 0.1 * slide
 
 
 def test_oracle_step_is_deterministic(oracle_lib):
