@@ -86,8 +86,17 @@ def _spmv_roofline(taccel):
                 algorithmic_bytes_per_launch=bytes_per_launch)
 
 
+def _set_friction(args, specs):
+    """--friction MU: the workload with the lagged friction potential (eps_v = 1e-3 m/s)."""
+    if args.friction > 0.0:
+        for sp in specs:
+            sp.params["friction"] = args.friction
+            sp.params["eps_v"] = 1e-3
+
+
 def run_single(args, taccel, scenes, np):
     spec = scenes.pad_press_slide_hull(0)
+    _set_friction(args, [spec])
     W, K = args.warmup, args.steps
     if W + K > spec.n_steps:
         sys.exit(f"warmup + steps must be <= {spec.n_steps}")
@@ -125,7 +134,7 @@ def run_single(args, taccel, scenes, np):
         config=dict(workload="gel pad 32x24x6 grid (5775 verts, 27648 tets) pressed and slid "
                              "by a 400-point convex hull (796 tris), 1 scene",
                     scenes=1, h=spec.params["h"], step_range=[W, W + K - 1],
-                    precision=args.precision),
+                    precision=args.precision, friction=args.friction),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         newton_iters_per_step=float(np.mean([s["newton_iters"] for s in stats])),
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
@@ -160,6 +169,7 @@ def run_batch(args, taccel, scenes, np):
     stage over all scenes."""
     n = args.scenes
     specs = scenes.uniform_batch(n)
+    _set_friction(args, specs)
     W, K = args.warmup, args.steps
     if W + K > specs[0].n_steps:
         sys.exit(f"warmup + steps must be <= {specs[0].n_steps}")
@@ -193,7 +203,8 @@ def run_batch(args, taccel, scenes, np):
         dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
         config=dict(workload=f"uniform batch of {n} small pads (243 verts, 768 tets) with "
                              "8-point hull indenters, pressed over 10 steps",
-                    scenes=n, precision=args.precision, step_range=[W, W + K - 1]),
+                    scenes=n, precision=args.precision, step_range=[W, W + K - 1],
+                    friction=args.friction),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         roofline=_spmv_roofline(taccel),
     )
@@ -301,6 +312,9 @@ def main():
     ap.add_argument("--workload", choices=["single", "batch", "serving", "copy"], default="single")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--scenes", type=int, default=256)
+    ap.add_argument("--friction", type=float, default=0.0,
+                    help="friction coefficient of the single/batch workload (default 0: the "
+                         "frictionless benchmark)")
     ap.add_argument("--phases", type=int, default=0,
                     help="extra steps after the timed region with per-phase host timing")
     ap.add_argument("--rate", type=float, default=200.0)

@@ -80,6 +80,10 @@ typedef struct {
                          product and the whole PCG in FP32 (FP32 accumulation); positions,
                          gradients, energies, distances, barrier, CCD, line search and the
                          Newton test in FP64.  All scenes of a batch share one precision. */
+  double friction;    /* Coulomb coefficient mu of the lagged friction potential D (Taccel
+                         App. A.3); 0: frictionless (no friction work at all).  >= 0. */
+  double eps_v;       /* velocity threshold (m/s) between static and sliding friction in the
+                         mollifier f1; must be > 0 when friction > 0. */
 } taccel_params;
 
 typedef struct {
@@ -243,6 +247,17 @@ taccel_status taccel_debug_fem(int32_t n, const double* rest, const double* x, d
 taccel_status taccel_debug_barrier(int32_t n, const int32_t* kinds, const double* x,
                                    const double* mollifier_eps, double dhat, double kappa,
                                    double* e, double* g, double* H, double* Hp, int32_t* types);
+/* Friction potential of n pairs (Taccel App. A.3).  Per pair: kind, the start-of-step
+ * configuration xn [n][12] from which the lagged data are taken (closest-point weights of
+ * the closest features, unit normal, lambda = -kappa m b'(d) with m the edge-edge mollifier
+ * value for mollifier_eps [n]) and the current configuration x [n][12].  Outputs lambda [n]
+ * (0 for a pair not closer than dhat), the energy mu lambda f0(|u|) [n], its gradient
+ * [n][12] and Hessian [n][12][12] (no h^2 factor; u is the tangential part of the change of
+ * the closest-point difference), with eps_v_h = eps_v * h.  All arrays are host memory. */
+taccel_status taccel_debug_friction(int32_t n, const int32_t* kinds, const double* xn,
+                                    const double* x, const double* mollifier_eps, double dhat,
+                                    double kappa, double mu, double eps_v_h, double* lambda,
+                                    double* e, double* g, double* H);
 /* Additive CCD of n pairs moving linearly by p: largest safe fraction t in [0,1]. */
 taccel_status taccel_debug_ccd(int32_t n, const int32_t* kinds, const double* x, const double* p,
                                double gap_ratio, int32_t max_iter, double* t);

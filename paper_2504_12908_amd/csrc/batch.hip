@@ -243,6 +243,23 @@ struct Batch::Impl {
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
   DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs, part_pairs;
+  // friction pairs of the current step, lagged at its start (scene-contiguous)
+  bool any_fric = false;
+  int nfric = 0;
+  DBuf<int> fv, fsoff;
+  DBuf<double> fw, fc0, fnrm, fmul, e_fric;
+  FricBufs fric_bufs() {
+    FricBufs F;
+    F.n = nfric;
+    F.v = fv.p;
+    F.w = fw.p;
+    F.c0 = fc0.p;
+    F.nrm = fnrm.p;
+    F.mul = fmul.p;
+    F.soff = fsoff.p;
+    return F;
+  }
+  void build_friction(const int* mask);
   // swept candidates in blocks of one scene (line-search partial sums), rebuilt per iteration
   static constexpr int kPairChunk = 1024;
   std::vector<int> tp_sc_h, tp_c0_h, tp_c1_h, tp_sblk_h;
@@ -478,6 +495,11 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     C.lam = d.soft.youngs * d.soft.poisson / ((1.0 + d.soft.poisson) * (1.0 - 2.0 * d.soft.poisson));
     C.pcg_eta = P.pcg_eta > 0 ? P.pcg_eta : (P.precision == TACCEL_MIXED ? 1e-3 : 1e-4);
     for (int c = 0; c < 3; ++c) C.grav[c] = P.gravity[c];
+    if (!(P.friction >= 0.0) || (P.friction > 0.0 && !(P.eps_v > 0.0)))
+      throw ApiError(TACCEL_ERR_ARG, "friction must be >= 0, with eps_v > 0 when friction > 0");
+    C.fmu = P.friction;
+    C.eh = P.eps_v * P.h;
+    if (C.fmu > 0.0) any_fric = true;
     C.precision = P.precision;
     if (P.precision != TACCEL_FP64 && P.precision != TACCEL_MIXED)
       throw ApiError(TACCEL_ERR_ARG, "precision must be TACCEL_FP64 or TACCEL_MIXED");
@@ -1276,6 +1298,52 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d
   }
 }
 
+// Friction pairs of the step (Taccel App. A.3): every pair closer than dhat at the
+// start-of-step positions in a scene with friction, with its lagged closest-point weights,
+// normal and mu * lambda, grouped by scene.
+void Batch::Impl::build_friction(const int* mask) {
+  hipStream_t s = stream();
+  std::vector<int> on(S, 0);
+  bool any = false;
+  for (int k = 0; k < S; ++k) {
+    on[k] = (!mask || mask[k]) && hsc[k].fmu > 0.0;
+    any = any || on[k];
+  }
+  if (!any) return;
+  h2d(act.p, on.data(), S);
+  View V = view();
+  launch_cpos(V, s);
+  std::vector<int> overflow(S, 0);
+  const int ncand = broad_phase(cpos.p, nullptr, 0, cq, ct, &overflow);
+  cflag.ensure(&mem, std::max(ncand, 1));
+  cpos_idx.ensure(&mem, std::max(ncand, 1));
+  launch_narrow(V, ncand, cq.p, ct.p, cflag.p, s);
+  const int n = scan(cflag.p, cpos_idx.p, ncand);
+  pkind.ensure(&mem, std::max(n, 1));
+  pv.ensure(&mem, 4 * (size_t)std::max(n, 1));
+  pmeps.ensure(&mem, std::max(n, 1));
+  pscene.ensure(&mem, std::max(n, 1));
+  launch_compact_pairs(V, ncand, cq.p, ct.p, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
+  fv.ensure(&mem, 4 * (size_t)std::max(n, 1));
+  fw.ensure(&mem, 4 * (size_t)std::max(n, 1));
+  fc0.ensure(&mem, 3 * (size_t)std::max(n, 1));
+  fnrm.ensure(&mem, 3 * (size_t)std::max(n, 1));
+  fmul.ensure(&mem, std::max(n, 1));
+  fsoff.ensure(&mem, S + 1);
+  nfric = n;
+  launch_fric_build(V, n, pkind.p, pv.p, pmeps.p, fric_bufs(), s);
+  // per-scene ranges (the candidates, hence the pairs, come grouped by scene)
+  zero(scnt.p, sizeof(int) * (S + 1));
+  launch_count_scene(n, pscene.p, scnt.p, s);
+  std::vector<int> cnt(S);
+  d2h(cnt.data(), scnt.p, S);
+  sync();
+  std::vector<int> off(S + 1, 0);
+  for (int k = 0; k < S; ++k) off[k + 1] = off[k] + cnt[k];
+  if (off[S] != n) throw ApiError(TACCEL_ERR_HIP, "internal: friction pair count mismatch");
+  h2d(fsoff.p, off.data(), S + 1);
+}
+
 void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail,
                                    std::vector<int>& nan_, std::vector<int>& pcg_it,
                                    std::vector<int>& n_active, std::vector<int>& halvings) {
@@ -1311,12 +1379,14 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   cpos_idx.ensure(&mem, std::max(ncand, 1));
   launch_narrow(V, ncand, cqp, ctp, cflag.p, s);
   const int np = scan(cflag.p, cpos_idx.p, ncand);
+  // the step's friction pairs follow the barrier pairs in the pair arrays
+  const int npf = np + nfric;
   pkind.ensure(&mem, std::max(np, 1));
-  pv.ensure(&mem, 4 * (size_t)std::max(np, 1));
+  pv.ensure(&mem, 4 * (size_t)std::max(npf, 1));
   pmeps.ensure(&mem, std::max(np, 1));
   pscene.ensure(&mem, std::max(np, 1));
-  pg.ensure(&mem, 12 * (size_t)std::max(np, 1));
-  ph.ensure(&mem, 144 * (size_t)std::max(np, 1));
+  pg.ensure(&mem, 12 * (size_t)std::max(npf, 1));
+  ph.ensure(&mem, 144 * (size_t)std::max(npf, 1));
   launch_compact_pairs(V, ncand, cqp, ctp, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
   zero(scnt.p, sizeof(int) * (S + 1));
   launch_count_scene(np, pscene.p, scnt.p, s);
@@ -1337,12 +1407,13 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_assemble_grad(V, g.p, mem.side2);
   HIPCHECK(hipEventRecord(ev_join2, mem.side2));
   // ---- contact and body blocks: emit, sort by (row, col), reduce
-  const int nitems = np + Nb;
+  if (nfric > 0) launch_fric_derivs(V, fric_bufs(), np, pv.p, pg.p, ph.p, s);
+  const int nitems = npf + Nb;
   hcnt.ensure(&mem, std::max(nitems, 1));
   gcnt.ensure(&mem, std::max(nitems, 1));
   hoff.ensure(&mem, std::max(nitems, 1));
   goff.ensure(&mem, std::max(nitems, 1));
-  launch_contrib_count(V, np, pv.p, hcnt.p, gcnt.p, s);
+  launch_contrib_count(V, npf, pv.p, hcnt.p, gcnt.p, s);
   scan_async(hcnt.p, hoff.p, nitems, scalars.p + 3);
   scan_async(gcnt.p, goff.p, nitems, scalars.p + 4);
   int hg[2];
@@ -1355,7 +1426,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   for (DBuf<uint64_t>* b : {&gkey, &gkey2}) b->ensure(&mem, std::max(ng, 1));
   for (DBuf<int>* b : {&gidx, &gidx2, &gsrc}) b->ensure(&mem, std::max(ng, 1));
   gcoef.ensure(&mem, std::max(ng, 1));
-  launch_contrib_emit(V, np, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
+  launch_contrib_emit(V, npf, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
                       gsrc.p, gcoef.p, s);
   sort(hkey.p, hidx.p, hkey2.p, hidx2.p, nh, bits_for((uint64_t)Nn * (uint64_t)Nn));
   sort(gkey.p, gidx.p, gkey2.p, gidx2.p, ng, bits_for((uint64_t)Nn));
@@ -1511,6 +1582,9 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   L.cand_off = cand_off.p;
   L.part_pairs = part_pairs.p;
   L.dE = dE.p;
+  e_fric.ensure(&mem, (kTrials + 1) * (size_t)std::max(nfric, 1));
+  L.F = fric_bufs();
+  L.e_fric = e_fric.p;
   std::vector<int> pending(S, 0);
   std::vector<double> base(S);
   int npending = 0;
@@ -1610,6 +1684,8 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   h2d(bstar.p, hstar.data(), hstar.size());
   launch_predict(V, s);
   xn_valid = true;
+  nfric = 0;
+  if (any_fric) build_friction(mask);
   std::vector<int> infeasible_target(S, 0);
   if (!hmove_nodes.empty()) {
     mv_nodes.upload(&mem, hmove_nodes);
@@ -1855,6 +1931,7 @@ size_t Batch::Impl::device_bytes() const {
   add(hsrc); add(gsrc); add(hidx2); add(gidx2); add(hkey); add(gkey); add(hkey2); add(gkey2);
   add(sflag); add(segid); add(segstart); add(drow); add(dcol); add(rowcnt); add(drowptr); add(scratch);
   add(e_pairs); add(part_nodes); add(part_tets); add(part_pairs);
+  add(fv); add(fsoff); add(fw); add(fc0); add(fnrm); add(fmul); add(e_fric);
   add(tp_sc); add(tp_b0); add(tp_b1); add(tp_sblk);
   add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
   add(cg_d); add(cg_ainv); add(cg_rc); add(P_qc); add(cg_rca0); add(cg_rca1); add(cg_dw); add(bp_tmp); add(cg_sc_ts0);
@@ -1926,6 +2003,8 @@ Batch::~Batch() {
            &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
            &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs, &I.part_pairs)
   FREE_ALL(&I.tp_sc, &I.tp_b0, &I.tp_b1, &I.tp_sblk)
+  FREE_ALL(&I.fw, &I.fc0, &I.fnrm, &I.fmul, &I.e_fric)
+  FREE_ALL(&I.fv, &I.fsoff)
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m, &I.cg_sc_ts0,
            &I.cg_sc_tsn, &I.cg_sc_tsend, &I.bp_tmp)

@@ -218,6 +218,34 @@ taccel_status taccel_debug_barrier(int32_t n, const int32_t* kinds, const double
   return fetch(types, dt, n);
 }
 
+taccel_status taccel_debug_friction(int32_t n, const int32_t* kinds, const double* xn, const double* x,
+                                    const double* meps, double dhat, double kappa, double mu,
+                                    double eps_v_h, double* lambda, double* e, double* g, double* H) {
+  if (n < 0 || (n > 0 && (!kinds || !xn || !x || !meps || !lambda || !e || !g || !H)))
+    return fail(TACCEL_ERR_ARG, "debug_friction: bad arguments");
+  if (!(dhat > 0.0) || !(eps_v_h > 0.0) || !(mu >= 0.0))
+    return fail(TACCEL_ERR_ARG, "debug_friction: dhat and eps_v_h must be > 0, mu >= 0");
+  if (n == 0) return TACCEL_OK;
+  for (int k = 0; k < n; ++k)
+    if (kinds[k] != 0 && kinds[k] != 1) return fail(TACCEL_ERR_ARG, "debug_friction: kind must be 0 or 1");
+  Dev dk(sizeof(int) * n), dxn(sizeof(double) * 12 * n), dx(sizeof(double) * 12 * n), dm(sizeof(double) * n),
+      dl(sizeof(double) * n), de(sizeof(double) * n), dg(sizeof(double) * 12 * n), dH(sizeof(double) * 144 * n);
+  if (!dk.p || !dxn.p || !dx.p || !dm.p || !dl.p || !de.p || !dg.p || !dH.p)
+    return fail(TACCEL_ERR_OOM, "debug_friction: hipMalloc");
+  taccel_status st;
+  if ((st = hip_status(hipMemcpy(dk.p, kinds, sizeof(int) * n, hipMemcpyHostToDevice), "H2D")) != TACCEL_OK) return st;
+  if ((st = hip_status(hipMemcpy(dxn.p, xn, sizeof(double) * 12 * n, hipMemcpyHostToDevice), "H2D")) != TACCEL_OK) return st;
+  if ((st = hip_status(hipMemcpy(dx.p, x, sizeof(double) * 12 * n, hipMemcpyHostToDevice), "H2D")) != TACCEL_OK) return st;
+  if ((st = hip_status(hipMemcpy(dm.p, meps, sizeof(double) * n, hipMemcpyHostToDevice), "H2D")) != TACCEL_OK) return st;
+  tc::launch_debug_friction(n, dk.as<int>(), dxn.as<double>(), dx.as<double>(), dm.as<double>(), dhat, kappa, mu,
+                            eps_v_h, dl.as<double>(), de.as<double>(), dg.as<double>(), dH.as<double>(), nullptr);
+  if ((st = hip_status(hipDeviceSynchronize(), "debug_friction kernel")) != TACCEL_OK) return st;
+  if ((st = fetch(lambda, dl, n)) != TACCEL_OK) return st;
+  if ((st = fetch(e, de, n)) != TACCEL_OK) return st;
+  if ((st = fetch(g, dg, 12 * (size_t)n)) != TACCEL_OK) return st;
+  return fetch(H, dH, 144 * (size_t)n);
+}
+
 taccel_status taccel_debug_ccd(int32_t n, const int32_t* kinds, const double* x, const double* p,
                                double gap_ratio, int32_t max_iter, double* t) {
   if (n < 0 || (n > 0 && (!kinds || !x || !p || !t)) || max_iter <= 0 || !(gap_ratio > 0 && gap_ratio < 1))

@@ -437,6 +437,128 @@ TC_HD double barrier_energy(int kind, const double* x12, double meps, double dha
   return kappa * m * b;
 }
 
+// ------------------------------------------------------------------ friction (App. A.3)
+// The closest-point difference c = sum_v w_v x_v of a pair's closest features (first
+// primitive minus second; |c| is the distance) as weights w of the four local vertices, for
+// the distance type `type` returned by classify().
+TC_HD void closest_point_weights(int kind, int type, const double* x12, double* w) {
+  const d3 P[4] = {ld(x12), ld(x12 + 3), ld(x12 + 6), ld(x12 + 9)};
+  for (int v = 0; v < 4; ++v) w[v] = 0.0;
+  if (kind == KIND_PT) {
+    w[0] = 1.0;
+    if (type < 3) {
+      w[1 + type] = -1.0;
+    } else if (type < 6) {  // edges (1,2), (2,3), (3,1)
+      const int a = type - 2, b = type == 5 ? 1 : type - 1;
+      const d3 e = P[b] - P[a];
+      const double u = dot(P[0] - P[a], e) / dot(e, e);
+      w[a] = -(1.0 - u);
+      w[b] = -u;
+    } else {  // projection onto the plane, in barycentric coordinates
+      const d3 e1 = P[2] - P[1], e2 = P[3] - P[1], r = P[0] - P[1];
+      const double a11 = dot(e1, e1), a12 = dot(e1, e2), a22 = dot(e2, e2);
+      const double b1 = dot(r, e1), b2 = dot(r, e2);
+      const double det = a11 * a22 - a12 * a12;
+      const double l1 = (a22 * b1 - a12 * b2) / det, l2 = (a11 * b2 - a12 * b1) / det;
+      w[1] = -(1.0 - l1 - l2);
+      w[2] = -l1;
+      w[3] = -l2;
+    }
+    return;
+  }
+  if (type < 4) {
+    w[type < 2 ? 0 : 1] = 1.0;
+    w[(type & 1) ? 3 : 2] = -1.0;
+  } else if (type < 6) {  // a0 or a1 against edge b
+    const d3 e = P[3] - P[2];
+    const double t = dot(P[type - 4] - P[2], e) / dot(e, e);
+    w[type - 4] = 1.0;
+    w[2] = -(1.0 - t);
+    w[3] = -t;
+  } else if (type < 8) {  // b0 or b1 against edge a
+    const d3 e = P[1] - P[0];
+    const double t = dot(P[type - 4] - P[0], e) / dot(e, e);
+    w[0] = 1.0 - t;
+    w[1] = t;
+    w[type - 4] = -1.0;
+  } else {  // stationary point of |a0 + s d1 - b0 - t d2|^2
+    const d3 d1 = P[1] - P[0], d2 = P[3] - P[2], r = P[0] - P[2];
+    const double a = dot(d1, d1), b = dot(d1, d2), e = dot(d2, d2);
+    const double c = dot(d1, r), f = dot(d2, r);
+    const double den = a * e - b * b;
+    const double sa = (b * f - c * e) / den, tb = (a * f - b * c) / den;
+    w[0] = 1.0 - sa;
+    w[1] = sa;
+    w[2] = -(1.0 - tb);
+    w[3] = -tb;
+  }
+}
+
+// Magnitude of a pair's barrier normal force, -kappa m b'(d), at squared distance s (the
+// edge-edge mollifier value m taken at x12).
+TC_HD double normal_force(int kind, const double* x12, double s, double meps, double dhat,
+                          double kappa) {
+  double b, b1, b2;
+  barrier_d(sqrt(s), dhat, &b, &b1, &b2);
+  double m = 1.0;
+  if (kind == KIND_EE) {
+    const d3 n = cross(ld(x12 + 3) - ld(x12), ld(x12 + 9) - ld(x12 + 6));
+    const double c = dot(n, n);
+    if (c < meps) m = 2.0 * c / meps - c * c / (meps * meps);
+  }
+  return -kappa * m * b1;
+}
+
+// f0 of the friction mollifier at y = |u| with eh = eps_v h: the integral of f1 (f1(y) =
+// 2y/eh - y^2/eh^2 below eh, 1 above) from eh to y, plus eh.
+TC_HD double friction_f0(double y, double eh) {
+  return y < eh ? y * y * (1.0 / eh - y / (3.0 * eh * eh)) + eh / 3.0 : y;
+}
+// f1(y)/y and f1'(y) (their common limit 2/eh at y = 0).
+TC_HD void friction_f1(double y, double eh, double* f1y, double* df1) {
+  if (y < eh) {
+    *f1y = 2.0 / eh - y / (eh * eh);
+    *df1 = 2.0 / eh - 2.0 * y / (eh * eh);
+  } else {
+    *f1y = 1.0 / y;
+    *df1 = 0.0;
+  }
+}
+
+// Tangential part u of (sum_v w_v x_v - c0) for the lagged normal n.
+TC_HD d3 friction_u(const double* x12, const double* w, const d3& c0, const d3& n) {
+  d3 dl = mk(0, 0, 0);
+  for (int v = 0; v < 4; ++v) dl = dl + w[v] * ld(x12 + 3 * v);
+  dl = dl - c0;
+  return dl - dot(n, dl) * n;
+}
+
+// Gradient g[12] and Hessian H[144] of mul * f0(|u|) with u = (I - n n^T)(sum w_v x_v - c0):
+// g_v = mul w_v (f1/y) u, H_ab = mul w_a w_b [ (f1/y) (I - n n^T) + (f1' - f1/y) uh uh^T ]
+// (uh = u/|u|; the second term vanishes at u = 0).  Positive semidefinite: f1' >= 0 and
+// f1/y > 0.  Returns the energy.
+TC_HD double friction_derivs(const double* x12, const double* w, const d3& c0, const d3& n,
+                             double mul, double eh, double* g, double* H) {
+  const d3 u = friction_u(x12, w, c0, n);
+  const double y = sqrt(dot(u, u));
+  double f1y, df1;
+  friction_f1(y, eh, &f1y, &df1);
+  const d3 uh = y > 0.0 ? (1.0 / y) * u : mk(0, 0, 0);
+  double H3[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      H3[3 * i + j] = f1y * ((i == j ? 1.0 : 0.0) - at(n, i) * at(n, j)) + (df1 - f1y) * at(uh, i) * at(uh, j);
+  for (int a = 0; a < 4; ++a) {
+    st(g + 3 * a, (mul * w[a] * f1y) * u);
+    for (int b = 0; b < 4; ++b) {
+      const double s = mul * w[a] * w[b];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H[12 * (3 * a + i) + 3 * b + j] = s * H3[3 * i + j];
+    }
+  }
+  return mul * friction_f0(y, eh);
+}
+
 // Additive CCD by conservative advancement: with the common mean displacement removed, the
 // pair distance shrinks at most at rate lp = (largest displacement on one side) + (largest
 // on the other).  Advance by a fraction of distance / lp; stop before the distance falls

@@ -166,6 +166,26 @@ void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipSt
 void launch_ccd(const View& V, int n, const int* cand_q, const int* cand_t,
                 unsigned long long* amin, hipStream_t s);
 void launch_scene_offsets(const View& V, int n, const int* cand_q, int* off, hipStream_t s);
+// Friction pairs of the current step, lagged at its start (scene-contiguous): four contact
+// vertex ids, closest-point weights, c0 = sum w_v x_v at the start, unit normal, mu lambda;
+// soff [S+1] the first pair of each scene.
+struct FricBufs {
+  int n;
+  int* v;        // [n][4]
+  double* w;     // [n][4]
+  double* c0;    // [n][3]
+  double* nrm;   // [n][3]
+  double* mul;   // [n]
+  const int* soff;
+};
+void launch_fric_build(const View& V, int n, const int* pkind, const int* pv, const double* pmeps,
+                       const FricBufs& F, hipStream_t s);
+void launch_fric_derivs(const View& V, const FricBufs& F, int off, int* pv, double* pg, double* ph,
+                        hipStream_t s);
+void launch_debug_friction(int n, const int* kinds, const double* xn, const double* x,
+                           const double* meps, double dhat, double kappa, double mu, double eh,
+                           double* lam, double* e, double* g, double* H, hipStream_t s);
+
 struct LsBufs {
   const double* p;        // node-space direction
   const double* abase;    // [S] largest trial step of this launch
@@ -177,6 +197,8 @@ struct LsBufs {
   const int* cand_off;    // [S+1]
   double* part_pairs;     // [pair blocks][8] sums of the pair energy differences
   double* dE;             // [S][8]
+  FricBufs F;             // friction pairs (F.n = 0: none)
+  double* e_fric;         // [F.n][9] like e_pairs
 };
 void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& TT, const BlockTable& TP,
                         int ncand, const int* cand_q, const int* cand_t, const LsBufs& L, hipStream_t s);

@@ -722,6 +722,62 @@ __global__ void __launch_bounds__(64) k_barrier_hess(View V, int np, const int* 
   for (int i = threadIdx.x; i < 144; i += 64) ph[144 * (size_t)k + i] = L.H[i];
 }
 
+// ------------------------------------------------------------------ friction
+// Lagged data of the n compacted pairs (closer than dhat at the start-of-step positions in
+// cpos); one thread per pair.
+__global__ void k_fric_build(View V, int n, const int* pkind, const int* pv, const double* pmeps,
+                             FricBufs F) {
+  const int k = gid();
+  if (k >= n) return;
+  int ids[4];
+  for (int v = 0; v < 4; ++v) ids[v] = pv[4 * k + v];
+  const SceneConst& sc = V.sc[V.cvscene[ids[0]]];
+  double x12[12], w[4];
+  gather12(V.cpos, ids, x12);
+  const int kind = pkind[k];
+  int type;
+  const double s = pair_sqdist(kind, x12, &type);
+  closest_point_weights(kind, type, x12, w);
+  d3 c = mk(0, 0, 0);
+  for (int v = 0; v < 4; ++v) c = c + w[v] * ld(x12 + 3 * v);
+  const double cn = sqrt(dot(c, c));
+  const bool ok = s > 0.0 && s < sc.dhat * sc.dhat && cn > 0.0;
+  for (int v = 0; v < 4; ++v) {
+    F.v[4 * k + v] = ids[v];
+    F.w[4 * k + v] = w[v];
+  }
+  st(F.c0 + 3 * k, c);
+  st(F.nrm + 3 * k, ok ? (1.0 / cn) * c : mk(0, 0, 0));
+  F.mul[k] = ok ? sc.fmu * normal_force(kind, x12, s, pmeps[k], sc.dhat, sc.kappa) : 0.0;
+}
+
+// Friction pairs appended to the contact pair arrays at off..off+n-1: vertex ids, gradient
+// and Hessian (times h^2) at the current positions; zero for scenes not iterating.
+__global__ void k_fric_derivs(View V, FricBufs F, int off, int* pv, double* pg, double* ph) {
+  const int k = gid();
+  if (k >= F.n) return;
+  int ids[4];
+  double w[4];
+  for (int v = 0; v < 4; ++v) {
+    ids[v] = F.v[4 * k + v];
+    w[v] = F.w[4 * k + v];
+    pv[4 * (size_t)(off + k) + v] = ids[v];
+  }
+  const int s = V.cvscene[ids[0]];
+  const SceneConst& sc = V.sc[s];
+  double* G = pg + 12 * (size_t)(off + k);
+  double* H = ph + 144 * (size_t)(off + k);
+  const double mul = V.act[s] ? sc.h * sc.h * F.mul[k] : 0.0;
+  if (mul == 0.0) {
+    for (int i = 0; i < 12; ++i) G[i] = 0.0;
+    for (int i = 0; i < 144; ++i) H[i] = 0.0;
+    return;
+  }
+  double x12[12];
+  gather12(V.cpos, ids, x12);
+  friction_derivs(x12, w, ld(F.c0 + 3 * k), ld(F.nrm + 3 * k), mul, sc.eh, G, H);
+}
+
 // ------------------------------------------------------------------ affine bodies
 // Inertia 1/2 dy^T My dy with My = diag(m I3, Q (x) I3), y = [p; c1; c2; c3].
 __device__ void my_apply(const double* bm, const double* dy, double* out) {
@@ -1839,6 +1895,30 @@ __global__ void k_ls_pairs(View V, int n, const int* cq, const int* ct, LsBufs L
   L.e_pairs[kLsSlots * (size_t)k + slot] = e;
 }
 
+// Friction energies mu lambda h^2 f0(|u|) at the current point and the 8 trials.
+__global__ void k_ls_fric(View V, LsBufs L) {
+  const int g = gid();
+  const int k = g / kLsSlots, slot = g % kLsSlots;
+  if (k >= L.F.n) return;
+  int ids[4];
+  double w[4];
+  for (int v = 0; v < 4; ++v) {
+    ids[v] = L.F.v[4 * k + v];
+    w[v] = L.F.w[4 * k + v];
+  }
+  const int s = V.cvscene[ids[0]];
+  const SceneConst& sc = V.sc[s];
+  double x12[12], p12[12];
+  gather12(V.cpos, ids, x12);
+  gather12(V.cdisp, ids, p12);
+  if (slot > 0) {
+    const double a = trial_alpha(L.abase, s, slot - 1);
+    for (int i = 0; i < 12; ++i) x12[i] += a * p12[i];
+  }
+  const d3 u = friction_u(x12, w, ld(L.F.c0 + 3 * k), ld(L.F.nrm + 3 * k));
+  L.e_fric[kLsSlots * (size_t)k + slot] = sc.h * sc.h * L.F.mul[k] * friction_f0(sqrt(dot(u, u)), sc.eh);
+}
+
 // Energy differences of the swept pairs summed per block of one scene's candidates.
 __global__ void __launch_bounds__(TPB) k_ls_pair_sums(View V, BlockTable TP, LsBufs L) {
   __shared__ double red[TPB / kWave][kTrials];
@@ -1879,6 +1959,11 @@ __global__ void __launch_bounds__(TPB) k_ls_reduce(View V, BlockTable TN, BlockT
   }
   for (int b = TP.sblk[s] + t; b < TP.sblk[s + 1]; b += TPB)
     for (int k = 0; k < kTrials; ++k) acc[k] += L.part_pairs[kTrials * b + k];
+  if (L.F.n > 0)
+    for (int b = L.F.soff[s] + t; b < L.F.soff[s + 1]; b += TPB) {
+      const double* e = L.e_fric + kLsSlots * (size_t)b;
+      for (int k = 0; k < kTrials; ++k) acc[k] += e[1 + k] - e[0];
+    }
   wave_sum_n(acc);
   if ((t & (kWave - 1)) == 0)
     for (int k = 0; k < kTrials; ++k) red[t / kWave][k] = acc[k];
@@ -2011,6 +2096,32 @@ __global__ void k_debug_ccd(int n, const int* kinds, const double* x, const doub
   const int k = gid();
   if (k >= n) return;
   t[k] = accd(kinds[k], x + 12 * k, p + 12 * k, gap, max_iter);
+}
+
+__global__ void k_debug_friction(int n, const int* kinds, const double* xn, const double* x,
+                                 const double* meps, double dhat, double kappa, double mu,
+                                 double eh, double* lam, double* e, double* g, double* H) {
+  const int k = gid();
+  if (k >= n) return;
+  const double* xk = xn + 12 * (size_t)k;
+  int type;
+  const double s = pair_sqdist(kinds[k], xk, &type);
+  double w[4];
+  closest_point_weights(kinds[k], type, xk, w);
+  d3 c = mk(0, 0, 0);
+  for (int v = 0; v < 4; ++v) c = c + w[v] * ld(xk + 3 * v);
+  const double cn = sqrt(dot(c, c));
+  double* G = g + 12 * (size_t)k;
+  double* Hk = H + 144 * (size_t)k;
+  if (!(s > 0.0 && s < dhat * dhat && cn > 0.0)) {
+    lam[k] = 0.0;
+    e[k] = 0.0;
+    for (int i = 0; i < 12; ++i) G[i] = 0.0;
+    for (int i = 0; i < 144; ++i) Hk[i] = 0.0;
+    return;
+  }
+  lam[k] = normal_force(kinds[k], xk, s, meps[k], dhat, kappa);
+  e[k] = friction_derivs(x + 12 * (size_t)k, w, c, (1.0 / cn) * c, mu * lam[k], eh, G, Hk);
 }
 
 __global__ void k_debug_arap(int n, const double* A, double* e, double* g, double* H, double* Hp) {
@@ -2213,6 +2324,7 @@ void launch_line_search(const View& V, const BlockTable& TN, const BlockTable& T
   LAUNCH(k_ls_bodies, kLsSlots * V.Nb, 64, s, V, L);
   LAUNCH(k_ls_pairs, kLsSlots * ncand, 64, s, V, ncand, cq, ct, L);
   if (TP.nblk > 0) hipLaunchKernelGGL(k_ls_pair_sums, dim3(TP.nblk), dim3(TPB), 0, s, V, TP, L);
+  LAUNCH(k_ls_fric, kLsSlots * L.F.n, 64, s, V, L);
   hipLaunchKernelGGL(k_ls_reduce, dim3(V.S), dim3(TPB), 0, s, V, TN, TT, TP, L);
 }
 void launch_update(const View& V, const double* p, const double* alpha, hipStream_t s) {
@@ -2241,6 +2353,19 @@ void launch_debug_barrier(int n, const int* kinds, const double* x, const double
                           double dhat, double kappa, double* e, double* g, double* H, double* Hp,
                           int* types, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_debug_barrier, dim3(n), dim3(64), 0, s, n, kinds, x, meps, dhat, kappa, e, g, H, Hp, types);
+}
+void launch_fric_build(const View& V, int n, const int* pkind, const int* pv, const double* pmeps,
+                       const FricBufs& F, hipStream_t s) {
+  LAUNCH(k_fric_build, n, 64, s, V, n, pkind, pv, pmeps, F);
+}
+void launch_fric_derivs(const View& V, const FricBufs& F, int off, int* pv, double* pg, double* ph,
+                        hipStream_t s) {
+  LAUNCH(k_fric_derivs, F.n, 64, s, V, F, off, pv, pg, ph);
+}
+void launch_debug_friction(int n, const int* kinds, const double* xn, const double* x,
+                           const double* meps, double dhat, double kappa, double mu, double eh,
+                           double* lam, double* e, double* g, double* H, hipStream_t s) {
+  LAUNCH(k_debug_friction, n, 64, s, n, kinds, xn, x, meps, dhat, kappa, mu, eh, lam, e, g, H);
 }
 void launch_debug_ccd(int n, const int* kinds, const double* x, const double* p, double gap,
                       int max_iter, double* t, hipStream_t s) {

@@ -18,6 +18,7 @@ constexpr int kTetChunk = 256;
 // Per-scene constants, resident on the device.
 struct SceneConst {
   double h, dhat, kappa, kappa_s, stop, mu, lam, pcg_eta;
+  double fmu, eh;  // friction coefficient (0: none) and eps_v * h
   double grav[3];
   double cell, org[3];
   int node0, node1, tet0, tet1, cv0, cv1, q0, q1, body0, body1, tri0, tri1, edge0, edge1;

@@ -40,7 +40,8 @@ class taccel_params(C.Structure):
     _fields_ = [("h", C.c_double), ("dhat", C.c_double), ("kappa", C.c_double),
                 ("kappa_s", C.c_double), ("newton_tol", C.c_double),
                 ("gravity", C.c_double * 3), ("max_newton", C.c_int32), ("max_al", C.c_int32),
-                ("max_pcg", C.c_int32), ("pcg_eta", C.c_double), ("precision", C.c_int32)]
+                ("max_pcg", C.c_int32), ("pcg_eta", C.c_double), ("precision", C.c_int32),
+                ("friction", C.c_double), ("eps_v", C.c_double)]
 
 
 class taccel_scene_desc(C.Structure):
@@ -115,6 +116,9 @@ def lib():
         L.taccel_debug_barrier.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_double,
                                            _dp, _dp, _dp, _dp, _ip]
         L.taccel_debug_ccd.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_int32, _dp]
+        L.taccel_debug_friction.argtypes = [C.c_int32, _ip, _dp, _dp, _dp, C.c_double,
+                                            C.c_double, C.c_double, C.c_double, _dp, _dp, _dp,
+                                            _dp]
         L.taccel_debug_arap.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.taccel_debug_candidates.argtypes = [C.c_void_p, _dp, _dp, _ip, C.c_int32, _ip]
         L.taccel_server_create.argtypes = [C.POINTER(taccel_server_params),
@@ -199,6 +203,8 @@ class _Desc:
         d.params.max_pcg = p.get("max_pcg", 10000)
         d.params.pcg_eta = overrides.get("pcg_eta", 0.0) if overrides else 0.0
         d.params.precision = precision
+        d.params.friction = p.get("friction", 0.0)
+        d.params.eps_v = p.get("eps_v", 0.0)
         self.desc = d
         self.nv = len(verts)
         self.nb = nb
@@ -444,6 +450,16 @@ def debug_barrier(kinds, x, meps, dhat, kappa):
     _check(lib().taccel_debug_barrier(n, _i(kinds), _d(x), _d(meps), dhat, kappa, _d(e), _d(g),
                                       _d(H), _d(Hp), _i(t)), "debug_barrier")
     return e, g, H, Hp, t
+
+
+def debug_friction(kinds, xn, x, meps, dhat, kappa, mu, eps_v_h):
+    kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+    xn, x, meps = _f64(xn).reshape(-1, 12), _f64(x).reshape(-1, 12), _f64(meps)
+    n = len(kinds)
+    lam, e, g, H = np.zeros(n), np.zeros(n), np.zeros((n, 12)), np.zeros((n, 12, 12))
+    _check(lib().taccel_debug_friction(n, _i(kinds), _d(xn), _d(x), _d(meps), dhat, kappa, mu,
+                                       eps_v_h, _d(lam), _d(e), _d(g), _d(H)), "debug_friction")
+    return lam, e, g, H
 
 
 def debug_ccd(kinds, x, p, gap_ratio=0.1, max_iter=100000):

@@ -108,6 +108,34 @@ def test_barrier_parity(T, oracle_lib):
     assert nact > 100
 
 
+def test_friction_parity(T, oracle_lib):
+    """Friction potential of 256 pairs (lagged at xn, evaluated at x = xn + a displacement in
+    the static or the sliding regime): lambda, energy, gradient and Hessian of the HIP path
+    against the oracle's jets."""
+    say("friction parity: 256 pairs")
+    rng = np.random.default_rng(303)
+    cfg = _pair_configs(rng, 256)
+    kinds = np.array([c[0] for c in cfg])
+    XN = np.array([c[1] for c in cfg])
+    M = np.array([c[2] for c in cfg])
+    eh, mu = 1e-5, 0.5
+    scale = np.where(np.arange(256) % 4 < 2, 0.3 * eh, 5 * eh)
+    X = XN + rng.standard_normal(XN.shape) * scale[:, None] / 2
+    lam, e, g, H = T.debug_friction(kinds, XN, X, M, DHAT, 1e3, mu, eh)
+    nact = 0
+    for k in range(len(cfg)):
+        lo, eo, go, Ho = oracle_lib.pair_friction(kinds[k], XN[k], X[k], M[k], DHAT, 1e3, mu, eh)
+        if lo == 0.0:
+            assert lam[k] == 0.0 and e[k] == 0.0
+            continue
+        nact += 1
+        assert abs(lam[k] - lo) <= 1e-10 * lo
+        assert abs(e[k] - eo) <= 1e-9 * abs(eo)
+        assert np.abs(g[k] - go).max() <= 1e-8 * np.abs(go).max()
+        assert np.abs(H[k] - Ho).max() <= 1e-7 * np.abs(Ho).max()
+    assert nact > 200
+
+
 def test_ccd_parity(T, oracle_lib):
     say("ccd parity: 512 pairs")
     rng = np.random.default_rng(303)
@@ -208,6 +236,49 @@ def test_moving_dirichlet_teacher_forced(T, oracle_lib):
             f"active {st_g['n_active']} err {err:.3e} (tol {1e-8 * L:.3e})")
         assert err <= 1e-8 * L
     g.close()
+
+
+def test_friction_step_teacher_forced(T, oracle_lib):
+    """Friction (mu = 0.5): a cube pressed into the pad and slid; teacher-forced steps
+    within 1e-8 * L of the oracle."""
+    spec = S.pad_press_slide_friction(0, n_steps=6)
+    say(f"teacher-forced steps: {spec.name}")
+    o = oracle_lib.OracleScene(spec)
+    g = T.Scene(spec)
+    L = o.scale
+    for k in range(spec.n_steps):
+        x, v, q, qd = o.get_state()
+        g.set_state(x, v, q, qd)
+        rc_o, st_o = o.step(k)
+        rc_g, st_g = g.step(k)
+        assert rc_o == 0 and rc_g == T.OK, (k, rc_o, T.STATUS_NAMES[rc_g], st_g)
+        xo, _, qo, _ = o.get_state()
+        xg, _, qg, _ = g.get_state()
+        err = max(np.abs(xg - xo).max(), np.abs(qg[:, :3] - qo[:, :3]).max())
+        say(f"  step {k}: newton gpu {st_g['newton_iters']} oracle {st_o['newton_iters']} "
+            f"al {st_g['al_rounds']}/{st_o['al_rounds']} err {err:.3e} (tol {1e-8 * L:.3e})")
+        assert err <= 1e-8 * L
+    g.close()
+
+
+def test_friction_batch_equals_single(T):
+    """Friction and frictionless scenes in one batch: each scene bit for bit equal to the
+    same scene run alone."""
+    specs = [S.pad_press_slide_friction(0, n_steps=6), S.batch_member(0),
+             S.pad_press_slide_friction(2, n_steps=6, mu=0.3)]
+    say("friction batch of 3 vs single scenes, 4 steps")
+    b = T.Batch(specs)
+    singles = [T.Scene(s) for s in specs]
+    for k in range(4):
+        rc, per, st = b.step(k)
+        assert rc == T.OK, per
+        for i, sg in enumerate(singles):
+            r, _ = sg.step(k)
+            assert r == T.OK
+            assert np.array_equal(b.read(i, T.FIELD_X), sg.read(T.FIELD_X))
+    b.close()
+    for sg in singles:
+        sg.close()
 
 
 @pytest.mark.parametrize("seed", [1])
