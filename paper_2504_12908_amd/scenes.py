@@ -296,6 +296,52 @@ def pad_press_slide_friction(seed: int = 0, n_steps: int = 8, mu: float = 0.5,
     return spec
 
 
+def top_surface_tris(spec: SceneSpec) -> np.ndarray:
+    """Boundary triangles of the pad's top face (the coated, contact side), outward (+z)
+    oriented, in the order their tets appear: (f, 3) int32 soft-vertex ids."""
+    zt = spec.verts[:, 2].max()
+    count = {}
+    faces = []
+    for t in spec.tets:
+        for drop in range(4):
+            f = [int(v) for k, v in enumerate(t) if k != drop]
+            key = tuple(sorted(f))
+            count[key] = count.get(key, 0) + 1
+            faces.append((key, f))
+    out = []
+    for key, f in faces:
+        if count[key] != 1 or not np.all(spec.verts[f, 2] == zt):
+            continue
+        a, b, c = spec.verts[f]
+        if np.cross(b - a, c - a)[2] < 0:
+            f = [f[0], f[2], f[1]]
+        out.append(f)
+    return np.asarray(out, dtype=np.int32)
+
+
+def marker_layout(spec: SceneSpec, tris: np.ndarray, nx: int, ny: int, margin: float = 1.5 * MM):
+    """A regular nx-by-ny grid of markers on the top face (inset by ``margin``), each given as
+    the first of ``tris`` whose rest projection contains it and its barycentric coordinates:
+    (tri index into ``tris`` (m,), barycentric (m, 3))."""
+    lo = spec.verts[:, :2].min(0) + margin
+    hi = spec.verts[:, :2].max(0) - margin
+    gx, gy = np.meshgrid(np.linspace(lo[0], hi[0], nx), np.linspace(lo[1], hi[1], ny))
+    pts = np.stack([gx.ravel(), gy.ravel()], axis=1)
+    P = spec.verts[tris][:, :, :2]
+    idx, bary = [], []
+    for q in pts:
+        a, b, c = P[:, 0], P[:, 1], P[:, 2]
+        den = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])
+        l1 = ((q[0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (q[1] - a[:, 1])) / den
+        l2 = ((b[:, 0] - a[:, 0]) * (q[1] - a[:, 1]) - (q[0] - a[:, 0]) * (b[:, 1] - a[:, 1])) / den
+        inside = np.flatnonzero((l1 >= 0) & (l2 >= 0) & (l1 + l2 <= 1))
+        k = int(inside[0])
+        idx.append(k)
+        b = np.maximum([1.0 - l1[k] - l2[k], l1[k], l2[k]], 0.0)
+        bary.append(b / b.sum())
+    return np.asarray(idx, dtype=np.int32), np.asarray(bary, dtype=np.float64)
+
+
 def batch_member(i: int, n_steps: int = 10) -> SceneSpec:
     rng = np.random.default_rng(1000 + i)
     pad_lo = (-10 * MM, -10 * MM, 0.0)
