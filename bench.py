@@ -276,6 +276,42 @@ def run_serving(args, taccel, scenes, np):
     )
 
 
+def run_tactile(args, taccel, scenes, np):
+    """Tactile outputs of the benchmark pad after two press steps: a 640x480 depth and normal
+    map of its coated face (1,536 triangles) at 50 um, and 1,200 markers, per call (each call
+    includes the readback of its outputs to host memory)."""
+    MM = scenes.MM
+    spec = scenes.pad_press_slide_hull(0)
+    sc = taccel.Scene(spec)
+    for k in range(2):
+        if sc.step(k)[0] != taccel.OK:
+            sys.exit("tactile workload: press step failed")
+    tris = scenes.top_surface_tris(spec)
+    idx, bary = scenes.marker_layout(spec, tris, 40, 30)
+    cam = taccel.camera((-16 * MM, -12 * MM, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.05 * MM,
+                        640, 480)
+    for _ in range(args.warmup):
+        sc.depth_map(cam, tris)
+        sc.markers(tris[idx], bary)
+    taccel.device_synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sc.depth_map(cam, tris)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        sc.markers(tris[idx], bary)
+    t2 = time.perf_counter()
+    sc.close()
+    K = args.steps
+    return dict(metric="depth+normal maps per second (640x480, incl. readback)",
+                value=K / (t1 - t0), unit="maps/s", n_gpus=1, steps=K, warmup=args.warmup,
+                ms_per_step=(t1 - t0) * 1e3 / K, higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload="coated face of the 32x24x6 pad (1536 triangles), 640x480 "
+                                     "orthographic depth and normal map at 50 um; 1200 markers"),
+                markers_ms_per_call=(t2 - t1) * 1e3 / K)
+
+
 def run_copy(args, taccel, scenes, np):
     """Counter calibration: three device-to-device copies of 256 MiB (a plain copy kernel of
     known size) through the HIP runtime."""
@@ -309,7 +345,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "serving", "copy"], default="single")
+    ap.add_argument("--workload", choices=["single", "batch", "serving", "tactile", "copy"],
+                    default="single")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--scenes", type=int, default=256)
     ap.add_argument("--friction", type=float, default=0.0,
@@ -331,7 +368,8 @@ def main():
 
     from paper_2504_12908_amd import scenes, taccel
 
-    run = dict(single=run_single, batch=run_batch, serving=run_serving, copy=run_copy)[args.workload]
+    run = dict(single=run_single, batch=run_batch, serving=run_serving, tactile=run_tactile,
+               copy=run_copy)[args.workload]
     out = run(args, taccel, scenes, np)
     print(json.dumps(out), flush=True)
 

@@ -169,6 +169,45 @@ taccel_status taccel_batch_write(taccel_batch* b, int32_t scene, taccel_field f,
                                  size_t bytes);
 void taccel_batch_destroy(taccel_batch* b);
 
+/* ---- Tactile outputs of the current state (Taccel Sec. 3.6) ----------------------------
+ * Markers: marker k lies on the soft-body triangle tris[k][0..2] (the caller's soft vertex
+ * ids) at barycentric coordinates bary[k][0..2] (each in [0, 1]).  Writes its current
+ * position pos[k][3] = sum_u bary[k][u] x[tris[k][u]] and its flow flow[k][3] = pos[k] minus
+ * the same combination of the rest positions.  All arrays are host memory of m entries;
+ * TACCEL_ERR_ARG for an id out of range or a coordinate outside [0, 1]. */
+taccel_status taccel_markers(const taccel_scene* s, int32_t m, const int32_t* tris,
+                             const double* bary, double* pos, double* flow);
+taccel_status taccel_batch_markers(const taccel_batch* b, int32_t scene, int32_t m,
+                                   const int32_t* tris, const double* bary, double* pos,
+                                   double* flow);
+
+/* Image plane of a depth map: pixel (i, j) (row i < height, column j < width) is the ray from
+ * origin + (j + 1/2) pixel axis_u + (i + 1/2) pixel axis_v along axis_n = axis_u x axis_v.
+ * axis_u and axis_v must be orthonormal (to 1e-9); width * height <= 2^26. */
+typedef struct {
+  double origin[3];
+  double axis_u[3];
+  double axis_v[3];
+  double pixel;  /* pixel pitch (m) */
+  int32_t width, height;
+} taccel_camera;
+
+/* Depth and normal maps of the deformed surface given by ntri triangles tris[ntri][3] (the
+ * caller's soft vertex ids; e.g. the pad's coated face), seen orthographically from the
+ * camera's image plane.  A triangle covers a pixel when the pixel centre lies in its
+ * projection onto the plane (edges included).  depth[i][j] is the smallest ray parameter
+ * over the covering triangles (+inf where none covers); normal[i][j][3] is the unit normal
+ * of the covering triangle that attains it (the lowest index on ties), turned to face the
+ * image plane (normal . axis_n <= 0), zero where none covers.  The coverage and depth
+ * arithmetic is plain IEEE FP64 without fused multiply-add, so any evaluation of the same
+ * expressions reproduces every pixel bit for bit.  depth: [height][width], normal:
+ * [height][width][3], host memory. */
+taccel_status taccel_depth_map(const taccel_scene* s, const taccel_camera* cam, int32_t ntri,
+                               const int32_t* tris, double* depth, double* normal);
+taccel_status taccel_batch_depth_map(const taccel_batch* b, int32_t scene,
+                                     const taccel_camera* cam, int32_t ntri,
+                                     const int32_t* tris, double* depth, double* normal);
+
 /* ---- Serving: continuous batching of time-step requests -------------------------------
  * A request is one scene plus a script of n_steps per-step targets (a rollout, e.g. one
  * tactile press-and-slide episode, Sec. 5).  Requests are admitted in arrival order into

@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtaccel.so")
-SOURCES = ["kernels.hip", "prims.hip", "batch.hip", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "prims.hip", "tactile.hip", "batch.hip", "capi.cpp", "server.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

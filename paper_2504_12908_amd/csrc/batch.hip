@@ -15,6 +15,7 @@
 #include "coarse.h"
 #include "kernels.h"
 #include "prims.h"
+#include "tactile.h"
 
 namespace tc {
 
@@ -260,6 +261,20 @@ struct Batch::Impl {
     return F;
   }
   void build_friction(const int* mask);
+  // tactile outputs: rest positions of every node and work buffers
+  DBuf<double> xrest, tac_bary, tac_pos, tac_flow, tac_depth, tac_normal;
+  DBuf<int> tac_nodes, tac_zidx;
+  DBuf<unsigned long long> tac_zkey;
+  // caller's soft vertex ids of scene k -> node ids (checked)
+  std::vector<int> soft_nodes(int k, int n, const int32_t* ids) const {
+    const HostScene& H = hs[k];
+    std::vector<int> out(n);
+    for (int i = 0; i < n; ++i) {
+      if (ids[i] < 0 || ids[i] >= H.nv) throw ApiError(TACCEL_ERR_ARG, "soft vertex id out of range");
+      out[i] = H.node0 + H.perm[ids[i]];
+    }
+    return out;
+  }
   // swept candidates in blocks of one scene (line-search partial sums), rebuilt per iteration
   static constexpr int kPairChunk = 1024;
   std::vector<int> tp_sc_h, tp_c0_h, tp_c1_h, tp_sblk_h;
@@ -912,6 +927,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   Mem* m = &mem;
   d_sc.upload(m, hsc);
   x.upload(m, h_x);
+  xrest.upload(m, h_x);
   xn.ensure(m, 3 * (size_t)Nn);
   xhat.ensure(m, 3 * (size_t)Nn);
   v.upload(m, std::vector<double>(3 * (size_t)Nn, 0.0));
@@ -1932,6 +1948,8 @@ size_t Batch::Impl::device_bytes() const {
   add(sflag); add(segid); add(segstart); add(drow); add(dcol); add(rowcnt); add(drowptr); add(scratch);
   add(e_pairs); add(part_nodes); add(part_tets); add(part_pairs);
   add(fv); add(fsoff); add(fw); add(fc0); add(fnrm); add(fmul); add(e_fric);
+  add(xrest); add(tac_bary); add(tac_pos); add(tac_flow); add(tac_depth); add(tac_normal);
+  add(tac_nodes); add(tac_zidx); add(tac_zkey);
   add(tp_sc); add(tp_b0); add(tp_b1); add(tp_sblk);
   add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
   add(cg_d); add(cg_ainv); add(cg_rc); add(P_qc); add(cg_rca0); add(cg_rca1); add(cg_dw); add(bp_tmp); add(cg_sc_ts0);
@@ -2005,6 +2023,9 @@ Batch::~Batch() {
   FREE_ALL(&I.tp_sc, &I.tp_b0, &I.tp_b1, &I.tp_sblk)
   FREE_ALL(&I.fw, &I.fc0, &I.fnrm, &I.fmul, &I.e_fric)
   FREE_ALL(&I.fv, &I.fsoff)
+  FREE_ALL(&I.xrest, &I.tac_bary, &I.tac_pos, &I.tac_flow, &I.tac_depth, &I.tac_normal)
+  FREE_ALL(&I.tac_nodes, &I.tac_zidx)
+  I.tac_zkey.free();
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m, &I.cg_sc_ts0,
            &I.cg_sc_tsn, &I.cg_sc_tsend, &I.bp_tmp)
@@ -2184,6 +2205,89 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
 }
 
 size_t Batch::device_bytes() const { return impl_->device_bytes(); }
+
+taccel_status Batch::markers(int k, int m, const int32_t* tris, const double* bary, double* pos,
+                             double* flow) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    if (m < 0 || (m > 0 && (!tris || !bary || !pos || !flow)))
+      throw ApiError(TACCEL_ERR_ARG, "markers: bad arguments");
+    if (m == 0) return TACCEL_OK;
+    for (int i = 0; i < 3 * m; ++i)
+      if (!(bary[i] >= 0.0 && bary[i] <= 1.0)) throw ApiError(TACCEL_ERR_ARG, "markers: barycentric coordinate outside [0, 1]");
+    const std::vector<int> nodes = I.soft_nodes(k, 3 * m, tris);
+    I.tac_nodes.upload(&I.mem, nodes);
+    I.tac_bary.upload(&I.mem, std::vector<double>(bary, bary + 3 * (size_t)m));
+    I.tac_pos.ensure(&I.mem, 3 * (size_t)m);
+    I.tac_flow.ensure(&I.mem, 3 * (size_t)m);
+    launch_markers(m, I.tac_nodes.p, I.tac_bary.p, I.x.p, I.xrest.p, I.tac_pos.p, I.tac_flow.p, I.stream());
+    I.d2h(pos, I.tac_pos.p, 3 * (size_t)m);
+    I.d2h(flow, I.tac_flow.p, 3 * (size_t)m);
+    I.sync();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
+
+taccel_status Batch::depth_map(int k, const taccel_camera* cam, int ntri, const int32_t* tris,
+                               double* depth, double* normal) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    if (!cam || ntri < 0 || (ntri > 0 && !tris) || !depth || !normal)
+      throw ApiError(TACCEL_ERR_ARG, "depth_map: bad arguments");
+    if (cam->width <= 0 || cam->height <= 0 || (long long)cam->width * cam->height > (1ll << 26))
+      throw ApiError(TACCEL_ERR_ARG, "depth_map: image must have 1 to 2^26 pixels");
+    if (!(cam->pixel > 0.0) || !std::isfinite(cam->pixel)) throw ApiError(TACCEL_ERR_ARG, "depth_map: pixel pitch must be > 0");
+    Camera c;
+    double uu = 0, vv = 0, uv = 0;
+    for (int i = 0; i < 3; ++i) {
+      c.o[i] = cam->origin[i];
+      c.eu[i] = cam->axis_u[i];
+      c.ev[i] = cam->axis_v[i];
+      uu += c.eu[i] * c.eu[i];
+      vv += c.ev[i] * c.ev[i];
+      uv += c.eu[i] * c.ev[i];
+      if (!std::isfinite(c.o[i])) throw ApiError(TACCEL_ERR_ARG, "depth_map: origin must be finite");
+    }
+    if (!(std::fabs(uu - 1.0) <= 1e-9 && std::fabs(vv - 1.0) <= 1e-9 && std::fabs(uv) <= 1e-9))
+      throw ApiError(TACCEL_ERR_ARG, "depth_map: axis_u and axis_v must be orthonormal");
+    // en = eu x ev, one product per statement (no fused multiply-add)
+    for (int i = 0; i < 3; ++i) {
+      const int a = (i + 1) % 3, b = (i + 2) % 3;
+      const double p = c.eu[a] * c.ev[b];
+      const double q = c.eu[b] * c.ev[a];
+      c.en[i] = p - q;
+    }
+    c.pix = cam->pixel;
+    c.W = cam->width;
+    c.H = cam->height;
+    const int npix = c.W * c.H;
+    const std::vector<int> nodes = I.soft_nodes(k, 3 * ntri, tris);
+    hipStream_t s = I.stream();
+    I.tac_nodes.upload(&I.mem, nodes.empty() ? std::vector<int>(3, 0) : nodes);
+    I.tac_zkey.ensure(&I.mem, npix);
+    I.tac_zidx.ensure(&I.mem, npix);
+    I.tac_depth.ensure(&I.mem, npix);
+    I.tac_normal.ensure(&I.mem, 3 * (size_t)npix);
+    launch_depth_clear(npix, I.tac_zkey.p, I.tac_zidx.p, s);
+    launch_depth_raster(c, ntri, I.tac_nodes.p, I.x.p, I.tac_zkey.p, I.tac_zidx.p, 0, s);
+    launch_depth_raster(c, ntri, I.tac_nodes.p, I.x.p, I.tac_zkey.p, I.tac_zidx.p, 1, s);
+    launch_depth_finish(c, I.tac_nodes.p, I.x.p, I.tac_zkey.p, I.tac_zidx.p, I.tac_depth.p, I.tac_normal.p, s);
+    I.d2h(depth, I.tac_depth.p, npix);
+    I.d2h(normal, I.tac_normal.p, 3 * (size_t)npix);
+    I.sync();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
 
 taccel_status Batch::debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
                                       int32_t* n) {

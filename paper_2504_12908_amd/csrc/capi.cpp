@@ -114,6 +114,30 @@ void taccel_batch_destroy(taccel_batch* b) {
   delete b;
 }
 
+taccel_status taccel_batch_markers(const taccel_batch* b, int32_t scene, int32_t m, const int32_t* tris,
+                                   const double* bary, double* pos, double* flow) {
+  if (!b) return fail(TACCEL_ERR_ARG, "batch_markers: NULL batch");
+  return b->b->markers(scene, m, tris, bary, pos, flow);
+}
+
+taccel_status taccel_batch_depth_map(const taccel_batch* b, int32_t scene, const taccel_camera* cam,
+                                     int32_t ntri, const int32_t* tris, double* depth, double* normal) {
+  if (!b) return fail(TACCEL_ERR_ARG, "batch_depth_map: NULL batch");
+  return b->b->depth_map(scene, cam, ntri, tris, depth, normal);
+}
+
+taccel_status taccel_markers(const taccel_scene* s, int32_t m, const int32_t* tris, const double* bary,
+                             double* pos, double* flow) {
+  if (!s) return fail(TACCEL_ERR_ARG, "markers: NULL scene");
+  return s->b->markers(0, m, tris, bary, pos, flow);
+}
+
+taccel_status taccel_depth_map(const taccel_scene* s, const taccel_camera* cam, int32_t ntri,
+                               const int32_t* tris, double* depth, double* normal) {
+  if (!s) return fail(TACCEL_ERR_ARG, "depth_map: NULL scene");
+  return s->b->depth_map(0, cam, ntri, tris, depth, normal);
+}
+
 taccel_status taccel_scene_create(const taccel_scene_desc* d, const taccel_runtime* rt, taccel_scene** out) {
   if (!d || !out) return fail(TACCEL_ERR_ARG, "scene_create: desc and out required");
   *out = nullptr;

@@ -103,6 +103,10 @@ class Batch {
   taccel_status write(int scene, taccel_field f, const void* src, size_t bytes);
   taccel_status debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
                                  int32_t* n);
+  taccel_status markers(int scene, int m, const int32_t* tris, const double* bary, double* pos,
+                        double* flow);
+  taccel_status depth_map(int scene, const taccel_camera* cam, int ntri, const int32_t* tris,
+                          double* depth, double* normal);
   int num_scenes() const { return S_; }
 
   struct Impl;

@@ -36,6 +36,40 @@ class taccel_body_desc(C.Structure):
                 ("density", C.c_double), ("prescribed", C.c_int32)]
 
 
+class taccel_camera(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("axis_u", C.c_double * 3),
+                ("axis_v", C.c_double * 3), ("pixel", C.c_double), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+def camera(origin, axis_u, axis_v, pixel, width, height):
+    """An image plane for depth maps (see taccel_camera)."""
+    c = taccel_camera()
+    c.origin = (C.c_double * 3)(*origin)
+    c.axis_u = (C.c_double * 3)(*axis_u)
+    c.axis_v = (C.c_double * 3)(*axis_v)
+    c.pixel = pixel
+    c.width, c.height = int(width), int(height)
+    return c
+
+
+def _markers(fn, args, tris, bary):
+    tris = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    bary = _f64(bary).reshape(-1, 3)
+    m = len(tris)
+    pos, flow = np.zeros((m, 3)), np.zeros((m, 3))
+    _check(fn(*args, m, _i(tris), _d(bary), _d(pos), _d(flow)), "markers")
+    return pos, flow
+
+
+def _depth_map(fn, args, cam, tris):
+    tris = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    depth = np.zeros((cam.height, cam.width))
+    normal = np.zeros((cam.height, cam.width, 3))
+    _check(fn(*args, C.byref(cam), len(tris), _i(tris), _d(depth), _d(normal)), "depth_map")
+    return depth, normal
+
+
 class taccel_params(C.Structure):
     _fields_ = [("h", C.c_double), ("dhat", C.c_double), ("kappa", C.c_double),
                 ("kappa_s", C.c_double), ("newton_tol", C.c_double),
@@ -116,6 +150,12 @@ def lib():
         L.taccel_debug_barrier.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_double,
                                            _dp, _dp, _dp, _dp, _ip]
         L.taccel_debug_ccd.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_int32, _dp]
+        L.taccel_markers.argtypes = [C.c_void_p, C.c_int32, _ip, _dp, _dp, _dp]
+        L.taccel_batch_markers.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _ip, _dp, _dp, _dp]
+        L.taccel_depth_map.argtypes = [C.c_void_p, C.POINTER(taccel_camera), C.c_int32, _ip,
+                                       _dp, _dp]
+        L.taccel_batch_depth_map.argtypes = [C.c_void_p, C.c_int32, C.POINTER(taccel_camera),
+                                             C.c_int32, _ip, _dp, _dp]
         L.taccel_debug_friction.argtypes = [C.c_int32, _ip, _dp, _dp, _dp, C.c_double,
                                             C.c_double, C.c_double, C.c_double, _dp, _dp, _dp,
                                             _dp]
@@ -287,6 +327,14 @@ class Scene:
             self.write(FIELD_Q, q)
             self.write(FIELD_QDOT, qd)
 
+    def markers(self, tris, bary):
+        """Marker positions and flows (m, 3) each (taccel_markers)."""
+        return _markers(lib().taccel_markers, (self.h,), tris, bary)
+
+    def depth_map(self, cam, tris):
+        """Depth (H, W) and normal (H, W, 3) maps of the surface ``tris`` (taccel_depth_map)."""
+        return _depth_map(lib().taccel_depth_map, (self.h,), cam, tris)
+
     def candidates(self, P0, P1=None):
         P0 = _f64(P0)
         P1c = _f64(P1) if P1 is not None else None
@@ -339,6 +387,12 @@ class Batch:
     def write(self, i, field, arr):
         a = _f64(arr)
         _check(lib().taccel_batch_write(self.h, i, field, a.ctypes.data, a.nbytes), "batch_write")
+
+    def markers(self, i, tris, bary):
+        return _markers(lib().taccel_batch_markers, (self.h, i), tris, bary)
+
+    def depth_map(self, i, cam, tris):
+        return _depth_map(lib().taccel_batch_depth_map, (self.h, i), cam, tris)
 
 
 class Server:
