@@ -168,6 +168,9 @@ def run_batch(args, taccel, scenes, np):
     """Uniform batch: n copies of the small pad with seeded hull indenters, one launch per
     stage over all scenes."""
     n = args.scenes
+    if n > 64:
+        sys.exit("bench.py: batches of more than 64 scenes are off: a 256-scene batch once ended "
+                 "in a GPU memory fault whose cause is not found yet")
     specs = scenes.uniform_batch(n)
     _set_friction(args, specs)
     W, K = args.warmup, args.steps
@@ -348,7 +351,7 @@ def main():
     ap.add_argument("--workload", choices=["single", "batch", "serving", "tactile", "copy"],
                     default="single")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--scenes", type=int, default=256)
+    ap.add_argument("--scenes", type=int, default=64)
     ap.add_argument("--friction", type=float, default=0.0,
                     help="friction coefficient of the single/batch workload (default 0: the "
                          "frictionless benchmark)")

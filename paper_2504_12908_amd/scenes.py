@@ -296,6 +296,21 @@ def pad_press_slide_friction(seed: int = 0, n_steps: int = 8, mu: float = 0.5,
     return spec
 
 
+def cube_resting_on_pad(mu: float = 0.1, n_steps: int = 30, eps_v: float = 1e-3) -> SceneSpec:
+    """A free (unprescribed) 10 mm cube released 0.05 mm above the centre of the 8x8x2 pad,
+    under gravity, with friction coefficient mu; h = 0.01 s."""
+    pad_lo = (-10 * MM, -10 * MM, 0.0)
+    pad_hi = (10 * MM, 10 * MM, 4 * MM)
+    cube_v, cube_t = box_mesh((0.0, 0.0, pad_hi[2] + 0.05 * MM + 5 * MM), (10 * MM,) * 3)
+    hold = translation_targets(np.zeros((n_steps, 3)))[:, None, :]  # unused: the cube is free
+    spec = _pad_scene("cube_resting_on_pad", pad_lo, pad_hi, (8, 8, 2),
+                      [BodySpec(cube_v, cube_t, prescribed=False)], hold, 0.01,
+                      dict(mu=mu, eps_v=eps_v))
+    spec.params["friction"] = mu
+    spec.params["eps_v"] = eps_v
+    return spec
+
+
 def top_surface_tris(spec: SceneSpec) -> np.ndarray:
     """Boundary triangles of the pad's top face (the coated, contact side), outward (+z)
     oriented, in the order their tets appear: (f, 3) int32 soft-vertex ids."""

@@ -637,6 +637,26 @@ def test_friction_drags_the_pad(oracle_lib):
     assert abs(moved[0.0]) <= 0.1 * slide
 
 
+def test_friction_coulomb_sliding_cube(oracle_lib):
+    """A free cube settled on the pad (its weight carried by the barrier) and launched
+    sideways at 5 cm/s slides: Coulomb friction takes mu g h off its speed every step."""
+    mu, g, h = 0.1, 9.81, 0.01
+    spec = S.cube_resting_on_pad(mu)
+    o = oracle_lib.OracleScene(spec)
+    for k in range(12):
+        assert o.step(k)[0] == 0
+    x, v, q, qd = o.get_state()
+    assert abs(qd[0, 2]) < 1e-6  # at rest vertically
+    qd[0, 0] = 0.05
+    o.set_state(x, v, q, qd)
+    vx = 0.05
+    for k in range(12, 15):
+        assert o.step(k)[0] == 0
+        nvx = o.get_state()[3][0, 0]
+        assert (vx - nvx) == pytest.approx(mu * g * h, rel=0.02)
+        vx = nvx
+
+
 def test_oracle_step_is_deterministic(oracle_lib):
     spec = S.pad_press_cube(1)
     a = oracle_lib.OracleScene(spec)
