@@ -261,36 +261,6 @@ def test_friction_step_teacher_forced(T, oracle_lib):
     g.close()
 
 
-def test_friction_sliding_cube_teacher_forced(T, oracle_lib):
-    """A free cube resting on the pad with friction, launched sideways: teacher-forced
-    settling and sliding steps within 1e-8 * L of the oracle."""
-    spec = S.cube_resting_on_pad(0.1)
-    say(f"teacher-forced steps: {spec.name} (free body, friction)")
-    o = oracle_lib.OracleScene(spec)
-    g = T.Scene(spec)
-    L = o.scale
-    steps = [0, 1, 2] + list(range(3, 12)) + [12, 13, 14]
-    for k in steps:
-        if k == 12:
-            x, v, q, qd = o.get_state()
-            qd[0, 0] = 0.05
-            o.set_state(x, v, q, qd)
-        x, v, q, qd = o.get_state()
-        if k in (3, 4, 5, 6, 7, 8, 9, 10, 11):  # settling: oracle only
-            assert o.step(k)[0] == 0
-            continue
-        g.set_state(x, v, q, qd)
-        rc_o, _ = o.step(k)
-        rc_g, st_g = g.step(k)
-        assert rc_o == 0 and rc_g == T.OK, (k, T.STATUS_NAMES[rc_g], st_g)
-        xo, _, qo, qdo = o.get_state()
-        xg, _, qg, qdg = g.get_state()
-        err = max(np.abs(xg - xo).max(), np.abs(qg[:, :3] - qo[:, :3]).max())
-        say(f"  step {k}: newton {st_g['newton_iters']} vx gpu {qdg[0, 0]:.6e} oracle {qdo[0, 0]:.6e} "
-            f"err {err:.3e} (tol {1e-8 * L:.3e})")
-        assert err <= 1e-8 * L
-
-
 def test_friction_batch_equals_single(T):
     """Friction and frictionless scenes in one batch: each scene bit for bit equal to the
     same scene run alone."""
