@@ -358,7 +358,11 @@ __global__ void __launch_bounds__(TPB) k_bp_query(View V, const double* P0, cons
         const int x = ql[0] + cc % nx, y = ql[1] + (cc / nx) % ny, z = ql[2] + cc / (nx * ny);
         const BpEntry& E = bp.entries[e];
         const int tt = E.t;
-        hit = E.cx == x && E.cy == y && E.cz == z && !(kind == 1 && tt - V.Ntr <= i) &&
+        // a bucket may also hold entries of other keys that hash to it: the entry must be of
+        // the query's scene, cell and primitive type (triangle targets for a point, edges for
+        // an edge), or its target index would be read as the wrong kind of primitive
+        hit = E.cx == x && E.cy == y && E.cz == z && E.scene == s && (tt >= V.Ntr) == (kind == 1) &&
+              !(kind == 1 && tt - V.Ntr <= i) &&
               max(ql[0], cell_of(E.lo[0] - sc.dhat, sc.org[0], inv)) == x &&
               max(ql[1], cell_of(E.lo[1] - sc.dhat, sc.org[1], inv)) == y &&
               max(ql[2], cell_of(E.lo[2] - sc.dhat, sc.org[2], inv)) == z &&
