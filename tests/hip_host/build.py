@@ -1,0 +1,42 @@
+"""Host build of the library's HIP sources against the emulation in this folder (test
+infrastructure only: the product loads the gfx950 build, never this one).
+
+The library's own sources compile unchanged as C++ for the host; ``hip/hip_runtime.h`` and
+``runtime.cpp`` supply the HIP subset they use.  The result, ``_build/libtaccel_host.so``, has the
+same C ABI as the GPU library.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2504_12908_amd", "csrc")
+OUT = os.path.join(HERE, "_build")
+LIB = os.path.join(OUT, "libtaccel_host.so")
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("kernels.hip", "prims.hip", "tactile.hip", "batch.hip", "capi.cpp", "server.cpp")]
+FLAGS = ["-std=c++17", "-O2", "-g", "-fPIC", "-U_FORTIFY_SOURCE", "-D_FORTIFY_SOURCE=0",
+         "-Wno-unknown-pragmas", "-I" + HERE, "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
+def build() -> str:
+    os.makedirs(OUT, exist_ok=True)
+
+    def one(src):
+        obj = os.path.join(OUT, os.path.basename(src) + ".o")
+        lang = ["-x", "c++"] if src.endswith(".hip") else []
+        subprocess.run(["g++"] + FLAGS + lang + ["-c", src, "-o", obj], check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        objs = list(ex.map(one, SOURCES + [os.path.join(HERE, "runtime.cpp")]))
+    subprocess.run(["g++", "-shared", "-rdynamic", "-o", LIB + ".tmp"] + objs + ["-lpthread"], check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,112 @@
+"""The library's HIP sources built for the host against the emulation in ``tests/hip_host``
+(every device allocation ends at a guard page and is unmapped when freed, so an access past a
+buffer or after its release faults at once).  Each case runs in a fresh interpreter that loads
+that build through the same C ABI; a memory error ends it with a non-zero status and the
+allocation the faulting address belongs to.
+
+Regression: a batch of 32 small pads used to fault at creation (a point query accepted an
+edge entry sharing its hash bucket, and the target index was then read as a triangle's).
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+
+
+@pytest.fixture(scope="module")
+def host_lib():
+    sys.path.insert(0, os.path.join(HERE, "hip_host"))
+    try:
+        import build as hb
+    finally:
+        sys.path.pop(0)
+    return hb.build()
+
+
+PRELUDE = """
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np
+from paper_2504_12908_amd import taccel as T, scenes as S
+T.LIB_PATH = {lib!r}
+T.lib()
+from oracle import binding as B
+"""
+
+
+def run(lib, body, timeout=600):
+    code = PRELUDE.format(root=ROOT, lib=lib) + body
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=timeout)
+    assert p.returncode == 0, (p.returncode, p.stdout[-2000:], p.stderr[-4000:])
+    assert "DONE" in p.stdout, p.stdout[-2000:]
+    return p.stdout
+
+
+def test_host_build_element_evaluators(host_lib):
+    """The host build computes the same barrier and friction derivatives as the oracle."""
+    run(host_lib, """
+x = np.concatenate([[4e-4, 4e-4, 5e-5], [0, 0, 0, 1.5e-3, 0, 0, 0, 1.5e-3, 0]])
+e, g, H, Hp, t = T.debug_barrier(np.array([0]), x[None], np.array([0.0]), 1e-4, 1e3)
+eo, go, Ho, Hpo, to = B.pair_barrier(0, x, 0.0, 1e-4, 1e3)
+assert abs(e[0] - eo) <= 1e-12 * abs(eo) and np.abs(Hp[0] - Hpo).max() <= 1e-9 * np.abs(Hpo).max()
+xn = x.copy(); x1 = x.copy(); x1[:3] += [3e-5, -1e-5, 0.0]
+lam, e, g, H = T.debug_friction(np.array([0]), xn[None], x1[None], np.array([0.0]), 1e-4, 1e3, 0.5, 1e-5)
+lo, eo, go, Ho = B.pair_friction(0, xn, x1, 0.0, 1e-4, 1e3, 0.5, 1e-5)
+assert abs(lam[0] - lo) <= 1e-12 * lo and abs(e[0] - eo) <= 1e-10 * abs(eo)
+print("DONE")
+""")
+
+
+def test_host_build_candidates_match_oracle(host_lib):
+    """Broad phase of one scene (pad and lowered cube) equal to the oracle's enumeration."""
+    run(host_lib, """
+import ctypes as C
+spec = S.pad_press_cube(0)
+spec.bodies[0].verts = spec.bodies[0].verts + np.array([0, 0, 5e-3])
+g = T.Scene(spec)
+o = B.OracleScene(spec)
+P = np.zeros((o.nw, 3)); B.lib().orc_world_positions(o.h, P.ctypes.data_as(C.POINTER(C.c_double)))
+P[o.nv:, 2] -= 5e-3 - 2e-5
+cg = set(map(tuple, g.candidates(P)))
+co = np.zeros((200000, 5), dtype=np.int32)
+n = B.lib().orc_candidates(o.h, P.ctypes.data_as(C.POINTER(C.c_double)), None,
+                           co.ctypes.data_as(C.POINTER(C.c_int32)), 200000)
+assert cg == set(map(tuple, co[:n])) and n > 1000, (len(cg), n)
+print("DONE")
+""")
+
+
+def test_host_build_batch_of_32_is_created(host_lib):
+    """Creating a batch of 32 small pads runs the all-scene broad phase and the zero-distance
+    check over its candidates; it used to fault on out-of-range targets."""
+    run(host_lib, """
+b = T.Batch(S.uniform_batch(32))
+b.close()
+print("DONE")
+""")
+
+
+def test_host_build_tactile_maps(host_lib):
+    """Depth map and markers of the host build equal the oracle's definitions (rest state)."""
+    run(host_lib, """
+from oracle import tactile as TO
+spec = S.pad_press_cube(0)
+g = T.Scene(spec)
+tris = S.top_surface_tris(spec)
+idx, bary = S.marker_layout(spec, tris, 5, 5)
+pos, flow = g.markers(tris[idx], bary)
+po, fo = TO.markers(spec.verts, spec.verts, tris[idx], bary)
+assert np.array_equal(pos, po) and np.all(flow == 0)
+cam = T.camera((-11e-3, -11e-3, 0.0), (1.0, 0, 0), (0, 1.0, 0), 0.7e-3, 32, 32)
+d, nrm = g.depth_map(cam, tris)
+do, no = TO.depth_map(spec.verts, tris, (-11e-3, -11e-3, 0.0), (1.0, 0, 0), (0, 1.0, 0), 0.7e-3, 32, 32)
+assert np.array_equal(np.isfinite(d), np.isfinite(do)) and np.array_equal(d[np.isfinite(d)], do[np.isfinite(do)])
+print("DONE")
+""")
