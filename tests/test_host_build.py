@@ -110,3 +110,25 @@ do, no = TO.depth_map(spec.verts, tris, (-11e-3, -11e-3, 0.0), (1.0, 0, 0), (0, 
 assert np.array_equal(np.isfinite(d), np.isfinite(do)) and np.array_equal(d[np.isfinite(d)], do[np.isfinite(do)])
 print("DONE")
 """)
+
+
+def test_host_build_multiscene_newton_iterations(host_lib):
+    """One Newton iteration (then the roll-back of the unconverged step) of a 32-scene batch
+    and of a batch mixing friction and frictionless scenes runs without a memory error."""
+    run(host_lib, """
+specs = S.uniform_batch(32)
+for sp in specs:
+    sp.params["max_newton"] = 1
+b = T.Batch(specs, pcg_eta=0.5)
+rc, per, st = b.step(0)
+assert set(per.tolist()) <= {0, 3}, per
+b.close()
+specs = [S.pad_press_slide_friction(0, n_steps=6), S.batch_member(0), S.pad_press_slide_friction(2, n_steps=6, mu=0.3)]
+for sp in specs:
+    sp.params["max_newton"] = 2
+b = T.Batch(specs, pcg_eta=0.5)
+rc, per, st = b.step(0)
+assert set(per.tolist()) <= {0, 3}, per
+b.close()
+print("DONE")
+""")
