@@ -364,8 +364,8 @@ def main():
     ap.add_argument("--max-cohorts", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (scenes shard across GPUs without "
-              "communication; no multi-GPU run is part of it)", file=sys.stderr)
+        print("bench.py: measures one GPU only (scenes would shard across GPUs without "
+              "communication; there is no multi-GPU run)", file=sys.stderr)
         sys.exit(1)
     import numpy as np
 
