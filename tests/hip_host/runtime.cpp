@@ -9,6 +9,7 @@
 #include <csignal>
 #include <execinfo.h>
 #include <map>
+#include <mutex>
 #include <sys/mman.h>
 #include <ucontext.h>
 #include <unistd.h>
@@ -226,11 +227,15 @@ static void run_grid(dim3 grid, dim3 block, const std::function<void()>& body) {
       }
 }
 
+// Kernels of host threads that share the runtime (the server's cohorts) run one at a time.
+std::recursive_mutex g_exec;
+
 void launch(hipStream_t s, dim3 grid, dim3 block, std::function<void()> body) {
   if (s && s->capturing) {
     s->rec.push_back([grid, block, body]() { run_grid(grid, block, body); });
     return;
   }
+  std::lock_guard<std::recursive_mutex> lk(g_exec);
   run_grid(grid, block, body);
 }
 }  // namespace emu
@@ -239,9 +244,16 @@ void launch(hipStream_t s, dim3 grid, dim3 block, std::function<void()> body) {
 namespace {
 struct Region { char* base; size_t total; bool freed; };
 std::map<void*, Region> g_regions;
+struct Tag { size_t n; int serial; };
+std::map<void*, Tag> g_tags;
+int g_serial = 0;
+
 const size_t kPage = 4096;
 
+std::mutex g_alloc;
+
 void* guarded(size_t n) {
+  std::lock_guard<std::mutex> lk(g_alloc);
   const size_t n16 = (std::max<size_t>(n, 1) + 15) & ~size_t(15);
   const size_t data = (n16 + kPage - 1) & ~(kPage - 1);
   const size_t total = kPage + data + kPage;
@@ -252,10 +264,12 @@ void* guarded(size_t n) {
   char* p = base + kPage + data - n16;
   std::memset(p, 0x7F, n16);
   g_regions[p] = {base, total, false};
+  g_tags[p] = {n, ++g_serial};
   return p;
 }
 hipError_t release(void* p) {
   if (!p) return hipSuccess;
+  std::lock_guard<std::mutex> lk(g_alloc);
   auto it = g_regions.find(p);
   if (it == g_regions.end()) { fprintf(stderr, "host build: free of unknown pointer %p\n", p); abort(); }
   if (it->second.freed) { fprintf(stderr, "host build: double free %p\n", p); abort(); }
@@ -266,9 +280,6 @@ hipError_t release(void* p) {
 }  // namespace
 
 namespace {
-struct Tag { size_t n; int serial; };
-std::map<void*, Tag> g_tags;
-int g_serial = 0;
 void on_segv(int, siginfo_t* si, void*) {
   char* a = (char*)si->si_addr;
   fprintf(stderr, "host build: memory fault at %p\n", (void*)a);
@@ -300,9 +311,9 @@ struct Installer {
 } g_installer;
 }  // namespace
 
-hipError_t hipMalloc(void** p, size_t n) { *p = guarded(n); g_tags[*p] = {n, ++g_serial}; return *p ? hipSuccess : hipErrorOutOfMemory; }
+hipError_t hipMalloc(void** p, size_t n) { *p = guarded(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
 hipError_t hipFree(void* p) { return release(p); }
-hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = guarded(n); g_tags[*p] = {n, ++g_serial}; return *p ? hipSuccess : hipErrorOutOfMemory; }
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = guarded(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
 hipError_t hipHostFree(void* p) { return release(p); }
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { if (n) std::memcpy(d, s, n); return hipSuccess; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { if (n) std::memcpy(d, s, n); return hipSuccess; }
@@ -329,6 +340,10 @@ hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g) {
 }
 hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*, size_t) { *e = new EmuGraphExec{g->ops}; return hipSuccess; }
 hipError_t hipGraphExecUpdate(hipGraphExec_t e, hipGraph_t g, hipGraphNode_t*, hipGraphExecUpdateResult* r) { e->ops = g->ops; *r = hipGraphExecUpdateSuccess; return hipSuccess; }
-hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) { for (auto& f : e->ops) f(); return hipSuccess; }
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  std::lock_guard<std::recursive_mutex> lk(emu::g_exec);
+  for (auto& f : e->ops) f();
+  return hipSuccess;
+}
 hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t e) { delete e; return hipSuccess; }
