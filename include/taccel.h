@@ -169,7 +169,7 @@ taccel_status taccel_batch_write(taccel_batch* b, int32_t scene, taccel_field f,
                                  size_t bytes);
 void taccel_batch_destroy(taccel_batch* b);
 
-/* ---- Tactile outputs of the current state (Taccel Sec. 3.6) ----------------------------
+/* ---- Tactile outputs of the current state (Taccel Sec. 4.2) ----------------------------
  * Markers: marker k lies on the soft-body triangle tris[k][0..2] (the caller's soft vertex
  * ids) at barycentric coordinates bary[k][0..2] (each in [0, 1]).  Writes its current
  * position pos[k][3] = sum_u bary[k][u] x[tris[k][u]] and its flow flow[k][3] = pos[k] minus

@@ -59,6 +59,11 @@ def lib():
         L.orc_create.argtypes = [C.POINTER(_Desc), C.c_char_p, C.c_int32]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(_Stats)]
+        L.orc_step_begin.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_step_finish.argtypes = [C.c_void_p, C.POINTER(_Stats)]
+        L.orc_system.argtypes = [C.c_void_p, C.c_uint32, _dp, _dp, C.c_int32, _ip, _ip, _dp,
+                                 C.c_int32, _ip, _ip]
+        L.orc_newton_direction.argtypes = [C.c_void_p, _dp, C.c_int32]
         L.orc_num_world_verts.argtypes = [C.c_void_p]
         L.orc_scene_scale.argtypes = [C.c_void_p]
         L.orc_scene_scale.restype = C.c_double
@@ -166,6 +171,57 @@ class OracleScene:
         rc = lib().orc_step(self.h, _d(bt), _d(dt), C.byref(st))
         return rc, dict(status=st.status, newton_iters=st.newton_iters,
                         al_rounds=st.al_rounds)
+
+    def _targets(self, k, body_targets, dir_targets):
+        if body_targets is None:
+            body_targets = self.spec.body_targets[k]
+        if dir_targets is None:
+            dir_targets = (self.spec.dirichlet_targets[k] if self.n_moving
+                           else np.zeros((1, 3)))
+        bt = _f64(np.asarray(body_targets).reshape(-1) if self.nb else np.zeros(12))
+        dt = _f64(np.asarray(dir_targets).reshape(-1) if self.n_moving else np.zeros(3))
+        return bt, dt
+
+    def step_begin(self, k=None, body_targets=None, dir_targets=None):
+        bt, dt = self._targets(k, body_targets, dir_targets)
+        return lib().orc_step_begin(self.h, _d(bt), _d(dt))
+
+    def step_finish(self):
+        st = _Stats()
+        rc = lib().orc_step_finish(self.h, C.byref(st))
+        return rc, dict(status=st.status, newton_iters=st.newton_iters,
+                        al_rounds=st.al_rounds)
+
+    TERMS = dict(inertia=1, elastic=2, body_stiffness=4, constraint=8, contact=16, friction=32,
+                 all=63)
+
+    def system(self, terms="all"):
+        """Newton system of the current state: (energy, G[n_nodes, 3], blocks dict
+        {(row, col): 3x3}, node_of[nv + nb])."""
+        t = self.TERMS[terms] if isinstance(terms, str) else int(terms)
+        e = C.c_double()
+        nblk = C.c_int32()
+        node_of = np.zeros(self.nv + max(self.nb, 1), dtype=np.int32)
+        nn = lib().orc_system(self.h, t, C.byref(e), None, 0, None, None, None, 0,
+                              C.byref(nblk), None)
+        G = np.zeros(max(3 * nn, 1))
+        nb = nblk.value
+        rows = np.zeros(max(nb, 1), dtype=np.int32)
+        cols = np.zeros(max(nb, 1), dtype=np.int32)
+        vals = np.zeros((max(nb, 1), 9))
+        lib().orc_system(self.h, t, C.byref(e), _d(G), 3 * nn, _i(rows), _i(cols), _d(vals), nb,
+                         C.byref(nblk), _i(node_of))
+        blocks = {(int(r), int(c)): vals[k].reshape(3, 3) for k, (r, c) in
+                  enumerate(zip(rows[:nb], cols[:nb]))}
+        return e.value, G[:3 * nn].reshape(-1, 3), blocks, node_of[:self.nv + self.nb]
+
+    def newton_direction(self):
+        nn = lib().orc_newton_direction(self.h, None, 0)
+        if nn < 0:
+            raise RuntimeError("oracle factorisation broke down")
+        p = np.zeros(max(3 * nn, 1))
+        lib().orc_newton_direction(self.h, _d(p), 3 * nn)
+        return p[:3 * nn].reshape(-1, 3)
 
     def get_state(self):
         x = np.zeros((self.nv, 3))

@@ -991,16 +991,27 @@ static int vertex_nodes(const Scene& S, const Dofs& D, int w, int* node, double*
 }
 
 // ---------------------------------------------------------------- energy
-static double total_energy(const Scene& S, const vector<Pair>& pairs) {
+// Terms of the incremental potential, selectable for tests (all of them in the solve).
+enum : unsigned {
+  kTermInertia = 1,      // soft lumped inertia and body inertia
+  kTermElastic = 2,      // neo-Hookean elasticity, h^2 V Psi
+  kTermBodyStiff = 4,    // affine-body orthogonality (ARAP) term
+  kTermConstraint = 8,   // augmented-Lagrangian kinematic constraint
+  kTermContact = 16,     // barrier of the active pairs
+  kTermFriction = 32,    // lagged friction potential
+  kTermAll = 63
+};
+
+static double total_energy(const Scene& S, const vector<Pair>& pairs, unsigned terms = kTermAll) {
   double E = 0.0;
   for (int i = 0; i < S.nv; ++i)
-    if (S.dir[i] == 0) {
+    if ((terms & kTermInertia) && S.dir[i] == 0) {
       const V3 d = S.x[i] - S.xhat[i];
       E += 0.5 * S.mass[i] * dot(d, d);
     }
   const double h2 = S.h * S.h;
   double Eel = 0.0;
-  for (size_t e = 0; e < S.tets.size(); ++e) {
+  for (size_t e = 0; e < S.tets.size() && (terms & kTermElastic); ++e) {
     double x12[12];
     for (int a = 0; a < 4; ++a)
       for (int c = 0; c < 3; ++c) x12[3 * a + c] = S.x[S.tets[e][a]][c];
@@ -1016,12 +1027,12 @@ static double total_energy(const Scene& S, const vector<Pair>& pairs) {
     double q = 0.0;
     for (int a = 0; a < 12; ++a)
       for (int c = 0; c < 12; ++c) q += dy[a] * b.My[12 * a + c] * dy[c];
-    E += 0.5 * q;
+    if (terms & kTermInertia) E += 0.5 * q;
     double A[9];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) A[3 * i + j] = b.y[3 + 3 * j + i];
-    E += h2 * S.kappa_s * b.vol * arap_energy(A);
-    if (b.prescribed) {
+    if (terms & kTermBodyStiff) E += h2 * S.kappa_s * b.vol * arap_energy(A);
+    if (b.prescribed && (terms & kTermConstraint)) {
       double c[12];
       for (int k = 0; k < 12; ++k) c[k] = b.y[k] - b.ystar[k];
       double cc = 0.0, lc = 0.0;
@@ -1037,6 +1048,7 @@ static double total_energy(const Scene& S, const vector<Pair>& pairs) {
   world_positions(S, P);
   double Eb = 0.0;
   for (const Pair& pr : pairs) {
+    if (!(terms & kTermContact)) break;
     int w[4];
     pair_verts(S, pr, w);
     double x12[12];
@@ -1046,6 +1058,7 @@ static double total_energy(const Scene& S, const vector<Pair>& pairs) {
     Eb += pe;
   }
   for (const FPair& f : S.fric) {
+    if (!(terms & kTermFriction)) break;
     double x12[12];
     gather12(P, f.w, x12);
     Eb += friction_eval(f, x12, S.epsv * S.h, nullptr, nullptr);
@@ -1056,19 +1069,19 @@ static double total_energy(const Scene& S, const vector<Pair>& pairs) {
 
 // ---------------------------------------------------------------- gradient and Hessian
 static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
-                     vector<double>& G, BlockMatrix& H) {
+                     vector<double>& G, BlockMatrix& H, unsigned terms = kTermAll) {
   const double h2 = S.h * S.h;
   G.assign(3 * D.n_nodes, 0.0);
   H = BlockMatrix();
   H.n_nodes = D.n_nodes;
   for (int i = 0; i < S.nv; ++i) {
     const int n = D.soft_node[i];
-    if (n < 0) continue;
+    if (n < 0 || !(terms & kTermInertia)) continue;
     for (int c = 0; c < 3; ++c) G[3 * n + c] += S.mass[i] * (S.x[i][c] - S.xhat[i][c]);
     auto& blk = H.at(n, n);
     for (int c = 0; c < 3; ++c) blk[4 * c] += S.mass[i];
   }
-  for (size_t e = 0; e < S.tets.size(); ++e) {
+  for (size_t e = 0; e < S.tets.size() && (terms & kTermElastic); ++e) {
     double x12[12], en, g[12], Hp[144];
     for (int a = 0; a < 4; ++a)
       for (int c = 0; c < 3; ++c) x12[3 * a + c] = S.x[S.tets[e][a]][c];
@@ -1090,15 +1103,17 @@ static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
     const Body& b = S.bodies[bi];
     const int n0 = D.body_node[bi];
     if (n0 < 0) continue;
-    double g[12] = {0}, Hb[144];
-    for (int k = 0; k < 144; ++k) Hb[k] = b.My[k];
-    for (int a = 0; a < 12; ++a)
-      for (int c = 0; c < 12; ++c) g[a] += b.My[12 * a + c] * (b.y[c] - b.yhat[c]);
+    double g[12] = {0}, Hb[144] = {0};
+    if (terms & kTermInertia) {
+      for (int k = 0; k < 144; ++k) Hb[k] = b.My[k];
+      for (int a = 0; a < 12; ++a)
+        for (int c = 0; c < 12; ++c) g[a] += b.My[12 * a + c] * (b.y[c] - b.yhat[c]);
+    }
     double A[9], ga[9], Hap[81];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) A[3 * i + j] = b.y[3 + 3 * j + i];
     arap_eval(A, ga, nullptr, Hap);
-    const double ks = h2 * S.kappa_s * b.vol;
+    const double ks = (terms & kTermBodyStiff) ? h2 * S.kappa_s * b.vol : 0.0;
     // A row-major index 3i+j  <->  y index 3 + 3j + i.
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
@@ -1107,7 +1122,7 @@ static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
           for (int l = 0; l < 3; ++l)
             Hb[12 * (3 + 3 * j + i) + 3 + 3 * l + k] += ks * Hap[9 * (3 * i + j) + 3 * k + l];
       }
-    if (b.prescribed) {
+    if (b.prescribed && (terms & kTermConstraint)) {
       for (int a = 0; a < 12; ++a)
         for (int c = 0; c < 12; ++c) {
           g[a] += b.My[12 * a + c] * (b.kappaA * (b.y[c] - b.ystar[c]) - b.lambda[c]);
@@ -1127,6 +1142,8 @@ static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
   world_positions(S, P);
   const size_t npair = active.size();
   for (size_t k = 0; k < npair + S.fric.size(); ++k) {
+    if (k < npair && !(terms & kTermContact)) continue;
+    if (k >= npair && !(terms & kTermFriction)) continue;
     int w[4];
     double x12[12], e, g[12], Hp[144];
     if (k < npair) {
@@ -1370,7 +1387,9 @@ static void diagnostics(const Scene& S, double* dmin_out, double* jmin_out, int*
   *jmin_out = jmin;
 }
 
-static int step(Scene& S, const double* body_targets, const double* dir_targets, orc_stats* st) {
+// First half of a time step: prediction (Sec. 3.2 Eq. 1), kinematic targets, the friction
+// lag and the jump of moving Dirichlet vertices.  Returns kOk or kInfeasible.
+static int step_begin(Scene& S, const double* body_targets, const double* dir_targets) {
   S.ls_log.clear();
   S.xn = S.x;
   const double h = S.h;
@@ -1438,10 +1457,16 @@ static int step(Scene& S, const double* body_targets, const double* dir_targets,
     }
     if (!ok) {
       S.x = keep;
-      if (st) st->status = kInfeasible;
       return kInfeasible;
     }
   }
+  return kOk;
+}
+
+// Second half: Newton loops with the augmented-Lagrangian rounds and snaps (Sec. 3.4), then
+// the velocity update (App. A.2 Eq. A2), or a roll-back to the start of the step.
+static int step_finish(Scene& S, orc_stats* st) {
+  const double h = S.h;
   int iters = 0, rounds = 0, status = kOk;
   for (;;) {
     ++rounds;
@@ -1481,6 +1506,36 @@ static int step(Scene& S, const double* body_targets, const double* dir_targets,
   for (Body& b : S.bodies)
     for (int k = 0; k < 12; ++k) b.yd[k] = (b.y[k] - b.yn[k]) / h;
   return kOk;
+}
+
+static int step(Scene& S, const double* body_targets, const double* dir_targets, orc_stats* st) {
+  const int rc = step_begin(S, body_targets, dir_targets);
+  if (rc != kOk) {
+    if (st) st->status = rc;
+    return rc;
+  }
+  return step_finish(S, st);
+}
+
+// The Newton system at the current state over the current unknowns: active pairs of the
+// current positions, energy, gradient and projected Hessian of the selected terms.
+static int current_system(const Scene& S, unsigned terms, double* energy, vector<double>& G,
+                          BlockMatrix& H, Dofs& D) {
+  D = make_dofs(S);
+  vector<V3> P;
+  world_positions(S, P);
+  vector<Pair> cand, active;
+  brute_candidates(S, P, nullptr, cand);
+  for (const Pair& pr : cand) {
+    int w[4];
+    pair_verts(S, pr, w);
+    double x12[12];
+    gather12(P, w, x12);
+    if (pair_sqdist(pr.kind, x12) < S.dhat * S.dhat) active.push_back(pr);
+  }
+  assemble(S, D, active, G, H, terms);
+  if (energy) *energy = total_energy(S, active, terms);
+  return D.n_nodes;
 }
 
 static Scene* create(const orc_desc* d, std::string& err) {
@@ -1640,6 +1695,48 @@ void orc_destroy(void* s) { delete static_cast<Scene*>(s); }
 int32_t orc_step(void* s, const double* body_targets, const double* dir_targets, orc_stats* st) {
   if (st) std::memset(st, 0, sizeof(*st));
   return step(*static_cast<Scene*>(s), body_targets, dir_targets, st);
+}
+int32_t orc_step_begin(void* s, const double* body_targets, const double* dir_targets) {
+  return step_begin(*static_cast<Scene*>(s), body_targets, dir_targets);
+}
+int32_t orc_step_finish(void* s, orc_stats* st) {
+  if (st) std::memset(st, 0, sizeof(*st));
+  return step_finish(*static_cast<Scene*>(s), st);
+}
+int32_t orc_system(const void* s, uint32_t terms, double* energy, double* G, int32_t g_cap,
+                   int32_t* brow, int32_t* bcol, double* bval, int32_t blk_cap, int32_t* n_blocks,
+                   int32_t* node_of) {
+  const Scene& S = *static_cast<const Scene*>(s);
+  vector<double> Gv;
+  BlockMatrix H;
+  Dofs D;
+  const int nn = current_system(S, terms, energy, Gv, H, D);
+  for (int k = 0; k < (int)Gv.size() && k < g_cap; ++k) G[k] = Gv[k];
+  const int nb = (int)H.keys.size();
+  for (int b = 0; b < nb && b < blk_cap; ++b) {
+    brow[b] = H.keys[b].first;
+    bcol[b] = H.keys[b].second;
+    for (int k = 0; k < 9; ++k) bval[9 * b + k] = H.blocks[b][k];
+  }
+  *n_blocks = nb;
+  if (node_of) {
+    for (int i = 0; i < S.nv; ++i) node_of[i] = D.soft_node[i];
+    for (size_t b = 0; b < S.bodies.size(); ++b) node_of[S.nv + b] = D.body_node[b];
+  }
+  return nn;
+}
+int32_t orc_newton_direction(const void* s, double* p, int32_t cap) {
+  const Scene& S = *static_cast<const Scene*>(s);
+  vector<double> Gv, sol;
+  BlockMatrix H;
+  Dofs D;
+  const int nn = current_system(S, kTermAll, nullptr, Gv, H, D);
+  vector<double> rhs(Gv.size());
+  for (size_t k = 0; k < Gv.size(); ++k) rhs[k] = -Gv[k];
+  if (nn == 0) return 0;
+  if (!skyline_solve(H, rhs, sol)) return -1;
+  for (int k = 0; k < (int)sol.size() && k < cap; ++k) p[k] = sol[k];
+  return nn;
 }
 int32_t orc_num_world_verts(const void* s) { return static_cast<const Scene*>(s)->nw; }
 double orc_scene_scale(const void* s) { return static_cast<const Scene*>(s)->L; }

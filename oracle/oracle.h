@@ -56,6 +56,26 @@ void orc_destroy(void* s);
  * 2, in increasing vertex order. */
 int32_t orc_step(void* s, const double* body_targets, const double* dir_targets,
                  orc_stats* st);
+/* The same step in two halves, so a test can inspect the system at the start of the step:
+ * orc_step_begin predicts, sets the targets and the friction lag and moves the moving
+ * Dirichlet vertices (returns 0 or 7); orc_step_finish runs the Newton loops and the
+ * augmented-Lagrangian rounds and returns the status of orc_step. */
+int32_t orc_step_begin(void* s, const double* body_targets, const double* dir_targets);
+int32_t orc_step_finish(void* s, orc_stats* st);
+/* Newton system of the current state, over the current unknowns: free soft vertices in
+ * increasing order (one 3-dof node each), then 4 pseudo-nodes (p, c1, c2, c3) per affine body
+ * not fixed on its target; the pairs closer than dhat at the current positions are active.
+ * terms selects energy terms (1 inertia, 2 elasticity, 4 body orthogonality, 8 kinematic
+ * constraint, 16 barrier, 32 friction; 63 all).  Writes the energy, the gradient
+ * G[3 n_nodes] (at most g_cap values), the projected Hessian as 3x3 blocks (row node, column
+ * node, 9 values row-major; at most blk_cap blocks; *n_blocks gets the count) and node_of
+ * [nv + nb]: first node of each soft vertex and body, -1 when it has none.  Returns n_nodes. */
+int32_t orc_system(const void* s, uint32_t terms, double* energy, double* G, int32_t g_cap,
+                   int32_t* brow, int32_t* bcol, double* bval, int32_t blk_cap, int32_t* n_blocks,
+                   int32_t* node_of);
+/* Newton direction p = -H^-1 G of that system (all terms) by the skyline Cholesky solve.
+ * Returns n_nodes, or -1 when the factorisation breaks down. */
+int32_t orc_newton_direction(const void* s, double* p, int32_t cap);
 int32_t orc_num_world_verts(const void* s);
 double orc_scene_scale(const void* s); /* rest bounding-box diagonal of the whole scene */
 /* Brute-force minimum distance over all admissible pairs, minimum det(F) over tets and the

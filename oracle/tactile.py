@@ -1,4 +1,4 @@
-"""Tactile outputs of a deformed gel pad, written out from their definitions (Taccel Sec. 3.6).
+"""Tactile outputs of a deformed gel pad, written out from their definitions (Taccel Sec. 4.2).
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg of
 the benchmark may import this module; the GPU library never does.

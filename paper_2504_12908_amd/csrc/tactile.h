@@ -1,4 +1,4 @@
-// Tactile outputs of the deformed pad (Taccel Sec. 3.6): marker positions and flows, and
+// Tactile outputs of the deformed pad (Taccel Sec. 4.2): marker positions and flows, and
 // depth / normal maps of the coated surface seen orthographically from an image plane.
 #pragma once
 #include <hip/hip_runtime.h>

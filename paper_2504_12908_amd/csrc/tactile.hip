@@ -1,4 +1,4 @@
-// Tactile outputs (Taccel Sec. 3.6).  Markers: one thread per marker.  Depth map: one
+// Tactile outputs (Taccel Sec. 4.2).  Markers: one thread per marker.  Depth map: one
 // wavefront per triangle walks the pixels of its bounding box (a scatter with 64-bit atomic
 // minima on an order-preserving key of the ray parameter, then on the triangle index), so the
 // result does not depend on the order in which wavefronts run.  The coverage and depth

@@ -1,4 +1,4 @@
-"""GPU parity of the tactile outputs (Taccel Sec. 3.6) through the C-ABI: marker positions and
+"""GPU parity of the tactile outputs (Taccel Sec. 4.2) through the C-ABI: marker positions and
 flows and depth maps bit for bit equal to the oracle's definitions on the same state (the
 coverage and depth arithmetic is FMA-free FP64 on both sides), normal maps within 1e-15."""
 import numpy as np

@@ -746,3 +746,138 @@ def test_kuhn_mesh_counts(cells, nv, nt, sv, st, se):
     assert len(verts) - len(edges) + len(bd) == 2
     vols = [np.linalg.det(X[t[1:]] - X[t[0]]) / 6 for t in T]
     assert min(vols) > 0 and sum(vols) == pytest.approx(1.0, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------- edge-edge mollifier
+def _crossing_edges(d, sin_th, la=2e-3, lb=1.6e-3):
+    """Edge a along x through the origin, edge b at height d through (0, 0, d) turned by an
+    angle with sine sin_th about z: the segments cross in projection, so the closest points
+    are interior and the distance is d."""
+    c = math.sqrt(1.0 - sin_th ** 2)
+    a0, a1 = np.array([-la / 2, 0, 0]), np.array([la / 2, 0, 0])
+    u = np.array([c, sin_th, 0.0]) * lb / 2
+    b0, b1 = np.array([0, 0, d]) - u, np.array([0, 0, d]) + u
+    return np.concatenate([a0, a1, b0, b1])
+
+
+def test_edge_edge_mollifier_closed_form(oracle_lib):
+    """Near-parallel edge-edge pairs carry IPC's mollifier m(c) = 2c/eps - c^2/eps^2 below eps
+    and 1 above, c = |(a1 - a0) x (b1 - b0)|^2 (App. A.3, the edge-edge form of the barrier
+    sum): at c = eps/4 the pair energy is 7/16 of the unmollified kappa b(d), at c = eps/2 it
+    is 3/4, at c >= eps the full value."""
+    la, lb = 2e-3, 1.6e-3
+    eps = 1e-3 * la ** 2 * lb ** 2
+    d = 0.4 * DHAT
+    b_closed = -(d - DHAT) ** 2 * math.log(d / DHAT)
+    for frac, m_expect in ((0.25, 2 * 0.25 - 0.25 ** 2), (0.5, 2 * 0.5 - 0.25), (1.0, 1.0),
+                           (3.0, 1.0)):
+        sin_th = math.sqrt(frac * eps) / (la * lb)
+        x = _crossing_edges(d, sin_th, la, lb)
+        s = oracle_lib.pair_sqdist(1, x)[0]
+        assert s == pytest.approx(d * d, rel=1e-12)
+        e, *_ = oracle_lib.pair_barrier(1, x, eps, DHAT, 1e3)
+        assert e == pytest.approx(1e3 * m_expect * b_closed, rel=1e-10), frac
+    # exactly parallel edges carry no barrier energy; the point-edge pairs take it over
+    e, *_ = oracle_lib.pair_barrier(1, _crossing_edges(d, 0.0, la, lb), eps, DHAT, 1e3)
+    assert e == 0.0
+
+
+def test_edge_edge_mollifier_uses_rest_lengths_in_scene(oracle_lib):
+    """In a scene the mollifier threshold of an edge pair is eps = 1e-3 |a_rest|^2 |b_rest|^2
+    from the rest lengths of both edges, and the barrier sum enters the incremental potential
+    as h^2 kappa sum m_k b(d_k) (Sec. 3.2 Eq. 2 with A_k = 1).  The pad is stretched by 10 %
+    in x and y (current edge lengths differ from rest), the cube is turned by 1 degree about z so its
+    bottom edges are nearly parallel to the pad's edges, and lowered to 30 um above the
+    pad: the scene's contact energy equals the sum over its active pairs evaluated with rest
+    thresholds, and differs from the sum with current-length thresholds."""
+    spec = S.pad_press_cube(0)
+    o = oracle_lib.OracleScene(spec)
+    x, v, q, qd = o.get_state()
+    x = x.copy()
+    x[:, :2] *= 1.1
+    cube0 = spec.bodies[0].verts
+    c0 = cube0.mean(axis=0)
+    phi = math.radians(1.0)
+    R = np.array([[math.cos(phi), -math.sin(phi), 0], [math.sin(phi), math.cos(phi), 0], [0, 0, 1]])
+    drop = np.array([0.0, 0.0, -(0.05e-3 - 3e-5)])
+    t = c0 - R @ c0 + drop
+    q = np.concatenate([t, R.ravel()])[None]
+    o.set_state(x, v, q, qd)
+    e_scene, *_ = o.system("contact")
+    P = o.world_positions()
+    rest = np.concatenate([spec.verts, cube0])
+    h = spec.params["h"]
+    tot_rest = tot_cur = 0.0
+    n_moll = 0
+    for kind, *w in o.candidates(P):
+        x12 = P[w].ravel()
+        s = oracle_lib.pair_sqdist(kind, x12)[0]
+        if s >= DHAT ** 2:
+            continue
+        if kind == 1:
+            eps_rest = 1e-3 * np.sum((rest[w[1]] - rest[w[0]]) ** 2) * np.sum((rest[w[3]] - rest[w[2]]) ** 2)
+            eps_cur = 1e-3 * np.sum((P[w[1]] - P[w[0]]) ** 2) * np.sum((P[w[3]] - P[w[2]]) ** 2)
+            cc = np.sum(np.cross(P[w[1]] - P[w[0]], P[w[3]] - P[w[2]]) ** 2)
+            n_moll += cc < eps_rest
+        else:
+            eps_rest = eps_cur = 0.0
+        tot_rest += oracle_lib.pair_barrier(kind, x12, eps_rest, DHAT, spec.params["kappa"])[0]
+        tot_cur += oracle_lib.pair_barrier(kind, x12, eps_cur, DHAT, spec.params["kappa"])[0]
+    assert n_moll > 0
+    assert e_scene == pytest.approx(h * h * tot_rest, rel=1e-12)
+    assert abs(h * h * tot_cur - e_scene) > 1e-4 * e_scene
+
+
+# ----------------------------------------------------------------------------- Newton system
+def _dense(blocks, nn):
+    H = np.zeros((3 * nn, 3 * nn))
+    for (r, c), b in blocks.items():
+        H[3 * r:3 * r + 3, 3 * c:3 * c + 3] += b
+    return H
+
+
+@pytest.mark.parametrize("make", [lambda: S.pad_press_cube(0), lambda: S.pad_push_moving(1, n_steps=4)])
+def test_converged_steps_are_stationary(oracle_lib, make):
+    """Sec. 3.2 Eq. 1: the new state minimises the incremental potential over the free
+    unknowns, so its gradient vanishes there.  After every converged step (prescribed bodies
+    fixed on their targets), the gradient over the free unknowns is at most 1e-6 of the largest
+    per-unknown sum of the magnitudes of the terms that balance (inertia, elasticity, body
+    orthogonality, constraint, barrier): each term is far from zero on its own, and a missing
+    term or a solve that stops short leaves a residual of the order of that term."""
+    spec = make()
+    o = oracle_lib.OracleScene(spec)
+    for k in range(spec.n_steps):
+        rc, _ = o.step(k)
+        assert rc == 0
+        _, G, _, node_of = o.system()
+        scale = np.zeros_like(G)
+        for term in ("inertia", "elastic", "body_stiffness", "constraint", "contact"):
+            scale += np.abs(o.system(term)[1])
+        assert np.abs(G).max() <= 1e-6 * scale.max(), (k, np.abs(G).max(), scale.max())
+
+
+def test_skyline_solve_matches_dense_solve(oracle_lib):
+    """The oracle's skyline Cholesky (reverse Cuthill-McKee envelope) against numpy's dense LU
+    solve of the same assembled system, at the start of steps (prescribed body free, with its
+    augmented-Lagrangian penalty) and at converged states (body fixed): backward error below
+    1e-14 and agreement to 100 eps cond(H)."""
+    spec = S.pad_press_cube(0)
+    o = oracle_lib.OracleScene(spec)
+    seen_body = False
+    for k in range(3):
+        assert o.step_begin(k) == 0
+        for when in ("start", "end"):
+            if when == "end":
+                assert o.step_finish()[0] == 0
+            _, G, B, node_of = o.system()
+            nn = len(G)
+            seen_body |= node_of[o.nv] >= 0
+            H = _dense(B, nn)
+            assert np.abs(H - H.T).max() <= 1e-14 * np.abs(H).max()
+            p = o.newton_direction().ravel()
+            pn = np.linalg.solve(H, -G.ravel())
+            backward = np.abs(H @ p + G.ravel()).max() / (np.abs(H).max() * np.abs(p).max())
+            assert backward <= 1e-14, (k, when, backward)
+            cond = np.linalg.cond(H)
+            assert np.abs(p - pn).max() <= 100 * np.finfo(float).eps * cond * np.abs(pn).max()
+    assert seen_body

@@ -1,4 +1,4 @@
-"""Pins of the tactile-output oracle (markers, depth and normal maps; Taccel Sec. 3.6) against
+"""Pins of the tactile-output oracle (markers, depth and normal maps; Taccel Sec. 4.2) against
 closed forms: rest and rigid-motion flows, flat and tilted surfaces, coverage of a
 rectangle, the nearer of two surfaces."""
 import math
