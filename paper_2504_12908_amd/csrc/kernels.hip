@@ -1358,7 +1358,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   const int blk = xcd_block(TS.nblk);
   if (blk < 0) return;
   const int s = TS.sc[blk];
-  if (V.pdone[s]) return;  // one uniform load: the blocks of converged scenes stay cheap
+  // The blocks of converged scenes stay cheap.  The scene's first block may set this flag
+  // during this launch (below), so the wave takes one value for all its lanes; a wave that
+  // still sees 0 finds the same convergence test true and returns before any barrier.
+  if (__builtin_amdgcn_readfirstlane(V.pdone[s])) return;
   const T* Prz_cur = parity ? B.P_rz1 : B.P_rz0;
   const T* Prz_old = parity ? B.P_rz0 : B.P_rz1;
   const T* pold = parity ? B.p1 : B.p0;

@@ -33,7 +33,7 @@ def build() -> str:
 
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(one, SOURCES + [os.path.join(HERE, "runtime.cpp")]))
-    subprocess.run(["g++", "-shared", "-rdynamic", "-o", LIB + ".tmp"] + objs + ["-lpthread"], check=True)
+    subprocess.run(["g++", "-shared", "-rdynamic", "-o", LIB + ".tmp"] + objs + ["-lpthread", "-ldl"], check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

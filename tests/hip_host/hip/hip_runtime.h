@@ -10,13 +10,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <type_traits>
 #include <vector>
 
 #define __global__
 #define __device__
 #define __host__
 #define __forceinline__ inline
-#define __shared__ static
+#define __shared__ static thread_local
 #define __constant__ static
 #define __launch_bounds__(...)
 
@@ -55,7 +56,7 @@ const dim3& tidx();
 const dim3& bidx();
 const dim3& bdim();
 const dim3& gdim();
-enum { OP_SHFL = 1, OP_SHFL_XOR, OP_SHFL_UP, OP_BALLOT, OP_ALL, OP_DPP, OP_READLANE, OP_SYNC, OP_WAVEBAR };
+enum { OP_SHFL = 1, OP_SHFL_XOR, OP_SHFL_UP, OP_BALLOT, OP_ALL, OP_DPP, OP_READLANE, OP_SYNC, OP_WAVEBAR, OP_READFIRST };
 uint64_t lane_op(int kind, uint64_t val, int a, int b, int c, int d, int e);
 void launch(hipStream_t s, dim3 grid, dim3 block, std::function<void()> body);
 template <class T> inline uint64_t bits(T v) { uint64_t u = 0; std::memcpy(&u, &v, sizeof(T)); return u; }
@@ -79,6 +80,7 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask,
   return (int)(uint32_t)emu::lane_op(emu::OP_DPP, ((uint64_t)(uint32_t)old << 32) | (uint32_t)src, ctrl, row_mask, bank_mask, bound ? 1 : 0, 0);
 }
 inline int __builtin_amdgcn_readlane(int v, int lane) { return (int)(uint32_t)emu::lane_op(emu::OP_READLANE, (uint32_t)v, lane, 0, 0, 0, 0); }
+inline int __builtin_amdgcn_readfirstlane(int v) { return (int)(uint32_t)emu::lane_op(emu::OP_READFIRST, (uint32_t)v, 0, 0, 0, 0, 0); }
 inline void __builtin_amdgcn_wave_barrier() { emu::lane_op(emu::OP_WAVEBAR, 0, 0, 0, 0, 0, 0); }
 inline void __syncthreads() { emu::lane_op(emu::OP_SYNC, 0, 0, 0, 0, 0, 0); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
@@ -87,10 +89,27 @@ inline double __longlong_as_double(long long v) { double d; std::memcpy(&d, &v, 
 inline int __float_as_int(float f) { int v; std::memcpy(&v, &f, 4); return v; }
 inline float __int_as_float(int v) { float f; std::memcpy(&f, &v, 4); return f; }
 
-template <class T> inline T atomicAdd(T* p, T v) { T o = *p; *p = o + v; return o; }
-template <class T> inline T atomicMin(T* p, T v) { T o = *p; if (v < o) *p = v; return o; }
-template <class T> inline T atomicMax(T* p, T v) { T o = *p; if (v > o) *p = v; return o; }
-template <class T> inline T atomicOr(T* p, T v) { T o = *p; *p = o | v; return o; }
+// Blocks of a launch run on several host threads, so atomics are real ones.
+template <class T> inline T atomicAdd(T* p, T v) {
+  if constexpr (std::is_integral<T>::value) {
+    return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+  } else {
+    T o = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (!__atomic_compare_exchange_n(p, &o, o + v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {}
+    return o;
+  }
+}
+template <class T> inline T atomicMin(T* p, T v) {
+  T o = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (v < o && !__atomic_compare_exchange_n(p, &o, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {}
+  return o;
+}
+template <class T> inline T atomicMax(T* p, T v) {
+  T o = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (v > o && !__atomic_compare_exchange_n(p, &o, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {}
+  return o;
+}
+template <class T> inline T atomicOr(T* p, T v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 
 inline int min(int a, int b) { return a < b ? a : b; }
 inline int max(int a, int b) { return a > b ? a : b; }

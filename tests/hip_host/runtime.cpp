@@ -1,15 +1,20 @@
 // Runtime of the host build: one fiber per lane (started with ucontext, switched with
-// setjmp/longjmp), wavefront exchanges between the blocked lanes of a wave, and device
-// allocations that end at a guard page and are unmapped for good when freed, so any access past
-// the end of a buffer or after its release faults at once; the fault handler names the
-// allocation the address belongs to.
+// setjmp/longjmp), wavefront exchanges between the blocked lanes of a wave, the blocks of a
+// launch spread over a pool of host threads (each runs whole blocks, with its own fibers and
+// its own copy of the workgroup-shared arrays), and device allocations that end at a guard page
+// and are unmapped for good when freed, so any access past the end of a buffer or after its
+// release faults at once; the fault handler names the allocation the address belongs to.
 #include "hip/hip_runtime.h"
 
+#include <atomic>
+#include <condition_variable>
 #include <csetjmp>
 #include <csignal>
+#include <dlfcn.h>
 #include <execinfo.h>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <sys/mman.h>
 #include <ucontext.h>
 #include <unistd.h>
@@ -31,14 +36,19 @@ struct Lane {
   int kind = 0;
   uint64_t val = 0, res = 0;
   int a = 0, b = 0, c = 0, d = 0;
+  void* ra = nullptr;  // call site of the pending wavefront operation
+  void* bt[10] = {};   // its call chain, kept when TACCEL_HOST_TRACE is set
+  int nbt = 0;
 };
-std::vector<Lane> g_lanes;
-Lane* g_cur = nullptr;
-jmp_buf g_sched;
-ucontext_t g_tmp;
-dim3 g_bidx, g_bdim, g_gdim;
-const std::function<void()>* g_body = nullptr;
-dim3 g_host_tid(0, 0, 0);
+const bool g_trace = getenv("TACCEL_HOST_TRACE") != nullptr;
+thread_local std::vector<Lane> g_lanes;
+thread_local Lane* g_cur = nullptr;
+thread_local jmp_buf g_sched;
+thread_local ucontext_t g_tmp;
+thread_local dim3 g_bidx;
+dim3 g_bdim, g_gdim;
+thread_local const std::function<void()>* g_body = nullptr;
+const dim3 g_host_tid(0, 0, 0);
 
 void trampoline() {
   Lane* L = g_cur;
@@ -55,6 +65,26 @@ void resume(Lane* L) {
 
 [[noreturn]] void die(const char* m) {
   fprintf(stderr, "host build FATAL: %s\n", m);
+  fflush(stderr);
+  abort();
+}
+
+// A wavefront operation that the wave's lanes do not meet together: name every lane's state
+// and the function it waits in, then stop.
+[[noreturn]] void die_wave(const char* m, const Lane* any) {
+  fprintf(stderr, "host build FATAL: %s (block %u,%u,%u)\n", m, g_bidx.x, g_bidx.y, g_bidx.z);
+  const int w0 = any->t & ~63;
+  for (int i = w0; i < std::min<int>((int)g_lanes.size(), w0 + 64); ++i) {
+    const Lane& L = g_lanes[i];
+    Dl_info info{};
+    const bool found = L.ra && dladdr(L.ra, &info);
+    const char* fn = found && info.dli_sname ? info.dli_sname : "?";
+    const long off = found ? (long)((char*)L.ra - (char*)info.dli_fbase) : 0;
+    fprintf(stderr, "  lane %d: done=%d kind=%d a=%d in %s (+0x%lx)", i & 63, (int)L.done, L.kind, L.a, fn, off);
+    for (int k = 1; k < L.nbt; ++k)
+      if (dladdr(L.bt[k], &info)) fprintf(stderr, " <- +0x%lx", (long)((char*)L.bt[k] - (char*)info.dli_fbase));
+    fprintf(stderr, "\n");
+  }
   fflush(stderr);
   abort();
 }
@@ -82,10 +112,17 @@ void resolve_group(std::vector<Lane*>& grp) {
       if (kind == OP_SHFL) src = seg + (L->a & (w - 1));
       else if (kind == OP_SHFL_XOR) src = lane ^ L->a;
       else src = lane - L->a;
-      if (src < seg || src >= seg + w || !by_lane[src]) L->res = L->val;
+      // a source outside the segment reads the lane's own value; an inactive source lane
+      // holds no defined value on the hardware, so reading one is a bug
+      if (src < seg || src >= seg + w) L->res = L->val;
+      else if (!by_lane[src]) die_wave("shuffle reads an inactive lane", L);
       else L->res = by_lane[src]->val;
+    } else if (kind == OP_READFIRST) {
+      int first = 0;
+      while (!by_lane[first]) ++first;
+      L->res = by_lane[first]->val & 0xffffffffull;
     } else if (kind == OP_READLANE) {
-      if (!by_lane[L->a]) die("readlane of an inactive lane");
+      if (!by_lane[L->a]) die_wave("readlane of an inactive lane", L);
       L->res = by_lane[L->a]->val & 0xffffffffull;
     } else if (kind == OP_DPP) {
       const uint32_t old = (uint32_t)(L->val >> 32);
@@ -110,7 +147,7 @@ void resolve_group(std::vector<Lane*>& grp) {
       if (src < 0) {
         L->res = bound ? 0 : old;
       } else if (!by_lane[src]) {
-        die("DPP reads an inactive lane");
+        die_wave("DPP reads an inactive lane", L);
       } else {
         L->res = by_lane[src]->val & 0xffffffffull;
       }
@@ -151,7 +188,7 @@ void run_block(const std::function<void()>& body) {
       {
         Lane* first = nullptr;
         bool same = true, any_sync = false;
-        static std::vector<Lane*> grp;
+        static thread_local std::vector<Lane*> grp;
         grp.clear();
         for (int i = 64 * w; i < std::min(n, 64 * w + 64); ++i) {
           Lane& L = g_lanes[i];
@@ -211,20 +248,87 @@ uint64_t lane_op(int kind, uint64_t val, int a, int b, int c, int d, int e) {
   L->kind = kind;
   L->val = val;
   L->a = a; L->b = b; L->c = c; L->d = d;
+  L->ra = __builtin_return_address(0);
+  if (g_trace) L->nbt = backtrace(L->bt, 10);
   L->blocked = true;
   if (_setjmp(L->ctx) == 0) _longjmp(g_sched, 1);
   return L->res;
 }
 
+// Blocks of one launch are taken in turn by the calling thread and the pool's workers.
+struct Pool {
+  std::mutex m;
+  std::condition_variable cv, done_cv;
+  std::vector<std::thread> workers;
+  uint64_t gen = 0;
+  int busy = 0;
+  std::atomic<long long> next{0};
+  long long nblocks = 0;
+  const std::function<void()>* body = nullptr;
+  dim3 grid;
+
+  static int size() {
+    const char* e = getenv("TACCEL_HOST_THREADS");
+    int n = e ? atoi(e) : (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(n, 64));
+  }
+  void work() {
+    for (long long i; (i = next.fetch_add(1)) < nblocks;) {
+      g_bidx = dim3((unsigned)(i % grid.x), (unsigned)((i / grid.x) % grid.y),
+                    (unsigned)(i / ((long long)grid.x * grid.y)));
+      run_block(*body);
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return gen != seen; });
+        seen = gen;
+      }
+      work();
+      std::lock_guard<std::mutex> lk(m);
+      if (--busy == 0) done_cv.notify_all();
+    }
+  }
+  void run(dim3 g, const std::function<void()>& b) {
+    const long long n = (long long)g.x * g.y * g.z;
+    if (workers.empty()) {
+      const int k = size() - 1;
+      for (int i = 0; i < k; ++i) {
+        workers.emplace_back([this] { loop(); });
+        workers.back().detach();
+      }
+    }
+    if (n <= 1 || workers.empty()) {
+      for (long long i = 0; i < n; ++i) {
+        g_bidx = dim3((unsigned)(i % g.x), (unsigned)((i / g.x) % g.y), (unsigned)(i / ((long long)g.x * g.y)));
+        run_block(b);
+      }
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(m);
+      grid = g;
+      body = &b;
+      nblocks = n;
+      next = 0;
+      busy = (int)workers.size();
+      ++gen;
+    }
+    cv.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(m);
+    done_cv.wait(lk, [&] { return busy == 0; });
+  }
+};
+Pool& g_pool = *new Pool;  // never destroyed: its detached workers wait on it until exit
+
 static void run_grid(dim3 grid, dim3 block, const std::function<void()>& body) {
   g_gdim = grid;
   g_bdim = block;
-  for (unsigned z = 0; z < grid.z; ++z)
-    for (unsigned y = 0; y < grid.y; ++y)
-      for (unsigned x = 0; x < grid.x; ++x) {
-        g_bidx = dim3(x, y, z);
-        run_block(body);
-      }
+  g_pool.run(grid, body);
 }
 
 // Kernels of host threads that share the runtime (the server's cohorts) run one at a time.
