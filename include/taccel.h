@@ -132,7 +132,16 @@ typedef enum {
   TACCEL_FIELD_V = 1,    /* double[nv][3] soft-vertex velocities */
   TACCEL_FIELD_Q = 2,    /* double[n_bodies][12] body maps (t, A row-major) of creation pose */
   TACCEL_FIELD_QDOT = 3, /* double[n_bodies][12] their rates */
-  TACCEL_FIELD_BODY_X = 4 /* double[sum body nv][3] body vertex world positions (read only) */
+  TACCEL_FIELD_BODY_X = 4, /* double[sum body nv][3] body vertex world positions (read only) */
+  TACCEL_FIELD_CONTACTS = 5, /* int32[n_active][5] (read only): the contact pairs closer than
+                            dhat at the current positions (Sec. 3.2 Eq. 2: the active set of
+                            the barrier sum), each as kind (0 point-triangle, 1 edge-edge) and
+                            four world vertex ids (soft vertices 0..nv-1, then the body
+                            vertices in order) in the order of taccel_debug_candidates, the
+                            records sorted.  Its size changes with the state: ask
+                            taccel_state_bytes first. */
+  TACCEL_FIELD_STATS = 6 /* taccel_step_stats of the scene's last step (read only; zeros
+                            before the first step and after a reset) */
 } taccel_field;
 
 typedef struct taccel_scene taccel_scene;
@@ -154,6 +163,16 @@ taccel_status taccel_state_read(const taccel_scene* s, taccel_field f, void* dst
  * the next as a starting guess, are cleared by a write of Q and by a failed step. */
 taccel_status taccel_state_write(taccel_scene* s, taccel_field f, const void* src, size_t bytes);
 void taccel_scene_destroy(taccel_scene* s);
+/* Current size in bytes of a field (CONTACTS: computed from the current positions). */
+taccel_status taccel_state_bytes(const taccel_scene* s, taccel_field f, size_t* bytes);
+/* Device-pointer variant of taccel_state_read: writes the same bytes to device memory dst
+ * (on this scene's device), in an operation ordered on the scene's stream, and returns after
+ * it completes.  Fields X, V, Q, QDOT and BODY_X; ARG for a size mismatch or another field. */
+taccel_status taccel_state_read_device(const taccel_scene* s, taccel_field f, void* dst,
+                                       size_t bytes);
+/* Back to the creation state (the paper's API resets environments, Sec. 4.3): rest positions,
+ * zero velocities, every body at its creation pose at rest, multipliers cleared, STATS zero. */
+taccel_status taccel_scene_reset(taccel_scene* s);
 
 /* n independent scenes solved together: every stage is one launch over all scenes,
  * reductions are per scene, a scene that fails is rolled back without affecting others. */
@@ -167,6 +186,12 @@ taccel_status taccel_batch_read(const taccel_batch* b, int32_t scene, taccel_fie
                                 size_t bytes);
 taccel_status taccel_batch_write(taccel_batch* b, int32_t scene, taccel_field f, const void* src,
                                  size_t bytes);
+taccel_status taccel_batch_state_bytes(const taccel_batch* b, int32_t scene, taccel_field f,
+                                      size_t* bytes);
+taccel_status taccel_batch_read_device(const taccel_batch* b, int32_t scene, taccel_field f,
+                                       void* dst, size_t bytes);
+/* taccel_scene_reset for the scenes with mask[k] != 0 ([n] host bytes; NULL: all scenes). */
+taccel_status taccel_batch_reset(taccel_batch* b, const uint8_t* mask);
 void taccel_batch_destroy(taccel_batch* b);
 
 /* ---- Tactile outputs of the current state (Taccel Sec. 4.2) ----------------------------

@@ -72,6 +72,7 @@ def lib():
         L.orc_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_world_positions.argtypes = [C.c_void_p, _dp]
         L.orc_ls_log.argtypes = [C.c_void_p, _dp, C.c_int32]
+        L.orc_newton_log.argtypes = [C.c_void_p, _dp, C.c_int32]
         L.orc_candidates.argtypes = [C.c_void_p, _dp, _dp, _ip, C.c_int32]
         L.orc_nh_tet.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
         L.orc_pair_barrier.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, C.c_double,
@@ -254,6 +255,14 @@ class OracleScene:
         out = np.zeros(max(n, 1))
         lib().orc_ls_log(self.h, _d(out), n)
         return out[:n].reshape(-1, 2)
+
+    def newton_log(self):
+        """Per Newton iteration of the last step: (AL round, iteration, max |p|, CCD bound,
+        step size, active pairs, max kappa_A, max body residual)."""
+        n = lib().orc_newton_log(self.h, None, 0)
+        out = np.zeros(max(n, 1))
+        lib().orc_newton_log(self.h, _d(out), n)
+        return out[:n].reshape(-1, 8)
 
     def candidates(self, P0, P1=None):
         P0 = _f64(P0)

@@ -842,7 +842,10 @@ struct Scene {
   vector<FPair> fric;
   // diagnostics
   vector<double> ls_log;
+  vector<double> it_log;  // per Newton iteration of the last step, kItLog values each
+  int al_round = 0;
 };
+constexpr int kItLog = 8;
 
 static void world_positions(const Scene& S, vector<V3>& P) {
   P.resize(S.nw);
@@ -1225,6 +1228,8 @@ static double min_ccd(const Scene& S, const vector<V3>& P0, const vector<V3>& di
 enum { kOk = 0, kNotConverged = 3, kLineSearchFailed = 4, kALFailed = 5, kNaN = 6, kInfeasible = 7 };
 
 // One Newton loop on the current constraint set.  Returns a status and counts iterations.
+static double body_residual(const Body& b);
+
 static int newton_loop(Scene& S, int* iters) {
   const Dofs D = make_dofs(S);
   vector<Pair> cand, active, swept;
@@ -1281,6 +1286,17 @@ static int newton_loop(Scene& S, int* iters) {
       }
     }
     apply_step(S, D, p, alpha);
+    {
+      double kap = 0.0, res = 0.0;
+      for (const Body& b : S.bodies)
+        if (b.prescribed && !b.snapped) {
+          kap = std::max(kap, b.kappaA);
+          res = std::max(res, body_residual(b));
+        }
+      const double row[kItLog] = {(double)S.al_round, (double)it, pmax, amax, alpha,
+                                  (double)active.size(), kap, res};
+      S.it_log.insert(S.it_log.end(), row, row + kItLog);
+    }
     if (last) return kOk;
   }
   return kNotConverged;
@@ -1468,8 +1484,10 @@ static int step_begin(Scene& S, const double* body_targets, const double* dir_ta
 static int step_finish(Scene& S, orc_stats* st) {
   const double h = S.h;
   int iters = 0, rounds = 0, status = kOk;
+  S.it_log.clear();
   for (;;) {
     ++rounds;
+    S.al_round = rounds;
     status = newton_loop(S, &iters);
     if (status != kOk) break;
     bool pending = false;
@@ -1777,6 +1795,13 @@ void orc_world_positions(const void* s, double* out) {
   for (int w = 0; w < S.nw; ++w)
     for (int c = 0; c < 3; ++c) out[3 * w + c] = P[w][c];
 }
+int32_t orc_newton_log(const void* s, double* out, int32_t cap) {
+  const Scene& S = *static_cast<const Scene*>(s);
+  const int n = (int)S.it_log.size();
+  for (int k = 0; k < n && k < cap; ++k) out[k] = S.it_log[k];
+  return n;
+}
+
 int32_t orc_ls_log(const void* s, double* out, int32_t cap) {
   const Scene& S = *static_cast<const Scene*>(s);
   const int n = (int)S.ls_log.size();

@@ -88,6 +88,11 @@ void orc_set_state(void* s, const double* x, const double* v, const double* q,
                    const double* qd);
 /* World positions of all contact-capable vertices: soft vertices, then body vertices. */
 void orc_world_positions(const void* s, double* out);
+/* Newton log of the last step: 8 values per Newton iteration (augmented-Lagrangian round
+ * from 1, iteration within its loop, max vertex displacement of the direction, CCD bound,
+ * accepted step size, active pairs, largest kappa_A and body residual over the prescribed
+ * bodies not yet snapped, after the update).  Returns the number of values. */
+int32_t orc_newton_log(const void* s, double* out, int32_t cap);
 /* Line-search log of the last step: pairs (E(z), E(z+alpha p)) for each Newton update. */
 int32_t orc_ls_log(const void* s, double* out, int32_t cap);
 

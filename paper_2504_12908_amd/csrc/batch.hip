@@ -215,6 +215,7 @@ struct Batch::Impl {
   bool xn_valid = false;       // xn holds the positions at the start of the current step
   std::vector<int> act_host;   // host copy of act for the current Newton iteration
   int pcg_last_max = 0;        // largest PCG iteration count of the previous solve
+  std::vector<taccel_step_stats> last_stats;  // per scene: statistics of its last step
   bool validate_only = false;  // build() stops after the host-side checks
   int mixed = 0;  // 1: FP32 Hessian blocks, assembly, SpMV and PCG (taccel_precision MIXED)
   // dynamic work buffers
@@ -261,6 +262,7 @@ struct Batch::Impl {
     return F;
   }
   void build_friction(const int* mask);
+  std::vector<int32_t> contacts(int k);
   // tactile outputs: rest positions of every node and work buffers
   DBuf<double> xrest, tac_bary, tac_pos, tac_flow, tac_depth, tac_normal;
   DBuf<int> tac_nodes, tac_zidx;
@@ -451,6 +453,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   S = n;
   hs.resize(S);
   hsc.resize(S);
+  last_stats.assign(S, taccel_step_stats{});
   std::vector<double> h_x, h_mass, h_Dminv_aos, h_tvol;
   std::vector<int> h_nfree, h_nbody, h_tv_aos, h_tscene;
   std::vector<int> h_bcv0, h_bcv1;
@@ -1317,6 +1320,37 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d
 // Friction pairs of the step (Taccel App. A.3): every pair closer than dhat at the
 // start-of-step positions in a scene with friction, with its lagged closest-point weights,
 // normal and mu * lambda, grouped by scene.
+// Pairs of scene k closer than dhat at the current positions (broad and narrow phase on the
+// device), as 5-int records in the caller's world vertex ids, sorted.
+std::vector<int32_t> Batch::Impl::contacts(int k) {
+  hipStream_t s = stream();
+  View V = view();
+  std::vector<int> on(S, 0);
+  on[k] = 1;
+  h2d(act.p, on.data(), S);
+  launch_cpos(V, s);
+  const int nc = broad_phase(cpos.p, nullptr, 0, cq, ct);
+  cflag.ensure(&mem, std::max(nc, 1));
+  cpos_idx.ensure(&mem, std::max(nc, 1));
+  launch_narrow(V, nc, cq.p, ct.p, cflag.p, s);
+  const int np = scan(cflag.p, cpos_idx.p, nc);
+  DBuf<int> rec;
+  rec.ensure(&mem, 5 * (size_t)std::max(np, 1));
+  launch_contact_records(V, nc, cq.p, ct.p, cflag.p, cpos_idx.p, rec.p, s);
+  std::vector<int32_t> out(5 * (size_t)np);
+  d2h(out.data(), rec.p, out.size());
+  sync();
+  rec.free();
+  cover_valid = false;
+  std::vector<std::array<int32_t, 5>> r(np);
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < 5; ++j) r[i][j] = out[5 * (size_t)i + j];
+  std::sort(r.begin(), r.end());
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < 5; ++j) out[5 * (size_t)i + j] = r[i][j];
+  return out;
+}
+
 void Batch::Impl::build_friction(const int* mask) {
   hipStream_t s = stream();
   std::vector<int> on(S, 0);
@@ -1927,6 +1961,16 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       stats[k].step_ms = ms;
     }
     if (status[k] != TACCEL_OK && first_bad == TACCEL_OK) first_bad = (taccel_status)status[k];
+    if (!mask || mask[k]) {
+      taccel_step_stats& ls = last_stats[k];
+      ls.status = status[k];
+      ls.newton_iters = tot_nit[k];
+      ls.al_rounds = rounds[k];
+      ls.pcg_iters = tot_pcg[k];
+      ls.n_active = nact_last[k];
+      ls.ls_halvings = tot_halv[k];
+      ls.step_ms = ms;
+    }
   }
   return first_bad;
 }
@@ -2100,6 +2144,7 @@ static size_t field_count(const Batch::Impl& I, int k, taccel_field f) {
       for (const auto& b : H.bodies) n += 3 * (size_t)b.nv;
       return n;
     }
+    default: break;
   }
   return 0;
 }
@@ -2108,6 +2153,21 @@ taccel_status Batch::read(int k, taccel_field f, void* dst, size_t bytes) {
   try {
     Impl& I = *impl_;
     if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    if (f == TACCEL_FIELD_STATS) {
+      if (bytes != sizeof(taccel_step_stats) || !dst)
+        throw ApiError(TACCEL_ERR_ARG, "state_read: STATS takes one taccel_step_stats");
+      std::memcpy(dst, &I.last_stats[k], sizeof(taccel_step_stats));
+      return TACCEL_OK;
+    }
+    if (f == TACCEL_FIELD_CONTACTS) {
+      const std::vector<int32_t> c = I.contacts(k);
+      if (bytes != c.size() * sizeof(int32_t) || (!c.empty() && !dst))
+        throw ApiError(TACCEL_ERR_ARG, "state_read: size mismatch (expected " +
+                                           std::to_string(c.size() * sizeof(int32_t)) + " bytes)");
+      if (!c.empty()) std::memcpy(dst, c.data(), bytes);
+      return TACCEL_OK;
+    }
+    if (f < TACCEL_FIELD_X || f > TACCEL_FIELD_BODY_X) throw ApiError(TACCEL_ERR_ARG, "unknown field");
     const size_t cnt = field_count(I, k, f);
     if (bytes != cnt * sizeof(double) || (cnt && !dst))
       throw ApiError(TACCEL_ERR_ARG, "state_read: size mismatch (expected " + std::to_string(cnt * 8) + " bytes)");
@@ -2157,11 +2217,116 @@ taccel_status Batch::read(int k, taccel_field f, void* dst, size_t bytes) {
   }
 }
 
+taccel_status Batch::field_bytes(int k, taccel_field f, size_t* bytes) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    if (!bytes) throw ApiError(TACCEL_ERR_ARG, "state_bytes: NULL output");
+    if (f == TACCEL_FIELD_STATS) *bytes = sizeof(taccel_step_stats);
+    else if (f == TACCEL_FIELD_CONTACTS) *bytes = I.contacts(k).size() * sizeof(int32_t);
+    else if (f >= TACCEL_FIELD_X && f <= TACCEL_FIELD_BODY_X) *bytes = field_count(I, k, f) * sizeof(double);
+    else throw ApiError(TACCEL_ERR_ARG, "unknown field");
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
+
+taccel_status Batch::read_device(int k, taccel_field f, void* dst, size_t bytes) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    if (f < TACCEL_FIELD_X || f > TACCEL_FIELD_BODY_X)
+      throw ApiError(TACCEL_ERR_ARG, "read_device: fields X, V, Q, QDOT and BODY_X only");
+    const size_t cnt = field_count(I, k, f);
+    if (bytes != cnt * sizeof(double) || (cnt && !dst))
+      throw ApiError(TACCEL_ERR_ARG, "read_device: size mismatch (expected " + std::to_string(cnt * 8) + " bytes)");
+    if (cnt == 0) return TACCEL_OK;
+    const HostScene& H = I.hs[k];
+    hipStream_t s = I.stream();
+    double* out = static_cast<double*>(dst);
+    DBuf<int> idx;
+    DBuf<double> com;
+    if (f == TACCEL_FIELD_X || f == TACCEL_FIELD_V || f == TACCEL_FIELD_BODY_X) {
+      std::vector<int> h;
+      if (f == TACCEL_FIELD_BODY_X) {
+        // body vertices in world order -> their contact vertices
+        std::vector<int> cv_of(H.cv_world.size() + (size_t)H.nv, -1);
+        for (size_t li = 0; li < H.cv_world.size(); ++li) {
+          const int w = H.cv_world[li];
+          if (w >= H.nv) cv_of[w - H.nv] = H.cv0 + (int)li;
+        }
+        for (size_t i = 0; i < cnt / 3; ++i) {
+          if (cv_of[i] < 0) throw ApiError(TACCEL_ERR_ARG, "read_device: body vertex without contact vertex");
+          h.push_back(cv_of[i]);
+        }
+        launch_cpos(I.view(), s);
+      } else {
+        for (int u = 0; u < H.nv; ++u) h.push_back(H.node0 + H.perm[u]);
+      }
+      idx.upload(&I.mem, h);
+      const double* src = f == TACCEL_FIELD_X ? I.x.p : f == TACCEL_FIELD_V ? I.v.p : I.cpos.p;
+      launch_gather3((int)h.size(), idx.p, src, out, s);
+    } else {
+      std::vector<double> c0(3 * (size_t)H.nb);
+      for (int b = 0; b < H.nb; ++b)
+        for (int j = 0; j < 3; ++j) c0[3 * b + j] = H.bodies[b].com0[j];
+      com.upload(&I.mem, c0);
+      const int n_soft_pad = (H.nv + 3) / 4 * 4;
+      const double* y = (f == TACCEL_FIELD_QDOT ? I.v.p : I.x.p) + 3 * (size_t)(H.node0 + n_soft_pad);
+      launch_body_public(H.nb, y, com.p, out, s);
+    }
+    I.sync();
+    idx.free();
+    com.free();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
+
+taccel_status Batch::reset(const uint8_t* mask) {
+  try {
+    Impl& I = *impl_;
+    hipStream_t s = I.stream();
+    // runs of consecutive selected scenes are contiguous in the node and body arrays
+    for (int k = 0; k < S_;) {
+      if (mask && !mask[k]) {
+        ++k;
+        continue;
+      }
+      int e = k;
+      while (e + 1 < S_ && (!mask || mask[e + 1])) ++e;
+      const size_t n0 = I.hs[k].node0, n1 = I.hs[e].node1;
+      HIPCHECK(hipMemcpyAsync(I.x.p + 3 * n0, I.xrest.p + 3 * n0, sizeof(double) * 3 * (n1 - n0),
+                              hipMemcpyDeviceToDevice, s));
+      I.zero(I.v.p + 3 * n0, sizeof(double) * 3 * (n1 - n0));
+      const size_t b0 = I.hsc[k].body0, b1 = I.hsc[e].body1;
+      if (b1 > b0) I.zero(I.blam.p + 12 * b0, sizeof(double) * 12 * (b1 - b0));
+      for (int j = k; j <= e; ++j) I.last_stats[j] = taccel_step_stats{};
+      k = e + 1;
+    }
+    I.cover_valid = false;
+    I.sync();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
+
 taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes) {
   try {
     Impl& I = *impl_;
     if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
-    if (f == TACCEL_FIELD_BODY_X) throw ApiError(TACCEL_ERR_ARG, "BODY_X is read-only");
+    if (f == TACCEL_FIELD_BODY_X || f == TACCEL_FIELD_CONTACTS || f == TACCEL_FIELD_STATS)
+      throw ApiError(TACCEL_ERR_ARG, "field is read-only");
+    if (f < TACCEL_FIELD_X || f > TACCEL_FIELD_BODY_X) throw ApiError(TACCEL_ERR_ARG, "unknown field");
     const size_t cnt = field_count(I, k, f);
     if (bytes != cnt * sizeof(double) || (cnt && !src)) throw ApiError(TACCEL_ERR_ARG, "state_write: size mismatch");
     const HostScene& H = I.hs[k];

@@ -108,6 +108,22 @@ taccel_status taccel_batch_write(taccel_batch* b, int32_t scene, taccel_field f,
   return b->b->write(scene, f, src, bytes);
 }
 
+taccel_status taccel_batch_state_bytes(const taccel_batch* b, int32_t scene, taccel_field f, size_t* bytes) {
+  if (!b) return fail(TACCEL_ERR_ARG, "batch_state_bytes: NULL batch");
+  return b->b->field_bytes(scene, f, bytes);
+}
+
+taccel_status taccel_batch_read_device(const taccel_batch* b, int32_t scene, taccel_field f, void* dst,
+                                       size_t bytes) {
+  if (!b) return fail(TACCEL_ERR_ARG, "batch_read_device: NULL batch");
+  return b->b->read_device(scene, f, dst, bytes);
+}
+
+taccel_status taccel_batch_reset(taccel_batch* b, const uint8_t* mask) {
+  if (!b) return fail(TACCEL_ERR_ARG, "batch_reset: NULL batch");
+  return b->b->reset(mask);
+}
+
 void taccel_batch_destroy(taccel_batch* b) {
   if (!b) return;
   delete b->b;
@@ -167,6 +183,21 @@ taccel_status taccel_state_read(const taccel_scene* s, taccel_field f, void* dst
 taccel_status taccel_state_write(taccel_scene* s, taccel_field f, const void* src, size_t bytes) {
   if (!s) return fail(TACCEL_ERR_ARG, "state_write: NULL scene");
   return s->b->write(0, f, src, bytes);
+}
+
+taccel_status taccel_state_bytes(const taccel_scene* s, taccel_field f, size_t* bytes) {
+  if (!s) return fail(TACCEL_ERR_ARG, "state_bytes: NULL scene");
+  return s->b->field_bytes(0, f, bytes);
+}
+
+taccel_status taccel_state_read_device(const taccel_scene* s, taccel_field f, void* dst, size_t bytes) {
+  if (!s) return fail(TACCEL_ERR_ARG, "state_read_device: NULL scene");
+  return s->b->read_device(0, f, dst, bytes);
+}
+
+taccel_status taccel_scene_reset(taccel_scene* s) {
+  if (!s) return fail(TACCEL_ERR_ARG, "scene_reset: NULL scene");
+  return s->b->reset(nullptr);
 }
 
 void taccel_scene_destroy(taccel_scene* s) {

@@ -70,6 +70,10 @@ void launch_compact_pairs(const View& V, int n, const int* cand_q, const int* ca
                           int* pscene, hipStream_t s);
 
 // element derivatives
+void launch_contact_records(const View& V, int n, const int* cand_q, const int* cand_t,
+                            const int* flag, const int* pos, int* out, hipStream_t s);
+void launch_gather3(int n, const int* idx, const double* src, double* out, hipStream_t s);
+void launch_body_public(int nb, const double* y, const double* com0, double* out, hipStream_t s);
 void launch_count_scene(int n, const int* pscene, int* cnt, hipStream_t s);
 void launch_fem_hess(const View& V, int mixed, hipStream_t s);
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,

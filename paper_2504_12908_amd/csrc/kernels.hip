@@ -498,6 +498,55 @@ __global__ void k_compact_pairs(View V, int n, const int* cq, const int* ct, con
   pscene[o] = V.qscene[cq[k]];
 }
 
+// Active pairs as records of the caller's world vertex ids: kind, then PT: point and sorted
+// triangle; EE: both edges sorted, the lexicographically smaller edge first.
+__global__ void k_contact_records(View V, int n, const int* cq, const int* ct, const int* flag,
+                                  const int* pos, int* out) {
+  const int k = gid();
+  if (k >= n || !flag[k]) return;
+  int ids[4];
+  const int kind = cand_verts(V, cq[k], ct[k], ids);
+  int w[4];
+  for (int v = 0; v < 4; ++v) w[v] = V.cvworld[ids[v]];
+  if (kind == 0) {
+    if (w[1] > w[2]) { const int t = w[1]; w[1] = w[2]; w[2] = t; }
+    if (w[2] > w[3]) { const int t = w[2]; w[2] = w[3]; w[3] = t; }
+    if (w[1] > w[2]) { const int t = w[1]; w[1] = w[2]; w[2] = t; }
+  } else {
+    if (w[0] > w[1]) { const int t = w[0]; w[0] = w[1]; w[1] = t; }
+    if (w[2] > w[3]) { const int t = w[2]; w[2] = w[3]; w[3] = t; }
+    if (w[2] < w[0] || (w[2] == w[0] && w[3] < w[1])) {
+      int t = w[0]; w[0] = w[2]; w[2] = t;
+      t = w[1]; w[1] = w[3]; w[3] = t;
+    }
+  }
+  int* o = out + 5 * (size_t)pos[k];
+  o[0] = kind;
+  for (int v = 0; v < 4; ++v) o[1 + v] = w[v];
+}
+
+// Readout into caller device memory: out[i] = src[idx[i]] for 3-vectors, and affine-body
+// states y = [p; c1; c2; c3] (p at the centre of mass com0) turned into the public map
+// q = (t = p - A com0, A row-major) of creation-pose vertices (for rates the same linear map).
+__global__ void k_gather3(int n, const int* idx, const double* src, double* out) {
+  const int i = gid();
+  if (i >= n) return;
+  const int j = idx[i];
+  for (int c = 0; c < 3; ++c) out[3 * (size_t)i + c] = src[3 * (size_t)j + c];
+}
+__global__ void k_body_public(int nb, const double* y, const double* com0, double* out) {
+  const int b = gid();
+  if (b >= nb) return;
+  const double* yb = y + 12 * (size_t)b;
+  double* q = out + 12 * (size_t)b;
+  for (int i = 0; i < 3; ++i) {
+    double acc = yb[i];
+    for (int j = 0; j < 3; ++j) acc -= yb[3 + 3 * j + i] * com0[3 * b + j];
+    q[i] = acc;
+    for (int j = 0; j < 3; ++j) q[3 + 3 * i + j] = yb[3 + 3 * j + i];
+  }
+}
+
 // ------------------------------------------------------------------ FEM (4 lanes per tet)
 template <class T>
 __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
@@ -2218,6 +2267,16 @@ void launch_compact_pairs(const View& V, int n, const int* cq, const int* ct, co
                           const int* pos, int* pkind, int* pv, double* pmeps, int* pscene,
                           hipStream_t s) {
   LAUNCH(k_compact_pairs, n, TPB, s, V, n, cq, ct, flag, pos, pkind, pv, pmeps, pscene);
+}
+void launch_contact_records(const View& V, int n, const int* cq, const int* ct, const int* flag,
+                            const int* pos, int* out, hipStream_t s) {
+  LAUNCH(k_contact_records, n, TPB, s, V, n, cq, ct, flag, pos, out);
+}
+void launch_gather3(int n, const int* idx, const double* src, double* out, hipStream_t s) {
+  LAUNCH(k_gather3, n, TPB, s, n, idx, src, out);
+}
+void launch_body_public(int nb, const double* y, const double* com0, double* out, hipStream_t s) {
+  LAUNCH(k_body_public, nb, 64, s, nb, y, com0, out);
 }
 void launch_count_scene(int n, const int* pscene, int* cnt, hipStream_t s) {
   LAUNCH(k_count_scene, n, TPB, s, n, pscene, cnt);

@@ -101,6 +101,10 @@ class Batch {
   size_t device_bytes() const;
   taccel_status read(int scene, taccel_field f, void* dst, size_t bytes);
   taccel_status write(int scene, taccel_field f, const void* src, size_t bytes);
+  taccel_status field_bytes(int scene, taccel_field f, size_t* bytes);
+  taccel_status read_device(int scene, taccel_field f, void* dst, size_t bytes);
+  // creation state for the scenes with mask[k] != 0 (all when mask is NULL)
+  taccel_status reset(const uint8_t* mask);
   taccel_status debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
                                  int32_t* n);
   taccel_status markers(int scene, int m, const int32_t* tris, const double* bary, double* pos,

@@ -20,7 +20,7 @@ _ip = C.POINTER(C.c_int32)
 OK, ERR_ARG, ERR_HIP, NOT_CONVERGED, LINESEARCH_FAILED, AL_FAILED, NAN, INFEASIBLE_TARGET, \
     ERR_OOM, INFEASIBLE, CANCELLED = range(11)
 FP64, MIXED = 0, 1
-FIELD_X, FIELD_V, FIELD_Q, FIELD_QDOT, FIELD_BODY_X = range(5)
+FIELD_X, FIELD_V, FIELD_Q, FIELD_QDOT, FIELD_BODY_X, FIELD_CONTACTS, FIELD_STATS = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_HIP", "NOT_CONVERGED", "LINESEARCH_FAILED", "AL_FAILED",
                 "NAN", "INFEASIBLE_TARGET", "ERR_OOM", "INFEASIBLE", "CANCELLED"]
 
@@ -145,6 +145,13 @@ def lib():
         L.taccel_batch_read.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_size_t]
         L.taccel_batch_write.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_size_t]
         L.taccel_batch_destroy.argtypes = [C.c_void_p]
+        L.taccel_state_bytes.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]
+        L.taccel_batch_state_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.POINTER(C.c_size_t)]
+        L.taccel_state_read_device.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]
+        L.taccel_batch_read_device.argtypes = [C.c_void_p, C.c_int32, C.c_int, C.c_void_p,
+                                               C.c_size_t]
+        L.taccel_scene_reset.argtypes = [C.c_void_p]
+        L.taccel_batch_reset.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
         L.taccel_debug_fem.argtypes = [C.c_int32, _dp, _dp, C.c_double, C.c_double, _dp, _dp,
                                        _dp, _dp]
         L.taccel_debug_barrier.argtypes = [C.c_int32, _ip, _dp, _dp, C.c_double, C.c_double,
@@ -281,6 +288,15 @@ def _field_shape(desc, field):
     return (sum(desc.body_nv), 3)
 
 
+def _read_contacts(bytes_fn, read_fn, head):
+    nb = C.c_size_t()
+    _check(bytes_fn(*head, FIELD_CONTACTS, C.byref(nb)), "state_bytes")
+    out = np.zeros((nb.value // 20, 5), dtype=np.int32)
+    _check(read_fn(*head, FIELD_CONTACTS, out.ctypes.data if out.size else None, nb.value),
+           "state_read")
+    return out
+
+
 class Scene:
     """One scene on the GPU (taccel_scene_*)."""
 
@@ -319,6 +335,28 @@ class Scene:
     def get_state(self):
         return (self.read(FIELD_X), self.read(FIELD_V), self.read(FIELD_Q),
                 self.read(FIELD_QDOT))
+
+    def contacts(self):
+        """Pairs closer than dhat at the current positions: (n, 5) int32 records."""
+        return _read_contacts(lib().taccel_state_bytes, lib().taccel_state_read, (self.h,))
+
+    def stats(self):
+        """taccel_step_stats of the last step (FIELD_STATS)."""
+        st = taccel_step_stats()
+        _check(lib().taccel_state_read(self.h, FIELD_STATS, C.addressof(st), C.sizeof(st)),
+               "state_read")
+        return st.as_dict()
+
+    def read_device(self, field, ptr, nbytes):
+        """Write a field to device memory at address ptr (taccel_state_read_device)."""
+        _check(lib().taccel_state_read_device(self.h, field, C.c_void_p(ptr), nbytes),
+               "state_read_device")
+
+    def field_shape(self, field):
+        return _field_shape(self._d, field)
+
+    def reset(self):
+        _check(lib().taccel_scene_reset(self.h), "scene_reset")
 
     def set_state(self, x, v, q, qd):
         self.write(FIELD_X, x)
@@ -387,6 +425,28 @@ class Batch:
     def write(self, i, field, arr):
         a = _f64(arr)
         _check(lib().taccel_batch_write(self.h, i, field, a.ctypes.data, a.nbytes), "batch_write")
+
+    def contacts(self, i):
+        return _read_contacts(lib().taccel_batch_state_bytes, lib().taccel_batch_read, (self.h, i))
+
+    def stats(self, i):
+        st = taccel_step_stats()
+        _check(lib().taccel_batch_read(self.h, i, FIELD_STATS, C.addressof(st), C.sizeof(st)),
+               "batch_read")
+        return st.as_dict()
+
+    def read_device(self, i, field, ptr, nbytes):
+        _check(lib().taccel_batch_read_device(self.h, i, field, C.c_void_p(ptr), nbytes),
+               "batch_read_device")
+
+    def reset(self, mask=None):
+        """Creation state for the scenes with mask[k] true (all when mask is None)."""
+        m = None
+        if mask is not None:
+            mm = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+            assert mm.shape == (self.n,)
+            m = mm.ctypes.data_as(C.POINTER(C.c_uint8))
+        _check(lib().taccel_batch_reset(self.h, m), "batch_reset")
 
     def markers(self, i, tris, bary):
         return _markers(lib().taccel_batch_markers, (self.h, i), tris, bary)
