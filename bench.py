@@ -1,17 +1,29 @@
 """Benchmark: Newton-converged env-steps/s of the IPC time step on one MI355X.
 
-Workload (one scene, FP64): a 32x24x6 mm gel pad meshed as a 32x24x6 hex grid split into
-6 tets per hex (5,775 vertices, 27,648 tets, bottom face fixed, neo-Hookean E = 0.3 MPa,
-nu = 0.45) pressed by a rigid 400-point random convex hull (796 triangles, 8 mm extent)
-that is lowered 1.0 mm over 50 steps and then slid 2 mm over 50 steps, h = 0.005 s,
-dhat = 1e-4 m, kappa = 1e3, Newton tolerance 1e-6.  Synthetic seeded input (seed 0).
+Default workload (the batched form of the method, FP64): 256 independent copies of the small
+gel pad (20x20x4 mm, 8x8x2 hex grid split into 6 tets per hex: 243 vertices, 768 tets, bottom
+face fixed, neo-Hookean E = 0.3 MPa, nu = 0.45, rho = 1000), each pressed by its own seeded
+rigid convex hull (8 points, 10 mm extent, rho = 2000) placed at an xy offset U(-3, 3) mm,
+0.05 mm above the pad, and lowered to a press depth U(0.3, 1.2) mm over 10 steps; h = 0.01 s,
+dhat = 1e-4 m, kappa = 1e3, Newton tolerance 1e-6.  Synthetic seeded input.  One launch per
+stage covers all scenes.
 
-A step is one call of taccel_step (predict, Newton loops with broad phase, narrow phase,
+A step is one call of taccel_batch_step (predict, Newton loops with broad phase, narrow phase,
 barrier / FEM / affine-body derivatives, assembly, PCG, CCD, line search, augmented
-Lagrangian rounds and snap, velocity update).  After W warm-up steps, K steps are timed
-with the device synchronised on both sides.  The PCG sparse matrix-vector kernel is timed
-with HIP events on the solver's stream over the timed region (roofline field).  The CPU
-FP64 oracle is timed on a bounded sample of the same workload (cpu_baseline field).
+Lagrangian rounds and snap, velocity update) for every scene.  After W warm-up steps the batch
+is reset to its creation state and K steps are timed with the device synchronised on both
+sides: the 10-step trajectory from its start, repeated (with a reset, inside the timed region)
+when K > 10.  Only Newton-converged scene-steps count.
+
+Beside it, in the same process:
+* plain FP64 one scene at a time: the first scenes of the same batch, each stepped alone
+  through its whole trajectory (vs_baseline is the ratio to this rate);
+* the benchmark pad alone (32x24x6 grid, 5,775 vertices, 27,648 tets, pressed 1 mm and slid
+  2 mm by a 796-triangle hull over 100 steps, h = 0.005 s), FP64, whole trajectory;
+* roofline: the PCG sparse-product kernel timed with HIP events on the solver's stream, in a
+  separate pass over the same trajectory after the timed region (the timing adds launches and
+  synchronisations, so it stays out of the timed steps);
+* cpu_baseline: the CPU FP64 oracle on the host's cores, one scene per thread.
 """
 import argparse
 import json
@@ -27,22 +39,54 @@ METRIC = "Newton-converged env-steps/sec on 1 GPU; p50/p99 step latency; vs plai
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(spec, k_warm, k_timed):
-    """Oracle on the host: warm-up steps, then time k_timed steps (one scene, one core)."""
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(specs, max_threads=16, budget_s=30.0):
+    """The oracle on the host, one scene per thread (ctypes releases the GIL), each scene
+    stepped through its whole script; bounded to about budget_s of wall time."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from oracle import binding as O
 
-    o = O.OracleScene(spec)
-    for k in range(k_warm):
-        o.step(k)
+    model, avail = _host_cpu()
+    threads = max(1, min(avail, max_threads, len(specs)))
+    t_stop = time.perf_counter() + budget_s
+
+    def run(sp):
+        o = O.OracleScene(sp)
+        ok = 0
+        for k in range(sp.n_steps):
+            if time.perf_counter() > t_stop:
+                break
+            rc, _ = o.step(k)
+            if rc != 0:
+                break
+            ok += 1
+        return ok
+
+    O.lib()
     t0 = time.perf_counter()
-    ok = 0
-    for k in range(k_warm, k_warm + k_timed):
-        rc, _ = o.step(k)
-        ok += rc == 0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        oks = list(ex.map(run, specs[:threads]))
     dt = time.perf_counter() - t0
-    return dict(value=ok / dt, unit="env-steps/s", cores=1, kind="oracle",
-                sample=f"steps {k_warm}..{k_warm + k_timed - 1} of the same scene after "
-                       f"{k_warm} warm-up step(s); one scene on one host core; {dt:.1f} s")
+    return dict(value=sum(oks) / dt, unit="env-steps/s", cores=threads, kind="oracle",
+                sample=f"scenes 0..{threads - 1} of the same workload, one per thread, each "
+                       f"from its first step ({sum(oks)} scene-steps in {dt:.1f} s)",
+                cpu_model=model, host_cpus_available=avail)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pcg_dir_spmv_pad32x24x6_hull796_fp64_traffic.txt")
@@ -94,124 +138,186 @@ def _set_friction(args, specs):
             sp.params["eps_v"] = 1e-3
 
 
-def run_single(args, taccel, scenes, np):
-    spec = scenes.pad_press_slide_hull(0)
-    _set_friction(args, [spec])
-    W, K = args.warmup, args.steps
-    if W + K > spec.n_steps:
-        sys.exit(f"warmup + steps must be <= {spec.n_steps}")
-    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
-    sc = taccel.Scene(spec, precision=prec)
-    for k in range(W):
-        rc, st = sc.step(k)
-        print(f"warmup step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
-              f"pcg={st['pcg_iters']} {st['step_ms']:.1f} ms", file=sys.stderr, flush=True)
+def _roofline_pass(taccel, step_fn, n_steps):
+    """The sparse-product kernel timed with HIP events on the solver's stream over a separate
+    pass of n_steps steps (after the timed region)."""
     taccel.device_synchronize()
     taccel.profile_reset()
     taccel.profile_enable(True)
-    lat = []
-    ok = 0
-    stats = []
+    for k in range(n_steps):
+        step_fn(k)
+    taccel.device_synchronize()
+    taccel.profile_enable(False)
+    roof = _spmv_roofline(taccel)
+    pcg = taccel.profile_query("pcg")
+    if pcg["launches"]:
+        roof["pcg_us_per_iter"] = pcg["total_ms"] * 1e3 / pcg["launches"]
+    roof["measured_over"] = f"steps 0..{n_steps - 1} of the trajectory, after the timed region"
+    return roof
+
+
+def _single_trajectory(taccel, spec, prec, log=None):
+    """One scene stepped alone through its whole script (FP64 unless prec says otherwise);
+    returns (Newton-converged steps, seconds, per-step latencies in ms, stats)."""
+    sc = taccel.Scene(spec, precision=prec)
+    taccel.device_synchronize()
+    ok, lat, stats = 0, [], []
     t0 = time.perf_counter()
-    for k in range(W, W + K):
+    for k in range(spec.n_steps):
         ts = time.perf_counter()
         rc, st = sc.step(k)
         lat.append((time.perf_counter() - ts) * 1e3)
-        ok += rc == taccel.OK
         stats.append(st)
+        if log:
+            print(f"{log} step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
+                  f"al={st['al_rounds']} pcg={st['pcg_iters']} {lat[-1]:.1f} ms",
+                  file=sys.stderr, flush=True)
         if rc != taccel.OK:
-            print(f"step {k} failed: {taccel.lib().taccel_last_error().decode()}", file=sys.stderr)
-        print(f"step {k}: {taccel.STATUS_NAMES[rc]} newton={st['newton_iters']} "
-              f"al={st['al_rounds']} pcg={st['pcg_iters']} active={st['n_active']} "
-              f"{lat[-1]:.1f} ms", file=sys.stderr, flush=True)
+            break
+        ok += 1
     taccel.device_synchronize()
     dt = time.perf_counter() - t0
-    taccel.profile_enable(False)
+    sc.close()
+    return ok, dt, lat, stats
+
+
+def run_single(args, taccel, scenes, np):
+    """The benchmark pad alone (5,775 vertices, 796-triangle hull), its whole 100-step press
+    and slide trajectory timed after a warm-up scene of W steps."""
+    spec = scenes.pad_press_slide_hull(0)
+    _set_friction(args, [spec])
+    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    if args.warmup > 0:
+        warm = taccel.Scene(spec, precision=prec)
+        for k in range(min(args.warmup, spec.n_steps)):
+            warm.step(k)
+        warm.close()
+    ok, dt, lat, stats = _single_trajectory(taccel, spec, prec, log="single")
+    n = len(lat)
     out = dict(
-        metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
-        ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
+        metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=n, warmup=args.warmup,
+        ms_per_step=dt * 1e3 / n, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
-        config=dict(workload="gel pad 32x24x6 grid (5775 verts, 27648 tets) pressed and slid "
-                             "by a 400-point convex hull (796 tris), 1 scene",
-                    scenes=1, h=spec.params["h"], step_range=[W, W + K - 1],
-                    precision=args.precision, friction=args.friction),
+        config=dict(workload="gel pad 32x24x6 grid (5775 verts, 27648 tets) pressed 1 mm and "
+                             "slid 2 mm by a 400-point convex hull (796 tris), 1 scene, whole "
+                             "100-step trajectory",
+                    scenes=1, h=spec.params["h"], precision=args.precision,
+                    friction=args.friction),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         newton_iters_per_step=float(np.mean([s["newton_iters"] for s in stats])),
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
-        roofline=_spmv_roofline(taccel),
     )
-    if prec == taccel.FP64:
-        out["roofline"]["traffic"] = _measured_traffic()
-    pcg = taccel.profile_query("pcg")
-    if pcg["launches"]:
-        out["pcg_us_per_iter"] = pcg["total_ms"] * 1e3 / pcg["launches"]
-    if args.phases > 0 and W + K + args.phases <= spec.n_steps:
-        # after the timed region: host wall time per Newton-iteration phase (every phase ends
+    sc = taccel.Scene(spec, precision=prec)
+    out["roofline"] = _roofline_pass(taccel, lambda k: sc.step(k), min(args.roofline_steps, spec.n_steps))
+    sc.close()
+    if args.phases > 0:
+        # host wall time of each Newton-iteration phase over the first steps (every phase ends
         # with a synchronisation here, so the sum exceeds an unprofiled iteration)
+        sc = taccel.Scene(spec, precision=prec)
         taccel.profile_reset()
         taccel.profile_enable(False, phases=True)
-        for k in range(W + K, W + K + args.phases):
+        for k in range(min(args.phases, spec.n_steps)):
             sc.step(k)
         taccel.profile_enable(False)
+        sc.close()
         ph = {name: taccel.profile_query(name) for name in taccel.PHASES}
         n_it = max(ph["solve"]["launches"], 1)
         out["phase_ms_per_newton_iter"] = {name: v["total_ms"] / n_it for name, v in ph.items()}
-    sc.close()
+    if prec == taccel.FP64:
+        out["roofline"]["traffic"] = _measured_traffic()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, 1, 1)
-        v = out["cpu_baseline"]["value"]
-        out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / v if v > 0 else None
+        out["cpu_baseline"] = cpu_baseline([spec], budget_s=args.cpu_budget)
     return out
 
 
 def run_batch(args, taccel, scenes, np):
     """Uniform batch: n copies of the small pad with seeded hull indenters, one launch per
-    stage over all scenes."""
+    stage over all scenes; the whole trajectory timed from its start."""
     n = args.scenes
-    if n > 64:
-        sys.exit("bench.py: batches of more than 64 scenes are off: a 256-scene batch once ended "
-                 "in a GPU memory fault whose cause is not found yet")
+    if n > 1024:
+        sys.exit("bench.py: batches of more than 1,024 scenes are off: a 4,096-scene batch "
+                 "once ended in a GPU memory fault whose cause is not shown")
     specs = scenes.uniform_batch(n)
     _set_friction(args, specs)
+    nst = specs[0].n_steps
     W, K = args.warmup, args.steps
-    if W + K > specs[0].n_steps:
-        sys.exit(f"warmup + steps must be <= {specs[0].n_steps}")
     prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
     if prec == taccel.MIXED and n > 1:
         sys.exit("bench.py: mixed precision runs one scene per batch (see include/taccel.h)")
+    t_create = time.perf_counter()
     b = taccel.Batch(specs, precision=prec)
+    t_create = time.perf_counter() - t_create
+    print(f"batch of {n} created in {t_create:.2f} s", file=sys.stderr, flush=True)
+    targets = [b.targets(k) for k in range(nst)]
     for k in range(W):
-        rc, per, st = b.step(k)
-        print(f"warmup step {k}: rc={taccel.STATUS_NAMES[rc]} {st[0]['step_ms']:.1f} ms",
+        rc, per, st = b.step(k % nst, targets[k % nst])
+        print(f"warmup step {k % nst}: ok={int((per == taccel.OK).sum())}/{n} "
+              f"{st[0]['step_ms']:.1f} ms", file=sys.stderr, flush=True)
+    b.reset()
+    taccel.device_synchronize()
+    lat, ok, newton, per_ok = [], 0, [], np.zeros(n, dtype=np.int64)
+    t0 = time.perf_counter()
+    for i in range(K):
+        k = i % nst
+        ts = time.perf_counter()
+        if i > 0 and k == 0:
+            b.reset()
+        rc, per, st = b.step(k, targets[k])
+        lat.append((time.perf_counter() - ts) * 1e3)
+        good = per == taccel.OK
+        ok += int(good.sum())
+        per_ok += good
+        newton.append(max(s["newton_iters"] for s in st))
+        print(f"step {k}: ok={int(good.sum())}/{n} max_newton={newton[-1]} "
+              f"mean_newton={np.mean([s['newton_iters'] for s in st]):.1f} {lat[-1]:.1f} ms",
               file=sys.stderr, flush=True)
     taccel.device_synchronize()
-    taccel.profile_reset()
-    taccel.profile_enable(True)
-    lat, ok, newton = [], 0, []
-    t0 = time.perf_counter()
-    for k in range(W, W + K):
-        ts = time.perf_counter()
-        rc, per, st = b.step(k)
-        lat.append((time.perf_counter() - ts) * 1e3)
-        ok += int((per == taccel.OK).sum())
-        newton.append(max(s["newton_iters"] for s in st))
-        print(f"step {k}: ok={int((per == taccel.OK).sum())}/{n} max_newton={newton[-1]} "
-              f"{lat[-1]:.1f} ms", file=sys.stderr, flush=True)
-    taccel.device_synchronize()
     dt = time.perf_counter() - t0
-    taccel.profile_enable(False)
+    value = ok / dt
     out = dict(
-        metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
+        metric=METRIC, value=value, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
-        config=dict(workload=f"uniform batch of {n} small pads (243 verts, 768 tets) with "
-                             "8-point hull indenters, pressed over 10 steps",
-                    scenes=n, precision=args.precision, step_range=[W, W + K - 1],
-                    friction=args.friction),
+        config=dict(workload=f"uniform batch of {n} small pads (243 verts, 768 tets each) with "
+                             "seeded 8-point hull indenters, pressed over the whole 10-step "
+                             "trajectory", scenes=n, precision=args.precision,
+                    steps_per_trajectory=nst, friction=args.friction),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-        roofline=_spmv_roofline(taccel),
+        scene_steps_ok=ok, scene_steps=n * K, max_newton_per_step=int(max(newton)),
+        create_s=t_create,
     )
+    # plain FP64, one scene at a time: the first scenes of the same batch, whole trajectories
+    m = max(1, min(args.plain_scenes, n))
+    plain_ok, plain_dt = 0, 0.0
+    if m > 0:
+        warm = taccel.Scene(specs[0])
+        warm.step(0)
+        warm.close()
+        for sp in specs[:m]:
+            o_, d_, _, _ = _single_trajectory(taccel, sp, taccel.FP64)
+            plain_ok += o_
+            plain_dt += d_
+    plain = plain_ok / plain_dt if plain_dt > 0 else None
+    out["plain_fp64_one_at_a_time"] = dict(
+        value=plain, unit="env-steps/s", scenes=m,
+        sample=f"scenes 0..{m - 1} of the batch, each alone (taccel_step, FP64) through its "
+               f"{nst}-step trajectory")
+    out["vs_baseline"] = value / plain if plain else None
+    b.reset()
+    out["roofline"] = _roofline_pass(taccel, lambda k: b.step(k, targets[k]), nst)
     b.close()
+    if args.c2:
+        spec = scenes.pad_press_slide_hull(0)
+        o_, d_, lat2, _ = _single_trajectory(taccel, spec, taccel.FP64)
+        out["single_benchmark_pad_fp64"] = dict(
+            value=o_ / d_, unit="env-steps/s", steps_ok=o_, p50_ms=float(np.percentile(lat2, 50)),
+            p99_ms=float(np.percentile(lat2, 99)),
+            workload="gel pad 32x24x6 grid (5775 verts) pressed and slid by a 796-triangle "
+                     "hull, whole 100-step trajectory, alone")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(specs, budget_s=args.cpu_budget)
+        v = out["cpu_baseline"]["value"]
+        out["cpu_baseline"]["gpu_over_cpu"] = value / v if v > 0 else None
     return out
 
 
@@ -349,14 +455,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["single", "batch", "serving", "tactile", "copy"],
-                    default="single")
+                    default="batch")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--scenes", type=int, default=64)
+    ap.add_argument("--scenes", type=int, default=256)
+    ap.add_argument("--plain-scenes", type=int, default=16,
+                    help="scenes of the batch also stepped one at a time (FP64 comparator)")
+    ap.add_argument("--roofline-steps", type=int, default=10,
+                    help="steps of the separate sparse-product timing pass (single workload)")
+    ap.add_argument("--cpu-budget", type=float, default=30.0,
+                    help="seconds of the oracle's host run (cpu_baseline)")
+    ap.add_argument("--no-c2", dest="c2", action="store_false",
+                    help="skip the benchmark pad's one-scene trajectory beside the batch")
     ap.add_argument("--friction", type=float, default=0.0,
                     help="friction coefficient of the single/batch workload (default 0: the "
                          "frictionless benchmark)")
     ap.add_argument("--phases", type=int, default=0,
-                    help="extra steps after the timed region with per-phase host timing")
+                    help="single workload: steps of a separate pass with per-phase host timing")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=1.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)

@@ -1071,8 +1071,11 @@ static double total_energy(const Scene& S, const vector<Pair>& pairs, unsigned t
 }
 
 // ---------------------------------------------------------------- gradient and Hessian
+// exact: the FEM and barrier Hessians enter unprojected (Newton's method proper); otherwise
+// each is replaced by its nearest positive semidefinite matrix (projected Newton).
 static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
-                     vector<double>& G, BlockMatrix& H, unsigned terms = kTermAll) {
+                     vector<double>& G, BlockMatrix& H, unsigned terms = kTermAll,
+                     bool exact = false) {
   const double h2 = S.h * S.h;
   G.assign(3 * D.n_nodes, 0.0);
   H = BlockMatrix();
@@ -1088,7 +1091,8 @@ static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
     double x12[12], en, g[12], Hp[144];
     for (int a = 0; a < 4; ++a)
       for (int c = 0; c < 3; ++c) x12[3 * a + c] = S.x[S.tets[e][a]][c];
-    nh_tet_eval(S.rest[e].data(), x12, S.mu, S.lam, &en, g, nullptr, Hp);
+    if (exact) nh_tet_eval(S.rest[e].data(), x12, S.mu, S.lam, &en, g, Hp, nullptr);
+    else nh_tet_eval(S.rest[e].data(), x12, S.mu, S.lam, &en, g, nullptr, Hp);
     for (int a = 0; a < 4; ++a) {
       const int na = D.soft_node[S.tets[e][a]];
       if (na < 0) continue;
@@ -1153,7 +1157,8 @@ static void assemble(const Scene& S, const Dofs& D, const vector<Pair>& active,
       const Pair& pr = active[k];
       pair_verts(S, pr, w);
       gather12(P, w, x12);
-      pair_eval(pr.kind, x12, pair_meps(S, pr), S.dhat, S.kappa, &e, g, nullptr, Hp);
+      if (exact) pair_eval(pr.kind, x12, pair_meps(S, pr), S.dhat, S.kappa, &e, g, Hp, nullptr);
+      else pair_eval(pr.kind, x12, pair_meps(S, pr), S.dhat, S.kappa, &e, g, nullptr, Hp);
     } else {
       // friction: the exact Hessian, positive semidefinite by construction (the lagged normal
       // and weights make u linear in x, and f0 is convex in |u| with f1 >= 0)
@@ -1237,6 +1242,7 @@ static int newton_loop(Scene& S, int* iters) {
   vector<double> G, p;
   BlockMatrix H;
   const double stop = S.tol * S.h * S.L;
+  double prev_alpha = 0.0, prev_pmax = 0.0;
   for (int it = 0; it < S.max_newton; ++it) {
     ++*iters;
     world_positions(S, P);
@@ -1249,13 +1255,22 @@ static int newton_loop(Scene& S, int* iters) {
       gather12(P, w, x12);
       if (pair_sqdist(pr.kind, x12) < S.dhat * S.dhat) active.push_back(pr);
     }
-    assemble(S, D, active, G, H);
+    // Close to the minimiser (the last step was a full one and small against dhat) the
+    // Hessian is taken exactly, so that the iteration converges quadratically; when that
+    // system is not positive definite, the projected one is solved instead.
+    const bool exact = it > 0 && prev_alpha == 1.0 && prev_pmax <= 1e-2 * S.dhat;
+    assemble(S, D, active, G, H, kTermAll, exact);
     for (double gv : G)
       if (!std::isfinite(gv)) return kNaN;
     vector<double> rhs(G.size());
     for (size_t k = 0; k < G.size(); ++k) rhs[k] = -G[k];
     if (D.n_nodes == 0) return kOk;
-    if (!skyline_solve(H, rhs, p)) return kNaN;
+    bool solved = skyline_solve(H, rhs, p);
+    if (!solved && exact) {
+      assemble(S, D, active, G, H);
+      solved = skyline_solve(H, rhs, p);
+    }
+    if (!solved) return kNaN;
     world_displacement(S, D, p, disp);
     double pmax = 0.0;
     for (const V3& d : disp)
@@ -1286,6 +1301,8 @@ static int newton_loop(Scene& S, int* iters) {
       }
     }
     apply_step(S, D, p, alpha);
+    prev_alpha = alpha;
+    prev_pmax = pmax;
     {
       double kap = 0.0, res = 0.0;
       for (const Body& b : S.bodies)

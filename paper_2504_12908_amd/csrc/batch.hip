@@ -202,7 +202,11 @@ struct Batch::Impl {
   DBuf<double> bmass, bvol, bstar, blam, bkap, bgrad, bhess, bpinv;
   DBuf<int> cvn, cvb, cvfix, cvscene, cvworld, trv, edv, qkind, qidx, qscene;
   DBuf<double> cvx, cpos, cdisp, cend, elen2;
-  DBuf<int> act, pdone;
+  DBuf<int> act, pdone, exact, indef;
+  // per scene, the previous Newton iteration of its current loop: step size and max vertex
+  // displacement of the direction (they decide whether this iteration uses exact Hessians)
+  std::vector<double> prev_alpha, prev_pmax;
+  std::vector<int> exact_h;
   // block tables
   DBuf<int> tn_sc, tn_b0, tn_b1, tn_sblk, tt_sc, tt_b0, tt_b1, tt_sblk, ts_sc, ts_b0, ts_b1, ts_sblk;
   BlockTable TN, TT, TS;
@@ -327,7 +331,7 @@ struct Batch::Impl {
     V.cvn = cvn.p; V.cvb = cvb.p; V.cvx = cvx.p; V.cvfix = cvfix.p; V.cvscene = cvscene.p;
     V.cvworld = cvworld.p; V.cpos = cpos.p; V.cdisp = cdisp.p; V.trv = trv.p; V.edv = edv.p;
     V.elen2 = elen2.p; V.qkind = qkind.p; V.qidx = qidx.p; V.qscene = qscene.p;
-    V.act = act.p; V.pdone = pdone.p;
+    V.act = act.p; V.pdone = pdone.p; V.exact = exact.p;
     return V;
   }
 
@@ -454,6 +458,9 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   hs.resize(S);
   hsc.resize(S);
   last_stats.assign(S, taccel_step_stats{});
+  prev_alpha.assign(S, 0.0);
+  prev_pmax.assign(S, 0.0);
+  exact_h.assign(S, 0);
   std::vector<double> h_x, h_mass, h_Dminv_aos, h_tvol;
   std::vector<int> h_nfree, h_nbody, h_tv_aos, h_tscene;
   std::vector<int> h_bcv0, h_bcv1;
@@ -985,6 +992,8 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   qscene.upload(m, h_qscene);
   act.upload(m, std::vector<int>(S, 0));
   pdone.upload(m, std::vector<int>(S, 1));
+  exact.upload(m, std::vector<int>(S, 0));
+  indef.upload(m, std::vector<int>(S, 0));
   tn_sc.upload(m, tn_sc_h);
   tn_b0.upload(m, tn_b0_h);
   tn_b1.upload(m, tn_b1_h);
@@ -1180,6 +1189,7 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.P_rr = reinterpret_cast<T*>(P_rr.p);
   B.P_gg = reinterpret_cast<T*>(P_gg.p);
   B.iters = iters.p;
+  B.indef = indef.p;
   B.cg_on = cg_on;
   B.cg_blk_agg = cg_blk_agg.p;
   B.cg_agg_b0 = cg_agg_b0.p;
@@ -1441,97 +1451,127 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   zero(scnt.p, sizeof(int) * (S + 1));
   launch_count_scene(np, pscene.p, scnt.p, s);
   phase_end(0);
-  // ---- element derivatives
-  // Three independent chains, joined before the contact blocks are reduced: the contact
-  // Hessians (one wavefront per pair: long and narrow) on the second stream, the FEM and
-  // affine-body terms with the static assembly on the third, and the emission and sort of the
-  // contact blocks here.
-  HIPCHECK(hipEventRecord(ev_fork, s));
-  HIPCHECK(hipStreamWaitEvent(mem.side, ev_fork, 0));
-  HIPCHECK(hipStreamWaitEvent(mem.side2, ev_fork, 0));
-  launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
-  HIPCHECK(hipEventRecord(ev_join, mem.side));
-  launch_fem_hess(V, mixed, mem.side2);
-  launch_body_hess(V, mem.side2);
-  launch_assemble_bsr(V, nnz, brow.p, mixed, mem.side2);
-  launch_assemble_grad(V, g.p, mem.side2);
-  HIPCHECK(hipEventRecord(ev_join2, mem.side2));
-  // ---- contact and body blocks: emit, sort by (row, col), reduce
-  if (nfric > 0) launch_fric_derivs(V, fric_bufs(), np, pv.p, pg.p, ph.p, s);
-  const int nitems = npf + Nb;
-  hcnt.ensure(&mem, std::max(nitems, 1));
-  gcnt.ensure(&mem, std::max(nitems, 1));
-  hoff.ensure(&mem, std::max(nitems, 1));
-  goff.ensure(&mem, std::max(nitems, 1));
-  launch_contrib_count(V, npf, pv.p, hcnt.p, gcnt.p, s);
-  scan_async(hcnt.p, hoff.p, nitems, scalars.p + 3);
-  scan_async(gcnt.p, goff.p, nitems, scalars.p + 4);
-  int hg[2];
-  d2h(hg, scalars.p + 3, 2);
-  sync();
-  const int nh = hg[0], ng = hg[1];
-  for (DBuf<uint64_t>* b : {&hkey, &hkey2}) b->ensure(&mem, std::max(nh, 1));
-  for (DBuf<int>* b : {&hidx, &hidx2, &hsrc}) b->ensure(&mem, std::max(nh, 1));
-  hcoef.ensure(&mem, std::max(nh, 1));
-  for (DBuf<uint64_t>* b : {&gkey, &gkey2}) b->ensure(&mem, std::max(ng, 1));
-  for (DBuf<int>* b : {&gidx, &gidx2, &gsrc}) b->ensure(&mem, std::max(ng, 1));
-  gcoef.ensure(&mem, std::max(ng, 1));
-  launch_contrib_emit(V, npf, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
-                      gsrc.p, gcoef.p, s);
-  sort(hkey.p, hidx.p, hkey2.p, hidx2.p, nh, bits_for((uint64_t)Nn * (uint64_t)Nn));
-  sort(gkey.p, gidx.p, gkey2.p, gidx2.p, ng, bits_for((uint64_t)Nn));
-  const int nmax = std::max(nh, ng);
-  sflag.ensure(&mem, std::max(nmax, 1));
-  segid.ensure(&mem, std::max(nmax, 1));
-  segstart.ensure(&mem, std::max(nmax, 1) + 1);
-  // Hessian blocks.  The segment counts stay on the device (scalars 6 and 7): the records
-  // bound them, so buffers and grids are sized by the record counts and the reductions read
-  // the exact counts themselves.
-  int* nseg_d = scalars.p + 6;
-  int* ngseg_d = scalars.p + 7;
-  launch_seg_flags(nh, hkey.p, sflag.p, s);
-  scan_async(sflag.p, segid.p, nh, nseg_d);
-  launch_seg_start(nh, sflag.p, segid.p, segstart.p, s);
-  drow.ensure(&mem, std::max(nh, 1));
-  dcol.ensure(&mem, std::max(nh, 1));
-  dval.ensure(&mem, 9 * (size_t)std::max(nh, 1));
-  zero(rowcnt.p, sizeof(int) * (Nn + 1));
-  HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
-  HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
-  launch_reduce_blocks(V, nh, nseg_d, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p,
-                       dcol.p, dval.p, rowcnt.p, mixed, s);
-  scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
-  // gradient entries
-  launch_seg_flags(ng, gkey.p, sflag.p, s);
-  scan_async(sflag.p, segid.p, ng, ngseg_d);
-  launch_seg_start(ng, sflag.p, segid.p, segstart.p, s);
-  launch_reduce_grad(V, ng, ngseg_d, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
-  // ---- preconditioner and PCG
-  zero(bad.p, sizeof(int) * S);
-  launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, mixed, s);
-  {
-    // pdone = !act
-    std::vector<int> ha(S);
-    for (int k = 0; k < S; ++k) ha[k] = !act_host[k];
-    h2d(pdone.p, ha.data(), S);
+  // Exact (unprojected) FEM and barrier Hessians for the scenes whose previous iteration of
+  // this Newton loop took the full step with max vertex displacement <= 1e-2 dhat; the
+  // projected ones otherwise, and again, in this same iteration, for a scene whose exact
+  // system PCG finds not positive definite.
+  std::vector<int> hbad(S, 0);
+  for (int k = 0; k < S; ++k) {
+    exact_h[k] = act_host[k] && prev_alpha[k] == 1.0 && prev_pmax[k] <= 1e-2 * hsc[k].dhat;
+    pcg_it[k] = 0;
   }
-  zero(iters.p, sizeof(int) * S);
-  phase_end(1);
-  if (mixed) {
-    const PcgBufsT<float> B = pcg_bufs<float>();
-    launch_pcg_init(V, TN, B, s);
-    launch_pcg_coarse(V, TN, B, B.P_rz0, s);
-    run_pcg(V, B, nseg_d);
-  } else {
-    const PcgBufsT<double> B = pcg_bufs<double>();
-    launch_pcg_init(V, TN, B, s);
-    launch_pcg_coarse(V, TN, B, B.P_rz0, s);
-    run_pcg(V, B, nseg_d);
+  std::vector<int> attempt_act = act_host;
+  for (int attempt = 0;; ++attempt) {
+    h2d(exact.p, exact_h.data(), S);
+    zero(indef.p, sizeof(int) * S);
+    // ---- element derivatives
+    // Three independent chains, joined before the contact blocks are reduced: the contact
+    // Hessians (one wavefront per pair: long and narrow) on the second stream, the FEM and
+    // affine-body terms with the static assembly on the third, and the emission and sort of the
+    // contact blocks here.
+    HIPCHECK(hipEventRecord(ev_fork, s));
+    HIPCHECK(hipStreamWaitEvent(mem.side, ev_fork, 0));
+    HIPCHECK(hipStreamWaitEvent(mem.side2, ev_fork, 0));
+    launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
+    HIPCHECK(hipEventRecord(ev_join, mem.side));
+    launch_fem_hess(V, mixed, mem.side2);
+    launch_body_hess(V, mem.side2);
+    launch_assemble_bsr(V, nnz, brow.p, mixed, mem.side2);
+    launch_assemble_grad(V, g.p, mem.side2);
+    HIPCHECK(hipEventRecord(ev_join2, mem.side2));
+    // ---- contact and body blocks: emit, sort by (row, col), reduce
+    if (nfric > 0) launch_fric_derivs(V, fric_bufs(), np, pv.p, pg.p, ph.p, s);
+    const int nitems = npf + Nb;
+    hcnt.ensure(&mem, std::max(nitems, 1));
+    gcnt.ensure(&mem, std::max(nitems, 1));
+    hoff.ensure(&mem, std::max(nitems, 1));
+    goff.ensure(&mem, std::max(nitems, 1));
+    launch_contrib_count(V, npf, pv.p, hcnt.p, gcnt.p, s);
+    scan_async(hcnt.p, hoff.p, nitems, scalars.p + 3);
+    scan_async(gcnt.p, goff.p, nitems, scalars.p + 4);
+    int hg[2];
+    d2h(hg, scalars.p + 3, 2);
+    sync();
+    const int nh = hg[0], ng = hg[1];
+    for (DBuf<uint64_t>* b : {&hkey, &hkey2}) b->ensure(&mem, std::max(nh, 1));
+    for (DBuf<int>* b : {&hidx, &hidx2, &hsrc}) b->ensure(&mem, std::max(nh, 1));
+    hcoef.ensure(&mem, std::max(nh, 1));
+    for (DBuf<uint64_t>* b : {&gkey, &gkey2}) b->ensure(&mem, std::max(ng, 1));
+    for (DBuf<int>* b : {&gidx, &gidx2, &gsrc}) b->ensure(&mem, std::max(ng, 1));
+    gcoef.ensure(&mem, std::max(ng, 1));
+    launch_contrib_emit(V, npf, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
+                        gsrc.p, gcoef.p, s);
+    sort(hkey.p, hidx.p, hkey2.p, hidx2.p, nh, bits_for((uint64_t)Nn * (uint64_t)Nn));
+    sort(gkey.p, gidx.p, gkey2.p, gidx2.p, ng, bits_for((uint64_t)Nn));
+    const int nmax = std::max(nh, ng);
+    sflag.ensure(&mem, std::max(nmax, 1));
+    segid.ensure(&mem, std::max(nmax, 1));
+    segstart.ensure(&mem, std::max(nmax, 1) + 1);
+    // Hessian blocks.  The segment counts stay on the device (scalars 6 and 7): the records
+    // bound them, so buffers and grids are sized by the record counts and the reductions read
+    // the exact counts themselves.
+    int* nseg_d = scalars.p + 6;
+    int* ngseg_d = scalars.p + 7;
+    launch_seg_flags(nh, hkey.p, sflag.p, s);
+    scan_async(sflag.p, segid.p, nh, nseg_d);
+    launch_seg_start(nh, sflag.p, segid.p, segstart.p, s);
+    drow.ensure(&mem, std::max(nh, 1));
+    dcol.ensure(&mem, std::max(nh, 1));
+    dval.ensure(&mem, 9 * (size_t)std::max(nh, 1));
+    zero(rowcnt.p, sizeof(int) * (Nn + 1));
+    HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
+    HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
+    launch_reduce_blocks(V, nh, nseg_d, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p,
+                         dcol.p, dval.p, rowcnt.p, mixed, s);
+    scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
+    // gradient entries
+    launch_seg_flags(ng, gkey.p, sflag.p, s);
+    scan_async(sflag.p, segid.p, ng, ngseg_d);
+    launch_seg_start(ng, sflag.p, segid.p, segstart.p, s);
+    launch_reduce_grad(V, ng, ngseg_d, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
+    // ---- preconditioner and PCG
+    zero(bad.p, sizeof(int) * S);
+    launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, mixed, s);
+    {
+      // pdone = !act
+      std::vector<int> ha(S);
+      for (int k = 0; k < S; ++k) ha[k] = !attempt_act[k];
+      h2d(pdone.p, ha.data(), S);
+    }
+    zero(iters.p, sizeof(int) * S);
+    phase_end(1);
+    if (mixed) {
+      const PcgBufsT<float> B = pcg_bufs<float>();
+      launch_pcg_init(V, TN, B, s);
+      launch_pcg_coarse(V, TN, B, B.P_rz0, s);
+      run_pcg(V, B, nseg_d);
+    } else {
+      const PcgBufsT<double> B = pcg_bufs<double>();
+      launch_pcg_init(V, TN, B, s);
+      launch_pcg_coarse(V, TN, B, B.P_rz0, s);
+      run_pcg(V, B, nseg_d);
+    }
+    phase_end(2);
+    std::vector<int> it_h(S), bad_h(S), indef_h(S);
+    d2h(it_h.data(), iters.p, S);
+    d2h(bad_h.data(), bad.p, S);
+    d2h(indef_h.data(), indef.p, S);
+    sync();
+    bool retry = false;
+    for (int k = 0; k < S; ++k) {
+      if (!attempt_act[k]) continue;
+      pcg_it[k] += it_h[k];
+      hbad[k] = bad_h[k];
+      attempt_act[k] = exact_h[k] && indef_h[k];
+      if (attempt_act[k]) {
+        exact_h[k] = 0;
+        retry = true;
+      }
+    }
+    if (!retry || attempt > 0) break;
+    h2d(act.p, attempt_act.data(), S);
   }
-  phase_end(2);
-  d2h(pcg_it.data(), iters.p, S);
-  std::vector<int> hbad(S);
-  d2h(hbad.data(), bad.p, S);
+  h2d(act.p, act_host.data(), S);
   // ---- convergence check on the Newton direction
   unsigned long long* pmax = u64s.p;
   unsigned long long* amin = u64s.p + S;
@@ -1553,6 +1593,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     std::memcpy(&pm, &hp[k], sizeof(double));
     nan_[k] = hbad[k] || !std::isfinite(pm) || bp_bad[k];
     last[k] = pm <= hs[k].stop;
+    if (act_host[k]) prev_pmax[k] = pm;
   }
   // a scene with a non-finite direction (or an exploded box) takes no further part in this
   // iteration: its sweep would cover the whole grid
@@ -1688,6 +1729,8 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   }
   h2d(alpha.p, alpha_h.data(), S);
   launch_update(V, dx.p, alpha.p, s);
+  for (int k = 0; k < S; ++k)
+    if (act_host[k]) prev_alpha[k] = alpha_h[k];
   phase_end(5);
 }
 
@@ -1813,6 +1856,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       launch_al_apply(V, action.p, s);
     }
   }
+  std::fill(prev_alpha.begin(), prev_alpha.end(), 0.0);
   // ---- per-scene state machine
   enum { kNewton = 0, kDone = 1, kFailed = 2 };
   std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
@@ -1932,6 +1976,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       }
       ++rounds[k];
       nit[k] = 0;
+      prev_alpha[k] = 0.0;  // a new Newton loop starts projected
     }
   }
   // ---- finish: velocities for converged scenes, roll back failed ones
@@ -2078,7 +2123,7 @@ Batch::~Batch() {
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
            &I.clist, &I.vptr, &I.vlist, &I.brow, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,
            &I.cvn, &I.cvb, &I.cvfix, &I.cvscene, &I.cvworld, &I.trv, &I.edv, &I.qkind, &I.qidx, &I.qscene,
-           &I.act, &I.pdone, &I.tn_sc, &I.tn_b0, &I.tn_b1, &I.tn_sblk, &I.tt_sc, &I.tt_b0, &I.tt_b1,
+           &I.act, &I.pdone, &I.exact, &I.indef, &I.tn_sc, &I.tn_b0, &I.tn_b1, &I.tn_sblk, &I.tt_sc, &I.tt_b0, &I.tt_b1,
            &I.tt_sblk, &I.bp_tcell, &I.bp_tncell, &I.bp_toff, &I.bp_bcount, &I.bp_bstart, &I.bp_bfill,
            &I.bp_qcount, &I.bp_qoff, &I.cq, &I.ct, &I.sq, &I.st, &I.cflag, &I.cpos_idx, &I.pkind, &I.pv,
            &I.pscene, &I.hcnt, &I.gcnt, &I.hoff, &I.goff, &I.hidx, &I.gidx, &I.hsrc, &I.gsrc, &I.hidx2,

@@ -114,6 +114,7 @@ struct PcgBufsT {
   const T* dval;
   T *P_pq, *P_rz0, *P_rz1, *P_rr, *P_gg;
   int* iters;
+  int* indef;  // [S] set when PCG meets a direction of non-positive curvature (p.Ap <= 0)
   int max_iters;
   // coarse level (cg_on = 0: block Jacobi alone)
   int cg_on;

@@ -570,12 +570,14 @@ __global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
   for (int c = 0; c < 3; ++c) V.gloc[12 * t + 3 * a + c] = w[3 * a + c];
   Modes m;
   nh_modes(F, sc.mu, sc.lam, m);
+  // every mode (the exact Hessian), or the modes of positive eigenvalue (its PSD projection)
+  const bool exact = V.exact[s] != 0;
   double acc[36];
   for (int k = 0; k < 36; ++k) acc[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const double lk = m.lam[k];
-    if (!(lk > 0.0)) continue;
+    if (exact ? !isfinite(lk) : !(lk > 0.0)) continue;
     double Q[9];
     mode_matrix(m, k, Q);
     pullback(Q, Dm, 1.0, w);
@@ -770,7 +772,8 @@ __global__ void __launch_bounds__(64) k_barrier_hess(View V, int np, const int* 
   int type;
   gather12(V.cpos, ids, x12);
   wave_barrier_derivs(pkind[k], x12, pmeps[k], sc.dhat, sc.h * sc.h * sc.kappa, L, &e, &type);
-  wave_barrier_project(L);
+  // one pair per workgroup: the flag is uniform, so the projection's barriers are too
+  if (!V.exact[V.cvscene[ids[0]]]) wave_barrier_project(L);
   if (threadIdx.x < 12) pg[12 * (size_t)k + threadIdx.x] = L.g[threadIdx.x];
   for (int i = threadIdx.x; i < 144; i += 64) ph[144 * (size_t)k + i] = L.H[i];
 }
@@ -1457,7 +1460,8 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   }
   const T eta = (T)V.sc[s].pcg_eta;
   // iters[s] is only written by k_pcg_update, so every wave sees the same count here
-  const bool conv = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters;
+  const bool conv = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters ||
+                    B.indef[s];
   if (conv) {
     if (blk == TS.sblk[s] && threadIdx.x == 0) V.pdone[s] = 1;
     return;
@@ -1632,6 +1636,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
   wave_total_n(tot);
   const T rzs = tot[0], pqs = tot[1];
   const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
+  // a direction of non-positive curvature: the system is not positive definite (CG stops;
+  // the next sparse product sees the flag, written only here, in the scene's first block)
+  if (!(pqs > (T)0) && rzs > (T)0 && blk == TN.sblk[s] && threadIdx.x == 0) B.indef[s] = 1;
   // ---- node update: x += alpha p, r -= alpha q, z = D^{-1} r
   T r[3] = {(T)0, (T)0, (T)0};
   if (live) {

@@ -85,6 +85,9 @@ struct View {
   // per-scene state
   int* act;    // scene takes part in the current Newton iteration
   int* pdone;  // PCG finished for the scene
+  // 1: the scene's FEM and barrier Hessians enter the Newton system exactly (unprojected) in
+  // this iteration; 0: projected to positive semidefinite
+  const int* exact;
 };
 
 // A batch of independent scenes solved together.

@@ -408,9 +408,13 @@ class Batch:
 
     __del__ = close
 
-    def step(self, k):
+    def targets(self, k):
+        """Targets of step k of every scene's script, marshalled once (pass to step)."""
         ts = [_Targets(s, k) for s in self.specs]
-        arr = (taccel_targets * self.n)(*[t.t for t in ts])
+        return ts, (taccel_targets * self.n)(*[t.t for t in ts])
+
+    def step(self, k, targets=None):
+        ts, arr = targets if targets is not None else self.targets(k)
         per = np.zeros(self.n, dtype=np.int32)
         st = (taccel_step_stats * self.n)()
         rc = lib().taccel_batch_step(self.h, arr, _i(per), st)
