@@ -328,6 +328,23 @@ taccel_status taccel_debug_ccd(int32_t n, const int32_t* kinds, const double* x,
 /* ARAP term |A - R(A)|^2 of n 3x3 matrices (row-major): e, g [n][9], H, Hp [n][9][9]. */
 taccel_status taccel_debug_arap(int32_t n, const double* A, double* e, double* g, double* H,
                                 double* Hp);
+/* Newton system of the scene's first Newton iteration of its next step (Sec. 3.2 Eq. 1 with
+ * Sec. 3.3-3.4 and App. A.2-A.5: the incremental potential with barrier, affine-body and
+ * constraint terms): the step is begun as taccel_step would begin it with these targets
+ * (prediction, moving Dirichlet vertices, body targets, bodies already on their target
+ * fixed), the pairs closer than dhat are found, and the gradient and the projected Hessian
+ * are assembled exactly as the solver assembles them; then the scene is put back where it was
+ * (its carried multipliers cleared, as after a failed step).  Nodes are numbered in the
+ * caller's terms: soft vertex i is node i, body b has nodes nv + 4b + (0: its centre-of-mass
+ * position p, 1-3: the columns c1, c2, c3 of its affine map).  grad [nv + 4 nb][3]
+ * (nullable) is zero at nodes that are not unknowns (fixed or moving vertices, fixed bodies);
+ * the Hessian comes as 3x3 blocks (row node, column node, 9 values row-major), sorted by
+ * (row, column), both nodes unknowns, duplicates summed: up to cap of them are written and
+ * *n_blocks gets their number.  Single scene only; ARG otherwise, INFEASIBLE_TARGET when the
+ * targets cannot be reached. */
+taccel_status taccel_debug_system(taccel_scene* s, const taccel_targets* t, double* grad,
+                                  int32_t* brow, int32_t* bcol, double* bval, int32_t cap,
+                                  int32_t* n_blocks);
 /* Broad phase of a scene on given world positions P0 (and P1 for the swept test, or NULL):
  * world vertex ids are soft vertices 0..nv-1 then body vertices in order.  Writes up to cap
  * candidates as 5 int32 (kind, four world ids: PT point + sorted triangle; EE sorted edges,

@@ -267,6 +267,10 @@ struct Batch::Impl {
   }
   void build_friction(const int* mask);
   std::vector<int32_t> contacts(int k);
+  int prepare_pairs(std::vector<int>& bp_bad);
+  int* derivatives(int np, int npf);
+  void begin_step(const taccel_targets* tg, const int* mask, std::vector<int>& infeasible_target,
+                  std::vector<char>& snapped_host);
   // tactile outputs: rest positions of every node and work buffers
   DBuf<double> xrest, tac_bary, tac_pos, tac_flow, tac_depth, tac_normal;
   DBuf<int> tac_nodes, tac_zidx;
@@ -1404,22 +1408,12 @@ void Batch::Impl::build_friction(const int* mask) {
   h2d(fsoff.p, off.data(), S + 1);
 }
 
-void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail,
-                                   std::vector<int>& nan_, std::vector<int>& pcg_it,
-                                   std::vector<int>& n_active, std::vector<int>& halvings) {
+// Pairs closer than dhat at the current positions of the iterating scenes, compacted into the
+// pair arrays (kind, vertices, mollifier threshold, scene) with per-scene counts; returns their
+// number.  bp_bad flags scenes whose boxes overflowed the grid.
+int Batch::Impl::prepare_pairs(std::vector<int>& bp_bad) {
   hipStream_t s = stream();
   View V = view();
-  Profiler& prof = profiler();
-  auto t_mark = std::chrono::steady_clock::now();
-  auto phase_end = [&](int ph) {  // profiling only: attribute the wall time since the last mark
-    if (!prof.phases) return;
-    sync();
-    const auto now = std::chrono::steady_clock::now();
-    prof.phase_ms[ph] += std::chrono::duration<double, std::milli>(now - t_mark).count();
-    t_mark = now;
-  };
-  if (prof.phases) ++prof.phase_calls;
-  std::vector<int> bp_bad(S, 0), bp_bad2(S, 0);  // scenes whose boxes overflowed the grid
   launch_cpos(V, s);
   // ---- active pairs at the current point: from the covering set of the previous
   // iteration when it is still valid, else from a static broad phase
@@ -1450,6 +1444,103 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   launch_compact_pairs(V, ncand, cqp, ctp, cflag.p, cpos_idx.p, pkind.p, pv.p, pmeps.p, pscene.p, s);
   zero(scnt.p, sizeof(int) * (S + 1));
   launch_count_scene(np, pscene.p, scnt.p, s);
+  return np;
+}
+
+// Gradient and Newton-system blocks of the iterating scenes at the current positions, for the
+// np pairs prepared above and the step's friction pairs after them (npf in all): element
+// derivatives, the static FEM blocks, and the contact and body blocks emitted, sorted by
+// (row, col) and reduced into the dynamic block rows.  Returns the device count of dynamic
+// blocks.
+int* Batch::Impl::derivatives(int np, int npf) {
+  hipStream_t s = stream();
+  View V = view();
+  // ---- element derivatives
+  // Three independent chains, joined before the contact blocks are reduced: the contact
+  // Hessians (one wavefront per pair: long and narrow) on the second stream, the FEM and
+  // affine-body terms with the static assembly on the third, and the emission and sort of the
+  // contact blocks here.
+  HIPCHECK(hipEventRecord(ev_fork, s));
+  HIPCHECK(hipStreamWaitEvent(mem.side, ev_fork, 0));
+  HIPCHECK(hipStreamWaitEvent(mem.side2, ev_fork, 0));
+  launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
+  HIPCHECK(hipEventRecord(ev_join, mem.side));
+  launch_fem_hess(V, mixed, mem.side2);
+  launch_body_hess(V, mem.side2);
+  launch_assemble_bsr(V, nnz, brow.p, mixed, mem.side2);
+  launch_assemble_grad(V, g.p, mem.side2);
+  HIPCHECK(hipEventRecord(ev_join2, mem.side2));
+  // ---- contact and body blocks: emit, sort by (row, col), reduce
+  if (nfric > 0) launch_fric_derivs(V, fric_bufs(), np, pv.p, pg.p, ph.p, s);
+  const int nitems = npf + Nb;
+  hcnt.ensure(&mem, std::max(nitems, 1));
+  gcnt.ensure(&mem, std::max(nitems, 1));
+  hoff.ensure(&mem, std::max(nitems, 1));
+  goff.ensure(&mem, std::max(nitems, 1));
+  launch_contrib_count(V, npf, pv.p, hcnt.p, gcnt.p, s);
+  scan_async(hcnt.p, hoff.p, nitems, scalars.p + 3);
+  scan_async(gcnt.p, goff.p, nitems, scalars.p + 4);
+  int hg[2];
+  d2h(hg, scalars.p + 3, 2);
+  sync();
+  const int nh = hg[0], ng = hg[1];
+  for (DBuf<uint64_t>* b : {&hkey, &hkey2}) b->ensure(&mem, std::max(nh, 1));
+  for (DBuf<int>* b : {&hidx, &hidx2, &hsrc}) b->ensure(&mem, std::max(nh, 1));
+  hcoef.ensure(&mem, std::max(nh, 1));
+  for (DBuf<uint64_t>* b : {&gkey, &gkey2}) b->ensure(&mem, std::max(ng, 1));
+  for (DBuf<int>* b : {&gidx, &gidx2, &gsrc}) b->ensure(&mem, std::max(ng, 1));
+  gcoef.ensure(&mem, std::max(ng, 1));
+  launch_contrib_emit(V, npf, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
+                      gsrc.p, gcoef.p, s);
+  sort(hkey.p, hidx.p, hkey2.p, hidx2.p, nh, bits_for((uint64_t)Nn * (uint64_t)Nn));
+  sort(gkey.p, gidx.p, gkey2.p, gidx2.p, ng, bits_for((uint64_t)Nn));
+  const int nmax = std::max(nh, ng);
+  sflag.ensure(&mem, std::max(nmax, 1));
+  segid.ensure(&mem, std::max(nmax, 1));
+  segstart.ensure(&mem, std::max(nmax, 1) + 1);
+  // Hessian blocks.  The segment counts stay on the device (scalars 6 and 7): the records
+  // bound them, so buffers and grids are sized by the record counts and the reductions read
+  // the exact counts themselves.
+  int* nseg_d = scalars.p + 6;
+  int* ngseg_d = scalars.p + 7;
+  launch_seg_flags(nh, hkey.p, sflag.p, s);
+  scan_async(sflag.p, segid.p, nh, nseg_d);
+  launch_seg_start(nh, sflag.p, segid.p, segstart.p, s);
+  drow.ensure(&mem, std::max(nh, 1));
+  dcol.ensure(&mem, std::max(nh, 1));
+  dval.ensure(&mem, 9 * (size_t)std::max(nh, 1));
+  zero(rowcnt.p, sizeof(int) * (Nn + 1));
+  HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
+  HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
+  launch_reduce_blocks(V, nh, nseg_d, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p,
+                       dcol.p, dval.p, rowcnt.p, mixed, s);
+  scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
+  // gradient entries
+  launch_seg_flags(ng, gkey.p, sflag.p, s);
+  scan_async(sflag.p, segid.p, ng, ngseg_d);
+  launch_seg_start(ng, sflag.p, segid.p, segstart.p, s);
+  launch_reduce_grad(V, ng, ngseg_d, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
+  return nseg_d;
+}
+
+void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_fail,
+                                   std::vector<int>& nan_, std::vector<int>& pcg_it,
+                                   std::vector<int>& n_active, std::vector<int>& halvings) {
+  hipStream_t s = stream();
+  View V = view();
+  Profiler& prof = profiler();
+  auto t_mark = std::chrono::steady_clock::now();
+  auto phase_end = [&](int ph) {  // profiling only: attribute the wall time since the last mark
+    if (!prof.phases) return;
+    sync();
+    const auto now = std::chrono::steady_clock::now();
+    prof.phase_ms[ph] += std::chrono::duration<double, std::milli>(now - t_mark).count();
+    t_mark = now;
+  };
+  if (prof.phases) ++prof.phase_calls;
+  std::vector<int> bp_bad(S, 0), bp_bad2(S, 0);  // scenes whose boxes overflowed the grid
+  const int np = prepare_pairs(bp_bad);
+  const int npf = np + nfric;
   phase_end(0);
   // Exact (unprojected) FEM and barrier Hessians for the scenes whose previous iteration of
   // this Newton loop took the full step with max vertex displacement <= 1e-2 dhat; the
@@ -1464,71 +1555,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   for (int attempt = 0;; ++attempt) {
     h2d(exact.p, exact_h.data(), S);
     zero(indef.p, sizeof(int) * S);
-    // ---- element derivatives
-    // Three independent chains, joined before the contact blocks are reduced: the contact
-    // Hessians (one wavefront per pair: long and narrow) on the second stream, the FEM and
-    // affine-body terms with the static assembly on the third, and the emission and sort of the
-    // contact blocks here.
-    HIPCHECK(hipEventRecord(ev_fork, s));
-    HIPCHECK(hipStreamWaitEvent(mem.side, ev_fork, 0));
-    HIPCHECK(hipStreamWaitEvent(mem.side2, ev_fork, 0));
-    launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
-    HIPCHECK(hipEventRecord(ev_join, mem.side));
-    launch_fem_hess(V, mixed, mem.side2);
-    launch_body_hess(V, mem.side2);
-    launch_assemble_bsr(V, nnz, brow.p, mixed, mem.side2);
-    launch_assemble_grad(V, g.p, mem.side2);
-    HIPCHECK(hipEventRecord(ev_join2, mem.side2));
-    // ---- contact and body blocks: emit, sort by (row, col), reduce
-    if (nfric > 0) launch_fric_derivs(V, fric_bufs(), np, pv.p, pg.p, ph.p, s);
-    const int nitems = npf + Nb;
-    hcnt.ensure(&mem, std::max(nitems, 1));
-    gcnt.ensure(&mem, std::max(nitems, 1));
-    hoff.ensure(&mem, std::max(nitems, 1));
-    goff.ensure(&mem, std::max(nitems, 1));
-    launch_contrib_count(V, npf, pv.p, hcnt.p, gcnt.p, s);
-    scan_async(hcnt.p, hoff.p, nitems, scalars.p + 3);
-    scan_async(gcnt.p, goff.p, nitems, scalars.p + 4);
-    int hg[2];
-    d2h(hg, scalars.p + 3, 2);
-    sync();
-    const int nh = hg[0], ng = hg[1];
-    for (DBuf<uint64_t>* b : {&hkey, &hkey2}) b->ensure(&mem, std::max(nh, 1));
-    for (DBuf<int>* b : {&hidx, &hidx2, &hsrc}) b->ensure(&mem, std::max(nh, 1));
-    hcoef.ensure(&mem, std::max(nh, 1));
-    for (DBuf<uint64_t>* b : {&gkey, &gkey2}) b->ensure(&mem, std::max(ng, 1));
-    for (DBuf<int>* b : {&gidx, &gidx2, &gsrc}) b->ensure(&mem, std::max(ng, 1));
-    gcoef.ensure(&mem, std::max(ng, 1));
-    launch_contrib_emit(V, npf, pv.p, hoff.p, goff.p, hkey.p, hidx.p, hsrc.p, hcoef.p, gkey.p, gidx.p,
-                        gsrc.p, gcoef.p, s);
-    sort(hkey.p, hidx.p, hkey2.p, hidx2.p, nh, bits_for((uint64_t)Nn * (uint64_t)Nn));
-    sort(gkey.p, gidx.p, gkey2.p, gidx2.p, ng, bits_for((uint64_t)Nn));
-    const int nmax = std::max(nh, ng);
-    sflag.ensure(&mem, std::max(nmax, 1));
-    segid.ensure(&mem, std::max(nmax, 1));
-    segstart.ensure(&mem, std::max(nmax, 1) + 1);
-    // Hessian blocks.  The segment counts stay on the device (scalars 6 and 7): the records
-    // bound them, so buffers and grids are sized by the record counts and the reductions read
-    // the exact counts themselves.
-    int* nseg_d = scalars.p + 6;
-    int* ngseg_d = scalars.p + 7;
-    launch_seg_flags(nh, hkey.p, sflag.p, s);
-    scan_async(sflag.p, segid.p, nh, nseg_d);
-    launch_seg_start(nh, sflag.p, segid.p, segstart.p, s);
-    drow.ensure(&mem, std::max(nh, 1));
-    dcol.ensure(&mem, std::max(nh, 1));
-    dval.ensure(&mem, 9 * (size_t)std::max(nh, 1));
-    zero(rowcnt.p, sizeof(int) * (Nn + 1));
-    HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
-    HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
-    launch_reduce_blocks(V, nh, nseg_d, hkey.p, hidx.p, segstart.p, hsrc.p, hcoef.p, ph.p, drow.p,
-                         dcol.p, dval.p, rowcnt.p, mixed, s);
-    scan_async(rowcnt.p, drowptr.p, Nn + 1, scalars.p + 5);
-    // gradient entries
-    launch_seg_flags(ng, gkey.p, sflag.p, s);
-    scan_async(sflag.p, segid.p, ng, ngseg_d);
-    launch_seg_start(ng, sflag.p, segid.p, segstart.p, s);
-    launch_reduce_grad(V, ng, ngseg_d, gkey.p, gidx.p, segstart.p, gsrc.p, gcoef.p, pg.p, g.p, s);
+    int* nseg_d = derivatives(np, npf);
     // ---- preconditioner and PCG
     zero(bad.p, sizeof(int) * S);
     launch_precond(V, drowptr.p, dcol.p, dval.p, pinv.p, bad.p, mixed, s);
@@ -1734,9 +1761,12 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   phase_end(5);
 }
 
-taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
-                                taccel_step_stats* stats, const int* mask) {
-  const auto t_start = std::chrono::steady_clock::now();
+// Start of a step for the scenes of mask (all when NULL): targets, prediction, the jump of the
+// moving Dirichlet vertices (infeasible_target flags scenes whose jump collides or inverts),
+// body penalties reset, start-of-step body residuals, and the bodies already on their target
+// snapped (snapped_host).
+void Batch::Impl::begin_step(const taccel_targets* tg, const int* mask,
+                             std::vector<int>& infeasible_target, std::vector<char>& snapped_host) {
   hipStream_t s = stream();
   View V = view();
   // ---- targets: body y* (host conversion of the public affine maps), moving vertices
@@ -1779,7 +1809,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   xn_valid = true;
   nfric = 0;
   if (any_fric) build_friction(mask);
-  std::vector<int> infeasible_target(S, 0);
+  infeasible_target.assign(S, 0);
   if (!hmove_nodes.empty()) {
     mv_nodes.upload(&mem, hmove_nodes);
     mv_tgt.upload(&mem, hmove);
@@ -1837,7 +1867,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
     }
   // a prescribed body already on its target (zero residual) is snapped before the first Newton
   // iteration: its constraint holds, and the relative snap test could never accept it
-  std::vector<char> snapped_host(Nb, 0);
+  snapped_host.assign(Nb, 0);
   {
     std::vector<int> held(Nb, 0);
     bool any_held = false;
@@ -1856,6 +1886,19 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       launch_al_apply(V, action.p, s);
     }
   }
+}
+
+taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_scene,
+                                taccel_step_stats* stats, const int* mask) {
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = stream();
+  View V = view();
+  std::vector<int> infeasible_target;
+  std::vector<char> snapped_host;
+  begin_step(tg, mask, infeasible_target, snapped_host);
+  unsigned long long* bres = u64s.p + 2 * S;
+  std::vector<unsigned long long> hres(Nb + 1);
+  int bglob = 0;
   std::fill(prev_alpha.begin(), prev_alpha.end(), 0.0);
   // ---- per-scene state machine
   enum { kNewton = 0, kDone = 1, kFailed = 2 };
@@ -2330,6 +2373,121 @@ taccel_status Batch::read_device(int k, taccel_field f, void* dst, size_t bytes)
   } catch (const ApiError& e) {
     set_last_error(e.what());
     impl_->discard_pending();
+    return e.st;
+  }
+}
+
+taccel_status Batch::debug_system(const taccel_targets* tg, double* grad, int32_t* brow_out,
+                                  int32_t* bcol_out, double* bval_out, int32_t cap,
+                                  int32_t* n_blocks) {
+  Impl& I = *impl_;
+  bool begun = false;
+  // the scene goes back to the start of the step whatever happens after begin_step
+  auto restore = [&]() {
+    if (!begun) return;
+    begun = false;
+    View V = I.view();
+    const int one = 1;
+    I.h2d(I.failflag.p, &one, 1);
+    launch_rollback(V, I.failflag.p, I.stream());
+    launch_body_clear_lambda(V, I.failflag.p, I.stream());
+    I.cover_valid = false;
+    I.sync();
+  };
+  try {
+    if (I.S != 1) throw ApiError(TACCEL_ERR_ARG, "debug_system works on a single scene");
+    if (!n_blocks || (cap > 0 && (!brow_out || !bcol_out || !bval_out)))
+      throw ApiError(TACCEL_ERR_ARG, "debug_system: NULL output");
+    const HostScene& H = I.hs[0];
+    std::vector<int> infeasible;
+    std::vector<char> snapped;
+    begun = true;
+    I.begin_step(tg, nullptr, infeasible, snapped);
+    if (infeasible[0]) throw ApiError(TACCEL_INFEASIBLE_TARGET, "debug_system: infeasible targets");
+    // the first Newton iteration of the step: projected Hessians, a fresh broad phase
+    I.act_host.assign(1, 1);
+    I.h2d(I.act.p, I.act_host.data(), 1);
+    I.exact_h.assign(1, 0);
+    I.h2d(I.exact.p, I.exact_h.data(), 1);
+    I.cover_valid = false;
+    std::vector<int> bp_bad(1, 0);
+    const int np = I.prepare_pairs(bp_bad);
+    I.derivatives(np, np + I.nfric);
+    const int Nn = I.Nn;
+    std::vector<double> g(3 * (size_t)Nn);
+    std::vector<int> rp(Nn + 1), drp(Nn + 1), cl(I.nnz), nf(Nn);
+    I.d2h(g.data(), I.g.p, g.size());
+    I.d2h(rp.data(), I.rowptr.p, rp.size());
+    I.d2h(drp.data(), I.drowptr.p, drp.size());
+    I.d2h(cl.data(), I.col.p, cl.size());
+    I.d2h(nf.data(), I.nfree.p, nf.size());
+    I.sync();
+    const int ndyn = drp[Nn];
+    std::vector<int> dcl(std::max(ndyn, 1));
+    std::vector<double> sv(9 * (size_t)I.nnz), dv(9 * (size_t)std::max(ndyn, 1));
+    I.d2h(dcl.data(), I.dcol.p, ndyn);
+    if (I.mixed) {
+      std::vector<float> a(sv.size()), b(dv.size());
+      I.d2h(a.data(), reinterpret_cast<const float*>(I.val.p), a.size());
+      I.d2h(b.data(), reinterpret_cast<const float*>(I.dval.p), 9 * (size_t)ndyn);
+      I.sync();
+      for (size_t k = 0; k < a.size(); ++k) sv[k] = a[k];
+      for (size_t k = 0; k < 9 * (size_t)ndyn; ++k) dv[k] = b[k];
+    } else {
+      I.d2h(sv.data(), I.val.p, sv.size());
+      I.d2h(dv.data(), I.dval.p, 9 * (size_t)ndyn);
+      I.sync();
+    }
+    restore();
+    // internal node -> caller's node (soft vertices in the caller's order, then 4 per body)
+    std::vector<int> ext(Nn, -1);
+    for (int u = 0; u < H.nv; ++u) ext[H.node0 + H.perm[u]] = u;
+    const int npad = (H.nv + 3) / 4 * 4;
+    for (int b = 0; b < H.nb; ++b)
+      for (int j = 0; j < 4; ++j) ext[H.node0 + npad + 4 * b + j] = H.nv + 4 * b + j;
+    const int next = H.nv + 4 * H.nb;
+    if (grad) {
+      std::fill(grad, grad + 3 * (size_t)next, 0.0);
+      for (int n = 0; n < Nn; ++n)
+        if (ext[n] >= 0 && nf[n])
+          for (int c = 0; c < 3; ++c) grad[3 * (size_t)ext[n] + c] = g[3 * (size_t)n + c];
+    }
+    std::vector<std::pair<std::pair<int, int>, std::array<double, 9>>> blocks;
+    auto add = [&](int r, int c, const double* v) {
+      if (ext[r] < 0 || ext[c] < 0 || !nf[r] || !nf[c]) return;
+      std::array<double, 9> a;
+      for (int k = 0; k < 9; ++k) a[k] = v[k];
+      blocks.push_back({{ext[r], ext[c]}, a});
+    };
+    for (int r = 0; r < Nn; ++r) {
+      for (int k = rp[r]; k < rp[r + 1]; ++k) add(r, cl[k], sv.data() + 9 * (size_t)k);
+      for (int k = drp[r]; k < drp[r + 1]; ++k) add(r, dcl[k], dv.data() + 9 * (size_t)k);
+    }
+    std::sort(blocks.begin(), blocks.end(),
+              [](const auto& a, const auto& b) { return a.first < b.first; });
+    int nb = 0;
+    for (size_t k = 0; k < blocks.size(); ++k) {
+      if (nb > 0 && blocks[k].first == blocks[k - 1].first) {
+        if (nb <= cap)
+          for (int e = 0; e < 9; ++e) bval_out[9 * (size_t)(nb - 1) + e] += blocks[k].second[e];
+        continue;
+      }
+      if (nb < cap) {
+        brow_out[nb] = blocks[k].first.first;
+        bcol_out[nb] = blocks[k].first.second;
+        for (int e = 0; e < 9; ++e) bval_out[9 * (size_t)nb + e] = blocks[k].second[e];
+      }
+      ++nb;
+    }
+    *n_blocks = nb;
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    try {
+      restore();
+    } catch (const ApiError&) {
+    }
     return e.st;
   }
 }

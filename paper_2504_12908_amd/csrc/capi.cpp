@@ -206,6 +206,13 @@ void taccel_scene_destroy(taccel_scene* s) {
   delete s;
 }
 
+taccel_status taccel_debug_system(taccel_scene* s, const taccel_targets* t, double* grad,
+                                  int32_t* brow, int32_t* bcol, double* bval, int32_t cap,
+                                  int32_t* n_blocks) {
+  if (!s) return fail(TACCEL_ERR_ARG, "debug_system: NULL scene");
+  return s->b->debug_system(t, grad, brow, bcol, bval, cap, n_blocks);
+}
+
 taccel_status taccel_debug_candidates(taccel_scene* s, const double* P0, const double* P1, int32_t* out,
                                       int32_t cap, int32_t* n) {
   if (!s || !P0 || !n || (cap > 0 && !out)) return fail(TACCEL_ERR_ARG, "debug_candidates: bad arguments");

@@ -108,6 +108,8 @@ class Batch {
   taccel_status read_device(int scene, taccel_field f, void* dst, size_t bytes);
   // creation state for the scenes with mask[k] != 0 (all when mask is NULL)
   taccel_status reset(const uint8_t* mask);
+  taccel_status debug_system(const taccel_targets* t, double* grad, int32_t* brow, int32_t* bcol,
+                             double* bval, int32_t cap, int32_t* n_blocks);
   taccel_status debug_candidates(const double* P0, const double* P1, int32_t* out, int32_t cap,
                                  int32_t* n);
   taccel_status markers(int scene, int m, const int32_t* tris, const double* bary, double* pos,

@@ -168,6 +168,8 @@ def lib():
                                             _dp]
         L.taccel_debug_arap.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.taccel_debug_candidates.argtypes = [C.c_void_p, _dp, _dp, _ip, C.c_int32, _ip]
+        L.taccel_debug_system.argtypes = [C.c_void_p, C.POINTER(taccel_targets), _dp, _ip, _ip,
+                                          _dp, C.c_int32, _ip]
         L.taccel_server_create.argtypes = [C.POINTER(taccel_server_params),
                                            C.POINTER(taccel_runtime), C.POINTER(C.c_void_p)]
         L.taccel_server_submit.argtypes = [C.c_void_p, C.POINTER(taccel_scene_desc), C.c_int32,
@@ -372,6 +374,25 @@ class Scene:
     def depth_map(self, cam, tris):
         """Depth (H, W) and normal (H, W, 3) maps of the surface ``tris`` (taccel_depth_map)."""
         return _depth_map(lib().taccel_depth_map, (self.h,), cam, tris)
+
+    def debug_system(self, k=None, body_targets=None, dirichlet_targets=None):
+        """Newton system of the first iteration of step k (taccel_debug_system): gradient
+        (nv + 4 nb, 3) and {(row, col): 3x3} blocks in the caller's node numbering."""
+        t = _Targets(self.spec, k, body_targets, dirichlet_targets)
+        nn = self._d.nv + 4 * self._d.nb
+        grad = np.zeros((nn, 3))
+        n = C.c_int32()
+        _check(lib().taccel_debug_system(self.h, C.byref(t.t), _d(grad), None, None, None, 0,
+                                         C.byref(n)), "debug_system")
+        cap = n.value
+        rows = np.zeros(max(cap, 1), dtype=np.int32)
+        cols = np.zeros(max(cap, 1), dtype=np.int32)
+        vals = np.zeros((max(cap, 1), 9))
+        _check(lib().taccel_debug_system(self.h, C.byref(t.t), _d(grad), _i(rows), _i(cols),
+                                         _d(vals), cap, C.byref(n)), "debug_system")
+        blocks = {(int(r), int(c)): vals[i].reshape(3, 3)
+                  for i, (r, c) in enumerate(zip(rows[:n.value], cols[:n.value]))}
+        return grad, blocks
 
     def candidates(self, P0, P1=None):
         P0 = _f64(P0)

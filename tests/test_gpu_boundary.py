@@ -128,3 +128,56 @@ def test_batch_reset_mask(T):
             assert np.array_equal(b.read(i, T.FIELD_V), np.zeros_like(specs[i].verts))
             assert b.stats(i)["newton_iters"] == 0
     b.close()
+
+
+def _oracle_system_in_caller_nodes(o, nv, nb):
+    e, G, blocks, node_of = o.system()
+    to_ext = {}
+    for i in range(nv):
+        if node_of[i] >= 0:
+            to_ext[int(node_of[i])] = i
+    for b in range(nb):
+        if node_of[nv + b] >= 0:
+            for j in range(4):
+                to_ext[int(node_of[nv + b]) + j] = nv + 4 * b + j
+    g = np.zeros((nv + 4 * nb, 3))
+    for n, ext in to_ext.items():
+        g[ext] = G[n]
+    H = {(to_ext[r], to_ext[c]): v for (r, c), v in blocks.items()}
+    return g, H
+
+
+@pytest.mark.parametrize("case", ["cube_step0", "cube_step6_teacher_forced", "friction_step2"])
+def test_newton_system_matches_oracle(T, oracle_lib, case):
+    """The assembled Newton system (gradient and every 3x3 block of the projected Hessian) of
+    the first iteration of a step, GPU against the oracle's plain assembly: the same block
+    pattern, and every entry within 1e-12 of the largest (measured: about 2e-15)."""
+    B = oracle_lib
+    if case.startswith("friction"):
+        spec = S.pad_press_slide_friction(0, n_steps=6)
+    else:
+        spec = S.pad_press_cube(0)
+    k = {"cube_step0": 0, "cube_step6_teacher_forced": 6, "friction_step2": 2}[case]
+    g = T.Scene(spec)
+    o = B.OracleScene(spec)
+    for j in range(k):
+        assert o.step(j)[0] == 0
+    if k:
+        g.set_state(*o.get_state())  # also clears the GPU's carried multipliers
+    grad, H = g.debug_system(k)
+    assert o.step_begin(k) == 0
+    nv, nb = len(spec.verts), len(spec.bodies)
+    go, Ho = _oracle_system_in_caller_nodes(o, nv, nb)
+    gs = np.abs(go).max()
+    hs = max(np.abs(v).max() for v in Ho.values())
+    say(f"{case}: {len(H)} blocks (oracle {len(Ho)}), |G| {gs:.3e}, |H| {hs:.3e}")
+    assert set(H) == set(Ho)
+    assert np.abs(grad - go).max() <= 1e-12 * gs
+    err = max(np.abs(H[key] - Ho[key]).max() for key in Ho)
+    say(f"  max |dG| {np.abs(grad - go).max():.3e}, max |dH| {err:.3e}")
+    assert err <= 1e-12 * hs
+    # the call leaves the state where it was: the step itself still matches the oracle's
+    rc, st = g.step(k)
+    assert rc == T.OK and o.step_finish()[0] == 0
+    assert np.abs(g.read(T.FIELD_X) - o.get_state()[0]).max() <= 1e-8 * o.scale
+    g.close()
