@@ -195,8 +195,8 @@ struct Batch::Impl {
   DBuf<double> x, xn, xhat, v, mass;
   DBuf<int> nfree, nscene, nbody, ntype;
   DBuf<int> tv, tscene;
-  DBuf<double> Dminv, tvol, Hloc, gloc;
-  DBuf<int> rowptr, col, diag, cptr, clist, vptr, vlist, brow;
+  DBuf<double> Dminv, tvol;
+  DBuf<int> rowptr, col, diag, vptr, vlist;
   DBuf<double> val;
   DBuf<int> bnode, bscene, bpres, bsnap, bcv0, bcv1;
   DBuf<double> bmass, bvol, bstar, blam, bkap, bgrad, bhess, bpinv;
@@ -324,10 +324,10 @@ struct Batch::Impl {
     View V;
     V.S = S; V.Nn = Nn; V.Nt = Nt; V.Nb = Nb; V.Ncv = Ncv; V.Ntr = Ntr; V.Ned = Ned; V.Nq = Nq;
     V.sc = d_sc.p;
-    V.x = x.p; V.xn = xn.p; V.xhat = xhat.p; V.v = v.p; V.mass = mass.p;
+    V.x = x.p; V.xrest = xrest.p; V.xn = xn.p; V.xhat = xhat.p; V.v = v.p; V.mass = mass.p;
     V.nfree = nfree.p; V.nscene = nscene.p; V.nbody = nbody.p; V.ntype = ntype.p;
-    V.tv = tv.p; V.Dminv = Dminv.p; V.tvol = tvol.p; V.tscene = tscene.p; V.Hloc = Hloc.p; V.gloc = gloc.p;
-    V.rowptr = rowptr.p; V.col = col.p; V.val = val.p; V.diag = diag.p; V.cptr = cptr.p; V.clist = clist.p;
+    V.tv = tv.p; V.Dminv = Dminv.p; V.tvol = tvol.p; V.tscene = tscene.p;
+    V.rowptr = rowptr.p; V.col = col.p; V.val = val.p; V.diag = diag.p;
     V.vptr = vptr.p; V.vlist = vlist.p;
     V.bnode = bnode.p; V.bscene = bscene.p; V.bmass = bmass.p; V.bvol = bvol.p; V.bpres = bpres.p;
     V.bstar = bstar.p; V.blam = blam.p; V.bkap = bkap.p; V.bsnap = bsnap.p; V.bgrad = bgrad.p;
@@ -474,7 +474,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   std::vector<int> tn_sc_h, tn_b0_h, tn_b1_h, tn_sblk_h, tt_sc_h, tt_b0_h, tt_b1_h, tt_sblk_h;
   std::vector<int> ts_sc_h, ts_b0_h, ts_b1_h, ts_sblk_h;
   // static BSR built per scene and concatenated
-  std::vector<int> h_rowptr(1, 0), h_col, h_diag, h_cptr(1, 0), h_clist, h_vptr(1, 0), h_vlist, h_brow;
+  std::vector<int> h_rowptr(1, 0), h_col, h_diag, h_vptr(1, 0), h_vlist;
   for (int s = 0; s < S; ++s) {
     const taccel_scene_desc& du = descs[s];  // caller's vertex order
     HostScene& H = hs[s];
@@ -606,14 +606,6 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
         for (int j : a) {
           if (j == i) dpos = (int)h_col.size();
           h_col.push_back(node0 + j);
-          h_brow.push_back(node);
-          // contributions (tet, a, b) with tet vertex a = i and b = j
-          for (int code : inc[i]) {
-            const int tet = code >> 2, la = code & 3;
-            for (int lb = 0; lb < 4; ++lb)
-              if (h_tv_aos[4 * tet + lb] == node0 + j) h_clist.push_back(16 * tet + 4 * la + lb);
-          }
-          h_cptr.push_back((int)h_clist.size());
         }
         h_diag.push_back(dpos);
         for (int code : inc[i]) h_vlist.push_back(code);
@@ -954,16 +946,11 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   tscene.upload(m, h_tscene);
   Dminv.upload(m, h_Dminv);
   tvol.upload(m, h_tvol);
-  Hloc.ensure(m, 144 * (size_t)Nt);
-  gloc.ensure(m, 12 * (size_t)Nt);
   rowptr.upload(m, h_rowptr);
   col.upload(m, h_col);
   diag.upload(m, h_diag);
-  cptr.upload(m, h_cptr);
-  clist.upload(m, h_clist);
   vptr.upload(m, h_vptr);
   vlist.upload(m, h_vlist);
-  brow.upload(m, h_brow);
   val.ensure(m, 9 * (size_t)nnz);
   bnode.upload(m, h_bnode);
   bscene.upload(m, h_bscene);
@@ -1465,10 +1452,8 @@ int* Batch::Impl::derivatives(int np, int npf) {
   HIPCHECK(hipStreamWaitEvent(mem.side2, ev_fork, 0));
   launch_barrier_hess(V, np, pkind.p, pv.p, pmeps.p, pg.p, ph.p, mem.side);
   HIPCHECK(hipEventRecord(ev_join, mem.side));
-  launch_fem_hess(V, mixed, mem.side2);
+  launch_fem_rows(V, g.p, mixed, mem.side2);
   launch_body_hess(V, mem.side2);
-  launch_assemble_bsr(V, nnz, brow.p, mixed, mem.side2);
-  launch_assemble_grad(V, g.p, mem.side2);
   HIPCHECK(hipEventRecord(ev_join2, mem.side2));
   // ---- contact and body blocks: emit, sort by (row, col), reduce
   if (nfric > 0) launch_fric_derivs(V, fric_bufs(), np, pv.p, pg.p, ph.p, s);
@@ -2066,12 +2051,12 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
 size_t Batch::Impl::device_bytes() const {
   size_t n = 0;
   auto add = [&](const auto& buf) { n += buf.cap * sizeof(*buf.p); };
-  add(x); add(xn); add(xhat); add(v); add(mass); add(Dminv); add(tvol); add(Hloc); add(gloc); add(val);
+  add(x); add(xn); add(xhat); add(v); add(mass); add(Dminv); add(tvol); add(val);
   add(bmass); add(bvol); add(bstar); add(blam); add(bkap); add(bgrad); add(bhess); add(bpinv); add(cvx);
   add(cpos); add(cdisp); add(cend); add(elen2); add(bp_tbox); add(pmeps); add(pg); add(ph); add(hcoef);
   add(gcoef); add(dval); add(g); add(r); add(z); add(p); add(p1); add(q); add(dx); add(pinv);
   add(nfree); add(nscene); add(nbody); add(ntype); add(tv); add(tscene); add(rowptr); add(col);
-  add(diag); add(cptr); add(clist); add(vptr); add(vlist); add(brow); add(cvn); add(cvb); add(cvfix);
+  add(diag); add(vptr); add(vlist); add(cvn); add(cvb); add(cvfix);
   add(cvscene); add(cvworld); add(trv); add(edv); add(qkind); add(qidx); add(qscene); add(bp_tcell);
   add(bp_tncell); add(bp_toff); add(bp_bcount); add(bp_bstart); add(bp_bfill); add(bp_qcount);
   add(bp_qoff); add(bp_entries); add(cq); add(ct); add(sq); add(st); add(cflag); add(cpos_idx);
@@ -2147,7 +2132,7 @@ Batch::~Batch() {
   if (I.pcg_exec) (void)hipGraphExecDestroy(I.pcg_exec);
   if (I.pcg_graph) (void)hipGraphDestroy(I.pcg_graph);
 #define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
-  FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.Hloc, &I.gloc, &I.val, &I.bmass,
+  FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.val, &I.bmass,
            &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,
            &I.cend, &I.elen2, &I.bp_tbox, &I.pmeps, &I.pg, &I.ph, &I.hcoef, &I.gcoef, &I.dval, &I.g, &I.r,
            &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
@@ -2163,8 +2148,8 @@ Batch::~Batch() {
            &I.cg_sc_tsn, &I.cg_sc_tsend, &I.bp_tmp)
   FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc, &I.P_qc, &I.cg_rca0, &I.cg_rca1, &I.cg_dw)
   I.cg_sc_off.free();
-  FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag, &I.cptr,
-           &I.clist, &I.vptr, &I.vlist, &I.brow, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,
+  FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag,
+           &I.vptr, &I.vlist, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,
            &I.cvn, &I.cvb, &I.cvfix, &I.cvscene, &I.cvworld, &I.trv, &I.edv, &I.qkind, &I.qidx, &I.qscene,
            &I.act, &I.pdone, &I.exact, &I.indef, &I.tn_sc, &I.tn_b0, &I.tn_b1, &I.tn_sblk, &I.tt_sc, &I.tt_b0, &I.tt_b1,
            &I.tt_sblk, &I.bp_tcell, &I.bp_tncell, &I.bp_toff, &I.bp_bcount, &I.bp_bstart, &I.bp_bfill,

@@ -24,12 +24,24 @@ TC_HD d3 cross(const d3& a, const d3& b) {
 TC_HD double at(const d3& a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
 
 // 3x3 matrices are row-major double[9].
-TC_HD double det3(const double* A) {
+// Scalar traits of the templated 3x3 routines: the Jacobi stopping ratio (off-diagonal over
+// diagonal mass, about the square of the unit roundoff) and a tiny positive norm.
+template <class R> struct Tiny;
+template <> struct Tiny<double> {
+  static constexpr double jacobi = 1e-34, norm = 1e-300;
+};
+template <> struct Tiny<float> {
+  static constexpr float jacobi = 1e-14f, norm = 1e-30f;
+};
+
+template <class R>
+TC_HD R det3(const R* A) {
   return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
          A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 // Cofactor matrix (= det(A) * A^{-T}).
-TC_HD void cofactor3(const double* A, double* C) {
+template <class R>
+TC_HD void cofactor3(const R* A, R* C) {
   C[0] = A[4] * A[8] - A[5] * A[7];
   C[1] = A[5] * A[6] - A[3] * A[8];
   C[2] = A[3] * A[7] - A[4] * A[6];
@@ -40,13 +52,15 @@ TC_HD void cofactor3(const double* A, double* C) {
   C[7] = A[2] * A[3] - A[0] * A[5];
   C[8] = A[0] * A[4] - A[1] * A[3];
 }
-TC_HD void matmul3(const double* A, const double* B, double* C) {
+template <class R>
+TC_HD void matmul3(const R* A, const R* B, R* C) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
 }
 // C = A * B^T
-TC_HD void matmul3_bt(const double* A, const double* B, double* C) {
+template <class R>
+TC_HD void matmul3_bt(const R* A, const R* B, R* C) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       C[3 * i + j] = A[3 * i] * B[3 * j] + A[3 * i + 1] * B[3 * j + 1] + A[3 * i + 2] * B[3 * j + 2];
@@ -55,31 +69,32 @@ TC_HD void matmul3_bt(const double* A, const double* B, double* C) {
 // Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations.  A is row-major and is
 // destroyed; on return w holds the eigenvalues and V (row-major) the eigenvectors as
 // columns.
-TC_HD void sym_eig3(double* A, double* w, double* V) {
-  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+template <class R>
+TC_HD void sym_eig3(R* A, R* w, R* V) {
+  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? R(1) : R(0);
   for (int sweep = 0; sweep < 10; ++sweep) {
-    const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
-    const double dia = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
-    if (off <= 1e-34 * dia || off == 0.0) break;
+    const R off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    const R dia = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+    if (off <= Tiny<R>::jacobi * dia || off == R(0)) break;
     for (int pq = 0; pq < 3; ++pq) {
       const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
-      const double apq = A[3 * p + q];
-      if (apq == 0.0) continue;
-      const double theta = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
-      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      const R apq = A[3 * p + q];
+      if (apq == R(0)) continue;
+      const R theta = (A[3 * q + q] - A[3 * p + p]) / (R(2) * apq);
+      const R t = (theta >= R(0) ? R(1) : R(-1)) / (fabs(theta) + sqrt(theta * theta + R(1)));
+      const R c = R(1) / sqrt(t * t + R(1)), s = t * c;
       for (int k = 0; k < 3; ++k) {
-        const double akp = A[3 * k + p], akq = A[3 * k + q];
+        const R akp = A[3 * k + p], akq = A[3 * k + q];
         A[3 * k + p] = c * akp - s * akq;
         A[3 * k + q] = s * akp + c * akq;
       }
       for (int k = 0; k < 3; ++k) {
-        const double apk = A[3 * p + k], aqk = A[3 * q + k];
+        const R apk = A[3 * p + k], aqk = A[3 * q + k];
         A[3 * p + k] = c * apk - s * aqk;
         A[3 * q + k] = s * apk + c * aqk;
       }
       for (int k = 0; k < 3; ++k) {
-        const double vkp = V[3 * k + p], vkq = V[3 * k + q];
+        const R vkp = V[3 * k + p], vkq = V[3 * k + q];
         V[3 * k + p] = c * vkp - s * vkq;
         V[3 * k + q] = s * vkp + c * vkq;
       }
@@ -93,8 +108,9 @@ TC_HD void sym_eig3(double* A, double* w, double* V) {
 // Rotation-variant SVD F = U diag(s) V^T with det U = det V = +1 (s[2] carries the sign
 // of det F), singular values in decreasing order of magnitude.  V from the eigenvectors of
 // F^T F; U by Gram-Schmidt on the columns of F V.
-TC_HD void svd3(const double* F, double* U, double* s, double* V) {
-  double A[9], w[3];
+template <class R>
+TC_HD void svd3(const R* F, R* U, R* s, R* V) {
+  R A[9], w[3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       A[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
@@ -103,35 +119,49 @@ TC_HD void svd3(const double* F, double* U, double* s, double* V) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2 - a; ++b)
       if (w[b] < w[b + 1]) {
-        const double tw = w[b]; w[b] = w[b + 1]; w[b + 1] = tw;
+        const R tw = w[b]; w[b] = w[b + 1]; w[b + 1] = tw;
         for (int k = 0; k < 3; ++k) {
-          const double tv = V[3 * k + b]; V[3 * k + b] = V[3 * k + b + 1]; V[3 * k + b + 1] = tv;
+          const R tv = V[3 * k + b]; V[3 * k + b] = V[3 * k + b + 1]; V[3 * k + b + 1] = tv;
         }
       }
-  if (det3(V) < 0.0)
+  if (det3(V) < R(0))
     for (int k = 0; k < 3; ++k) V[3 * k + 2] = -V[3 * k + 2];
-  double B[9];
+  R B[9];
   matmul3(F, V, B);
-  d3 b0 = mk(B[0], B[3], B[6]), b1 = mk(B[1], B[4], B[7]), b2 = mk(B[2], B[5], B[8]);
-  double n0 = sqrt(dot(b0, b0));
-  d3 u0 = n0 > 0.0 ? (1.0 / n0) * b0 : mk(1, 0, 0);
-  d3 r1 = b1 - dot(u0, b1) * u0;
-  double n1 = sqrt(dot(r1, r1));
-  d3 u1;
-  if (n1 > 1e-300) {
-    u1 = (1.0 / n1) * r1;
-  } else {  // any unit vector orthogonal to u0
-    d3 t = fabs(u0.x) < 0.9 ? mk(1, 0, 0) : mk(0, 1, 0);
-    t = t - dot(u0, t) * u0;
-    u1 = (1.0 / sqrt(dot(t, t))) * t;
+  // columns b_j of F V; u0 = b0 / |b0|, u1 from b1 orthogonalised against u0, u2 = u0 x u1
+  const R b0[3] = {B[0], B[3], B[6]}, b1[3] = {B[1], B[4], B[7]}, b2[3] = {B[2], B[5], B[8]};
+  const R n0 = sqrt(b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2]);
+  R u0[3];
+  if (n0 > R(0)) {
+    for (int k = 0; k < 3; ++k) u0[k] = b0[k] / n0;
+  } else {
+    u0[0] = R(1); u0[1] = R(0); u0[2] = R(0);
   }
-  d3 u2 = cross(u0, u1);
+  const R d01 = u0[0] * b1[0] + u0[1] * b1[1] + u0[2] * b1[2];
+  R r1[3];
+  for (int k = 0; k < 3; ++k) r1[k] = b1[k] - d01 * u0[k];
+  const R n1 = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+  R u1[3];
+  if (n1 > Tiny<R>::norm) {
+    for (int k = 0; k < 3; ++k) u1[k] = r1[k] / n1;
+  } else {  // any unit vector orthogonal to u0
+    R t[3] = {R(0), R(0), R(0)};
+    t[fabs(u0[0]) < R(0.9) ? 0 : 1] = R(1);
+    const R d = u0[0] * t[0] + u0[1] * t[1] + u0[2] * t[2];
+    for (int k = 0; k < 3; ++k) t[k] -= d * u0[k];
+    const R nt = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int k = 0; k < 3; ++k) u1[k] = t[k] / nt;
+  }
+  const R u2[3] = {u0[1] * u1[2] - u0[2] * u1[1], u0[2] * u1[0] - u0[0] * u1[2],
+                   u0[0] * u1[1] - u0[1] * u1[0]};
   s[0] = n0;
-  s[1] = dot(u1, b1);
-  s[2] = dot(u2, b2);
-  U[0] = u0.x; U[3] = u0.y; U[6] = u0.z;
-  U[1] = u1.x; U[4] = u1.y; U[7] = u1.z;
-  U[2] = u2.x; U[5] = u2.y; U[8] = u2.z;
+  s[1] = u1[0] * b1[0] + u1[1] * b1[1] + u1[2] * b1[2];
+  s[2] = u2[0] * b2[0] + u2[1] * b2[1] + u2[2] * b2[2];
+  for (int k = 0; k < 3; ++k) {
+    U[3 * k] = u0[k];
+    U[3 * k + 1] = u1[k];
+    U[3 * k + 2] = u2[k];
+  }
 }
 
 // Projected Hessian of an isotropic energy psi(sigma) in F space, as 9 rank-one modes

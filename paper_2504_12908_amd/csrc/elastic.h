@@ -36,14 +36,45 @@ TC_HD void nh_stress(const double* F, double mu, double lam, double* P) {
   for (int k = 0; k < 9; ++k) P[k] = mu * F[k] + (lam * lnJ - mu) * C[k] * invJ;
 }
 
+// The same stress in single precision from the displacement gradient G = F - I, in forms
+// without the cancellations of F - F^{-T} and ln J near the rest state:
+//   F - F^{-T} = F^{-T} (G + G^T + G^T G),  J - 1 = tr G + (tr^2 G - tr G^2)/2 + det G,
+//   ln J = log1p(J - 1),  P = mu (F - F^{-T}) + lambda ln J F^{-T}.
+TC_HD void nh_stress_disp(const float* G, float mu, float lam, float* P) {
+  float F[9], C[9];
+  for (int k = 0; k < 9; ++k) F[k] = G[k] + ((k % 4 == 0) ? 1.0f : 0.0f);
+  cofactor3(F, C);
+  const float trG = G[0] + G[4] + G[8];
+  float trG2 = 0.0f;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) trG2 += G[3 * i + j] * G[3 * j + i];
+  const float Jm1 = trG + 0.5f * (trG * trG - trG2) + det3(G);
+  const float J = 1.0f + Jm1;
+  const float lnJ = log1pf(Jm1);
+  // E2 = G + G^T + G^T G (= F^T F - I); F^{-T} = C / J
+  float E2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      E2[3 * i + j] = G[3 * i + j] + G[3 * j + i] +
+                      (G[i] * G[j] + G[3 + i] * G[3 + j] + G[6 + i] * G[6 + j]);
+  const float invJ = 1.0f / J;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      // (F^{-T} E2)_{ij} = sum_k C_ik E2_kj / J
+      const float fe = (C[3 * i] * E2[j] + C[3 * i + 1] * E2[3 + j] + C[3 * i + 2] * E2[6 + j]) * invJ;
+      P[3 * i + j] = mu * fe + lam * lnJ * C[3 * i + j] * invJ;
+    }
+}
+
 // Vertex-space pull-back of an F-space matrix M: w = vol * B^T vec(M), i.e. the columns of
 // M D_m^{-T} for vertices 1..3 and minus their sum for vertex 0.
-TC_HD void pullback(const double* M, const double* Dminv, double scale, double* w12) {
+template <class R>
+TC_HD void pullback(const R* M, const R* Dminv, R scale, R* w12) {
   for (int i = 0; i < 3; ++i) {
-    double s = 0.0;
+    R s = R(0);
     for (int a = 0; a < 3; ++a) {
-      const double v = scale * (M[3 * i] * Dminv[3 * a] + M[3 * i + 1] * Dminv[3 * a + 1] +
-                                M[3 * i + 2] * Dminv[3 * a + 2]);
+      const R v = scale * (M[3 * i] * Dminv[3 * a] + M[3 * i + 1] * Dminv[3 * a + 1] +
+                           M[3 * i + 2] * Dminv[3 * a + 2]);
       w12[3 * (a + 1) + i] = v;
       s += v;
     }
@@ -52,26 +83,29 @@ TC_HD void pullback(const double* M, const double* Dminv, double scale, double* 
 }
 
 // Eigen-structure of an isotropic energy at F: SVD and the 9 mode eigenvalues.
-struct Modes {
-  double U[9], V[9], E[9];  // E: eigenvectors of the 3x3 sigma-Hessian (columns)
-  double lam[9];            // 0..2 scaling, then (twist, flip) for pairs (0,1),(0,2),(1,2)
+template <class R>
+struct ModesT {
+  R U[9], V[9], E[9];  // E: eigenvectors of the 3x3 sigma-Hessian (columns)
+  R lam[9];            // 0..2 scaling, then (twist, flip) for pairs (0,1),(0,2),(1,2)
 };
+using Modes = ModesT<double>;
 
-TC_HD void nh_modes(const double* F, double mu, double lam, Modes& m) {
-  double s[3];
+template <class R>
+TC_HD void nh_modes(const R* F, R mu, R lam, ModesT<R>& m) {
+  R s[3];
   svd3(F, m.U, s, m.V);
-  const double lnJ = log(det3(F));
-  double hs[9];
+  const R lnJ = log(det3(F));
+  R hs[9];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
-      hs[3 * i + j] = i == j ? mu + (mu + lam * (1.0 - lnJ)) / (s[i] * s[i]) : lam / (s[i] * s[j]);
-  double A[9], w[3];
+      hs[3 * i + j] = i == j ? mu + (mu + lam * (R(1) - lnJ)) / (s[i] * s[i]) : lam / (s[i] * s[j]);
+  R A[9], w[3];
   for (int k = 0; k < 9; ++k) A[k] = hs[k];
   sym_eig3(A, w, m.E);
   for (int k = 0; k < 3; ++k) m.lam[k] = w[k];
   const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
   for (int p = 0; p < 3; ++p) {
-    const double inv = 1.0 / (s[pa[p]] * s[pb[p]]);
+    const R inv = R(1) / (s[pa[p]] * s[pb[p]]);
     m.lam[3 + 2 * p] = mu + (lam * lnJ - mu) * inv;      // twist
     m.lam[4 + 2 * p] = mu + (mu - lam * lnJ) * inv;      // flip
   }
@@ -95,7 +129,8 @@ TC_HD void arap_modes(const double* A, Modes& m, double* e, double* grad /*9, ro
 }
 
 // F-space matrix Q_k of mode k (row-major).
-TC_HD void mode_matrix(const Modes& m, int k, double* Q) {
+template <class R>
+TC_HD void mode_matrix(const ModesT<R>& m, int k, R* Q) {
   if (k < 3) {
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j)
@@ -104,9 +139,9 @@ TC_HD void mode_matrix(const Modes& m, int k, double* Q) {
     return;
   }
   const int p = (k - 3) >> 1;
-  const double sb = ((k - 3) & 1) ? 1.0 : -1.0;
+  const R sb = ((k - 3) & 1) ? R(1) : R(-1);
   const int a = p == 2 ? 1 : 0, b = p == 0 ? 1 : 2;
-  const double r = 0.70710678118654752440;
+  const R r = R(0.70710678118654752440);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       Q[3 * i + j] = r * (m.U[3 * i + a] * m.V[3 * j + b] + sb * m.U[3 * i + b] * m.V[3 * j + a]);

@@ -75,14 +75,14 @@ void launch_contact_records(const View& V, int n, const int* cand_q, const int* 
 void launch_gather3(int n, const int* idx, const double* src, double* out, hipStream_t s);
 void launch_body_public(int nb, const double* y, const double* com0, double* out, hipStream_t s);
 void launch_count_scene(int n, const int* pscene, int* cnt, hipStream_t s);
-void launch_fem_hess(const View& V, int mixed, hipStream_t s);
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
                          const double* pmeps, double* pg, double* ph, hipStream_t s);
 void launch_body_hess(const View& V, hipStream_t s);
 
 // assembly
-void launch_assemble_bsr(const View& V, int nnz, const int* brow, int mixed, hipStream_t s);
-void launch_assemble_grad(const View& V, double* g, hipStream_t s);
+// Static block rows of the Newton system (elasticity and lumped mass) and the gradient of
+// every node (inertia and elasticity; zero for body and padding nodes) of the iterating scenes.
+void launch_fem_rows(const View& V, double* g, int mixed, hipStream_t s);
 void launch_contrib_count(const View& V, int np, const int* pv, int* hcnt, int* gcnt,
                           hipStream_t s);
 void launch_contrib_emit(const View& V, int np, const int* pv, const int* hoff, const int* goff,

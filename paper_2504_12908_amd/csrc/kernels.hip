@@ -547,49 +547,143 @@ __global__ void k_body_public(int nb, const double* y, const double* com0, doubl
   }
 }
 
-// ------------------------------------------------------------------ FEM (4 lanes per tet)
+// ------------------------------------------------------------------ FEM (one block-row per 32 lanes)
+// Static rows of the Newton system straight from the tets: for soft node n, every tet that
+// contains it (as its vertex a) is evaluated by one lane, which forms the tet's gradient entry
+// at a and the four 3x3 blocks (a, b) of its 12x12 Hessian (the analytic singular-value
+// eigensystem of the neo-Hookean density, every mode or only those of positive eigenvalue,
+// pulled back to vertex space); the row's lanes then sum them per stored block in the tets'
+// fixed order, add the lumped mass on the diagonal and write the row of the BSR and the
+// node's gradient (inertia plus elasticity).  Nothing per tet goes to memory.  T is the
+// type of the Hessian arithmetic and of the stored blocks: FP64, or FP32 in mixed precision,
+// where the gradient entry also comes in FP32 from the displacement gradient G = F - I
+// (formed from FP64 displacement differences) and is summed in FP64.
+constexpr int kFemRowLanes = 32, kFemRows = 4, kFemChunk = 24;
+
+// Entries 3a..3a+2 of a 12-vector, by selects rather than a dynamic index (which would put
+// the vector in scratch memory).
 template <class T>
-__global__ void __launch_bounds__(TPB) k_fem_hess(View V) {
-  const int g = gid();
-  const int t = g >> 2, a = g & 3;
-  if (t >= V.Nt) return;
-  const int s = V.tscene[t];
-  if (!V.act[s]) return;
-  const SceneConst& sc = V.sc[s];
+__device__ __forceinline__ void pick3(const T* w, int a, T* out) {
+  for (int i = 0; i < 3; ++i)
+    out[i] = a == 0 ? w[i] : (a == 1 ? w[3 + i] : (a == 2 ? w[6 + i] : w[9 + i]));
+}
+
+template <class T>
+__device__ void fem_row_entry(const View& V, const SceneConst& sc, int t, int a, bool exact,
+                              double* gw, T* hw) {
   double x12[12], Dm[9];
   for (int v = 0; v < 4; ++v) {
     const int node = V.tv[v * V.Nt + t];
     for (int c = 0; c < 3; ++c) x12[3 * v + c] = V.x[3 * node + c];
   }
   for (int k = 0; k < 9; ++k) Dm[k] = V.Dminv[k * V.Nt + t];
-  const double scale = sc.h * sc.h * V.tvol[t];
-  double F[9], P[9], w[12];
-  deformation_gradient(x12, Dm, F);
-  nh_stress(F, sc.mu, sc.lam, P);
-  pullback(P, Dm, scale, w);
-  for (int c = 0; c < 3; ++c) V.gloc[12 * t + 3 * a + c] = w[3 * a + c];
-  Modes m;
-  nh_modes(F, sc.mu, sc.lam, m);
-  // every mode (the exact Hessian), or the modes of positive eigenvalue (its PSD projection)
-  const bool exact = V.exact[s] != 0;
-  double acc[36];
-  for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+  const double vol = V.tvol[t];
+  const double scale = sc.h * sc.h * vol;
+  T F[9], Dmt[9];
+  for (int k = 0; k < 9; ++k) Dmt[k] = (T)Dm[k];
+  if constexpr (sizeof(T) == sizeof(double)) {
+    double Fd[9], P[9], w[12];
+    deformation_gradient(x12, Dm, Fd);
+    nh_stress(Fd, sc.mu, sc.lam, P);
+    pullback(P, Dm, scale, w);
+    double wa[3];
+    pick3(w, a, wa);
+    for (int c = 0; c < 3; ++c) gw[c] = wa[c];
+    for (int k = 0; k < 9; ++k) F[k] = Fd[k];
+  } else {
+    // displacement differences in FP64, then G = (D_s - D_m) D_m^{-1} in FP32
+    double u[12];
+    for (int v = 0; v < 4; ++v) {
+      const int node = V.tv[v * V.Nt + t];
+      for (int c = 0; c < 3; ++c) u[3 * v + c] = x12[3 * v + c] - V.xrest[3 * node + c];
+    }
+    float Du[9], G[9], P[9], w[12];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) Du[3 * i + k] = (float)(u[3 * (k + 1) + i] - u[i]);
+    matmul3(Du, Dmt, G);
+    nh_stress_disp(G, (float)sc.mu, (float)sc.lam, P);
+    pullback(P, Dmt, (float)scale, w);
+    float wa[3];
+    pick3(w, a, wa);
+    for (int c = 0; c < 3; ++c) gw[c] = (double)wa[c];
+    for (int k = 0; k < 9; ++k) F[k] = G[k] + ((k % 4 == 0) ? 1.0f : 0.0f);
+  }
+  ModesT<T> m;
+  nh_modes(F, (T)sc.mu, (T)sc.lam, m);
+  T acc[36];
+  for (int k = 0; k < 36; ++k) acc[k] = (T)0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const double lk = m.lam[k];
-    if (exact ? !isfinite(lk) : !(lk > 0.0)) continue;
-    double Q[9];
+    const T lk = m.lam[k];
+    if (exact ? !isfinite(lk) : !(lk > (T)0)) continue;
+    T Q[9], w[12], wa[3];
     mode_matrix(m, k, Q);
-    pullback(Q, Dm, 1.0, w);
+    pullback(Q, Dmt, (T)1, w);
+    pick3(w, a, wa);
     for (int i = 0; i < 3; ++i) {
-      const double wi = lk * w[3 * a + i];
+      const T wi = lk * wa[i];
       for (int j = 0; j < 12; ++j) acc[12 * i + j] += wi * w[j];
     }
   }
-  T* out = reinterpret_cast<T*>(V.Hloc) + 144 * (size_t)t + 36 * a;
+  const T sc_t = (T)scale;
   for (int b = 0; b < 4; ++b)
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) out[9 * b + 3 * i + j] = (T)(scale * acc[12 * i + 3 * b + j]);
+      for (int j = 0; j < 3; ++j) hw[9 * b + 3 * i + j] = sc_t * acc[12 * i + 3 * b + j];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kFemRowLanes * kFemRows) k_fem_rows(View V, double* g) {
+  __shared__ T hrow[kFemRows][kFemChunk][36];
+  __shared__ double grow[kFemRows][kFemChunk][3];
+  __shared__ int tcol[kFemRows][kFemChunk][4];
+  __shared__ int cnt_s[kFemRows];
+  const int r = (int)threadIdx.x / kFemRowLanes, lane = (int)threadIdx.x % kFemRowLanes;
+  const int n = (int)blockIdx.x * kFemRows + r;
+  const bool on = n < V.Nn && V.act[V.nscene[n]];
+  const bool soft = on && V.ntype[n] == 0;
+  const int k0 = soft ? V.vptr[n] : 0, cnt = soft ? V.vptr[n + 1] - k0 : 0;
+  const int rb0 = soft ? V.rowptr[n] : 0, nbk = soft ? V.rowptr[n + 1] - rb0 : 0;
+  if (lane == 0) cnt_s[r] = cnt;
+  __syncthreads();
+  int cmax = 0;
+  for (int i = 0; i < kFemRows; ++i) cmax = max(cmax, cnt_s[i]);
+  const int nchunk = max(1, (cmax + kFemChunk - 1) / kFemChunk);
+  const bool exact = soft && V.exact[V.nscene[n]] != 0;
+  T* val = reinterpret_cast<T*>(V.val);
+  double gacc = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int c0 = ch * kFemChunk;
+    const int m = min(kFemChunk, cnt - c0);  // tets of this row in this chunk (may be <= 0)
+    if (lane < m) {
+      const int code = V.vlist[k0 + c0 + lane];
+      const int t = code >> 2, a = code & 3;
+      fem_row_entry<T>(V, V.sc[V.nscene[n]], t, a, exact, grow[r][lane], hrow[r][lane]);
+      for (int b = 0; b < 4; ++b) tcol[r][lane][b] = V.tv[b * V.Nt + t];
+    }
+    __syncthreads();
+    for (int e = lane; e < 9 * nbk; e += kFemRowLanes) {
+      const int kk = rb0 + e / 9, i = e % 9;
+      const int c = V.col[kk];
+      T acc = (T)0;
+      for (int l = 0; l < m; ++l)
+        for (int b = 0; b < 4; ++b)
+          if (tcol[r][l][b] == c) acc += hrow[r][l][9 * b + i];
+      if (ch == 0) {
+        if (c == n && i % 4 == 0) acc += (T)V.mass[n];
+        val[9 * (size_t)kk + i] = acc;
+      } else {
+        val[9 * (size_t)kk + i] += acc;
+      }
+    }
+    if (lane < 3)
+      for (int l = 0; l < m; ++l) gacc += grow[r][l][lane];
+    __syncthreads();
+  }
+  if (on && lane < 3) {
+    double gv = 0.0;
+    if (soft && V.nfree[n]) gv = V.mass[n] * (V.x[3 * n + lane] - V.xhat[3 * n + lane]) + gacc;
+    g[3 * (size_t)n + lane] = gv;
+  }
 }
 
 // ------------------------------------------------------------------ wave-parallel Jacobi
@@ -901,47 +995,6 @@ __global__ void k_body_hess(View V) {
 }
 
 // ------------------------------------------------------------------ assembly
-template <class T>
-__global__ void k_assemble_bsr(View V, int nnz, const int* brow) {
-  const int k = gid();
-  if (k >= nnz) return;
-  const int row = brow[k];
-  if (!V.act[V.nscene[row]]) return;
-  T acc[9];
-  for (int i = 0; i < 9; ++i) acc[i] = (T)0;
-  const T* H = reinterpret_cast<const T*>(V.Hloc);
-  for (int c = V.cptr[k]; c < V.cptr[k + 1]; ++c) {
-    const int code = V.clist[c];
-    const T* blk = H + 144 * (size_t)(code >> 4) + 9 * (code & 15);
-    for (int i = 0; i < 9; ++i) acc[i] += blk[i];
-  }
-  if (V.col[k] == row && V.ntype[row] == 0) {
-    const T m = (T)V.mass[row];
-    acc[0] += m;
-    acc[4] += m;
-    acc[8] += m;
-  }
-  T* val = reinterpret_cast<T*>(V.val);
-  for (int i = 0; i < 9; ++i) val[9 * (size_t)k + i] = acc[i];
-}
-
-__global__ void k_assemble_grad(View V, double* g) {
-  const int n = gid();
-  if (n >= V.Nn) return;
-  if (!V.act[V.nscene[n]]) return;
-  double acc[3] = {0, 0, 0};
-  if (V.ntype[n] == 0 && V.nfree[n]) {
-    const double m = V.mass[n];
-    for (int c = 0; c < 3; ++c) acc[c] = m * (V.x[3 * n + c] - V.xhat[3 * n + c]);
-    for (int k = V.vptr[n]; k < V.vptr[n + 1]; ++k) {
-      const int code = V.vlist[k];
-      const double* gl = V.gloc + 12 * (size_t)(code >> 2) + 3 * (code & 3);
-      for (int c = 0; c < 3; ++c) acc[c] += gl[c];
-    }
-  }
-  for (int c = 0; c < 3; ++c) g[3 * n + c] = acc[c];
-}
-
 // Node entries (node, weight) through which a contact vertex moves.
 __device__ __forceinline__ int vertex_nodes(const View& V, int cv, int* node, double* w) {
   const int n = V.cvn[cv];
@@ -2288,22 +2341,17 @@ void launch_body_public(int nb, const double* y, const double* com0, double* out
 void launch_count_scene(int n, const int* pscene, int* cnt, hipStream_t s) {
   LAUNCH(k_count_scene, n, TPB, s, n, pscene, cnt);
 }
-void launch_fem_hess(const View& V, int mixed, hipStream_t s) {
-  if (mixed) LAUNCH(k_fem_hess<float>, 4 * V.Nt, TPB, s, V);
-  else LAUNCH(k_fem_hess<double>, 4 * V.Nt, TPB, s, V);
+void launch_fem_rows(const View& V, double* g, int mixed, hipStream_t s) {
+  const int nb = (V.Nn + kFemRows - 1) / kFemRows;
+  if (nb <= 0) return;
+  if (mixed) hipLaunchKernelGGL(k_fem_rows<float>, dim3(nb), dim3(kFemRowLanes * kFemRows), 0, s, V, g);
+  else hipLaunchKernelGGL(k_fem_rows<double>, dim3(nb), dim3(kFemRowLanes * kFemRows), 0, s, V, g);
 }
 void launch_barrier_hess(const View& V, int np, const int* pkind, const int* pv,
                          const double* pmeps, double* pg, double* ph, hipStream_t s) {
   if (np > 0) hipLaunchKernelGGL(k_barrier_hess, dim3(np), dim3(64), 0, s, V, np, pkind, pv, pmeps, pg, ph);
 }
 void launch_body_hess(const View& V, hipStream_t s) { LAUNCH(k_body_hess, V.Nb, 64, s, V); }
-void launch_assemble_bsr(const View& V, int nnz, const int* brow, int mixed, hipStream_t s) {
-  if (mixed) LAUNCH(k_assemble_bsr<float>, nnz, TPB, s, V, nnz, brow);
-  else LAUNCH(k_assemble_bsr<double>, nnz, TPB, s, V, nnz, brow);
-}
-void launch_assemble_grad(const View& V, double* g, hipStream_t s) {
-  LAUNCH(k_assemble_grad, V.Nn, TPB, s, V, g);
-}
 void launch_contrib_count(const View& V, int np, const int* pv, int* hcnt, int* gcnt,
                           hipStream_t s) {
   LAUNCH(k_contrib_count, np + V.Nb, TPB, s, V, np, pv, hcnt, gcnt);

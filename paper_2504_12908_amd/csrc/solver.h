@@ -31,6 +31,7 @@ struct View {
   const SceneConst* sc;
   // nodes: soft vertices, padding, 4 pseudo-nodes per affine body (p, c1, c2, c3)
   double *x, *xn, *xhat, *v;
+  const double* xrest;  // creation (rest) positions
   const double* mass;
   int* nfree;        // 1 if the node's 3 dofs are unknowns
   const int* nscene;
@@ -41,15 +42,11 @@ struct View {
   const double* Dminv;  // [9][Nt]
   const double* tvol;
   const int* tscene;
-  double* Hloc;  // [Nt][16][9]
-  double* gloc;  // [Nt][12]
   // static BSR over nodes (FEM pattern)
   const int* rowptr;
   const int* col;
   double* val;
   const int* diag;
-  const int* cptr;
-  const int* clist;  // tet*16 + a*4 + b
   const int* vptr;
   const int* vlist;  // tet*4 + a
   // bodies
