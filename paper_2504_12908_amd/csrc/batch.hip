@@ -535,10 +535,13 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     if (s == 0) mixed = P.precision == TACCEL_MIXED;
     else if (mixed != (P.precision == TACCEL_MIXED))
       throw ApiError(TACCEL_ERR_ARG, "all scenes of a batch must use the same precision");
-    // A 256-scene mixed-precision batch ended in a GPU memory fault whose cause is not yet
-    // identified; until it is, mixed precision runs one scene per object.
+    // A 256-scene mixed-precision batch ended in a GPU memory fault whose cause is not shown;
+    // until it is, mixed precision runs one scene per object.  (The host build of the tests
+    // defines TACCEL_HOST_MIXED_BATCHES to run such batches under its guard pages.)
+#ifndef TACCEL_HOST_MIXED_BATCHES
     if (mixed && n > 1)
       throw ApiError(TACCEL_ERR_ARG, "mixed precision is limited to one scene per batch");
+#endif
     // ---- nodes
     const int node0 = Nn;
     H.node0 = node0;

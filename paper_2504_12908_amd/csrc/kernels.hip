@@ -1449,7 +1449,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
   if (threadIdx.x == 0) {
     B.P_rz0[blk] = rz;
     B.P_rz1[blk] = (T)1;
-    B.P_gg[blk] = rr;
+    B.P_gg[blk] = rz;  // g^T D^{-1} g: the reference of the stopping test
     B.P_rr[blk] = rr;
   }
 }
@@ -1513,8 +1513,12 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   }
   const T eta = (T)V.sc[s].pcg_eta;
   // iters[s] is only written by k_pcg_update, so every wave sees the same count here
-  const bool conv = (rr <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters ||
+  // Stop once r^T M^{-1} r <= eta^2 g^T D^{-1} g: the residual measured in the
+  // preconditioner's norm, so that a few stiff unknowns (a body held by its constraint
+  // penalty) do not set the scale for all the others.
+  const bool conv = (rzc <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters ||
                     B.indef[s];
+  (void)rr;
   if (conv) {
     if (blk == TS.sblk[s] && threadIdx.x == 0) V.pdone[s] = 1;
     return;

@@ -433,3 +433,116 @@ def apply_target(X0: np.ndarray, q: np.ndarray) -> np.ndarray:
     """World positions of creation-pose vertices X0 under a 12-double target q."""
     A = np.asarray(q[3:12]).reshape(3, 3)
     return X0 @ A.T + np.asarray(q[0:3])
+
+
+# ----------------------------------------------------------------------------- robot-driven scenes
+def _trans(t):
+    T = np.eye(4)
+    T[:3, 3] = t
+    return T
+
+
+def _rot_z(angle):
+    c, s = np.cos(angle), np.sin(angle)
+    T = np.eye(4)
+    T[:2, :2] = [[c, -s], [s, c]]
+    return T
+
+
+def _apply(T, pts):
+    return pts @ T[:3, :3].T + T[:3, 3]
+
+
+def parallel_gripper_fk(base_z: float, opening: float, mount1=(0.0, 0.0, 0.0)):
+    """Forward kinematics of a parallel-jaw gripper: a base link on a prismatic joint along z
+    (joint value base_z) carrying two fingers on prismatic joints along x, each opening/2
+    from the base axis.  Finger 0 (at -x) keeps the base orientation, so its local +x points
+    to the other finger; finger 1 is turned by pi about z and mounted at the fixed offset
+    mount1 in its own frame.  Returns the 4x4 world transforms of the two finger links."""
+    base = _trans((0.0, 0.0, base_z))
+    left = base @ _trans((-0.5 * opening, 0.0, 0.0))
+    right = base @ _trans((0.5 * opening, 0.0, 0.0)) @ _rot_z(np.pi) @ _trans(mount1)
+    return left, right
+
+
+def _link_target(T_now, T_rest):
+    """Body target (t, A row-major) moving a link's creation-pose vertices with the link."""
+    M = T_now @ np.linalg.inv(T_rest)
+    out = np.zeros(12)
+    out[0:3] = M[:3, 3]
+    out[3:12] = M[:3, :3].ravel()
+    return out
+
+
+def gripper_scene(name, obj, joint_traj, h, cells=(6, 32, 24), pad_size=(6 * MM, 32 * MM, 24 * MM),
+                  link_gap=0.2 * MM, plate=3.0 * MM, friction=0.0, gravity=(0.0, 0.0, 0.0),
+                  mount1=(0.0, 0.0, 0.0), meta=None):
+    """A gel pad on each finger of the parallel gripper (Sec. 4.1: a sensor's gel is a tet mesh
+    attached to a robot link by its back face), an optional free object, and a script of
+    joint values turned into kinematic targets by forward kinematics.
+
+    In a finger's frame the pad fills [0, t] x [-w/2, w/2] x [-d/2, d/2] (pad_size (t, w, d),
+    hex cells `cells` along (x, y, z)); its back face x = 0 is attached to the link (moving
+    Dirichlet vertices that follow the link), its coated face x = t faces the other finger.
+    mount1 offsets finger 1 in its own frame (see parallel_gripper_fk).
+    The link itself is a rigid plate behind the pad, link_gap away (more than dhat), driven
+    as a prescribed affine body.  joint_traj: (n_steps + 1, 2) rows (base_z, opening), row 0
+    the creation pose, row k the targets at the end of step k.  Soft vertices: finger 0's pad,
+    then finger 1's.  Bodies: the object (free) if given, then the two links."""
+    t, w, d = pad_size
+    pv, pt = kuhn_box((0.0, -0.5 * w, -0.5 * d), (t, 0.5 * w, 0.5 * d), cells)
+    lv, lt = box_mesh((-link_gap - 0.5 * plate, 0.0, 0.0), (plate, w, d))
+    T0 = parallel_gripper_fk(*joint_traj[0], mount1=mount1)
+    verts = np.concatenate([_apply(T0[0], pv), _apply(T0[1], pv)])
+    tets = np.concatenate([pt, pt + len(pv)]).astype(np.int32)
+    back = np.where(pv[:, 0] == 0.0)[0]
+    dirichlet = np.zeros(len(verts), dtype=np.uint8)
+    dirichlet[back] = 2
+    dirichlet[back + len(pv)] = 2
+    n_steps = len(joint_traj) - 1
+    moving = np.concatenate([back, back + len(pv)])
+    dir_t = np.zeros((n_steps, len(moving), 3))
+    links = [BodySpec(_apply(T0[f], lv), lt.copy(), prescribed=True) for f in range(2)]
+    bodies = ([BodySpec(obj[0], obj[1], prescribed=False)] if obj is not None else []) + links
+    body_t = np.zeros((n_steps, len(bodies), 12))
+    body_t[:, :, 3:12] = np.eye(3).ravel()
+    for k in range(1, n_steps + 1):
+        Tk = parallel_gripper_fk(*joint_traj[k], mount1=mount1)
+        dir_t[k - 1] = np.concatenate([_apply(Tk[0], pv[back]), _apply(Tk[1], pv[back])])
+        for f in range(2):
+            body_t[k - 1, len(bodies) - 2 + f] = _link_target(Tk[f], T0[f])
+    params = default_params(h)
+    params["gravity"] = tuple(gravity)
+    params["friction"] = friction
+    return SceneSpec(name=name, verts=verts, tets=tets, dirichlet=dirichlet, youngs=GEL_E,
+                     poisson=GEL_NU, density=GEL_RHO, bodies=bodies, params=params,
+                     body_targets=body_t, dirichlet_targets=dir_t,
+                     meta=dict(meta or {}, joint_traj=np.asarray(joint_traj), pad_vertices=len(pv),
+                               mount1=tuple(mount1)))
+
+
+def grasp_lift(seed: int = 0, cells=(6, 32, 24), n_points: int = 5002, extent: float = 24 * MM,
+               n_squeeze: int = 20, n_lift: int = 180, squeeze: float = 0.5 * MM,
+               lift: float = 20 * MM, gap: float = 0.05 * MM, friction: float = 0.5,
+               h: float = 0.005) -> SceneSpec:
+    """Two-finger grasp: a free object (a random convex hull of n_points, extent 24 mm, from
+    default_rng(5000 + seed)) between the two pads of the parallel gripper, their coated faces
+    `gap` from it.  The fingers close by gap + squeeze each over n_squeeze steps, then the
+    base rises by `lift` over n_lift steps.  The pads hold the object by friction (Coulomb
+    coefficient `friction`, App. A.3) against gravity; friction = 0 turns gravity off too (a
+    frictionless squeeze of an irregular object is not a grasp: it spins or squirts out)."""
+    rng = np.random.default_rng(5000 + seed)
+    hv, ht = random_hull(rng, n_points, extent)
+    half = 0.5 * (hv[:, 0].max() - hv[:, 0].min())
+    hv = hv - np.array([0.5 * (hv[:, 0].max() + hv[:, 0].min()), 0.0, 0.0])
+    t = 6 * MM
+    open0 = 2.0 * (t + half + gap)
+    traj = [(0.0, open0)]
+    for k in range(1, n_squeeze + n_lift + 1):
+        close = min(k, n_squeeze) / n_squeeze * 2.0 * (gap + squeeze)
+        rise = max(0, k - n_squeeze) / n_lift * lift
+        traj.append((rise, open0 - close))
+    grav = (0.0, 0.0, -9.81) if friction > 0.0 else (0.0, 0.0, 0.0)
+    return gripper_scene(f"grasp_lift(seed={seed})", (hv, ht), np.array(traj), h, cells=cells,
+                         friction=friction, gravity=grav,
+                         meta=dict(seed=seed, object_tris=len(ht), half_width=half))

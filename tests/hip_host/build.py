@@ -18,7 +18,10 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libtaccel_host.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("kernels.hip", "prims.hip", "tactile.hip", "batch.hip", "capi.cpp", "server.cpp")]
+# TACCEL_HOST_MIXED_BATCHES: mixed-precision batches of several scenes, refused by the gfx950
+# build until the cause of their GPU fault is shown, run here under the guard pages.
 FLAGS = ["-std=c++17", "-O2", "-g", "-fPIC", "-U_FORTIFY_SOURCE", "-D_FORTIFY_SOURCE=0",
+         "-DTACCEL_HOST_MIXED_BATCHES",
          "-Wno-unknown-pragmas", "-I" + HERE, "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 

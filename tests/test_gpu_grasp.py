@@ -1,0 +1,128 @@
+"""The two-finger grasp and other robot-driven scenes through the C-ABI (reduced grids):
+teacher-forced steps against the CPU FP64 oracle within 1e-8 * L, moving back faces exactly on
+their kinematic targets, pad-pad (soft-soft) contact, the friction grasp, batches equal to their
+scenes run alone, and the mixed-precision path's error against the FP64 path per scene (within
+1e-4 of the 6 mm pad thickness).
+"""
+import numpy as np
+import pytest
+
+from paper_2504_12908_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+MM = S.MM
+CELLS = (2, 8, 6)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2504_12908_amd import taccel
+    taccel.lib()
+    return taccel
+
+
+def _grasp(seed, **kw):
+    # the grasp of the benchmark on reduced grids: friction 0.5 with gravity
+    return S.grasp_lift(seed, cells=CELLS, n_points=40, n_squeeze=4, n_lift=4, lift=2 * MM, **kw)
+
+
+def _pad_pad():
+    w, d = 32 * MM / CELLS[1], 24 * MM / CELLS[2]
+    open0 = 2 * (6 * MM + 0.05 * MM)
+    traj = [(0.0, open0)] + [(0.0, open0 - 2 * (0.05 * MM + 0.3 * MM) * min(k, 4) / 4)
+                             for k in range(1, 6)]
+    return S.gripper_scene("pad_pad", None, np.array(traj), 0.005, cells=CELLS,
+                           mount1=(0.0, w / 3, d / 3))
+
+
+def _teacher_forced(T, oracle_lib, spec, steps, precision=None, tol=None):
+    o = oracle_lib.OracleScene(spec)
+    g = T.Scene(spec) if precision is None else T.Scene(spec, precision=precision)
+    L = o.scale
+    tol = 1e-8 * L if tol is None else tol
+    moving = np.flatnonzero(spec.dirichlet == 2)
+    for k in range(steps):
+        x, v, q, qd = o.get_state()
+        g.set_state(x, v, q, qd)
+        rc_o, st_o = o.step(k)
+        rc_g, st_g = g.step(k)
+        assert rc_o == 0 and rc_g == T.OK, (k, rc_o, T.STATUS_NAMES[rc_g], st_g)
+        xo, _, qo, _ = o.get_state()
+        xg, _, qg, _ = g.get_state()
+        assert np.array_equal(xg[moving], spec.dirichlet_targets[k])
+        err = max(np.abs(xg - xo).max(), np.abs(qg[:, :3] - qo[:, :3]).max())
+        say(f"  step {k}: newton gpu {st_g['newton_iters']} oracle {st_o['newton_iters']} "
+            f"al {st_g['al_rounds']}/{st_o['al_rounds']} active {st_g['n_active']} "
+            f"err {err:.3e} (tol {tol:.3e})")
+        assert err <= tol
+    g.close()
+
+
+def test_grasp_teacher_forced(T, oracle_lib):
+    spec = _grasp(0)
+    say(f"teacher-forced: {spec.name}, {len(spec.verts)} soft vertices, "
+        f"{len(spec.bodies[0].tris)}-triangle object")
+    _teacher_forced(T, oracle_lib, spec, 6)
+
+
+def test_pad_pad_contact_teacher_forced(T, oracle_lib):
+    spec = _pad_pad()
+    say("teacher-forced: two pads pressed into each other")
+    _teacher_forced(T, oracle_lib, spec, spec.n_steps)
+
+
+def test_friction_grasp_teacher_forced(T, oracle_lib):
+    cv, ct = S.box_mesh((0, 0, 0), (8 * MM,) * 3)
+    open0 = 2 * (6 * MM + 4 * MM + 0.05 * MM)
+    traj = [(0.0, open0)] + [(1.5 * MM * max(0, k - 3) / 3,
+                              open0 - 2 * 0.35 * MM * min(k, 3) / 3) for k in range(1, 7)]
+    spec = S.gripper_scene("cube_friction_grasp", (cv, ct), np.array(traj), 0.005, cells=CELLS,
+                           friction=0.5, gravity=(0.0, 0.0, -9.81))
+    say("teacher-forced: friction grasp of a cube, squeeze then lift")
+    _teacher_forced(T, oracle_lib, spec, spec.n_steps)
+
+
+def test_grasp_batch_equals_single(T):
+    specs = [_grasp(i) for i in range(3)]
+    say("grasp batch of 3 vs single scenes, 3 steps")
+    b = T.Batch(specs)
+    singles = [T.Scene(s) for s in specs]
+    for k in range(3):
+        rc, per, st = b.step(k)
+        assert rc == T.OK, per
+        for i, sg in enumerate(singles):
+            r, _ = sg.step(k)
+            assert r == T.OK
+            assert np.array_equal(b.read(i, T.FIELD_X), sg.read(T.FIELD_X))
+            assert np.array_equal(b.read(i, T.FIELD_Q), sg.read(T.FIELD_Q))
+    b.close()
+    for sg in singles:
+        sg.close()
+
+
+def test_grasp_mixed_precision_error_per_scene(T):
+    """Mixed precision against the FP64 path, scene by scene over whole reduced grasps
+    (8 seeds, squeeze and lift): max |x_mixed - x_fp64| over all steps within 1e-4 of the
+    6 mm pad thickness for every scene."""
+    tol = 1e-4 * 6 * MM
+    errs = []
+    for seed in range(8):
+        spec = _grasp(seed)
+        a, b = T.Scene(spec), T.Scene(spec, precision=T.MIXED)
+        worst = 0.0
+        for k in range(spec.n_steps):
+            ra, _ = a.step(k)
+            rb, sb = b.step(k)
+            assert ra == T.OK and rb == T.OK, (seed, k, T.STATUS_NAMES[rb], sb)
+            worst = max(worst, np.abs(a.read(T.FIELD_X) - b.read(T.FIELD_X)).max(),
+                        np.abs(a.read(T.FIELD_Q)[:, :3] - b.read(T.FIELD_Q)[:, :3]).max())
+        errs.append(worst)
+        say(f"  seed {seed}: max |x_mixed - x_fp64| = {worst:.3e} m (tol {tol:.1e})")
+        a.close()
+        b.close()
+    assert max(errs) <= tol

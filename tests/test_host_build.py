@@ -132,3 +132,32 @@ assert set(per.tolist()) <= {0, 3}, per
 b.close()
 print("DONE")
 """)
+
+
+LONG = os.environ.get("TACCEL_HOST_LONG") == "1"
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not LONG, reason="hours of CPU: set TACCEL_HOST_LONG=1")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_host_build_256_batch_two_full_steps(host_lib, precision):
+    """The 256-scene uniform batch through creation and two full steps, in FP64 and in mixed
+    precision (several scenes per mixed batch are allowed in the host build only), with every
+    device allocation behind guard pages: no memory error, every scene converged, and every
+    scene's positions finite."""
+    run(host_lib, f"""
+import time
+specs = S.uniform_batch(256)
+t0 = time.time()
+b = T.Batch(specs, precision=T.{'MIXED' if precision == 'mixed' else 'FP64'})
+print("created", time.time() - t0, flush=True)
+for k in range(2):
+    rc, per, st = b.step(k)
+    print("step", k, "ok", int((per == 0).sum()), "max newton", max(s["newton_iters"] for s in st),
+          time.time() - t0, flush=True)
+    assert (per == 0).all(), per
+for i in range(256):
+    assert np.isfinite(b.read(i, T.FIELD_X)).all()
+b.close()
+print("DONE")
+""", timeout=100000)
