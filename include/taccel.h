@@ -288,8 +288,11 @@ taccel_status taccel_server_step_latencies(taccel_server* s, uint64_t req_id, do
                                            int32_t cap, int32_t* n);
 /* Forget a completed request (its final state and latencies). */
 taccel_status taccel_server_release(taccel_server* s, uint64_t req_id);
-/* Requests waiting for admission, cohorts running, device bytes held by running cohorts and
- * the peak of that figure (any pointer may be NULL). */
+/* Requests waiting for admission, cohorts running, the device bytes reserved by the running
+ * cohorts (a cohort reserves the estimated footprint of its requests, or what its creation
+ * took if more; its buffers may grow with its contacts up to that and no further: a step that
+ * would need more fails its requests with ERR_OOM, so the reservations never pass the budget)
+ * and the peak of the bytes the cohorts actually held (any pointer may be NULL). */
 taccel_status taccel_server_info(taccel_server* s, int32_t* queued, int32_t* running_cohorts,
                                  double* used_bytes, double* peak_bytes);
 /* Cancel queued requests, stop running cohorts after their current step (their requests

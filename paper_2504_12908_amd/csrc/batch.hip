@@ -50,8 +50,13 @@ struct Mem {
   hipStream_t side = nullptr;   // second stream: contact Hessians
   hipStream_t side2 = nullptr;  // third stream: FEM and affine-body terms and their assembly
   bool own_stream = false;
+  size_t held = 0;   // bytes allocated through this object and not yet released
+  size_t limit = 0;  // 0: no limit; else an allocation that would pass it fails with OOM
   void* alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
+    if (limit && held + bytes > limit)
+      throw ApiError(TACCEL_ERR_OOM, "device memory would exceed the object's limit of " +
+                                         std::to_string(limit) + " bytes");
     void* p = nullptr;
     if (rt.alloc) {
       p = rt.alloc(bytes, rt.ctx);
@@ -59,10 +64,12 @@ struct Mem {
     } else {
       HIPCHECK(hipMalloc(&p, bytes));
     }
+    held += bytes;
     return p;
   }
-  void release(void* p) {
+  void release(void* p, size_t bytes) {
     if (!p) return;
+    held -= std::min(held, bytes);
     // work queued on either stream may still read the buffer
     if (stream) (void)hipStreamSynchronize(stream);
     if (side) (void)hipStreamSynchronize(side);
@@ -80,8 +87,11 @@ struct DBuf {
   void ensure(Mem* mem, size_t n) {
     m = mem;
     if (n <= cap && p) return;
-    if (p) m->release(p);
     const size_t c = std::max<size_t>(n, cap + cap / 2);
+    // the old buffer goes first; if the new allocation fails the object holds none
+    if (p) m->release(p, sizeof(T) * std::max<size_t>(cap, 1));
+    p = nullptr;
+    cap = 0;
     p = static_cast<T*>(m->alloc(sizeof(T) * std::max<size_t>(c, 1)));
     cap = c;
   }
@@ -95,7 +105,7 @@ struct DBuf {
     }
   }
   void free() {
-    if (p && m) m->release(p);
+    if (p && m) m->release(p, sizeof(T) * std::max<size_t>(cap, 1));
     p = nullptr;
     cap = 0;
   }
@@ -2051,31 +2061,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   return first_bad;
 }
 
-size_t Batch::Impl::device_bytes() const {
-  size_t n = 0;
-  auto add = [&](const auto& buf) { n += buf.cap * sizeof(*buf.p); };
-  add(x); add(xn); add(xhat); add(v); add(mass); add(Dminv); add(tvol); add(val);
-  add(bmass); add(bvol); add(bstar); add(blam); add(bkap); add(bgrad); add(bhess); add(bpinv); add(cvx);
-  add(cpos); add(cdisp); add(cend); add(elen2); add(bp_tbox); add(pmeps); add(pg); add(ph); add(hcoef);
-  add(gcoef); add(dval); add(g); add(r); add(z); add(p); add(p1); add(q); add(dx); add(pinv);
-  add(nfree); add(nscene); add(nbody); add(ntype); add(tv); add(tscene); add(rowptr); add(col);
-  add(diag); add(vptr); add(vlist); add(cvn); add(cvb); add(cvfix);
-  add(cvscene); add(cvworld); add(trv); add(edv); add(qkind); add(qidx); add(qscene); add(bp_tcell);
-  add(bp_tncell); add(bp_toff); add(bp_bcount); add(bp_bstart); add(bp_bfill); add(bp_qcount);
-  add(bp_qoff); add(bp_entries); add(cq); add(ct); add(sq); add(st); add(cflag); add(cpos_idx);
-  add(pkind); add(pv); add(pscene); add(hcnt); add(gcnt); add(hoff); add(goff); add(hidx); add(gidx);
-  add(hsrc); add(gsrc); add(hidx2); add(gidx2); add(hkey); add(gkey); add(hkey2); add(gkey2);
-  add(sflag); add(segid); add(segstart); add(drow); add(dcol); add(rowcnt); add(drowptr); add(scratch);
-  add(e_pairs); add(part_nodes); add(part_tets); add(part_pairs);
-  add(fv); add(fsoff); add(fw); add(fc0); add(fnrm); add(fmul); add(e_fric);
-  add(xrest); add(tac_bary); add(tac_pos); add(tac_flow); add(tac_depth); add(tac_normal);
-  add(tac_nodes); add(tac_zidx); add(tac_zkey);
-  add(tp_sc); add(tp_b0); add(tp_b1); add(tp_sblk);
-  add(cg_blk_agg); add(cg_agg_b0); add(cg_agg_b1); add(cg_sc_a0); add(cg_sc_m); add(cg_sc_off);
-  add(cg_d); add(cg_ainv); add(cg_rc); add(P_qc); add(cg_rca0); add(cg_rca1); add(cg_dw); add(bp_tmp); add(cg_sc_ts0);
-  add(cg_sc_tsn); add(cg_sc_tsend);
-  return n;
-}
+size_t Batch::Impl::device_bytes() const { return mem.held; }
 
 void Batch::Impl::release_all() {
   if (h_pin) (void)hipHostFree(h_pin);
@@ -2561,6 +2547,7 @@ taccel_status Batch::write(int k, taccel_field f, const void* src, size_t bytes)
 }
 
 size_t Batch::device_bytes() const { return impl_->device_bytes(); }
+void Batch::set_byte_limit(size_t bytes) { impl_->mem.limit = bytes; }
 
 taccel_status Batch::markers(int k, int m, const int32_t* tris, const double* bary, double* pos,
                              double* flow) {

@@ -108,7 +108,8 @@ struct Server {
   std::map<uint64_t, std::unique_ptr<Request>> requests;
   std::deque<uint64_t> completed;
   uint64_t next_id = 1;
-  size_t used_bytes = 0;
+  size_t used_bytes = 0;  // reservations of the running cohorts (never above the budget)
+  size_t held_bytes = 0;  // what they hold now
   int running_cohorts = 0;
   bool stop = false;
   std::thread admit_thread;
@@ -126,6 +127,7 @@ struct Server {
   // request becomes visible to poll/read/release once finish() has run under the lock, after
   // which this thread no longer dereferences it (it may be released at any time).
   void run_cohort(std::vector<Request*> reqs, Batch* batch, size_t bytes) {
+    size_t held = batch->device_bytes();
     const int n = (int)reqs.size();
     std::vector<int> mask(n, 1), done(n, 0);
     std::vector<taccel_targets> tg(n);
@@ -157,6 +159,15 @@ struct Server {
       const auto t0 = Clock::now();
       batch->step(tg.data(), per.data(), st.data(), mask.data());
       const double dt = ms_since(t0, Clock::now());
+      {
+        // the cohort's buffers grow with its contacts, up to its reservation (the batch's
+        // byte limit); the server's peak counts what the cohorts hold
+        const size_t now = batch->device_bytes();
+        std::lock_guard<std::mutex> lk(mu);
+        held_bytes = held_bytes - held + now;
+        held = now;
+        peak_bytes = std::max(peak_bytes.load(), held_bytes);
+      }
       for (int i = 0; i < n; ++i) {
         if (!mask[i]) continue;
         Request* r = reqs[i];
@@ -176,6 +187,7 @@ struct Server {
     delete batch;
     std::lock_guard<std::mutex> lk(mu);
     used_bytes -= bytes;
+    held_bytes -= held;
     running_cohorts -= 1;
     cv_admit.notify_all();
   }
@@ -283,11 +295,19 @@ struct Server {
         running_cohorts -= 1;
         continue;
       }
-      // account the cohort's actual allocation from here on
+      // The cohort keeps its reservation: the batch may grow (contact pairs, candidates) up
+      // to it and no further (a step that would needs more fails with ERR_OOM), so the
+      // reservations of the running cohorts bound the device memory the server holds.  A
+      // cohort whose creation already took more than its estimate is charged that instead.
       const size_t actual = batch->device_bytes();
-      used_bytes = used_bytes - bytes + actual;
-      peak_bytes = std::max(peak_bytes.load(), used_bytes);
-      cohort_threads.emplace_back(&Server::run_cohort, this, take, batch, actual);
+      if (actual > bytes) {
+        used_bytes += actual - bytes;
+        bytes = actual;
+      }
+      batch->set_byte_limit(bytes);
+      held_bytes += actual;
+      peak_bytes = std::max(peak_bytes.load(), held_bytes);
+      cohort_threads.emplace_back(&Server::run_cohort, this, take, batch, bytes);
     }
   }
 };

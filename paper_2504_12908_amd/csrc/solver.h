@@ -98,7 +98,10 @@ class Batch {
   // mask (nullable): scenes with mask[k] == 0 are left untouched by this call
   taccel_status step(const taccel_targets* t, taccel_status* per_scene, taccel_step_stats* st,
                      const int* mask = nullptr);
-  size_t device_bytes() const;
+  size_t device_bytes() const;  // device memory the object holds now
+  // Device memory the object may hold from now on (0: no limit); an allocation past it fails
+  // the call that needs it with TACCEL_ERR_OOM.
+  void set_byte_limit(size_t bytes);
   taccel_status read(int scene, taccel_field f, void* dst, size_t bytes);
   taccel_status write(int scene, taccel_field f, const void* src, size_t bytes);
   taccel_status field_bytes(int scene, taccel_field f, size_t* bytes);
