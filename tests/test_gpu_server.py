@@ -125,6 +125,8 @@ def test_server_limits(T):
             done[c["req_id"]] = c
     assert seen_max <= 1
     assert all(done[r]["status"] == T.OK for r in ids)
+    # the cohorts held at most their reservations, which never passed the budget
+    assert 0 < srv.info()["peak_bytes"] <= 8e9
     srv.close()
 
     tiny = T.Server(hbm_budget_bytes=1024.0)
