@@ -321,6 +321,65 @@ def run_batch(args, taccel, scenes, np):
     return out
 
 
+def run_grasp(args, taccel, scenes, np):
+    """Two-finger grasp and lift (two 5,775-vertex pads on the fingers of a parallel gripper
+    driven by forward kinematics, a free 10,000-triangle hull held by friction), n scenes in
+    one batch; the first K steps of the 200-step trajectory timed.  With --precision mixed the
+    batch is one scene (mixed batches of several scenes are refused), and the line also gives
+    the mixed path's error against the FP64 path over the timed steps."""
+    n = args.scenes
+    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    if prec == taccel.MIXED and n > 1:
+        sys.exit("bench.py: mixed precision runs one scene per batch (see include/taccel.h)")
+    specs = [scenes.grasp_lift(i) for i in range(n)]
+    W, K = args.warmup, args.steps
+    nst = specs[0].n_steps
+    if K > nst:
+        sys.exit(f"steps must be <= {nst}")
+    b = taccel.Batch(specs, precision=prec)
+    targets = [b.targets(k) for k in range(K)]
+    for k in range(min(W, K)):
+        b.step(k, targets[k])
+    b.reset()
+    ref = taccel.Batch(specs) if prec == taccel.MIXED else None
+    taccel.device_synchronize()
+    lat, ok = [], 0
+    err = 0.0
+    t0 = time.perf_counter()
+    for k in range(K):
+        ts = time.perf_counter()
+        rc, per, st = b.step(k, targets[k])
+        lat.append((time.perf_counter() - ts) * 1e3)
+        ok += int((per == taccel.OK).sum())
+        print(f"step {k}: ok={int((per == taccel.OK).sum())}/{n} "
+              f"max_newton={max(s['newton_iters'] for s in st)} {lat[-1]:.1f} ms",
+              file=sys.stderr, flush=True)
+    taccel.device_synchronize()
+    dt = time.perf_counter() - t0
+    if ref is not None:
+        b.reset()
+        for k in range(K):
+            b.step(k, targets[k])
+            ref.step(k, targets[k])
+            err = max(err, float(np.abs(b.read(0, taccel.FIELD_X) - ref.read(0, taccel.FIELD_X)).max()))
+        ref.close()
+    out = dict(
+        metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
+        ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        config=dict(workload=f"two-finger grasp and lift, {n} scene(s): two 32x24x6-cell pads "
+                             "(11,550 verts, 55,296 tets) on gripper links, a free 10,000-triangle "
+                             "hull held by friction; first steps of the 200-step trajectory",
+                    scenes=n, precision=args.precision),
+        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+    )
+    if ref is not None:
+        out["mixed_vs_fp64_max_abs_m"] = err
+        out["mixed_tolerance_m"] = 1e-4 * 6e-3
+    b.close()
+    return out
+
+
 def run_serving(args, taccel, scenes, np):
     """Serving stream: Poisson arrivals, each request a 50-step rollout of a pad of random
     resolution with 1-3 hull indenters; continuous batching under an HBM budget."""
@@ -454,7 +513,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "serving", "tactile", "copy"],
+    ap.add_argument("--workload", choices=["single", "batch", "grasp", "serving", "tactile", "copy"],
                     default="batch")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--scenes", type=int, default=256)
@@ -485,8 +544,8 @@ def main():
 
     from paper_2504_12908_amd import scenes, taccel
 
-    run = dict(single=run_single, batch=run_batch, serving=run_serving, tactile=run_tactile,
-               copy=run_copy)[args.workload]
+    run = dict(single=run_single, batch=run_batch, grasp=run_grasp, serving=run_serving,
+               tactile=run_tactile, copy=run_copy)[args.workload]
     out = run(args, taccel, scenes, np)
     print(json.dumps(out), flush=True)
 
