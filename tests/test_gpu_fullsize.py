@@ -2,7 +2,8 @@
 
 * The benchmark scene itself (5,775-vertex pad, 796-triangle hull, FP64, one scene): three
   teacher-forced steps of the press (both sides start every step from the oracle's state),
-  max |x_gpu - x_oracle| <= 1e-8 * L, L the rest bounding-box diagonal.
+  max |x_gpu - x_oracle| <= 1e-8 * L, L the rest bounding-box diagonal (the slide phase is in
+  test_gpu_zy_slide_phase.py, collected late: it runs 75 steps).
 * The 256-scene uniform batch (one launch per stage over all scenes): two steps of the full
   batch, with sampled scenes compared against the oracle stepping the same scene from the same
   state (the oracle solves one scene at a time, so a sample keeps the test within seconds).
