@@ -242,8 +242,11 @@ taccel_status taccel_batch_depth_map(const taccel_batch* b, int32_t scene,
  * memory is released with its last request.  A new cohort is formed whenever requests are
  * waiting, fewer than max_cohorts run, and the estimated footprint of the requests taken fits
  * hbm_budget_bytes minus what running cohorts hold, so cohorts formed at different times
- * run concurrently.  A request's results are bitwise the same as stepping its scene alone
- * with taccel_step.  All calls are thread-safe. */
+ * run concurrently.  Waiting requests also take the slots that finished requests leave in a
+ * running cohort (FP64 cohorts): at a step boundary its unfinished requests and the newly
+ * admitted ones (same precision, within the cohort's reservation) form a new batch into which
+ * the unfinished requests' state moves bit for bit.  A request's results are bitwise the same
+ * as stepping its scene alone with taccel_step.  All calls are thread-safe. */
 typedef struct {
   double hbm_budget_bytes; /* device memory the server may hold (> 0) */
   int32_t max_cohort;      /* requests per cohort (<= 0: 64) */

@@ -2466,6 +2466,48 @@ taccel_status Batch::debug_system(const taccel_targets* tg, double* grad, int32_
   }
 }
 
+taccel_status Batch::export_state(int k, SceneState& out) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    const size_t n0 = I.hs[k].node0, n1 = I.hs[k].node1;
+    const size_t b0 = I.hsc[k].body0, b1 = I.hsc[k].body1;
+    out.x.resize(3 * (n1 - n0));
+    out.v.resize(3 * (n1 - n0));
+    out.lam.resize(12 * (b1 - b0));
+    I.d2h(out.x.data(), I.x.p + 3 * n0, out.x.size());
+    I.d2h(out.v.data(), I.v.p + 3 * n0, out.v.size());
+    I.d2h(out.lam.data(), I.blam.p + 12 * b0, out.lam.size());
+    I.sync();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
+
+taccel_status Batch::import_state(int k, const SceneState& in) {
+  try {
+    Impl& I = *impl_;
+    if (k < 0 || k >= S_) throw ApiError(TACCEL_ERR_ARG, "scene index out of range");
+    const size_t n0 = I.hs[k].node0, n1 = I.hs[k].node1;
+    const size_t b0 = I.hsc[k].body0, b1 = I.hsc[k].body1;
+    if (in.x.size() != 3 * (n1 - n0) || in.v.size() != 3 * (n1 - n0) || in.lam.size() != 12 * (b1 - b0))
+      throw ApiError(TACCEL_ERR_ARG, "import_state: the state is of another scene");
+    I.h2d(I.x.p + 3 * n0, in.x.data(), in.x.size());
+    I.h2d(I.v.p + 3 * n0, in.v.data(), in.v.size());
+    I.h2d(I.blam.p + 12 * b0, in.lam.data(), in.lam.size());
+    I.cover_valid = false;
+    I.sync();
+    return TACCEL_OK;
+  } catch (const ApiError& e) {
+    set_last_error(e.what());
+    impl_->discard_pending();
+    return e.st;
+  }
+}
+
 taccel_status Batch::reset(const uint8_t* mask) {
   try {
     Impl& I = *impl_;

@@ -128,12 +128,14 @@ struct Server {
   // which this thread no longer dereferences it (it may be released at any time).
   void run_cohort(std::vector<Request*> reqs, Batch* batch, size_t bytes) {
     size_t held = batch->device_bytes();
-    const int n = (int)reqs.size();
-    std::vector<int> mask(n, 1), done(n, 0);
-    std::vector<taccel_targets> tg(n);
-    std::vector<taccel_status> per(n);
-    std::vector<taccel_step_stats> st(n);
+    bool refill_ok = reqs[0]->scene->desc.params.precision != TACCEL_MIXED;
+    std::vector<int> done(reqs.size(), 0);
     for (;;) {
+      const int n = (int)reqs.size();
+      std::vector<int> mask(n, 1);
+      std::vector<taccel_targets> tg(n);
+      std::vector<taccel_status> per(n);
+      std::vector<taccel_step_stats> st(n);
       {
         std::lock_guard<std::mutex> lk(mu);
         if (stop)
@@ -168,6 +170,7 @@ struct Server {
         held = now;
         peak_bytes = std::max(peak_bytes.load(), held_bytes);
       }
+      bool freed = false;
       for (int i = 0; i < n; ++i) {
         if (!mask[i]) continue;
         Request* r = reqs[i];
@@ -180,9 +183,11 @@ struct Server {
           std::lock_guard<std::mutex> lk(mu);
           r->fields = std::move(f.fields);
           done[i] = 1;
+          freed = true;
           finish(r);
         }
       }
+      if (freed && refill_ok) refill(reqs, done, batch, bytes, held, refill_ok);
     }
     delete batch;
     std::lock_guard<std::mutex> lk(mu);
@@ -190,6 +195,96 @@ struct Server {
     held_bytes -= held;
     running_cohorts -= 1;
     cv_admit.notify_all();
+  }
+
+  // Waiting requests take the slots that finished requests left in a running cohort: at a step
+  // boundary the unfinished requests and newly admitted ones (arrival order, same precision,
+  // within the cohort's reservation) form a new batch, into which the unfinished requests'
+  // state moves bit for bit, so each continues exactly as it would have.  The old batch is
+  // released before the new one is built, so the cohort never holds more than its reservation.
+  // If the new batch cannot be built, the cohort goes on with its own requests and the new
+  // ones go back to the front of the queue (the admission thread then forms cohorts for them).
+  void refill(std::vector<Request*>& reqs, std::vector<int>& done, Batch*& batch, size_t bytes,
+              size_t& held, bool& refill_ok) {
+    std::vector<int> keep_idx;
+    size_t need = 0;
+    for (size_t i = 0; i < reqs.size(); ++i)
+      if (!done[i]) {
+        keep_idx.push_back((int)i);
+        need += reqs[i]->footprint;
+      }
+    if (keep_idx.empty()) return;  // the cohort ends; admission forms new cohorts
+    const int max_cohort = params.max_cohort > 0 ? params.max_cohort : 64;
+    const int prec = reqs[keep_idx[0]]->scene->desc.params.precision;
+    std::vector<Request*> add;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (stop) return;
+      while (!pending.empty() && (int)(keep_idx.size() + add.size()) < max_cohort) {
+        Request* r = pending.front();
+        if (r->scene->desc.params.precision != prec || need + r->footprint > bytes) break;
+        pending.pop_front();
+        need += r->footprint;
+        add.push_back(r);
+      }
+    }
+    if (add.empty()) return;
+    std::vector<Batch::SceneState> states(keep_idx.size());
+    std::vector<Request*> next;
+    for (size_t j = 0; j < keep_idx.size(); ++j) {
+      batch->export_state(keep_idx[j], states[j]);
+      next.push_back(reqs[keep_idx[j]]);
+    }
+    delete batch;
+    batch = nullptr;
+    taccel_runtime rt_local = rt;
+    rt_local.stream = nullptr;
+    auto build = [&](const std::vector<Request*>& rs) -> Batch* {
+      std::vector<taccel_scene_desc> descs;
+      for (Request* r : rs) descs.push_back(r->scene->desc);
+      Batch* b = nullptr;
+      std::string err;
+      if (Batch::create(descs.data(), (int)descs.size(), has_rt ? &rt_local : nullptr, &b, err) != TACCEL_OK)
+        return nullptr;
+      return b;
+    };
+    std::vector<Request*> all = next;
+    all.insert(all.end(), add.begin(), add.end());
+    Batch* nb = build(all);
+    if (!nb) {
+      nb = build(next);  // the cohort's own requests, as before
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto it = add.rbegin(); it != add.rend(); ++it) pending.push_front(*it);
+      refill_ok = false;
+      cv_admit.notify_all();
+      all = next;
+    } else {
+      const auto now = Clock::now();
+      for (Request* r : add) r->t_admit = now;
+    }
+    if (!nb) {  // the cohort's own scenes no longer build: they fail
+      std::lock_guard<std::mutex> lk(mu);
+      for (Request* r : next) {
+        r->status = TACCEL_ERR_OOM;
+        finish(r);
+      }
+      reqs.clear();
+      done.clear();
+      held_bytes -= held;
+      held = 0;
+      batch = nullptr;
+      return;
+    }
+    for (size_t j = 0; j < next.size(); ++j) nb->import_state((int)j, states[j]);
+    nb->set_byte_limit(bytes);
+    batch = nb;
+    reqs = all;
+    done.assign(reqs.size(), 0);
+    const size_t now_bytes = batch->device_bytes();
+    std::lock_guard<std::mutex> lk(mu);
+    held_bytes = held_bytes - held + now_bytes;
+    held = now_bytes;
+    peak_bytes = std::max(peak_bytes.load(), held_bytes);
   }
 
   struct HostFields {

@@ -117,6 +117,15 @@ class Batch {
   taccel_status depth_map(int scene, const taccel_camera* cam, int ntri, const int32_t* tris,
                           double* depth, double* normal);
   int num_scenes() const { return S_; }
+  // Everything of scene k that carries from one step to the next (node positions and
+  // velocities in the batch's internal order, the bodies' multipliers), bit for bit: a batch
+  // built from the same scene description takes it with import_state and continues exactly as
+  // this one would.
+  struct SceneState {
+    std::vector<double> x, v, lam;
+  };
+  taccel_status export_state(int scene, SceneState& out);
+  taccel_status import_state(int scene, const SceneState& in);
 
   struct Impl;
   Impl* impl_ = nullptr;

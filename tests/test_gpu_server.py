@@ -110,6 +110,38 @@ def test_server_staggered_cohorts(T):
     srv.close()
 
 
+def test_server_refills_running_cohort(T):
+    """Requests of uneven mesh sizes admitted into the slots a finished request leaves in the
+    one running cohort (max_cohorts = 1): the late request finishes before the long one (it
+    did not wait for the cohort to end), and every request's result is bitwise the same as
+    its scene stepped alone, across the move of the long request into the rebuilt batch."""
+    say("server: a late request refills a running cohort (uneven meshes)")
+    short = S.batch_member(40)                                  # 243-vertex pad, 8-point hull
+    long_ = S.pad_press_cube(41)                                # 243-vertex pad, cube
+    late = S.pad_press_slide_hull(42, n_steps=10, cells=(4, 4, 2), n_points=10)  # 75 vertices
+    srv = T.Server(hbm_budget_bytes=8e9, max_cohort=4, max_cohorts=1, coalesce_ms=1.0)
+    r_short = srv.submit(short, 2)
+    r_long = srv.submit(long_, 8)
+    time.sleep(0.05)
+    r_late = srv.submit(late, 3)
+    order = []
+    done = {}
+    t0 = time.time()
+    while len(done) < 3:
+        assert time.time() - t0 < 600
+        for c in srv.poll(wait_ms=50):
+            done[c["req_id"]] = c
+            order.append(c["req_id"])
+    assert all(done[r]["status"] == T.OK for r in (r_short, r_long, r_late)), done
+    assert order.index(r_late) < order.index(r_long), order
+    for rid, sp, n in ((r_short, short, 2), (r_long, long_, 8), (r_late, late, 3)):
+        st, ref = _alone(T, sp, n)
+        assert st == T.OK
+        for a, b in zip(_fields(T, srv, rid), ref):
+            assert np.array_equal(a, b)
+    srv.close()
+
+
 def test_server_limits(T):
     say("server: one cohort at a time; a budget nothing fits")
     specs = [S.batch_member(20 + i) for i in range(3)]
