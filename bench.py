@@ -428,10 +428,33 @@ def run_serving(args, taccel, scenes, np):
     info = srv.info()
     srv.close()
     waits = [done[r]["wait_ms"] for r in ids]
+    plain = None
+    if args.comparator:
+        # the same requests solved one at a time, each scene alone, FP64, in arrival order
+        t1 = time.perf_counter()
+        p_ok, p_lat, p_req_ok = 0, [], 0
+        for sp in reqs:
+            sc = taccel.Scene(sp)
+            good = 0
+            for k in range(sp.n_steps):
+                ts = time.perf_counter()
+                rc, _ = sc.step(k)
+                p_lat.append((time.perf_counter() - ts) * 1e3)
+                if rc != taccel.OK:
+                    break
+                good += 1
+            sc.close()
+            p_ok += good
+            p_req_ok += good == sp.n_steps
+        pdt = time.perf_counter() - t1
+        plain = dict(value=p_ok / pdt, unit="env-steps/s", requests_ok=p_req_ok, wall_s=pdt,
+                     p50_ms=float(np.percentile(p_lat, 50)), p99_ms=float(np.percentile(p_lat, 99)),
+                     sample="the same requests, each scene alone with taccel_step in FP64, one "
+                            "after another")
     return dict(
         metric=METRIC, value=ok_steps / dt, unit="env-steps/s", n_gpus=1, steps=len(reqs),
         warmup=0, ms_per_step=float(np.mean(lat)), higher_is_better=True, scaling="weak",
-        vs_baseline=None, dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
         config=dict(workload=f"serving stream: Poisson {args.rate}/s for {args.duration} s, "
                              "50-step rollouts of pads {16x12x4, 32x24x6, 48x36x8} with 1-3 "
                              "hull indenters of 200-8000 tris",
@@ -440,7 +463,8 @@ def run_serving(args, taccel, scenes, np):
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         requests_ok=n_ok, wall_s=dt, peak_device_gb=info["peak_bytes"] / 1e9,
         wait_p50_ms=float(np.percentile(waits, 50)), wait_p99_ms=float(np.percentile(waits, 99)),
-        roofline=None,
+        roofline=None, plain_fp64_one_at_a_time=plain,
+        vs_baseline=(ok_steps / dt) / plain["value"] if plain and plain["value"] > 0 else None,
     )
 
 
@@ -535,6 +559,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-cohort", type=int, default=64)
     ap.add_argument("--max-cohorts", type=int, default=4)
+    ap.add_argument("--no-comparator", dest="comparator", action="store_false",
+                    help="serving: skip solving the same requests one at a time in FP64")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only (scenes would shard across GPUs without "
