@@ -232,7 +232,14 @@ struct Server {
     std::vector<Batch::SceneState> states(keep_idx.size());
     std::vector<Request*> next;
     for (size_t j = 0; j < keep_idx.size(); ++j) {
-      batch->export_state(keep_idx[j], states[j]);
+      if (batch->export_state(keep_idx[j], states[j]) != TACCEL_OK) {
+        // the state cannot be moved: the cohort goes on as it is
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto it = add.rbegin(); it != add.rend(); ++it) pending.push_front(*it);
+        refill_ok = false;
+        cv_admit.notify_all();
+        return;
+      }
       next.push_back(reqs[keep_idx[j]]);
     }
     delete batch;
@@ -275,11 +282,17 @@ struct Server {
       batch = nullptr;
       return;
     }
-    for (size_t j = 0; j < next.size(); ++j) nb->import_state((int)j, states[j]);
     nb->set_byte_limit(bytes);
     batch = nb;
     reqs = all;
     done.assign(reqs.size(), 0);
+    for (size_t j = 0; j < next.size(); ++j)
+      if (nb->import_state((int)j, states[j]) != TACCEL_OK) {  // cannot continue it exactly
+        std::lock_guard<std::mutex> lk(mu);
+        next[j]->status = TACCEL_ERR_HIP;
+        done[j] = 1;
+        finish(next[j]);
+      }
     const size_t now_bytes = batch->device_bytes();
     std::lock_guard<std::mutex> lk(mu);
     held_bytes = held_bytes - held + now_bytes;
