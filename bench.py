@@ -326,7 +326,7 @@ def run_grasp(args, taccel, scenes, np):
     driven by forward kinematics, a free 10,000-triangle hull held by friction), n scenes in
     one batch; the first K steps of the 200-step trajectory timed.  With --precision mixed the
     batch is one scene (mixed batches of several scenes are refused), and the line also gives
-    the mixed path's error against the FP64 path over the timed steps."""
+    the mixed path's error against the FP64 path, step by step from the FP64 state."""
     n = args.scenes
     prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
     if prec == taccel.MIXED and n > 1:
@@ -357,8 +357,10 @@ def run_grasp(args, taccel, scenes, np):
     taccel.device_synchronize()
     dt = time.perf_counter() - t0
     if ref is not None:
-        b.reset()
+        # per step from a common start: the mixed scene takes the FP64 scene's state first
         for k in range(K):
+            for f in (taccel.FIELD_X, taccel.FIELD_V, taccel.FIELD_Q, taccel.FIELD_QDOT):
+                b.write(0, f, ref.read(0, f))
             b.step(k, targets[k])
             ref.step(k, targets[k])
             err = max(err, float(np.abs(b.read(0, taccel.FIELD_X) - ref.read(0, taccel.FIELD_X)).max()))
