@@ -281,7 +281,7 @@ def test_friction_batch_equals_single(T):
         sg.close()
 
 
-@pytest.mark.parametrize("seed", [1])
+@pytest.mark.parametrize("seed", [1, 2, 5])
 def test_c1_mixed_precision_teacher_forced(T, oracle_lib, seed):
     """Mixed precision (FP32 Hessian/SpMV/PCG, FP64 gradient, contact and CCD): every
     teacher-forced step within 1e-4 of the pad thickness (4 mm) of the FP64 oracle."""
