@@ -15,15 +15,18 @@
 //  * Log barrier b(d) = -(d - dhat)^2 ln(d/dhat) for 0 < d < dhat (App. A.3 Eq. A6) on
 //    point-triangle and edge-edge pairs of the surface meshes (App. A.3), unsquared
 //    Euclidean distance, near-parallel edge-edge pairs multiplied by the standard IPC
-//    mollifier.  Friction is not part of this path.
+//    mollifier.  Lagged friction mu lambda f0(|u|) (App. A.3) when a scene sets mu > 0.
 //  * Affine bodies (Sec. 3.3, App. A.4): y = [p; c1; c2; c3] with x = p + sum_j xbar_j c_j,
 //    xbar in the centre-of-mass frame, reduced mass My = J^T M J from exact volume
 //    integrals, an as-rigid-as-possible stiffness kappa_s V |A - R(A)|^2.
-//  * Minimisation by projected Newton: exact element derivatives by second-order
-//    forward-mode jets, per-element PSD projection by Jacobi eigen-decomposition with
-//    eigenvalues clamped at zero, a direct (skyline Cholesky) solve, additive continuous
-//    collision detection to bound the step, backtracking line search, convergence when the
-//    largest vertex displacement of the Newton direction is below tol * h * L.
+//  * Minimisation by Newton's method: exact element derivatives by second-order forward-mode
+//    jets; far from the minimiser each FEM and barrier Hessian is replaced by its nearest
+//    positive semidefinite matrix (Jacobi eigen-decomposition, eigenvalues clamped at zero),
+//    and once the last step of the loop was a full one of at most 1e-2 dhat the exact
+//    Hessians are used (the projected ones again if that system is not positive definite);
+//    a direct (skyline Cholesky) solve, additive continuous collision detection to bound the
+//    step, backtracking line search, convergence when the largest vertex displacement of the
+//    Newton direction is below tol * h * L.
 //  * Kinematic constraints: soft Dirichlet vertices are hard; prescribed affine bodies use
 //    the method of multipliers and are snapped onto their target once close enough and the
 //    snap is collision-free.
