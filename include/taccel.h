@@ -5,8 +5,10 @@
  * every scene by one backward-Euler step, x^{n+1} = argmin E(x) with
  *   E = 1/2 |x - x^n - h v^n|^2_M + h^2 (Phi_neoHookean + E_ext) + h^2 kappa sum_k b(d_k)
  * plus the affine-body terms and kinematic constraints (Sec. 3.2 Eq. 1, Sec. 3.3 Eq. 3-5,
- * Sec. 3.4 Eq. 6; App. A.1-A.5; barrier App. A.3 Eq. A6).  The minimiser is found by a
- * projected Newton method with block-Jacobi PCG, additive CCD and a backtracking line search.
+ * Sec. 3.4 Eq. 6; App. A.1-A.5; barrier App. A.3 Eq. A6).  The minimiser is found by Newton's
+ * method (element Hessians projected to positive semidefinite away from the minimiser, exact
+ * near it) with preconditioned CG (block Jacobi plus a rigid-mode coarse level), additive CCD
+ * and a backtracking line search.
  *
  * Conventions: SI units; 0-based int32 indices; arrays written [n][k] are row-major,
  * host memory unless a name ends in _device.  Inputs are borrowed for the duration of the
