@@ -246,7 +246,7 @@ struct Batch::Impl {
   DBuf<int> sflag, segid, segstart, drow, dcol, rowcnt, drowptr;
   DBuf<double> dval;
   DBuf<double> g, r, z, p, p1, q, dx, pinv;
-  DBuf<double> P_pq, P_rz0, P_rz1, P_rr, P_gg;
+  DBuf<double> P_pq, P_rz0, P_rz1, P_gg;
   // two-level preconditioner: coarse space of 6 rigid modes per aggregate of 64-node
   // blocks, with the inverse of its rest-state operator per scene
   DBuf<int> cg_blk_agg, cg_agg_b0, cg_agg_b1, cg_sc_a0, cg_sc_m;
@@ -1019,7 +1019,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   // PCG / line-search / misc
   for (DBuf<double>* b : {&g, &r, &z, &p, &p1, &q, &dx}) b->ensure(m, 3 * (size_t)Nn);
   pinv.ensure(m, 9 * (size_t)Nn);
-  for (DBuf<double>* b : {&P_rz0, &P_rz1, &P_rr, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
+  for (DBuf<double>* b : {&P_rz0, &P_rz1, &P_gg}) b->ensure(m, std::max(TN.nblk, 1));
   P_pq.ensure(m, std::max(TS.nblk, 1));
   cg_blk_agg.upload(m, cg_blk_agg_h);
   cg_agg_b0.upload(m, cg_agg_b0_h.empty() ? std::vector<int>(1, 0) : cg_agg_b0_h);
@@ -1190,7 +1190,6 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.P_pq = reinterpret_cast<T*>(P_pq.p);
   B.P_rz0 = reinterpret_cast<T*>(P_rz0.p);
   B.P_rz1 = reinterpret_cast<T*>(P_rz1.p);
-  B.P_rr = reinterpret_cast<T*>(P_rr.p);
   B.P_gg = reinterpret_cast<T*>(P_gg.p);
   B.iters = iters.p;
   B.indef = indef.p;
@@ -2124,7 +2123,7 @@ Batch::~Batch() {
   FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.val, &I.bmass,
            &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,
            &I.cend, &I.elen2, &I.bp_tbox, &I.pmeps, &I.pg, &I.ph, &I.hcoef, &I.gcoef, &I.dval, &I.g, &I.r,
-           &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_rr, &I.P_gg, &I.abase,
+           &I.z, &I.p, &I.p1, &I.q, &I.dx, &I.pinv, &I.P_pq, &I.P_rz0, &I.P_rz1, &I.P_gg, &I.abase,
            &I.alpha, &I.dE, &I.part_nodes, &I.part_tets, &I.e_bodies, &I.e_pairs, &I.part_pairs)
   FREE_ALL(&I.tp_sc, &I.tp_b0, &I.tp_b1, &I.tp_sblk)
   FREE_ALL(&I.fw, &I.fc0, &I.fnrm, &I.fmul, &I.e_fric)

@@ -112,7 +112,7 @@ struct PcgBufsT {
   const int* drowptr;
   const int* dcol;
   const T* dval;
-  T *P_pq, *P_rz0, *P_rz1, *P_rr, *P_gg;
+  T *P_pq, *P_rz0, *P_rz1, *P_gg;
   int* iters;
   int* indef;  // [S] set when PCG meets a direction of non-positive curvature (p.Ap <= 0)
   int max_iters;

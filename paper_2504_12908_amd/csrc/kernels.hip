@@ -1354,54 +1354,61 @@ __device__ void block_total256_n(T (&v)[N], T* lds) {
   __syncthreads();
 }
 
-// Lane-strided partial sum P[b0 + lane], P[b0 + lane + 64], ... < P[b1], with U loads in
-// flight per lane (added in the same order as a plain strided loop).
-template <int U, class T>
-__device__ __forceinline__ T strided_sum(const T* P, int b0, int b1, int lane) {
-  T acc = (T)0;
-  for (int k0 = b0 + lane; k0 < b1; k0 += kWave * U) {
-    T v[U];
+// Lane-strided partial sums of N arrays at once: acc[n] = P[n][b0[n] + lane] +
+// P[n][b0[n] + lane + 64] + ... (entries below b1[n]), added in that order.  Each pass has
+// U loads per array in flight, and every array's loads are issued before any of them is
+// waited for, so N sums cost one memory round trip per pass rather than N.  An array with a
+// shorter range contributes exact zeros past its end, so the result does not depend on U.
+template <int U, int N, class T>
+__device__ __forceinline__ void strided_sums(const T* const (&P)[N], const int (&b0)[N], const int (&b1)[N],
+                                             int lane, T (&acc)[N]) {
+  int len = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + kWave * u;
-      v[u] = k < b1 ? P[k] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) acc += v[u];
+  for (int n = 0; n < N; ++n) {
+    acc[n] = (T)0;
+    len = max(len, b1[n] - b0[n]);
   }
-  return acc;
+  for (int i0 = lane; i0 < len; i0 += kWave * U) {
+    T v[N][U];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = b0[n] + i0 + kWave * u;
+        v[n][u] = k < b1[n] ? P[n][k] : (T)0;
+      }
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[n] += v[n][u];
+  }
 }
 
-// Block partials of r.z and r.r and, with the coarse level on, the restriction of the
+// Block partials of r.z and, with the coarse level on, the restriction of the
 // residual onto the rigid modes u = t + w x d of the block's aggregate (d = scaled rest offset
 // from the aggregate centroid): P^T r = (sum r, sum d x r) over the block's soft nodes.  One
 // wave per 64-node block; lane 0 returns the sums.
 template <class T>
 __device__ __forceinline__ void block_partials(const View& V, const PcgBufsT<T>& B, int blk, int n, bool live,
-                                               const T* r, const T* z, T& rz, T& rr) {
-  T v[8] = {r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
-            (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+                                               const T* r, const T* z, T& rz) {
+  T v[7] = {r[0] * z[0] + r[1] * z[1] + r[2] * z[2], (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
   if (B.cg_on) {
     if (live && V.ntype[n] == 0) {
       const T* d = B.cg_d + 3 * n;
-      v[2] = r[0];
-      v[3] = r[1];
-      v[4] = r[2];
-      v[5] = d[1] * r[2] - d[2] * r[1];
-      v[6] = d[2] * r[0] - d[0] * r[2];
-      v[7] = d[0] * r[1] - d[1] * r[0];
+      v[1] = r[0];
+      v[2] = r[1];
+      v[3] = r[2];
+      v[4] = d[1] * r[2] - d[2] * r[1];
+      v[5] = d[2] * r[0] - d[0] * r[2];
+      v[6] = d[0] * r[1] - d[1] * r[0];
     }
     wave_total_n(v);
     if (threadIdx.x == 0)
-      for (int k = 0; k < 6; ++k) B.cg_rc[6 * blk + k] = v[2 + k];
+      for (int k = 0; k < 6; ++k) B.cg_rc[6 * blk + k] = v[1 + k];
   } else {
-    T w[2] = {v[0], v[1]};
-    wave_total_n(w);
-    v[0] = w[0];
-    v[1] = w[1];
+    v[0] = wave_total(v[0]);
   }
   rz = v[0];
-  rr = v[1];
 }
 
 // Preconditioned CG with two kernels per iteration k (parity = k & 1):
@@ -1444,19 +1451,50 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
     precond_apply<T>(V, B.pinv, n, n0, rs, z);
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
   }
-  T rz, rr;
-  block_partials<T>(V, B, blk, n, live, r, z, rz, rr);
+  T rz;
+  block_partials<T>(V, B, blk, n, live, r, z, rz);
   if (threadIdx.x == 0) {
     B.P_rz0[blk] = rz;
     B.P_rz1[blk] = (T)1;
     B.P_gg[blk] = rz;  // g^T D^{-1} g: the reference of the stopping test
-    B.P_rr[blk] = rr;
   }
+}
+
+// One 3x3 block of the sparse product with its operands: the block, and z and p_{k-1} at its
+// column.  None of it depends on beta, so it can be loaded before the scene scalars are known.
+template <class T>
+struct SpmvEntry {
+  T a[9], z[3], p[3];
+};
+template <class T>
+__device__ __forceinline__ void spmv_load(const T* val, const int* col, const T* z, const T* pold, int k,
+                                          SpmvEntry<T>& e) {
+  const T* A = val + 9 * (size_t)k;
+  for (int i = 0; i < 9; ++i) e.a[i] = A[i];
+  const int c = col[k];
+  for (int i = 0; i < 3; ++i) {
+    e.z[i] = z[3 * c + i];
+    e.p[i] = pold[3 * c + i];
+  }
+}
+// q += A (z + beta p_{k-1}) at the block's column
+template <class T>
+__device__ __forceinline__ void spmv_acc(const SpmvEntry<T>& e, T beta, T& q0, T& q1, T& q2) {
+  const T p0 = e.z[0] + beta * e.p[0];
+  const T p1 = e.z[1] + beta * e.p[1];
+  const T p2 = e.z[2] + beta * e.p[2];
+  q0 += e.a[0] * p0 + e.a[1] * p1 + e.a[2] * p2;
+  q1 += e.a[3] * p0 + e.a[4] * p1 + e.a[5] * p2;
+  q2 += e.a[6] * p0 + e.a[7] * p1 + e.a[8] * p2;
 }
 
 // One wave covers 4 block-rows (16 lanes each); every wave computes the scene scalars
 // itself, so the row loads are not held back behind a workgroup barrier (the only barrier
-// is in the closing p.q reduction).
+// is in the closing p.q reduction).  Each lane's first block of the static range (for most
+// rows every block: a row of the tet mesh has at most 15 static blocks) is loaded, operands
+// included, before the scene scalars, so the two chains of dependent loads overlap instead
+// of following each other.  The dynamic (contact and body) blocks, present on few rows,
+// follow the scalars: prefetching them too would cost occupancy on every row.
 template <class T>
 __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, BlockTable TS, PcgBufsT<T> B,
                                                       int parity) {
@@ -1471,6 +1509,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   const T* Prz_old = parity ? B.P_rz0 : B.P_rz1;
   const T* pold = parity ? B.p1 : B.p0;
   T* pnew = parity ? B.p0 : B.p1;
+  const T* sval = reinterpret_cast<const T*>(V.val);
   const int sub = threadIdx.x & (kRowLanes - 1);
   const int row = TS.b0[blk] + (int)(threadIdx.x / kRowLanes);
   const bool inrange = row < TS.b1[blk];
@@ -1499,17 +1538,21 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
       por[c] = pold[3 * row + c];
     }
   }
-  T rzc, rzo, rr, gg;
+  // the lane's first static block with its operands
+  const bool has_s = k0 + sub < k1;
+  SpmvEntry<T> es;
+  if (has_s) spmv_load(sval, V.col, B.z, pold, k0 + sub, es);
+  T rzc, rzo, gg;
   {
     const int lane = threadIdx.x & (kWave - 1);
     const int b0 = TN.sblk[s], b1 = TN.sblk[s + 1];
-    T v[4] = {strided_sum<2>(Prz_cur, b0, b1, lane), strided_sum<2>(Prz_old, b0, b1, lane),
-              strided_sum<2>(B.P_rr, b0, b1, lane), strided_sum<2>(B.P_gg, b0, b1, lane)};
+    const T* const P[3] = {Prz_cur, Prz_old, B.P_gg};
+    T v[3];
+    strided_sums<2>(P, {b0, b0, b0}, {b1, b1, b1}, lane, v);
     wave_total_n(v);
     rzc = v[0];
     rzo = v[1];
-    rr = v[2];
-    gg = v[3];
+    gg = v[2];
   }
   const T eta = (T)V.sc[s].pcg_eta;
   // iters[s] is only written by k_pcg_update, so every wave sees the same count here
@@ -1518,32 +1561,21 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   // penalty) do not set the scale for all the others.
   const bool conv = (rzc <= eta * eta * gg) || !(rzc > (T)0) || !(rzo > (T)0) || B.iters[s] >= B.max_iters ||
                     B.indef[s];
-  (void)rr;
   if (conv) {
     if (blk == TS.sblk[s] && threadIdx.x == 0) V.pdone[s] = 1;
     return;
   }
   const T beta = rzc / rzo;
   T q0 = (T)0, q1 = (T)0, q2 = (T)0;
-  for (int k = k0 + sub; k < k1; k += kRowLanes) {
-    const T* A = reinterpret_cast<const T*>(V.val) + 9 * (size_t)k;
-    const int c = V.col[k];
-    const T p0 = B.z[3 * c] + beta * pold[3 * c];
-    const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
-    const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
-    q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
-    q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
-    q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
+  // blocks in the order of a plain strided pass: static range, then dynamic range
+  if (has_s) spmv_acc(es, beta, q0, q1, q2);
+  for (int k = k0 + sub + kRowLanes; k < k1; k += kRowLanes) {
+    spmv_load(sval, V.col, B.z, pold, k, es);
+    spmv_acc(es, beta, q0, q1, q2);
   }
   for (int k = d0 + sub; k < d1; k += kRowLanes) {
-    const T* A = B.dval + 9 * (size_t)k;
-    const int c = B.dcol[k];
-    const T p0 = B.z[3 * c] + beta * pold[3 * c];
-    const T p1 = B.z[3 * c + 1] + beta * pold[3 * c + 1];
-    const T p2 = B.z[3 * c + 2] + beta * pold[3 * c + 2];
-    q0 += A[0] * p0 + A[1] * p1 + A[2] * p2;
-    q1 += A[3] * p0 + A[4] * p1 + A[5] * p2;
-    q2 += A[6] * p0 + A[7] * p1 + A[8] * p2;
+    spmv_load(B.dval, B.dcol, B.z, pold, k, es);
+    spmv_acc(es, beta, q0, q1, q2);
   }
   q0 = row16_total(q0);
   q1 = row16_total(q1);
@@ -1688,8 +1720,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
       for (int c = 0; c < 3; ++c) dn[c] = B.cg_d[3 * n + c];
   }
   // ---- scene scalars (every wave computes them itself)
-  T tot[2] = {strided_sum<2>(Prz_cur, TN.sblk[s], TN.sblk[s + 1], lane),
-              strided_sum<8>(B.P_pq, TS.sblk[s], TS.sblk[s + 1], lane)};
+  const T* const Ptot[2] = {Prz_cur, B.P_pq};
+  T tot[2];
+  strided_sums<4>(Ptot, {TN.sblk[s], TS.sblk[s]}, {TN.sblk[s + 1], TS.sblk[s + 1]}, lane, tot);
   wave_total_n(tot);
   const T rzs = tot[0], pqs = tot[1];
   const T alpha = pqs > (T)0 ? rzs / pqs : (T)0;
@@ -1742,12 +1775,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
   if (wid != 0) return;
   if (live)
     for (int c = 0; c < 3; ++c) B.z[3 * n + c] = z[c];
-  // block partials of r.z (z with its coarse part) and r.r
-  T sums[2] = {r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
-  wave_total_n(sums);
+  // block partial of r.z (z with its coarse part)
+  const T rz = wave_total(r[0] * z[0] + r[1] * z[1] + r[2] * z[2]);
   if (lane == 0) {
-    Prz_new[blk] = sums[0];
-    B.P_rr[blk] = sums[1];
+    Prz_new[blk] = rz;
     if (blk == TN.sblk[s]) ++B.iters[s];
   }
 }
