@@ -130,6 +130,12 @@ def _spmv_roofline(taccel):
                 algorithmic_bytes_per_launch=bytes_per_launch)
 
 
+def _precision(args, taccel):
+    """The --precision flag as the library's taccel_precision and the bench line's dtype."""
+    return {"fp64": (taccel.FP64, "f64"), "mixed": (taccel.MIXED, "f32+f64"),
+            "refined": (taccel.FP64_REFINED, "f64+f32")}[args.precision]
+
+
 def _set_friction(args, specs):
     """--friction MU: the workload with the lagged friction potential (eps_v = 1e-3 m/s)."""
     if args.friction > 0.0:
@@ -154,6 +160,20 @@ def _roofline_pass(taccel, step_fn, n_steps):
         roof["pcg_us_per_iter"] = pcg["total_ms"] * 1e3 / pcg["launches"]
     roof["measured_over"] = f"steps 0..{n_steps - 1} of the trajectory, after the timed region"
     return roof
+
+
+def _refine_ratio(taccel, spec, prec, steps=3):
+    """FP32 passes per Newton direction over the first steps of one scene (FP64_REFINED), in a
+    pass of its own after the timed region."""
+    sc = taccel.Scene(spec, precision=prec)
+    taccel.profile_reset()
+    taccel.profile_enable(True)
+    for k in range(min(steps, spec.n_steps)):
+        sc.step(k)
+    taccel.profile_enable(False)
+    sc.close()
+    r = taccel.profile_query("refine")
+    return r["launches"] / r["bytes"] if r["bytes"] else None
 
 
 def _single_trajectory(taccel, spec, prec, log=None):
@@ -186,7 +206,7 @@ def run_single(args, taccel, scenes, np):
     and slide trajectory timed after a warm-up scene of W steps."""
     spec = scenes.pad_press_slide_hull(0)
     _set_friction(args, [spec])
-    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    prec, dtype = _precision(args, taccel)
     if args.warmup > 0:
         warm = taccel.Scene(spec, precision=prec)
         for k in range(min(args.warmup, spec.n_steps)):
@@ -197,7 +217,7 @@ def run_single(args, taccel, scenes, np):
     out = dict(
         metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=n, warmup=args.warmup,
         ms_per_step=dt * 1e3 / n, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        dtype=dtype, data="synthetic",
         config=dict(workload="gel pad 32x24x6 grid (5775 verts, 27648 tets) pressed 1 mm and "
                              "slid 2 mm by a 400-point convex hull (796 tris), 1 scene, whole "
                              "100-step trajectory",
@@ -225,6 +245,8 @@ def run_single(args, taccel, scenes, np):
         out["phase_ms_per_newton_iter"] = {name: v["total_ms"] / n_it for name, v in ph.items()}
     if prec == taccel.FP64:
         out["roofline"]["traffic"] = _measured_traffic()
+    if prec == taccel.FP64_REFINED:
+        out["fp32_passes_per_direction"] = _refine_ratio(taccel, spec, prec)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline([spec], budget_s=args.cpu_budget)
     return out
@@ -241,7 +263,7 @@ def run_batch(args, taccel, scenes, np):
     _set_friction(args, specs)
     nst = specs[0].n_steps
     W, K = args.warmup, args.steps
-    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    prec, dtype = _precision(args, taccel)
     if prec == taccel.MIXED and n > 1:
         sys.exit("bench.py: mixed precision runs one scene per batch (see include/taccel.h)")
     t_create = time.perf_counter()
@@ -277,7 +299,7 @@ def run_batch(args, taccel, scenes, np):
     out = dict(
         metric=METRIC, value=value, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        dtype=dtype, data="synthetic",
         config=dict(workload=f"uniform batch of {n} small pads (243 verts, 768 tets each) with "
                              "seeded 8-point hull indenters, pressed over the whole 10-step "
                              "trajectory", scenes=n, precision=args.precision,
@@ -328,7 +350,7 @@ def run_grasp(args, taccel, scenes, np):
     batch is one scene (mixed batches of several scenes are refused), and the line also gives
     the mixed path's error against the FP64 path, step by step from the FP64 state."""
     n = args.scenes
-    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    prec, dtype = _precision(args, taccel)
     if prec == taccel.MIXED and n > 1:
         sys.exit("bench.py: mixed precision runs one scene per batch (see include/taccel.h)")
     specs = [scenes.grasp_lift(i) for i in range(n)]
@@ -368,7 +390,7 @@ def run_grasp(args, taccel, scenes, np):
     out = dict(
         metric=METRIC, value=ok / dt, unit="env-steps/s", n_gpus=1, steps=K, warmup=W,
         ms_per_step=dt * 1e3 / K, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        dtype=dtype, data="synthetic",
         config=dict(workload=f"two-finger grasp and lift, {n} scene(s): two 32x24x6-cell pads "
                              "(11,550 verts, 55,296 tets) on gripper links, a free 10,000-triangle "
                              "hull held by friction; first steps of the 200-step trajectory",
@@ -390,7 +412,7 @@ def run_serving(args, taccel, scenes, np):
     arrivals = scenes.serving_arrivals(args.rate, args.duration)
     print(f"generating {len(arrivals)} requests", file=sys.stderr, flush=True)
     reqs = [scenes.serving_request(i) for i in range(len(arrivals))]
-    prec = taccel.MIXED if args.precision == "mixed" else taccel.FP64
+    prec, dtype = _precision(args, taccel)
     srv = taccel.Server(hbm_budget_bytes=args.budget_gb * 1e9, max_cohort=args.max_cohort,
                         max_cohorts=args.max_cohorts, coalesce_ms=2.0)
     ids = [None] * len(reqs)
@@ -456,7 +478,7 @@ def run_serving(args, taccel, scenes, np):
     return dict(
         metric=METRIC, value=ok_steps / dt, unit="env-steps/s", n_gpus=1, steps=len(reqs),
         warmup=0, ms_per_step=float(np.mean(lat)), higher_is_better=True, scaling="weak",
-        dtype="f64" if prec == taccel.FP64 else "f32+f64", data="synthetic",
+        dtype=dtype, data="synthetic",
         config=dict(workload=f"serving stream: Poisson {args.rate}/s for {args.duration} s, "
                              "50-step rollouts of pads {16x12x4, 32x24x6, 48x36x8} with 1-3 "
                              "hull indenters of 200-8000 tris",
@@ -541,7 +563,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["single", "batch", "grasp", "serving", "tactile", "copy"],
                     default="batch")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "refined"], default="fp64",
+                    help="fp64; mixed (FP32 Hessians, SpMV and PCG); refined (FP64 system, FP32 "
+                         "PCG passes with FP64 residual refinement)")
     ap.add_argument("--scenes", type=int, default=256)
     ap.add_argument("--plain-scenes", type=int, default=16,
                     help="scenes of the batch also stepped one at a time (FP64 comparator)")

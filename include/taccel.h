@@ -40,8 +40,14 @@ typedef enum {
 } taccel_status;
 
 /* MIXED: FP32 Hessian blocks, assembly, SpMV and PCG; FP64 positions, gradient, contact,
- * CCD and convergence test.  A batch with more than one scene must use FP64 (ERR_ARG). */
-typedef enum { TACCEL_FP64 = 0, TACCEL_MIXED = 1 } taccel_precision;
+ * CCD and convergence test.  A batch with more than one scene must use FP64 or
+ * FP64_REFINED (ERR_ARG).
+ * FP64_REFINED: every term, block and the assembly in FP64, as FP64; the PCG iterations run
+ * on an FP32 copy of the FP64 system (half the bytes per sparse product), and the FP64
+ * residual of the system decides whether another FP32 pass solves for a correction
+ * (mixed-precision iterative refinement, the stronger-solver item of the paper's stated PCG
+ * bottleneck, Sec. 7), so the Newton direction meets the FP64 tolerance. */
+typedef enum { TACCEL_FP64 = 0, TACCEL_MIXED = 1, TACCEL_FP64_REFINED = 2 } taccel_precision;
 
 /* Soft body (the gel pad): nv rest vertices, nt tets of positive orientation.
  * dirichlet[i]: 0 free, 1 fixed, 2 moving (position prescribed each step); NULL = all free.
@@ -77,7 +83,8 @@ typedef struct {
   int32_t max_newton; /* per Newton loop; 0 -> 100 */
   int32_t max_al;     /* augmented-Lagrangian rounds; 0 -> 30 */
   int32_t max_pcg;    /* 0 -> 10000 */
-  double pcg_eta;     /* relative residual of PCG; 0 -> 1e-4 (FP64) or 1e-3 (MIXED) */
+  double pcg_eta;     /* relative residual of PCG; 0 -> 1e-4 (FP64, FP64_REFINED) or 1e-3
+                         (MIXED) */
   int32_t precision;  /* taccel_precision.  MIXED: Hessian blocks, their assembly, the sparse
                          product and the whole PCG in FP32 (FP32 accumulation); positions,
                          gradients, energies, distances, barrier, CCD, line search and the
@@ -370,6 +377,9 @@ taccel_status taccel_debug_candidates(taccel_scene* s, const double* P0, const d
  *     product must move once);
  *   "pcg": the PCG iterations of every solve (after initialisation) between two events;
  *     query returns the summed milliseconds and iterations (largest count per solve);
+ *   "refine" (FP64_REFINED, counted while bit 0 is on): query returns 0 ms, the number of
+ *     FP32 passes as launches and the number of Newton directions they solved as
+ *     algorithmic_bytes (passes per direction = launches / that count);
  *   "candidates", "derivatives", "solve", "check", "ccd", "line_search": host wall time of
  *     each phase of a Newton iteration (static candidates and narrow phase; element
  *     derivatives, assembly and preconditioner; PCG; convergence test; swept candidates and

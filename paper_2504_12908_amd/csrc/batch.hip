@@ -232,6 +232,16 @@ struct Batch::Impl {
   std::vector<taccel_step_stats> last_stats;  // per scene: statistics of its last step
   bool validate_only = false;  // build() stops after the host-side checks
   int mixed = 0;  // 1: FP32 Hessian blocks, assembly, SpMV and PCG (taccel_precision MIXED)
+  // 1: FP64 system, FP32 PCG passes with FP64 refinement (taccel_precision FP64_REFINED)
+  int refine = 0;
+  static constexpr int kRefinePasses = 3;  // FP32 solves per Newton direction, at most
+  // FP32 copies of the FP64 system for the passes, the FP32 coarse offsets, the correction of
+  // a pass, the FP64 residual and its per-block norms
+  DBuf<float> val32, dval32, pinv32, bpinv32, cg_d32, cg_dw32;
+  DBuf<double> dxc, gres, rpart;
+  int nh_last = 0;  // contact and body block records of the current Newton system
+  std::vector<int> tn_sblk_host;  // [S + 1] first TN block of each scene
+  std::vector<int> solve_refined(const View& V, const int* nseg_d, const std::vector<int>& act_s);
   // dynamic work buffers
   BroadPhase bp;
   DBuf<double> bp_tbox;
@@ -540,11 +550,14 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     C.eh = P.eps_v * P.h;
     if (C.fmu > 0.0) any_fric = true;
     C.precision = P.precision;
-    if (P.precision != TACCEL_FP64 && P.precision != TACCEL_MIXED)
-      throw ApiError(TACCEL_ERR_ARG, "precision must be TACCEL_FP64 or TACCEL_MIXED");
-    if (s == 0) mixed = P.precision == TACCEL_MIXED;
-    else if (mixed != (P.precision == TACCEL_MIXED))
+    if (P.precision != TACCEL_FP64 && P.precision != TACCEL_MIXED && P.precision != TACCEL_FP64_REFINED)
+      throw ApiError(TACCEL_ERR_ARG, "precision must be TACCEL_FP64, TACCEL_MIXED or TACCEL_FP64_REFINED");
+    if (s == 0) {
+      mixed = P.precision == TACCEL_MIXED;
+      refine = P.precision == TACCEL_FP64_REFINED;
+    } else if (mixed != (P.precision == TACCEL_MIXED) || refine != (P.precision == TACCEL_FP64_REFINED)) {
       throw ApiError(TACCEL_ERR_ARG, "all scenes of a batch must use the same precision");
+    }
     // A 256-scene mixed-precision batch ended in a GPU memory fault whose cause is not shown;
     // until it is, mixed precision runs one scene per object.  (The host build of the tests
     // defines TACCEL_HOST_MIXED_BATCHES to run such batches under its guard pages.)
@@ -848,6 +861,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     Nq = C.q1;
   }
   tn_sblk_h.push_back((int)tn_sc_h.size());
+  tn_sblk_host = tn_sblk_h;
   tt_sblk_h.push_back((int)tt_sc_h.size());
   ts_sblk_h.push_back((int)ts_sc_h.size());
   nnz = (int)h_col.size();
@@ -1062,6 +1076,17 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     cg_d.upload(m, cg_d_h);
     cg_dw.upload(m, dw_h);
   }
+  if (refine) {
+    // the FP32 passes read FP32 coarse offsets; the system and its preconditioner are
+    // converted from FP64 for every Newton direction
+    cg_d32.upload(m, std::vector<float>(cg_d_h.begin(), cg_d_h.end()));
+    cg_dw32.upload(m, std::vector<float>(dw_h.begin(), dw_h.end()));
+    val32.ensure(m, 9 * (size_t)std::max(nnz, 1));
+    pinv32.ensure(m, 9 * (size_t)std::max(Nn, 1));
+    bpinv32.ensure(m, 144 * (size_t)std::max(Nb, 1));
+    for (DBuf<double>* b : {&dxc, &gres}) b->ensure(m, 3 * (size_t)std::max(Nn, 1));
+    rpart.ensure(m, 2 * (size_t)std::max(TN.nblk, 1));
+  }
   sync();
   iters.ensure(m, S);
   bad.ensure(m, S);
@@ -1191,6 +1216,7 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.P_rz0 = reinterpret_cast<T*>(P_rz0.p);
   B.P_rz1 = reinterpret_cast<T*>(P_rz1.p);
   B.P_gg = reinterpret_cast<T*>(P_gg.p);
+  B.keep_gg = 0;
   B.iters = iters.p;
   B.indef = indef.p;
   B.cg_on = cg_on;
@@ -1268,7 +1294,7 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d
     prof.spmv_launches += kSample;
     prof.spmv_bytes += kSample * launch_bytes;
   }
-  const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, V.bpinv};
+  const std::vector<const void*> key = {B.dval, B.dcol, B.drowptr, B.pinv, B.dx, V.bpinv, V.val};
   if (!pcg_exec || key != pcg_key) {
     // (re)capture the chunk; when only buffer addresses changed, the existing executable
     // graph is updated in place rather than rebuilt
@@ -1328,6 +1354,83 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d
     prof.pcg_ms += ms;
     prof.pcg_iters += mx;
   }
+}
+
+// FP32 PCG with FP64 refinement (TACCEL_FP64_REFINED) for the scenes of act_s: the FP64
+// blocks and block-Jacobi inverses are rounded to FP32 once; each pass runs the FP32 PCG on
+// the current residual and adds its solution to dx in FP64; after a pass the FP64 residual
+// gres = g + H dx is measured in the FP64 block-Jacobi norm, and a scene whose
+// gres^T D^-1 gres exceeds eta^2 g^T D^-1 g (and whose pass met no direction of non-positive
+// curvature) takes another pass, at most kRefinePasses in all.  The passes' stopping test keeps
+// the first pass's reference, so every pass aims at eta relative to the Newton gradient.
+// Returns the PCG iterations per scene, summed over the passes.
+std::vector<int> Batch::Impl::solve_refined(const View& V, const int* nseg_d, const std::vector<int>& act_s) {
+  hipStream_t s = stream();
+  launch_to_f32(9 * (size_t)nnz, V.val, val32.p, s);
+  launch_to_f32(9 * (size_t)std::max(nh_last, 0), dval.p, dval32.p, s);
+  launch_to_f32(9 * (size_t)Nn, pinv.p, pinv32.p, s);
+  launch_to_f32(144 * (size_t)Nb, bpinv.p, bpinv32.p, s);
+  View V32 = V;
+  V32.val = reinterpret_cast<double*>(val32.p);      // read as FP32 by the PCG kernels
+  V32.bpinv = reinterpret_cast<double*>(bpinv32.p);  // the same
+  PcgBufsT<float> B = pcg_bufs<float>();
+  B.pinv = pinv32.p;
+  B.dval = dval32.p;
+  B.cg_d = cg_d32.p;
+  B.cg_dw = cg_dw32.p;
+  B.dx = dxc.p;
+  zero(dx.p, sizeof(double) * 3 * (size_t)Nn);
+  std::vector<int> total(S, 0), pending = act_s, it_h(S), indef_h(S);
+  std::vector<double> part;
+  for (int pass = 0;; ++pass) {
+    // pdone = !pending was set by the caller for the first pass
+    zero(iters.p, sizeof(int) * S);
+    zero(dxc.p, sizeof(double) * 3 * (size_t)Nn);  // scenes skipped by the pass add zero
+    launch_pcg_init(V32, TN, B, s);
+    launch_pcg_coarse(V32, TN, B, B.P_rz0, s);
+    run_pcg(V32, B, nseg_d);
+    launch_add3(3 * Nn, dxc.p, dx.p, s);
+    d2h(it_h.data(), iters.p, S);
+    d2h(indef_h.data(), indef.p, S);
+    sync();
+    Profiler& prof = profiler();
+    for (int k = 0; k < S; ++k)
+      if (pending[k]) {
+        total[k] += it_h[k];
+        if (prof.on) {
+          prof.refine_passes += 1;
+          prof.refine_dirs += pass == 0;
+        }
+      }
+    if (pass + 1 == kRefinePasses) break;
+    // FP64 residual of the scenes that took this pass
+    std::vector<int> hd(S);
+    for (int k = 0; k < S; ++k) hd[k] = !pending[k];
+    h2d(pdone.p, hd.data(), S);
+    launch_refine_resid(V, TS, drowptr.p, dcol.p, dval.p, g.p, dx.p, gres.p, s);
+    launch_refine_norm(V, TN, pinv.p, g.p, gres.p, rpart.p, s);
+    part.resize(2 * (size_t)std::max(TN.nblk, 1));
+    d2h(part.data(), rpart.p, part.size());
+    sync();
+    bool any = false;
+    for (int k = 0; k < S; ++k) {
+      if (!pending[k]) continue;
+      double rr = 0.0, gg = 0.0;  // block order: the same sum on every call
+      for (int b = tn_sblk_host[k]; b < tn_sblk_host[k + 1]; ++b) {
+        rr += part[2 * (size_t)b];
+        gg += part[2 * (size_t)b + 1];
+      }
+      const double eta = hsc[k].pcg_eta;
+      pending[k] = !indef_h[k] && std::isfinite(rr) && rr > eta * eta * gg;
+      any = any || pending[k];
+    }
+    if (!any) break;
+    for (int k = 0; k < S; ++k) hd[k] = !pending[k];
+    h2d(pdone.p, hd.data(), S);
+    B.g = gres.p;
+    B.keep_gg = 1;
+  }
+  return total;
 }
 
 // Friction pairs of the step (Taccel App. A.3): every pair closer than dhat at the
@@ -1506,6 +1609,8 @@ int* Batch::Impl::derivatives(int np, int npf) {
   drow.ensure(&mem, std::max(nh, 1));
   dcol.ensure(&mem, std::max(nh, 1));
   dval.ensure(&mem, 9 * (size_t)std::max(nh, 1));
+  if (refine) dval32.ensure(&mem, 9 * (size_t)std::max(nh, 1));
+  nh_last = nh;
   zero(rowcnt.p, sizeof(int) * (Nn + 1));
   HIPCHECK(hipStreamWaitEvent(s, ev_join, 0));
   HIPCHECK(hipStreamWaitEvent(s, ev_join2, 0));
@@ -1564,11 +1669,14 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     }
     zero(iters.p, sizeof(int) * S);
     phase_end(1);
+    std::vector<int> it_h(S), bad_h(S), indef_h(S);
     if (mixed) {
       const PcgBufsT<float> B = pcg_bufs<float>();
       launch_pcg_init(V, TN, B, s);
       launch_pcg_coarse(V, TN, B, B.P_rz0, s);
       run_pcg(V, B, nseg_d);
+    } else if (refine) {
+      it_h = solve_refined(V, nseg_d, attempt_act);
     } else {
       const PcgBufsT<double> B = pcg_bufs<double>();
       launch_pcg_init(V, TN, B, s);
@@ -1576,8 +1684,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
       run_pcg(V, B, nseg_d);
     }
     phase_end(2);
-    std::vector<int> it_h(S), bad_h(S), indef_h(S);
-    d2h(it_h.data(), iters.p, S);
+    if (!refine) d2h(it_h.data(), iters.p, S);
     d2h(bad_h.data(), bad.p, S);
     d2h(indef_h.data(), indef.p, S);
     sync();
@@ -2134,7 +2241,8 @@ Batch::~Batch() {
   FREE_ALL(&I.ts_sc, &I.ts_b0, &I.ts_b1, &I.ts_sblk)
   FREE_ALL(&I.cg_blk_agg, &I.cg_agg_b0, &I.cg_agg_b1, &I.cg_sc_a0, &I.cg_sc_m, &I.cg_sc_ts0,
            &I.cg_sc_tsn, &I.cg_sc_tsend, &I.bp_tmp)
-  FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc, &I.P_qc, &I.cg_rca0, &I.cg_rca1, &I.cg_dw)
+  FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc, &I.P_qc, &I.cg_rca0, &I.cg_rca1, &I.cg_dw, &I.dxc, &I.gres, &I.rpart)
+  FREE_ALL(&I.val32, &I.dval32, &I.pinv32, &I.bpinv32, &I.cg_d32, &I.cg_dw32)
   I.cg_sc_off.free();
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag,
            &I.vptr, &I.vlist, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,

@@ -354,6 +354,8 @@ void taccel_profile_reset(void) {
   p.spmv_bytes = 0.0;
   p.pcg_ms = 0.0;
   p.pcg_iters = 0;
+  p.refine_dirs = 0;
+  p.refine_passes = 0;
   for (double& v : p.phase_ms) v = 0.0;
   p.phase_calls = 0;
 }
@@ -373,6 +375,13 @@ taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t
     if (algorithmic_bytes) *algorithmic_bytes = 0.0;
     return TACCEL_OK;
   }
+  if (kernel && std::strcmp(kernel, "refine") == 0) {
+    // launches: FP32 passes; algorithmic_bytes: the Newton directions they solved
+    if (total_ms) *total_ms = 0.0;
+    if (launches) *launches = p.refine_passes;
+    if (algorithmic_bytes) *algorithmic_bytes = (double)p.refine_dirs;
+    return TACCEL_OK;
+  }
   for (int k = 0; kernel && k < tc::Profiler::kPhases; ++k)
     if (std::strcmp(kernel, tc::kPhaseNames[k]) == 0) {
       if (total_ms) *total_ms = p.phase_ms[k];
@@ -380,7 +389,7 @@ taccel_status taccel_profile_query(const char* kernel, double* total_ms, int64_t
       if (algorithmic_bytes) *algorithmic_bytes = 0.0;
       return TACCEL_OK;
     }
-  return fail(TACCEL_ERR_ARG, "profile_query: \"spmv\", \"pcg\" or a Newton-iteration phase name");
+  return fail(TACCEL_ERR_ARG, "profile_query: \"spmv\", \"pcg\", \"refine\" or a Newton-iteration phase name");
 }
 
 taccel_status taccel_device_synchronize(void) {

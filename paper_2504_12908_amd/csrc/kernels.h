@@ -102,10 +102,14 @@ void launch_precond(const View& V, const int* drowptr, const int* dcol, const vo
 
 // PCG over the node-block table TN (vector updates) and the row table TS (sparse product);
 // partial sums per block.  T is the arithmetic of the linear solve (double, or float in the
-// mixed-precision mode); the gradient g and the solution dx stay double.
+// mixed-precision mode and in the passes of the refined FP64 mode); the right-hand side -g and
+// the solution dx stay double.
 template <class T>
 struct PcgBufsT {
-  const double* g;
+  const double* g;  // the system is H dx = -g
+  int keep_gg;      // 1: keep P_gg, the stopping reference, from the previous solve (a
+                    // refinement pass is measured against the Newton gradient, not its own
+                    // right-hand side)
   T *r, *z, *p0, *p1, *q;
   double* dx;
   const T* pinv;
@@ -156,6 +160,8 @@ struct Profiler {
   double spmv_bytes = 0.0;
   double pcg_ms = 0.0;        // wall time of the PCG chunk replays (after initialisation)
   long long pcg_iters = 0;    // iterations of those solves (largest per solve)
+  long long refine_dirs = 0;    // Newton directions solved by FP32 passes (FP64_REFINED)
+  long long refine_passes = 0;  // the FP32 passes they took
   // host wall time per Newton-iteration phase (each phase ends with a stream synchronisation
   // while profiling): candidates, derivatives + assembly, linear solve, convergence check,
   // swept candidates + CCD, line search + update
@@ -168,6 +174,17 @@ Profiler& profiler();
 
 // convergence, CCD, line search, update
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s);
+// FP32 PCG with FP64 refinement (TACCEL_FP64_REFINED): FP32 copies of the FP64 system, the
+// FP64 residual gres = g + H dx of the scenes still refining (pdone = 0; zero on fixed rows),
+// its block-Jacobi norm and the gradient's per TN block (part[2 blk], part[2 blk + 1]), and
+// dx += c after a correction pass.
+void launch_to_f32(size_t n, const double* src, float* dst, hipStream_t s);
+void launch_refine_resid(const View& V, const BlockTable& TS, const int* drowptr, const int* dcol,
+                         const double* dval, const double* g, const double* dx, double* gres,
+                         hipStream_t s);
+void launch_refine_norm(const View& V, const BlockTable& TN, const double* pinv, const double* g,
+                        const double* gres, double* part, hipStream_t s);
+void launch_add3(int n, const double* c, double* dx, hipStream_t s);
 void launch_ccd(const View& V, int n, const int* cand_q, const int* cand_t,
                 unsigned long long* amin, hipStream_t s);
 void launch_scene_offsets(const View& V, int n, const int* cand_q, int* off, hipStream_t s);

@@ -1456,7 +1456,7 @@ __global__ void __launch_bounds__(kWave) k_pcg_init(View V, BlockTable TN, PcgBu
   if (threadIdx.x == 0) {
     B.P_rz0[blk] = rz;
     B.P_rz1[blk] = (T)1;
-    B.P_gg[blk] = rz;  // g^T D^{-1} g: the reference of the stopping test
+    if (!B.keep_gg) B.P_gg[blk] = rz;  // g^T D^{-1} g: the reference of the stopping test
   }
 }
 
@@ -1838,6 +1838,91 @@ __global__ void __launch_bounds__(kWave) k_pcg_coarse(View V, BlockTable TN, Pcg
     B.z[3 * n + 1] += e[1] + (e[5] * dn[0] - e[3] * dn[2]);
     B.z[3 * n + 2] += e[2] + (e[3] * dn[1] - e[4] * dn[0]);
   }
+}
+
+// ------------------------------------------------------------------ FP32 PCG, FP64 refinement
+__global__ void k_to_f32(size_t n, const double* src, float* dst) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// gres = g + H dx on the free rows (16 lanes per block-row, as the sparse product of the
+// PCG), zero on the others; scenes with pdone set are left alone.  With H dx = -g solved
+// exactly gres would vanish: it is the FP64 residual of the FP32 passes' solution.
+__global__ void __launch_bounds__(TPB) k_refine_resid(View V, BlockTable TS, const int* drowptr,
+                                                      const int* dcol, const double* dval,
+                                                      const double* g, const double* dx, double* gres) {
+  const int blk = xcd_block(TS.nblk);
+  if (blk < 0) return;
+  const int s = TS.sc[blk];
+  if (V.pdone[s]) return;  // set by the host before the launch: uniform over the workgroup
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int row = TS.b0[blk] + (int)(threadIdx.x / kRowLanes);
+  const bool inrange = row < TS.b1[blk];
+  const bool live = inrange && V.nfree[row];
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  if (live) {
+    for (int k = V.rowptr[row] + sub; k < V.rowptr[row + 1]; k += kRowLanes) {
+      const double* A = V.val + 9 * (size_t)k;
+      const double* x = dx + 3 * (size_t)V.col[k];
+      q0 += A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+      q1 += A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+      q2 += A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+    }
+    for (int k = drowptr[row] + sub; k < drowptr[row + 1]; k += kRowLanes) {
+      const double* A = dval + 9 * (size_t)k;
+      const double* x = dx + 3 * (size_t)dcol[k];
+      q0 += A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+      q1 += A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+      q2 += A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+    }
+  }
+  q0 = row16_total(q0);
+  q1 = row16_total(q1);
+  q2 = row16_total(q2);
+  if (inrange && sub == kRowLanes - 1) {
+    gres[3 * (size_t)row] = live ? g[3 * (size_t)row] + q0 : 0.0;
+    gres[3 * (size_t)row + 1] = live ? g[3 * (size_t)row + 1] + q1 : 0.0;
+    gres[3 * (size_t)row + 2] = live ? g[3 * (size_t)row + 2] + q2 : 0.0;
+  }
+}
+
+// Per TN block (one wavefront): gres^T D^-1 gres and g^T D^-1 g over its free nodes, with the
+// FP64 block-Jacobi inverse D^-1 (3x3 per soft node, 12x12 per affine body).
+__global__ void __launch_bounds__(kWave) k_refine_norm(View V, BlockTable TN, const double* pinv,
+                                                       const double* g, const double* gres, double* part) {
+  const int blk = xcd_block(TN.nblk);
+  if (blk < 0) return;
+  __shared__ double rs[kWave][3], gs[kWave][3];
+  const int s = TN.sc[blk];
+  if (V.pdone[s]) return;  // set by the host before the launch: uniform over the wavefront
+  const int n0 = TN.b0[blk];
+  const int n = n0 + (int)threadIdx.x;
+  const bool live = n < TN.b1[blk];
+  const bool f = live && V.nfree[n];
+  for (int c = 0; c < 3; ++c) {
+    rs[threadIdx.x][c] = f ? gres[3 * (size_t)n + c] : 0.0;
+    gs[threadIdx.x][c] = f ? g[3 * (size_t)n + c] : 0.0;
+  }
+  __syncthreads();
+  double zr[3] = {0.0, 0.0, 0.0}, zg[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    precond_apply<double>(V, pinv, n, n0, rs, zr);
+    precond_apply<double>(V, pinv, n, n0, gs, zg);
+  }
+  const int l = threadIdx.x;
+  double v[2] = {rs[l][0] * zr[0] + rs[l][1] * zr[1] + rs[l][2] * zr[2],
+                 gs[l][0] * zg[0] + gs[l][1] * zg[1] + gs[l][2] * zg[2]};
+  wave_total_n(v);
+  if (threadIdx.x == 0) {
+    part[2 * (size_t)blk] = v[0];
+    part[2 * (size_t)blk + 1] = v[1];
+  }
+}
+
+__global__ void k_add3(int n, const double* c, double* dx) {
+  const int i = gid();
+  if (i < n) dx[i] += c[i];
 }
 
 // Number of active pairs per scene (statistics).
@@ -2466,6 +2551,24 @@ template void launch_pcg_update<float>(const View&, const BlockTable&, const Blo
 void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipStream_t s) {
   LAUNCH(k_pmax, V.Nn + V.Ncv, TPB, s, V, p, pmax);
 }
+void launch_to_f32(size_t n, const double* src, float* dst, hipStream_t s) {
+  if (n == 0) return;
+  const size_t nb = std::min<size_t>((n + TPB - 1) / TPB, 65536);
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)nb), dim3(TPB), 0, s, n, src, dst);
+}
+void launch_refine_resid(const View& V, const BlockTable& TS, const int* drowptr, const int* dcol,
+                         const double* dval, const double* g, const double* dx, double* gres,
+                         hipStream_t s) {
+  if (TS.nblk > 0)
+    hipLaunchKernelGGL(k_refine_resid, dim3(xcd_grid(TS.nblk)), dim3(TPB), 0, s, V, TS, drowptr, dcol,
+                       dval, g, dx, gres);
+}
+void launch_refine_norm(const View& V, const BlockTable& TN, const double* pinv, const double* g,
+                        const double* gres, double* part, hipStream_t s) {
+  if (TN.nblk > 0)
+    hipLaunchKernelGGL(k_refine_norm, dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, pinv, g, gres, part);
+}
+void launch_add3(int n, const double* c, double* dx, hipStream_t s) { LAUNCH(k_add3, n, TPB, s, n, c, dx); }
 void launch_ccd(const View& V, int n, const int* cq, const int* ct, unsigned long long* amin,
                 hipStream_t s) {
   LAUNCH(k_ccd, n, 64, s, V, n, cq, ct, amin);

@@ -19,7 +19,7 @@ _ip = C.POINTER(C.c_int32)
 
 OK, ERR_ARG, ERR_HIP, NOT_CONVERGED, LINESEARCH_FAILED, AL_FAILED, NAN, INFEASIBLE_TARGET, \
     ERR_OOM, INFEASIBLE, CANCELLED = range(11)
-FP64, MIXED = 0, 1
+FP64, MIXED, FP64_REFINED = 0, 1, 2
 FIELD_X, FIELD_V, FIELD_Q, FIELD_QDOT, FIELD_BODY_X, FIELD_CONTACTS, FIELD_STATS = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_HIP", "NOT_CONVERGED", "LINESEARCH_FAILED", "AL_FAILED",
                 "NAN", "INFEASIBLE_TARGET", "ERR_OOM", "INFEASIBLE", "CANCELLED"]

@@ -134,6 +134,44 @@ print("DONE")
 """)
 
 
+def test_host_build_fp64_refined(host_lib):
+    """TACCEL_FP64_REFINED (FP32 PCG passes on an FP32 copy of the FP64 system, FP64 residual
+    refinement): teacher-forced cube steps match the oracle within 1e-8 L with a PCG tolerance
+    (1e-7) that one FP32 pass cannot meet, so refinement passes run (more passes than Newton
+    directions); a batch of two scenes equals each scene alone, bit for bit."""
+    out = run(host_lib, """
+spec = S.pad_press_cube(0)
+o = B.OracleScene(spec)
+g = T.Scene(spec, precision=T.FP64_REFINED, pcg_eta=1e-7)
+T.profile_reset(); T.profile_enable(True)
+for k in range(2):
+    g.set_state(*o.get_state())
+    rc_o, _ = o.step(k)
+    rc, st = g.step(k)
+    assert rc_o == 0 and rc == T.OK, (k, rc_o, rc)
+    err = np.abs(g.get_state()[0] - o.get_state()[0]).max()
+    assert err <= 1e-8 * o.scale, (k, err)
+T.profile_enable(False)
+ref = T.profile_query("refine")
+print("passes", ref["launches"], "directions", ref["bytes"])
+assert ref["launches"] > ref["bytes"] > 0, ref
+g.close()
+specs = [S.batch_member(1), S.batch_member(4)]
+b = T.Batch(specs, precision=T.FP64_REFINED)
+rc, per, st = b.step(0)
+assert rc == T.OK and list(per) == [0, 0], per
+for i, sp in enumerate(specs):
+    sc = T.Scene(sp, precision=T.FP64_REFINED)
+    assert sc.step(0)[0] == T.OK
+    assert np.array_equal(sc.read(T.FIELD_X), b.read(i, T.FIELD_X))
+    assert np.array_equal(sc.read(T.FIELD_Q), b.read(i, T.FIELD_Q))
+    sc.close()
+b.close()
+print("DONE")
+""")
+    print(out)
+
+
 LONG = os.environ.get("TACCEL_HOST_LONG") == "1"
 
 
