@@ -1356,7 +1356,8 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d
   }
 }
 
-// FP32 PCG with FP64 refinement (TACCEL_FP64_REFINED) for the scenes of act_s: the FP64
+// FP32 PCG with FP64 refinement (TACCEL_FP64_REFINED) for the scenes of act_s (the device's
+// act holds the same set; the directions of the other scenes are left as they are): the FP64
 // blocks and block-Jacobi inverses are rounded to FP32 once; each pass runs the FP32 PCG on
 // the current residual and adds its solution to dx in FP64; after a pass the FP64 residual
 // gres = g + H dx is measured in the FP64 block-Jacobi norm, and a scene whose
@@ -1379,7 +1380,6 @@ std::vector<int> Batch::Impl::solve_refined(const View& V, const int* nseg_d, co
   B.cg_d = cg_d32.p;
   B.cg_dw = cg_dw32.p;
   B.dx = dxc.p;
-  zero(dx.p, sizeof(double) * 3 * (size_t)Nn);
   std::vector<int> total(S, 0), pending = act_s, it_h(S), indef_h(S);
   std::vector<double> part;
   for (int pass = 0;; ++pass) {
@@ -1389,7 +1389,7 @@ std::vector<int> Batch::Impl::solve_refined(const View& V, const int* nseg_d, co
     launch_pcg_init(V32, TN, B, s);
     launch_pcg_coarse(V32, TN, B, B.P_rz0, s);
     run_pcg(V32, B, nseg_d);
-    launch_add3(3 * Nn, dxc.p, dx.p, s);
+    launch_refine_apply(V, dxc.p, dx.p, pass == 0, s);
     d2h(it_h.data(), iters.p, S);
     d2h(indef_h.data(), indef.p, S);
     sync();
@@ -1654,6 +1654,12 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     pcg_it[k] = 0;
   }
   std::vector<int> attempt_act = act_host;
+  // convergence measure of the Newton direction (max vertex displacement per scene), read
+  // back with the solve's counters: one synchronisation for both
+  unsigned long long* pmax = u64s.p;
+  unsigned long long* amin = u64s.p + S;
+  std::vector<unsigned long long> hp(S, 0ull), hp_att(S);
+  std::vector<int> hcount(S);
   for (int attempt = 0;; ++attempt) {
     h2d(exact.p, exact_h.data(), S);
     zero(indef.p, sizeof(int) * S);
@@ -1684,13 +1690,18 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
       run_pcg(V, B, nseg_d);
     }
     phase_end(2);
+    zero(pmax, sizeof(unsigned long long) * S);
+    launch_pmax(V, dx.p, pmax, s);  // the scenes of this attempt (device act)
     if (!refine) d2h(it_h.data(), iters.p, S);
     d2h(bad_h.data(), bad.p, S);
     d2h(indef_h.data(), indef.p, S);
+    d2h(hp_att.data(), pmax, S);
+    if (attempt == 0) d2h(hcount.data(), scnt.p, S);
     sync();
     bool retry = false;
     for (int k = 0; k < S; ++k) {
       if (!attempt_act[k]) continue;
+      hp[k] = hp_att[k];
       pcg_it[k] += it_h[k];
       hbad[k] = bad_h[k];
       attempt_act[k] = exact_h[k] && indef_h[k];
@@ -1703,16 +1714,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     h2d(act.p, attempt_act.data(), S);
   }
   h2d(act.p, act_host.data(), S);
-  // ---- convergence check on the Newton direction
-  unsigned long long* pmax = u64s.p;
-  unsigned long long* amin = u64s.p + S;
-  zero(pmax, sizeof(unsigned long long) * S);
-  launch_pmax(V, dx.p, pmax, s);
-  std::vector<unsigned long long> hp(S);
-  std::vector<int> hcount(S);
-  d2h(hp.data(), pmax, S);
-  d2h(hcount.data(), scnt.p, S);
-  sync();
+  // ---- convergence check on the Newton direction (hp, read with the last solve)
   const std::vector<int>& hact = act_host;
   pcg_last_max = 0;
   for (int k = 0; k < S; ++k) {

@@ -177,14 +177,14 @@ void launch_pmax(const View& V, const double* p, unsigned long long* pmax, hipSt
 // FP32 PCG with FP64 refinement (TACCEL_FP64_REFINED): FP32 copies of the FP64 system, the
 // FP64 residual gres = g + H dx of the scenes still refining (pdone = 0; zero on fixed rows),
 // its block-Jacobi norm and the gradient's per TN block (part[2 blk], part[2 blk + 1]), and
-// dx += c after a correction pass.
+// dx = c (first pass) or dx += c (correction pass) on the scenes of the call (act).
 void launch_to_f32(size_t n, const double* src, float* dst, hipStream_t s);
 void launch_refine_resid(const View& V, const BlockTable& TS, const int* drowptr, const int* dcol,
                          const double* dval, const double* g, const double* dx, double* gres,
                          hipStream_t s);
 void launch_refine_norm(const View& V, const BlockTable& TN, const double* pinv, const double* g,
                         const double* gres, double* part, hipStream_t s);
-void launch_add3(int n, const double* c, double* dx, hipStream_t s);
+void launch_refine_apply(const View& V, const double* c, double* dx, int assign, hipStream_t s);
 void launch_ccd(const View& V, int n, const int* cand_q, const int* cand_t,
                 unsigned long long* amin, hipStream_t s);
 void launch_scene_offsets(const View& V, int n, const int* cand_q, int* off, hipStream_t s);

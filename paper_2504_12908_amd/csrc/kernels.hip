@@ -1920,9 +1920,12 @@ __global__ void __launch_bounds__(kWave) k_refine_norm(View V, BlockTable TN, co
   }
 }
 
-__global__ void k_add3(int n, const double* c, double* dx) {
+// dx = c (first pass) or dx += c on the nodes of the scenes solved in this call (act):
+// the other scenes' directions are left as they are
+__global__ void k_refine_apply(View V, const double* c, double* dx, int assign) {
   const int i = gid();
-  if (i < n) dx[i] += c[i];
+  if (i >= 3 * V.Nn || !V.act[V.nscene[i / 3]]) return;
+  dx[i] = assign ? c[i] : dx[i] + c[i];
 }
 
 // Number of active pairs per scene (statistics).
@@ -2568,7 +2571,9 @@ void launch_refine_norm(const View& V, const BlockTable& TN, const double* pinv,
   if (TN.nblk > 0)
     hipLaunchKernelGGL(k_refine_norm, dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, pinv, g, gres, part);
 }
-void launch_add3(int n, const double* c, double* dx, hipStream_t s) { LAUNCH(k_add3, n, TPB, s, n, c, dx); }
+void launch_refine_apply(const View& V, const double* c, double* dx, int assign, hipStream_t s) {
+  LAUNCH(k_refine_apply, 3 * V.Nn, TPB, s, V, c, dx, assign);
+}
 void launch_ccd(const View& V, int n, const int* cq, const int* ct, unsigned long long* amin,
                 hipStream_t s) {
   LAUNCH(k_ccd, n, 64, s, V, n, cq, ct, amin);
