@@ -93,6 +93,12 @@ typedef struct {
                          App. A.3); 0: frictionless (no friction work at all).  >= 0. */
   double eps_v;       /* velocity threshold (m/s) between static and sliding friction in the
                          mollifier f1; must be > 0 when friction > 0. */
+  int32_t pcg_forcing; /* 0: every Newton system is solved to pcg_eta.  1: inexact Newton with
+                         Eisenstat-Walker forcing terms (the paper's relaxed convergence
+                         tolerances, Sec. 7): the first iteration of each Newton loop is
+                         solved to 0.01, iteration k to 0.9 (g_k'D^-1 g_k)/(g_k-1'D^-1 g_k-1)
+                         (not below 0.9 eta_k-1^2 when that exceeds 0.1), clamped to
+                         [pcg_eta, 0.01].  The converged state meets the same Newton test. */
 } taccel_params;
 
 typedef struct {

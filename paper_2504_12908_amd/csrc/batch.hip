@@ -216,6 +216,35 @@ struct Batch::Impl {
   // per scene, the previous Newton iteration of its current loop: step size and max vertex
   // displacement of the direction (they decide whether this iteration uses exact Hessians)
   std::vector<double> prev_alpha, prev_pmax;
+  // forcing terms (scenes with pcg_forcing): g'D^-1 g of the previous Newton iteration of the
+  // loop (-1 at a loop's start) and its tolerance, uploaded before every solve; the block
+  // partials of g'D^-1 g read back after it
+  std::vector<double> gg_prev_h, eta_prev_h;
+  DBuf<double> fg_prev;  // [2 S]: gg_prev, eta_prev
+  std::vector<double> ggd_h;
+  std::vector<float> ggf_h;
+  void gg_readback() {  // enqueued; valid after the next sync()
+    const size_t nb = (size_t)TN.nblk;
+    if (nb == 0) return;
+    if (mixed || refine) {
+      ggf_h.resize(nb);
+      d2h(ggf_h.data(), reinterpret_cast<const float*>(P_gg.p), nb);
+    } else {
+      ggd_h.resize(nb);
+      d2h(ggd_h.data(), P_gg.p, nb);
+    }
+  }
+  double gg_scene(int k) const {  // block order: the same sum on every call
+    double acc = 0.0;
+    for (int b = tn_sblk_host[k]; b < tn_sblk_host[k + 1]; ++b)
+      acc += (mixed || refine) ? (double)ggf_h[b] : ggd_h[b];
+    return acc;
+  }
+  // the tolerance the solve of scene k used (after gg_readback and its sync)
+  double eta_used(int k) const {
+    return hsc[k].forcing ? forcing_eta(hsc[k].pcg_eta, gg_scene(k), gg_prev_h[k], eta_prev_h[k])
+                          : hsc[k].pcg_eta;
+  }
   std::vector<int> exact_h;
   // block tables
   DBuf<int> tn_sc, tn_b0, tn_b1, tn_sblk, tt_sc, tt_b0, tt_b1, tt_sblk, ts_sc, ts_b0, ts_b1, ts_sblk;
@@ -484,6 +513,8 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   last_stats.assign(S, taccel_step_stats{});
   prev_alpha.assign(S, 0.0);
   prev_pmax.assign(S, 0.0);
+  gg_prev_h.assign(S, -1.0);
+  eta_prev_h.assign(S, 0.0);
   exact_h.assign(S, 0);
   std::vector<double> h_x, h_mass, h_Dminv_aos, h_tvol;
   std::vector<int> h_nfree, h_nbody, h_tv_aos, h_tscene;
@@ -550,6 +581,9 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     C.eh = P.eps_v * P.h;
     if (C.fmu > 0.0) any_fric = true;
     C.precision = P.precision;
+    if (P.pcg_forcing != 0 && P.pcg_forcing != 1)
+      throw ApiError(TACCEL_ERR_ARG, "pcg_forcing must be 0 or 1");
+    C.forcing = P.pcg_forcing;
     if (P.precision != TACCEL_FP64 && P.precision != TACCEL_MIXED && P.precision != TACCEL_FP64_REFINED)
       throw ApiError(TACCEL_ERR_ARG, "precision must be TACCEL_FP64, TACCEL_MIXED or TACCEL_FP64_REFINED");
     if (s == 0) {
@@ -1089,6 +1123,7 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
   }
   sync();
   iters.ensure(m, S);
+  fg_prev.ensure(m, 2 * (size_t)S);
   bad.ensure(m, S);
   infeasible.ensure(m, S);
   scnt.ensure(m, S + 1);
@@ -1217,6 +1252,8 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.P_rz1 = reinterpret_cast<T*>(P_rz1.p);
   B.P_gg = reinterpret_cast<T*>(P_gg.p);
   B.keep_gg = 0;
+  B.ggprev = fg_prev.p;
+  B.etaprev = fg_prev.p + S;
   B.iters = iters.p;
   B.indef = indef.p;
   B.cg_on = cg_on;
@@ -1411,6 +1448,7 @@ std::vector<int> Batch::Impl::solve_refined(const View& V, const int* nseg_d, co
     launch_refine_norm(V, TN, pinv.p, g.p, gres.p, rpart.p, s);
     part.resize(2 * (size_t)std::max(TN.nblk, 1));
     d2h(part.data(), rpart.p, part.size());
+    if (pass == 0) gg_readback();  // the first pass's reference: the tolerance it used
     sync();
     bool any = false;
     for (int k = 0; k < S; ++k) {
@@ -1420,7 +1458,7 @@ std::vector<int> Batch::Impl::solve_refined(const View& V, const int* nseg_d, co
         rr += part[2 * (size_t)b];
         gg += part[2 * (size_t)b + 1];
       }
-      const double eta = hsc[k].pcg_eta;
+      const double eta = eta_used(k);
       pending[k] = !indef_h[k] && std::isfinite(rr) && rr > eta * eta * gg;
       any = any || pending[k];
     }
@@ -1660,6 +1698,14 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
   unsigned long long* amin = u64s.p + S;
   std::vector<unsigned long long> hp(S, 0ull), hp_att(S);
   std::vector<int> hcount(S);
+  {
+    std::vector<double> fg(2 * (size_t)S);
+    for (int k = 0; k < S; ++k) {
+      fg[k] = gg_prev_h[k];
+      fg[S + k] = eta_prev_h[k];
+    }
+    h2d(fg_prev.p, fg.data(), fg.size());
+  }
   for (int attempt = 0;; ++attempt) {
     h2d(exact.p, exact_h.data(), S);
     zero(indef.p, sizeof(int) * S);
@@ -1697,6 +1743,7 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     d2h(indef_h.data(), indef.p, S);
     d2h(hp_att.data(), pmax, S);
     if (attempt == 0) d2h(hcount.data(), scnt.p, S);
+    gg_readback();
     sync();
     bool retry = false;
     for (int k = 0; k < S; ++k) {
@@ -1714,6 +1761,13 @@ void Batch::Impl::newton_iteration(std::vector<int>& last, std::vector<int>& ls_
     h2d(act.p, attempt_act.data(), S);
   }
   h2d(act.p, act_host.data(), S);
+  // forcing-term state for the next iteration of each loop
+  for (int k = 0; k < S; ++k)
+    if (act_host[k] && hsc[k].forcing) {
+      const double e = eta_used(k);
+      gg_prev_h[k] = gg_scene(k);
+      eta_prev_h[k] = e;
+    }
   // ---- convergence check on the Newton direction (hp, read with the last solve)
   const std::vector<int>& hact = act_host;
   pcg_last_max = 0;
@@ -2006,6 +2060,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
   std::vector<unsigned long long> hres(Nb + 1);
   int bglob = 0;
   std::fill(prev_alpha.begin(), prev_alpha.end(), 0.0);
+  std::fill(gg_prev_h.begin(), gg_prev_h.end(), -1.0);  // every Newton loop starts afresh
   // ---- per-scene state machine
   enum { kNewton = 0, kDone = 1, kFailed = 2 };
   std::vector<int> phase(S, kNewton), status(S, TACCEL_OK), nit(S, 0), tot_nit(S, 0), rounds(S, 1);
@@ -2126,6 +2181,7 @@ taccel_status Batch::Impl::step(const taccel_targets* tg, taccel_status* per_sce
       ++rounds[k];
       nit[k] = 0;
       prev_alpha[k] = 0.0;  // a new Newton loop starts projected
+      gg_prev_h[k] = -1.0;  // and with the loosest forcing term
     }
   }
   // ---- finish: velocities for converged scenes, roll back failed ones
@@ -2245,6 +2301,7 @@ Batch::~Batch() {
            &I.cg_sc_tsn, &I.cg_sc_tsend, &I.bp_tmp)
   FREE_ALL(&I.cg_d, &I.cg_ainv, &I.cg_rc, &I.P_qc, &I.cg_rca0, &I.cg_rca1, &I.cg_dw, &I.dxc, &I.gres, &I.rpart)
   FREE_ALL(&I.val32, &I.dval32, &I.pinv32, &I.bpinv32, &I.cg_d32, &I.cg_dw32)
+  I.fg_prev.free();
   I.cg_sc_off.free();
   FREE_ALL(&I.nfree, &I.nscene, &I.nbody, &I.ntype, &I.tv, &I.tscene, &I.rowptr, &I.col, &I.diag,
            &I.vptr, &I.vlist, &I.bnode, &I.bscene, &I.bpres, &I.bsnap, &I.bcv0, &I.bcv1,

@@ -110,6 +110,9 @@ struct PcgBufsT {
   int keep_gg;      // 1: keep P_gg, the stopping reference, from the previous solve (a
                     // refinement pass is measured against the Newton gradient, not its own
                     // right-hand side)
+  const double* ggprev;   // [S] g'D^-1 g of the previous Newton iteration of the loop (<= 0:
+                          // none) and the tolerance it was solved to: the forcing rule's
+  const double* etaprev;  // inputs (scenes with SceneConst::forcing set)
   T *r, *z, *p0, *p1, *q;
   double* dx;
   const T* pinv;
@@ -140,6 +143,20 @@ struct PcgBufsT {
   T *cg_rca0, *cg_rca1;       // [aggregates][6] restricted residual P^T r_k (by parity of k)
 };
 constexpr int kCoarseMaxAgg = 128;  // aggregates per scene (coarse dimension <= 768)
+
+// Forcing term of inexact Newton (Eisenstat and Walker 1996, choice 2 with gamma = 0.9,
+// alpha = 2 and its safeguard), on the preconditioned gradient norm: the relative PCG
+// tolerance of the current Newton system given gg = g'D^-1 g now and at the previous
+// iteration of the same Newton loop, and the previous tolerance; within [eta_min, kForcingMax].
+constexpr double kForcingMax = 0.01;
+__host__ __device__ inline double forcing_eta(double eta_min, double gg, double gg_prev, double eta_prev) {
+  if (!(gg_prev > 0.0)) return fmax(kForcingMax, eta_min);
+  double e = 0.9 * (gg / gg_prev);
+  const double sg = 0.9 * eta_prev * eta_prev;
+  if (sg > 0.1) e = fmax(e, sg);
+  if (!(e >= eta_min)) e = eta_min;  // also when gg / gg_prev is not a number
+  return fmin(e, fmax(kForcingMax, eta_min));
+}
 template <class T>
 void launch_pcg_init(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, hipStream_t s);
 template <class T>

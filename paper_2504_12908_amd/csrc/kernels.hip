@@ -1554,7 +1554,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
     rzo = v[1];
     gg = v[2];
   }
-  const T eta = (T)V.sc[s].pcg_eta;
+  // the relative tolerance: fixed, or the forcing term of this Newton iteration (every wave
+  // computes the same value from the same sums)
+  const T eta = (T)(V.sc[s].forcing ? forcing_eta(V.sc[s].pcg_eta, (double)gg, B.ggprev[s], B.etaprev[s])
+                                    : V.sc[s].pcg_eta);
   // iters[s] is only written by k_pcg_update, so every wave sees the same count here
   // Stop once r^T M^{-1} r <= eta^2 g^T D^{-1} g: the residual measured in the
   // preconditioner's norm, so that a few stiff unknowns (a body held by its constraint

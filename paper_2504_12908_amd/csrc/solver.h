@@ -22,7 +22,8 @@ struct SceneConst {
   double grav[3];
   double cell, org[3];
   int node0, node1, tet0, tet1, cv0, cv1, q0, q1, body0, body1, tri0, tri1, edge0, edge1;
-  int precision, pad;
+  int precision;
+  int forcing;  // 1: PCG tolerance per Newton iteration by the forcing rule (pcg_forcing)
 };
 
 // Raw device pointers of a batch; passed by value to every kernel.

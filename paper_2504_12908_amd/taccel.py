@@ -75,7 +75,7 @@ class taccel_params(C.Structure):
                 ("kappa_s", C.c_double), ("newton_tol", C.c_double),
                 ("gravity", C.c_double * 3), ("max_newton", C.c_int32), ("max_al", C.c_int32),
                 ("max_pcg", C.c_int32), ("pcg_eta", C.c_double), ("precision", C.c_int32),
-                ("friction", C.c_double), ("eps_v", C.c_double)]
+                ("friction", C.c_double), ("eps_v", C.c_double), ("pcg_forcing", C.c_int32)]
 
 
 class taccel_scene_desc(C.Structure):
@@ -254,6 +254,7 @@ class _Desc:
         d.params.precision = precision
         d.params.friction = p.get("friction", 0.0)
         d.params.eps_v = p.get("eps_v", 0.0)
+        d.params.pcg_forcing = int(p.get("pcg_forcing", 0))
         self.desc = d
         self.nv = len(verts)
         self.nb = nb

@@ -172,6 +172,37 @@ print("DONE")
     print(out)
 
 
+def test_host_build_pcg_forcing(host_lib):
+    """pcg_forcing = 1 (Eisenstat-Walker forcing terms for the PCG tolerance): a teacher-forced
+    cube step still matches the oracle within 1e-8 L, with fewer PCG iterations than the fixed
+    tolerance."""
+    run(host_lib, """
+spec = S.pad_press_cube(0)
+o = B.OracleScene(spec)
+x0 = o.get_state()
+rc_o, _ = o.step(0)
+assert rc_o == 0
+pcg = {}
+for f in (0, 1):
+    g = T.Scene(spec, pcg_forcing=f)
+    g.set_state(*x0)
+    rc, st = g.step(0)
+    assert rc == T.OK, rc
+    err = np.abs(g.get_state()[0] - o.get_state()[0]).max()
+    assert err <= 1e-8 * o.scale, (f, err)
+    pcg[f] = st["pcg_iters"]
+    g.close()
+print("pcg fixed", pcg[0], "forcing", pcg[1])
+assert pcg[1] < pcg[0], pcg
+try:
+    T.Scene(spec, pcg_forcing=2)
+    raise AssertionError("pcg_forcing=2 accepted")
+except T.TaccelError as e:
+    assert e.status == T.ERR_ARG, e
+print("DONE")
+""")
+
+
 LONG = os.environ.get("TACCEL_HOST_LONG") == "1"
 
 
