@@ -295,6 +295,7 @@ struct Batch::Impl {
   DBuf<int> cg_sc_ts0, cg_sc_tsn, cg_sc_tsend;
   DBuf<int> bp_tmp;  // broad phase: candidates in emitted order before the per-query sort
   int cg_on = 0;
+  int cg_mmax = 0;  // largest coarse dimension of a scene
   DBuf<int> iters, bad, infeasible, scnt, cand_off, action, okflag, failflag, snapcand;
   DBuf<unsigned long long> u64s;  // pmax [S], amin [S], body residuals [Nb]
   DBuf<double> abase, alpha, dE, part_nodes, part_tets, e_bodies, e_pairs, part_pairs;
@@ -949,6 +950,8 @@ void Batch::Impl::build(const taccel_scene_desc* descs, int n) {
     cg_sc_m_h[s] = build_coarse(cs, cg_blk_agg_h, cg_agg_b0_h, cg_agg_b1_h, cg_d_h, cg_ainv_h);
   }
   cg_on = cg_agg_b0_h.empty() ? 0 : 1;
+  cg_mmax = 0;
+  for (int m2 : cg_sc_m_h) cg_mmax = std::max(cg_mmax, m2);
   // TS blocks (16 rows) of each aggregate: both tables start at the scene's first node and
   // 64 is a multiple of 16, so the rows of a TN block are the TS blocks 4j .. 4j + 3
   static_assert(kNodeChunk % kRowChunk == 0, "TN blocks must hold whole TS blocks");
@@ -1257,6 +1260,7 @@ PcgBufsT<T> Batch::Impl::pcg_bufs() {
   B.iters = iters.p;
   B.indef = indef.p;
   B.cg_on = cg_on;
+  B.cg_mmax = cg_on ? cg_mmax : 0;
   B.cg_blk_agg = cg_blk_agg.p;
   B.cg_agg_b0 = cg_agg_b0.p;
   B.cg_agg_b1 = cg_agg_b1.p;

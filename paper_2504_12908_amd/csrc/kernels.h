@@ -125,6 +125,7 @@ struct PcgBufsT {
   int max_iters;
   // coarse level (cg_on = 0: block Jacobi alone)
   int cg_on;
+  int cg_mmax;                // largest coarse dimension of a scene (0 without the coarse level)
   const int* cg_blk_agg;      // [TN blocks] aggregate of the block, -1 if it has no soft node
   const int* cg_agg_b0;       // [aggregates] first TN block
   const int* cg_agg_b1;       // [aggregates] one past the last TN block

@@ -1623,13 +1623,18 @@ __global__ void __launch_bounds__(TPB) k_pcg_dir_spmv(View V, BlockTable TN, Blo
   }
 }
 
-template <class T>
-__global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, BlockTable TS,
-                                                    PcgBufsT<T> B, int parity) {
+// NT threads per 64-node block: 256 in general (the coarse entries of a scene spread over 4
+// wavefronts), 64 when no scene has more than 64 coarse entries (one wavefront per block does
+// all the work; with at most 64 entries the 256-thread form holds them all in its first
+// wavefront and adds exact zeros from the others, so both forms give the same bits).
+template <class T, int NT>
+__global__ void __launch_bounds__(NT) k_pcg_update(View V, BlockTable TN, BlockTable TS,
+                                                   PcgBufsT<T> B, int parity) {
+  static_assert(NT == kWave || NT == TPB, "one or four wavefronts per block");
   const int blk = xcd_block(TN.nblk);
   if (blk < 0) return;
   __shared__ T rs[kWave][3];
-  __shared__ T red[TPB / kWave][6];
+  __shared__ T red[NT / kWave][6];
   const int s = TN.sc[blk];
   if (V.pdone[s]) return;  // one uniform load: the blocks of converged scenes stay cheap
   const int wid = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
@@ -1658,7 +1663,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
     for (int i = 0; i < 9; ++i) P9[i] = B.pinv[9 * (size_t)n + i];
   }
   // ---- coarse operands (4 waves share the scene's coarse entries)
-  constexpr int kPerThread = 6 * kCoarseMaxAgg / TPB;
+  constexpr int kPerThread = NT == kWave ? 1 : 6 * kCoarseMaxAgg / TPB;
   const int a = B.cg_on ? B.cg_blk_agg[blk] : -1;
   int m = 0, la = 0;
   T rcj[kPerThread], qsj[kPerThread];
@@ -1681,7 +1686,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
     bool on[kPerThread];
 #pragma unroll
     for (int t = 0; t < kPerThread; ++t) {
-      const int j = (int)threadIdx.x + TPB * t;
+      const int j = (int)threadIdx.x + NT * t;
       on[t] = j < m;
       const int jj = on[t] ? j : 0;
       const int k = jj % 6, i0 = ts0 + tsn * (jj / 6), i1 = min(i0 + tsn, tsend);
@@ -1759,16 +1764,18 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(View V, BlockTable TN, Block
 #pragma unroll
     for (int t = 0; t < kPerThread; ++t) {
       const T rj = rcj[t] - alpha * qsj[t];
-      const int j = (int)threadIdx.x + TPB * t;
+      const int j = (int)threadIdx.x + NT * t;
       if (first && j < m && j / 6 == la) rc_next[j] = rj;
 #pragma unroll
       for (int q = 0; q < 6; ++q) e[q] += (T)Aij[t][q] * rj;
     }
     wave_total_n(e);
-    if (lane == 0)
-      for (int q = 0; q < 6; ++q) red[wid][q] = e[q];
-    __syncthreads();
-    for (int q = 0; q < 6; ++q) e[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    if constexpr (NT == TPB) {
+      if (lane == 0)
+        for (int q = 0; q < 6; ++q) red[wid][q] = e[q];
+      __syncthreads();
+      for (int q = 0; q < 6; ++q) e[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
     if (live && ntn == 0 && nfn) {
       z[0] += e[0] + (e[4] * dn[2] - e[5] * dn[1]);
       z[1] += e[1] + (e[5] * dn[0] - e[3] * dn[2]);
@@ -2539,8 +2546,11 @@ void launch_pcg_spmv(const View& V, const BlockTable& TN, const BlockTable& TS, 
 template <class T>
 void launch_pcg_update(const View& V, const BlockTable& TN, const BlockTable& TS, const PcgBufsT<T>& B,
                        int parity, hipStream_t s) {
-  if (TN.nblk > 0)
-    hipLaunchKernelGGL(k_pcg_update<T>, dim3(xcd_grid(TN.nblk)), dim3(TPB), 0, s, V, TN, TS, B, parity);
+  if (TN.nblk <= 0) return;
+  if (B.cg_mmax <= kWave)
+    hipLaunchKernelGGL((k_pcg_update<T, kWave>), dim3(xcd_grid(TN.nblk)), dim3(kWave), 0, s, V, TN, TS, B, parity);
+  else
+    hipLaunchKernelGGL((k_pcg_update<T, TPB>), dim3(xcd_grid(TN.nblk)), dim3(TPB), 0, s, V, TN, TS, B, parity);
 }
 template <class T>
 void launch_pcg_coarse(const View& V, const BlockTable& TN, const PcgBufsT<T>& B, T* prz, hipStream_t s) {
