@@ -148,3 +148,28 @@ def test_mixed_batch_of_several_scenes_is_refused():
         T.Batch([scenes.pad_press_cube(0), scenes.pad_press_cube(1)], precision=T.MIXED)
     assert ei.value.status == T.ERR_ARG
     assert "one scene per batch" in str(ei.value)
+
+
+def test_rejects_bad_precision_and_forcing():
+    T = _lib_or_skip()
+
+    def m(s):
+        s.params["pcg_forcing"] = 2
+    _expect_arg_error(T, _bad_spec(m), "pcg_forcing must be 0 or 1")
+    from paper_2504_12908_amd import scenes
+    with pytest.raises(T.TaccelError) as ei:
+        T.Scene(scenes.pad_press_cube(0), precision=7)
+    assert ei.value.status == T.ERR_ARG
+    assert "precision must be" in str(ei.value)
+
+
+def test_refined_and_fp64_scenes_do_not_share_a_batch():
+    T = _lib_or_skip()
+    from paper_2504_12908_amd import scenes
+    a = T._Desc(scenes.pad_press_cube(0), T.FP64_REFINED)
+    b = T._Desc(scenes.pad_press_cube(1), T.FP64)
+    ds = (T.taccel_scene_desc * 2)(a.desc, b.desc)
+    out = T.C.c_void_p()
+    st = T.lib().taccel_batch_create(ds, 2, None, T.C.byref(out))
+    assert st == T.ERR_ARG
+    assert b"same precision" in T.lib().taccel_last_error()
