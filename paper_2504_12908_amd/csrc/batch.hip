@@ -448,7 +448,10 @@ struct Batch::Impl {
 
   // PCG chunks replayed as a HIP graph (16 iterations = 32 kernels); re-captured when a
   // buffer it reads is reallocated or profiling is switched
-  hipGraph_t pcg_graph = nullptr;
+  // the graphs the executable was instantiated from or updated with: kept until the
+  // executable itself is destroyed (a tool that traces graph launches may still refer to
+  // the nodes it was built from)
+  std::vector<hipGraph_t> pcg_graphs;
   hipGraphExec_t pcg_exec = nullptr;
   std::vector<const void*> pcg_key;
   static constexpr int kPcgChunk = 16;
@@ -1362,9 +1365,12 @@ void Batch::Impl::run_pcg(const View& V, const PcgBufsT<T>& B, const int* nseg_d
         pcg_exec = nullptr;
       }
     }
-    if (pcg_graph) HIPCHECK(hipGraphDestroy(pcg_graph));
-    pcg_graph = graph;
-    if (!updated) HIPCHECK(hipGraphInstantiate(&pcg_exec, pcg_graph, nullptr, nullptr, 0));
+    if (!updated) {
+      for (hipGraph_t g0 : pcg_graphs) HIPCHECK(hipGraphDestroy(g0));
+      pcg_graphs.clear();
+    }
+    pcg_graphs.push_back(graph);  // owned from here on, also if instantiation fails
+    if (!updated) HIPCHECK(hipGraphInstantiate(&pcg_exec, graph, nullptr, nullptr, 0));
     pcg_key = key;
   }
   // chunks launched before the first convergence check: about 3/4 of the previous solve's
@@ -2287,7 +2293,7 @@ Batch::~Batch() {
   if (I.ev_join) (void)hipEventDestroy(I.ev_join);
   if (I.ev_join2) (void)hipEventDestroy(I.ev_join2);
   if (I.pcg_exec) (void)hipGraphExecDestroy(I.pcg_exec);
-  if (I.pcg_graph) (void)hipGraphDestroy(I.pcg_graph);
+  for (hipGraph_t g0 : I.pcg_graphs) (void)hipGraphDestroy(g0);
 #define FREE_ALL(...) for (auto* bptr : {__VA_ARGS__}) bptr->free();
   FREE_ALL(&I.x, &I.xn, &I.xhat, &I.v, &I.mass, &I.Dminv, &I.tvol, &I.val, &I.bmass,
            &I.bvol, &I.bstar, &I.blam, &I.bkap, &I.bgrad, &I.bhess, &I.bpinv, &I.cvx, &I.cpos, &I.cdisp,
