@@ -137,7 +137,10 @@ def _precision(args, taccel):
 
 
 def _set_friction(args, specs):
-    """--friction MU: the workload with the lagged friction potential (eps_v = 1e-3 m/s)."""
+    """--friction MU: the workload with the lagged friction potential (eps_v = 1e-3 m/s);
+    --pcg-forcing 1: PCG tolerances by forcing terms."""
+    for sp in specs:
+        sp.params["pcg_forcing"] = args.pcg_forcing
     if args.friction > 0.0:
         for sp in specs:
             sp.params["friction"] = args.friction
@@ -222,7 +225,7 @@ def run_single(args, taccel, scenes, np):
                              "slid 2 mm by a 400-point convex hull (796 tris), 1 scene, whole "
                              "100-step trajectory",
                     scenes=1, h=spec.params["h"], precision=args.precision,
-                    friction=args.friction),
+                    friction=args.friction, pcg_forcing=args.pcg_forcing),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         newton_iters_per_step=float(np.mean([s["newton_iters"] for s in stats])),
         pcg_iters_per_step=float(np.mean([s["pcg_iters"] for s in stats])),
@@ -303,7 +306,8 @@ def run_batch(args, taccel, scenes, np):
         config=dict(workload=f"uniform batch of {n} small pads (243 verts, 768 tets each) with "
                              "seeded 8-point hull indenters, pressed over the whole 10-step "
                              "trajectory", scenes=n, precision=args.precision,
-                    steps_per_trajectory=nst, friction=args.friction),
+                    steps_per_trajectory=nst, friction=args.friction,
+                    pcg_forcing=args.pcg_forcing),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         scene_steps_ok=ok, scene_steps=n * K, max_newton_per_step=int(max(newton)),
         create_s=t_create,
@@ -312,10 +316,16 @@ def run_batch(args, taccel, scenes, np):
     m = max(1, min(args.plain_scenes, n))
     plain_ok, plain_dt = 0, 0.0
     if m > 0:
-        warm = taccel.Scene(specs[0])
+        import copy
+        plain_specs = []
+        for sp in specs[:m]:  # plain: FP64 at the fixed PCG tolerance
+            sp2 = copy.copy(sp)
+            sp2.params = dict(sp.params, pcg_forcing=0)
+            plain_specs.append(sp2)
+        warm = taccel.Scene(plain_specs[0])
         warm.step(0)
         warm.close()
-        for sp in specs[:m]:
+        for sp in plain_specs:
             o_, d_, _, _ = _single_trajectory(taccel, sp, taccel.FP64)
             plain_ok += o_
             plain_dt += d_
@@ -578,6 +588,9 @@ def main():
     ap.add_argument("--friction", type=float, default=0.0,
                     help="friction coefficient of the single/batch workload (default 0: the "
                          "frictionless benchmark)")
+    ap.add_argument("--pcg-forcing", type=int, choices=[0, 1], default=0,
+                    help="single/batch: 1 = PCG tolerance per Newton iteration by Eisenstat-Walker "
+                         "forcing terms (default 0: the fixed tolerance)")
     ap.add_argument("--phases", type=int, default=0,
                     help="single workload: steps of a separate pass with per-phase host timing")
     ap.add_argument("--rate", type=float, default=200.0)
