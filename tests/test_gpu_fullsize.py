@@ -4,9 +4,7 @@
   teacher-forced steps of the press (both sides start every step from the oracle's state),
   max |x_gpu - x_oracle| <= 1e-8 * L, L the rest bounding-box diagonal (the slide phase is in
   test_gpu_zy_slide_phase.py, collected late: it runs 75 steps).
-* The 256-scene uniform batch (one launch per stage over all scenes): two steps of the full
-  batch, with sampled scenes compared against the oracle stepping the same scene from the same
-  state (the oracle solves one scene at a time, so a sample keeps the test within seconds).
+* The 256-scene uniform batch is in test_gpu_zzzz_batch256.py, collected last.
 """
 import numpy as np
 import pytest
@@ -46,35 +44,3 @@ def test_benchmark_scene_teacher_forced(T, oracle_lib):
             f"active {st_g['n_active']} err {err:.3e} (tol {1e-8 * L:.3e})")
         assert err <= 1e-8 * L
     g.close()
-
-
-@pytest.mark.skip(reason="a run of this 256-scene FP64 batch ended in a GPU memory fault; the "
-                         "cause (hash-bucket entries of the wrong primitive type accepted by the "
-                         "broad phase) is fixed and shown on a CPU build, and the case stays off "
-                         "until the fix has been run once on the GPU")
-def test_batch_256_sampled(T, oracle_lib):
-    specs = S.uniform_batch(256)
-    say("256-scene batch, 2 steps; scenes 0, 97 and 255 against the oracle")
-    b = T.Batch(specs)
-    picks = (0, 97, 255)
-    oracles = {i: oracle_lib.OracleScene(specs[i]) for i in picks}
-    for k in range(2):
-        # every sampled scene starts the step from the oracle's state
-        for i in picks:
-            x, v, q, qd = oracles[i].get_state()
-            b.write(i, T.FIELD_X, x)
-            b.write(i, T.FIELD_V, v)
-            b.write(i, T.FIELD_Q, q)
-            b.write(i, T.FIELD_QDOT, qd)
-        rc, per, st = b.step(k)
-        assert rc == T.OK, per
-        for i in picks:
-            rc_o, _ = oracles[i].step(k)
-            assert rc_o == 0
-            xo, _, qo, _ = oracles[i].get_state()
-            xg, qg = b.read(i, T.FIELD_X), b.read(i, T.FIELD_Q)
-            L = oracles[i].scale
-            err = max(np.abs(xg - xo).max(), np.abs(qg[:, :3] - qo[:, :3]).max())
-            say(f"  step {k} scene {i}: newton {st[i]['newton_iters']} err {err:.3e} (tol {1e-8 * L:.3e})")
-            assert err <= 1e-8 * L
-    b.close()
