@@ -232,19 +232,33 @@ LONG = os.environ.get("TACCEL_HOST_LONG") == "1"
 def test_host_build_256_batch_two_full_steps(host_lib, precision):
     """The 256-scene uniform batch through creation and two full steps, in FP64 and in mixed
     precision (several scenes per mixed batch are allowed in the host build only), with every
-    device allocation behind guard pages: no memory error, every scene converged, and every
-    scene's positions finite."""
+    device allocation behind guard pages: no memory error, every scene converged, every
+    scene's positions finite, and (FP64) scenes 0, 97 and 255, started from the oracle's state
+    each step, within 1e-8 L of the oracle.  PCG tolerance 1e-2 keeps the emulation to about
+    an hour on four threads (the converged states meet the same Newton test)."""
     run(host_lib, f"""
 import time
 specs = S.uniform_batch(256)
+fp64 = {precision == 'fp64'}
 t0 = time.time()
-b = T.Batch(specs, precision=T.{'MIXED' if precision == 'mixed' else 'FP64'})
+b = T.Batch(specs, precision=T.FP64 if fp64 else T.MIXED, pcg_eta=1e-2)
 print("created", time.time() - t0, flush=True)
+picks = (0, 97, 255)
+oracles = {{i: B.OracleScene(specs[i]) for i in picks}} if fp64 else {{}}
 for k in range(2):
+    for i, o in oracles.items():
+        x, v, q, qd = o.get_state()
+        b.write(i, T.FIELD_X, x); b.write(i, T.FIELD_V, v); b.write(i, T.FIELD_Q, q); b.write(i, T.FIELD_QDOT, qd)
     rc, per, st = b.step(k)
     print("step", k, "ok", int((per == 0).sum()), "max newton", max(s["newton_iters"] for s in st),
           time.time() - t0, flush=True)
     assert (per == 0).all(), per
+    for i, o in oracles.items():
+        assert o.step(k)[0] == 0
+        xo, _, qo, _ = o.get_state()
+        err = max(np.abs(b.read(i, T.FIELD_X) - xo).max(), np.abs(b.read(i, T.FIELD_Q)[:, :3] - qo[:, :3]).max())
+        print("  scene", i, "err", err, flush=True)
+        assert err <= 1e-8 * o.scale
 for i in range(256):
     assert np.isfinite(b.read(i, T.FIELD_X)).all()
 b.close()
