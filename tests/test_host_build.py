@@ -138,13 +138,14 @@ def test_host_build_fp64_refined(host_lib):
     """TACCEL_FP64_REFINED (FP32 PCG passes on an FP32 copy of the FP64 system, FP64 residual
     refinement): teacher-forced cube steps match the oracle within 1e-8 L with a PCG tolerance
     (1e-7) that one FP32 pass cannot meet, so refinement passes run (more passes than Newton
-    directions); a batch of two scenes equals each scene alone, bit for bit."""
+    directions; one step here, four in the GPU test file); a batch of two scenes equals each
+    scene alone, bit for bit."""
     out = run(host_lib, """
 spec = S.pad_press_cube(0)
 o = B.OracleScene(spec)
 g = T.Scene(spec, precision=T.FP64_REFINED, pcg_eta=1e-7)
 T.profile_reset(); T.profile_enable(True)
-for k in range(2):
+for k in range(1):
     g.set_state(*o.get_state())
     rc_o, _ = o.step(k)
     rc, st = g.step(k)
