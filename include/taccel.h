@@ -42,7 +42,7 @@ typedef enum {
 /* MIXED: FP32 Hessian blocks, assembly, SpMV and PCG; FP64 positions, gradient, contact,
  * CCD and convergence test.  A batch with more than one scene must use FP64 or
  * FP64_REFINED (ERR_ARG).
- * FP64_REFINED: every term, block and the assembly in FP64, as FP64; the PCG iterations run
+ * FP64_REFINED: every term, block and the assembly as in FP64 mode; the PCG iterations run
  * on an FP32 copy of the FP64 system (half the bytes per sparse product), and the FP64
  * residual of the system decides whether another FP32 pass solves for a correction
  * (mixed-precision iterative refinement, the stronger-solver item of the paper's stated PCG
